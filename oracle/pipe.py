@@ -1,0 +1,374 @@
+"""Oracle: discrete perturbation Navier-Stokes step for pulsatile pipe flow,
+its tangent and its exact discrete adjoint (all FP64, NumPy/SciPy).
+
+What is computed (paper Sec. 2 and 2.3; readings listed in the design notes):
+
+Fields are Fourier-Galerkin series in theta and z (Sec. 2.3, Fourier
+expansion), stored as complex coefficients F[c, j, m, kk] with component c in
+(r, theta, z), radial node j, azimuthal index m = 0..M and axial index kk in
+FFT order (k = 0..K, -K..-1); the m = 0 column is Hermitian in k.  The
+retained band |m| <= M = (N_theta-1)//3, |k| <= K = (N_z-1)//3 makes the
+N_theta x N_z physical grid a 3/2-rule dealiasing grid.
+
+The perturbation equation (Sec. 2, direct Navier-Stokes equations) is taken
+in rotational form,
+    du/dt = u x w + U x w + u x Om - grad p' - f_z e_z + (1/Re) lap u,
+with w = curl u, U = U(r,t) e_z the Womersley flow and Om = curl U; the
+gradient of (|u|^2/2 + U.u) is absorbed in the pressure.  Time stepping is the
+second-order predictor-corrector of Sec. 2.3: Crank-Nicolson on the viscous
+term, explicit Euler predictor and trapezoidal corrector for the convective
+terms, the pressure and the flux-holding gradient f_z implicit in both stages:
+    u*      = S(E u^n + N(u^n, t_n))
+    u^{n+1} = S(E u^n + (N(u^n, t_n) + N(u*, t_{n+1})) / 2).
+S is the per-mode solve of H u + grad p = R, div u = 0, u(1) = 0 with the
+influence-matrix correction for the wall (Sec. 2.3, wall boundary conditions)
+and, for the mean mode, the zero-flux constraint (Sec. 2, zero bulk velocity).
+
+The adjoint is the exact transpose of this discrete step in the W inner
+product <a,b>_W = 2 pi L_z sum_{k,m} c_m sum_j w_j Re(conj a . b), c_0 = 1,
+c_{m>0} = 2 (Sec. 2, definition of <...>).  Linear per-mode maps (E, curl,
+S) are materialised as dense matrices A, and their adjoints are formed as
+W^{-1} A^H W.  The convective adjoint uses the identity
+    <y, P_K F[a x b]>_W = <Y, a x b>_phys
+for band-limited y, which gives
+    N'(u)^dag y = P_K F[(Om + w_u) x Y] + curl^dag P_K F[Y x (U + u)].
+"""
+import numpy as np
+import scipy.linalg as sl
+
+from .radial import Radial
+from . import womersley
+
+
+def sizes(ntheta, nz):
+    """Retained band (M, K) of a N_theta x N_z 3/2-rule physical grid."""
+    return (ntheta - 1) // 3, (nz - 1) // 3
+
+
+class Pipe:
+    """One discretised problem: grid, flow parameters, time step."""
+
+    def __init__(self, nr, ntheta, nz, lz, re, wo, amp, dt, tau0=0.0):
+        self.nr, self.ntheta, self.nz = nr, ntheta, nz
+        self.lz, self.re, self.wo, self.amp = float(lz), float(re), float(wo), float(amp)
+        self.dt, self.tau0 = float(dt), float(tau0)
+        self.M, self.K = sizes(ntheta, nz)
+        self.nk = 2 * self.K + 1
+        kk = np.arange(self.nk)
+        self.kint = np.where(kk <= self.K, kk, kk - self.nk)
+        self.k0 = 2.0 * np.pi / self.lz
+        self.alpha = self.kint * self.k0
+        self.rad = Radial(nr)
+        self.r, self.w = self.rad.r, self.rad.w
+        self.cm = np.array([1.0] + [2.0] * self.M)
+        self.shape = (3, nr, self.M + 1, self.nk)
+        self._lu = {}
+        self._mats = {}
+        self.cache_bytes = 0
+        self.cache_limit = 4 << 30
+
+    # ------------------------------------------------------------------ basics
+    def zeros(self):
+        return np.zeros(self.shape, dtype=complex)
+
+    def wdot(self, a, b):
+        """<a, b>_W, the discrete form of the paper's volume integral."""
+        s = np.einsum('j,m,cjmk->', self.w, self.cm, (np.conj(a) * b).real)
+        return 2.0 * np.pi * self.lz * s
+
+    def energy(self, u):
+        return 0.5 * self.wdot(u, u)
+
+    def time(self, n):
+        return self.tau0 + n * self.dt
+
+    def base(self, t):
+        return womersley.base_flow(self.r, t, self.re, self.wo, self.amp)
+
+    def modes(self):
+        """Iterate (m, kk, alpha) over all stored modes."""
+        for m in range(self.M + 1):
+            for kk in range(self.nk):
+                yield m, kk, self.alpha[kk]
+
+    # ------------------------------------------------------- radial operators
+    def lap(self, n, alpha):
+        return self.rad.lap(n, alpha)
+
+    def _factor(self, kind, n, alpha):
+        key = (kind, abs(n), round(abs(alpha), 14))
+        f = self._lu.get(key)
+        if f is None:
+            L = self.lap(n, alpha)
+            if kind == 'H':
+                A = np.eye(self.nr) / self.dt - L / (2.0 * self.re)
+            else:
+                A = L
+            f = sl.lu_factor(A[:-1, :-1])
+            self._lu[key] = f
+        return f
+
+    def _inv(self, kind, n, alpha, b):
+        """Interior solve with wall column removed; b complex (nr-1, ...)."""
+        f = self._factor(kind, n, alpha)
+        return sl.lu_solve(f, b.real) + 1j * sl.lu_solve(f, b.imag)
+
+    def _par(self, n):
+        return self.rad.parity(n)
+
+    # ----------------------------------------------------- per-mode linear maps
+    def curl_mode(self, m, alpha, u):
+        """Spectral curl of one mode; u has shape (3, nr, ...)."""
+        r = self.r.reshape((-1,) + (1,) * (u.ndim - 2))
+        D1z = self.rad.D1[self._par(m)]
+        D1t = self.rad.D1[self._par(m + 1)]
+        ur, ut, uz = u[0], u[1], u[2]
+        wr = 1j * m / r * uz - 1j * alpha * ut
+        wt = 1j * alpha * ur - np.tensordot(D1z, uz, axes=(1, 0))
+        wz = np.tensordot(D1t, ut, axes=(1, 0)) + ut / r - 1j * m / r * ur
+        return np.stack([wr, wt, wz])
+
+    def E_mode(self, m, alpha, u):
+        """E u = u/dt + lap(u)/(2 Re), vector Laplacian in the (u+, u-) basis."""
+        up = u[0] + 1j * u[1]
+        um = u[0] - 1j * u[1]
+        c = 1.0 / (2.0 * self.re)
+        Ep = up / self.dt + c * np.tensordot(self.lap(m + 1, alpha), up, axes=(1, 0))
+        Em = um / self.dt + c * np.tensordot(self.lap(m - 1, alpha), um, axes=(1, 0))
+        Ez = u[2] / self.dt + c * np.tensordot(self.lap(m, alpha), u[2], axes=(1, 0))
+        return np.stack([0.5 * (Ep + Em), (Ep - Em) / 2j, Ez])
+
+    def S_mode(self, m, alpha, R, return_p=False):
+        """Solve H u + grad p = R, div u = 0, u(1) = 0 for one mode.
+
+        R has shape (3, nr, ncol).  Steps (Sec. 2.3 influence-matrix method):
+        particular pressure from lap p = div R with p(1) = 0, particular
+        velocities from H u = R - grad p with u(1) = 0; homogeneous pressure
+        lap p_h = 0, p_h(1) = 1, and H u_h = -grad p_h; the multiple of the
+        homogeneous pair that zeroes d(u_r)/dr at the wall (the discrete wall
+        divergence) is added.  The mean mode (0, 0) has u_r = 0 and its axial
+        part carries the flux-holding gradient f_z (Sec. 2, pressure split).
+        """
+        nr = self.nr
+        r = self.r[:, None]
+        ncol = R.shape[2]
+        u = np.zeros((3, nr, ncol), dtype=complex)
+        if m == 0 and alpha == 0.0:
+            u[1, :-1] = self._inv('H', 1, 0.0, R[1, :-1])
+            uz = self._inv('H', 0, 0.0, R[2, :-1])
+            g = self._inv('H', 0, 0.0, np.ones((nr - 1, 1), dtype=complex))
+            wi = self.w[:-1]
+            c = -(wi @ uz) / (wi @ g)
+            u[2, :-1] = uz + g * c[None, :]
+            return u
+        D1o = self.rad.D1[self._par(m + 1)]      # parity of u_r, u_theta, u+-
+        D1e = self.rad.D1[self._par(m)]          # parity of u_z and p
+        Rp = R[0] + 1j * R[1]
+        Rm = R[0] - 1j * R[1]
+        div = 0.5 * (D1o @ Rp + (1 + m) / r * Rp + D1o @ Rm + (1 - m) / r * Rm) + 1j * alpha * R[2]
+        p = np.zeros((nr, ncol), dtype=complex)
+        p[:-1] = self._inv('P', m, alpha, div[:-1])
+        gp = (D1e @ p - m / r * p)[:-1]
+        gm = (D1e @ p + m / r * p)[:-1]
+        gz = 1j * alpha * p[:-1]
+        up = np.zeros((nr, ncol), dtype=complex)
+        um = np.zeros((nr, ncol), dtype=complex)
+        uz = np.zeros((nr, ncol), dtype=complex)
+        up[:-1] = self._inv('H', m + 1, alpha, Rp[:-1] - gp)
+        um[:-1] = self._inv('H', m - 1, alpha, Rm[:-1] - gm)
+        uz[:-1] = self._inv('H', m, alpha, R[2, :-1] - gz)
+        # homogeneous pair
+        L = self.lap(m, alpha)
+        ph = np.zeros((nr, 1), dtype=complex)
+        ph[-1] = 1.0
+        ph[:-1] = -self._inv('P', m, alpha, L[:-1, -1:].astype(complex))
+        hp = np.zeros((nr, 1), dtype=complex)
+        hm = np.zeros((nr, 1), dtype=complex)
+        hz = np.zeros((nr, 1), dtype=complex)
+        hp[:-1] = self._inv('H', m + 1, alpha, -(D1e @ ph - m / r * ph)[:-1])
+        hm[:-1] = self._inv('H', m - 1, alpha, -(D1e @ ph + m / r * ph)[:-1])
+        hz[:-1] = self._inv('H', m, alpha, -(1j * alpha * ph)[:-1])
+        s = D1o[-1] @ (up + um)
+        sh = (D1o[-1] @ (hp + hm))[0]
+        a = -s / sh
+        up = up + hp * a[None, :]
+        um = um + hm * a[None, :]
+        uz = uz + hz * a[None, :]
+        u[0] = 0.5 * (up + um)
+        u[1] = (up - um) / 2j
+        u[2] = uz
+        if return_p:
+            return u, p + ph * a[None, :]
+        return u
+
+    def mode_matrix(self, kind, m, alpha):
+        """Dense 3nr x 3nr matrix of a per-mode linear map."""
+        n3 = 3 * self.nr
+        eye = np.eye(n3, dtype=complex).reshape(3, self.nr, n3)
+        if kind == 'S':
+            A = self.S_mode(m, alpha, eye)
+        elif kind == 'E':
+            A = self.E_mode(m, alpha, eye)
+        elif kind == 'C':
+            A = self.curl_mode(m, alpha, eye)
+        else:
+            raise ValueError(kind)
+        return A.reshape(n3, n3)
+
+    def adjoint_matrix(self, kind, m, alpha):
+        """W^{-1} A^H W for the per-mode map A (the W-adjoint)."""
+        A = self.mode_matrix(kind, m, alpha)
+        wv = np.tile(self.w, 3)
+        return (A.conj().T * wv[None, :]) / wv[:, None]
+
+    def _stack_m(self, kind, adjoint, m):
+        """Matrices of all axial modes at azimuthal index m, (nk, 3nr, 3nr)."""
+        key = (kind, adjoint, m)
+        A = self._mats.get(key)
+        if A is None:
+            f = self.adjoint_matrix if adjoint else self.mode_matrix
+            A = np.stack([f(kind, m, a) for a in self.alpha])
+            if self.cache_bytes + A.nbytes <= self.cache_limit:
+                self._mats[key] = A
+                self.cache_bytes += A.nbytes
+        return A
+
+    def apply_modes(self, F, kind, adjoint=False):
+        """Apply a per-mode map (kind in 'S', 'E', 'C') to a whole field."""
+        n3 = 3 * self.nr
+        out = np.empty_like(F)
+        for m in range(self.M + 1):
+            A = self._stack_m(kind, adjoint, m)
+            x = F[:, :, m, :].reshape(n3, self.nk)
+            out[:, :, m, :] = np.einsum('kab,bk->ak', A, x).reshape(3, self.nr, self.nk)
+        return out
+
+    def S(self, R):
+        return self.apply_modes(R, 'S')
+
+    def S_direct(self, R):
+        """S applied mode by mode through the literal solve (no matrices)."""
+        out = np.empty_like(R)
+        for m in range(self.M + 1):
+            for kk in range(self.nk):
+                out[:, :, m, kk:kk + 1] = self.S_mode(m, self.alpha[kk], R[:, :, m, kk:kk + 1])
+        return out
+
+    def curl(self, u):
+        out = np.empty_like(u)
+        for m in range(self.M + 1):
+            out[:, :, m, :] = self.curl_mode(m, self.alpha[None, :], u[:, :, m, :])
+        return out
+
+    def E(self, u):
+        return self.apply_modes(u, 'E')
+
+    # ---------------------------------------------------------- transforms
+    def to_phys(self, F):
+        """f(theta_a, z_b) = sum_{m,k} F e^{i(m theta_a + alpha_k z_b)}, real.
+
+        F has shape (..., M+1, nk); the m = 0 column enters through its real
+        part after the z transform (Hermitian series in theta)."""
+        lead = F.shape[:-2]
+        Z = np.zeros(lead + (self.nz, self.ntheta // 2 + 1), dtype=complex)
+        kpos = np.where(self.kint >= 0, self.kint, self.nz + self.kint)
+        Z[..., kpos, :self.M + 1] = np.swapaxes(F, -1, -2)
+        Z = np.fft.ifft(Z, axis=-2) * self.nz
+        Z[..., 0] = Z[..., 0].real
+        return np.fft.irfft(Z, n=self.ntheta, axis=-1) * self.ntheta   # (..., nz, ntheta)
+
+    def to_spec(self, f):
+        """P_K F f: coefficients (1/(Nt Nz)) sum f e^{-i(...)} on the retained band."""
+        X = np.fft.fft(np.fft.rfft(f, axis=-1), axis=-2) / (self.ntheta * self.nz)
+        kpos = np.where(self.kint >= 0, self.kint, self.nz + self.kint)
+        return np.swapaxes(X[..., kpos, :self.M + 1], -1, -2)
+
+    @staticmethod
+    def cross(a, b):
+        return np.stack([a[1] * b[2] - a[2] * b[1],
+                         a[2] * b[0] - a[0] * b[2],
+                         a[0] * b[1] - a[1] * b[0]])
+
+    # ------------------------------------------------------ nonlinear terms
+    def base_terms(self, v, wv, t):
+        """U x curl(v) + v x Om, mode-diagonal (U and Om depend on r only)."""
+        U, Om = self.base(t)
+        U = U[:, None, None]
+        Om = Om[:, None, None]
+        return np.stack([-U * wv[1] - Om * v[2], U * wv[0], Om * v[0]])
+
+    def N(self, u, t):
+        """N(u, t) = P_K F[u x w] + U x w + u x Om."""
+        w = self.curl(u)
+        nl = self.to_spec(self.cross(self.to_phys(u), self.to_phys(w)))
+        return nl + self.base_terms(u, w, t)
+
+    def N_tan(self, u, t, v):
+        """Tangent of N at u in direction v."""
+        wu, wv = self.curl(u), self.curl(v)
+        pu, pv = self.to_phys(u), self.to_phys(v)
+        nl = self.to_spec(self.cross(pv, self.to_phys(wu)) + self.cross(pu, self.to_phys(wv)))
+        return nl + self.base_terms(v, wv, t)
+
+    def N_adj(self, u, t, y):
+        """W-adjoint of the tangent of N at u, applied to y."""
+        U, Om = self.base(t)
+        wu = self.curl(u)
+        Y = self.to_phys(y)
+        a = self.to_spec(self.cross(self.to_phys(wu), Y))
+        b = self.to_spec(self.cross(Y, self.to_phys(u)))
+        Uc = U[:, None, None]
+        Oc = Om[:, None, None]
+        a = a + np.stack([Oc * y[2], np.zeros_like(y[1]), -Oc * y[0]])       # Om x y
+        b = b + np.stack([Uc * y[1], -Uc * y[0], np.zeros_like(y[2])])       # y x U
+        return a + self.apply_modes(b, 'C', adjoint=True)
+
+    # ------------------------------------------------------------ stepping
+    def step(self, u, n):
+        """u^n -> u^{n+1} (predictor-corrector)."""
+        t0, t1 = self.time(n), self.time(n + 1)
+        Nn = self.N(u, t0)
+        Eu = self.E(u)
+        us = self.S(Eu + Nn)
+        Ns = self.N(us, t1)
+        return self.S(Eu + 0.5 * (Nn + Ns))
+
+    def predictor(self, u, n):
+        return self.S(self.E(u) + self.N(u, self.time(n)))
+
+    def step_tan(self, u, n, v):
+        """Tangent of the step at u^n in direction v."""
+        t0, t1 = self.time(n), self.time(n + 1)
+        us = self.predictor(u, n)
+        Ev = self.E(v)
+        Nv = self.N_tan(u, t0, v)
+        vs = self.S(Ev + Nv)
+        return self.S(Ev + 0.5 * (Nv + self.N_tan(us, t1, vs)))
+
+    def step_adj(self, u, n, lam):
+        """W-adjoint of the step tangent at u^n applied to lam^{n+1}."""
+        t0, t1 = self.time(n), self.time(n + 1)
+        us = self.predictor(u, n)
+        muC = self.apply_modes(lam, 'S', adjoint=True)
+        lstar = 0.5 * self.N_adj(us, t1, muC)
+        muP = self.apply_modes(lstar, 'S', adjoint=True)
+        return (self.apply_modes(muC + muP, 'E', adjoint=True)
+                + self.N_adj(u, t0, 0.5 * muC + muP))
+
+    def forward(self, u0, nsteps, keep=False):
+        """Integrate nsteps; returns u^N (and all u^n, n < N, if keep)."""
+        u = u0
+        hist = []
+        for n in range(nsteps):
+            if keep:
+                hist.append(u)
+            u = self.step(u, n)
+        return (u, hist) if keep else u
+
+    def gradient(self, u0, nsteps):
+        """J = E(u^N) and its W-gradient lam^0 (unprojected)."""
+        uN, hist = self.forward(u0, nsteps, keep=True)
+        lam = uN.copy()
+        for n in range(nsteps - 1, -1, -1):
+            lam = self.step_adj(hist[n], n, lam)
+        return self.energy(uN), uN, lam
