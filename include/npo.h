@@ -1,0 +1,165 @@
+/*
+ * npo.h -- C ABI of the MI355X hot path of the nonlinear-optimal-perturbation
+ * (NLOP) method for pulsatile pipe flow: Keuchel & Avila, "Nonlinear optimal
+ * perturbation growth in pulsatile pipe flow", arXiv 2509.10103.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Units are the paper's (Sec. 2): lengths in pipe radii, velocities in twice
+ * the mean bulk velocity, time in radius / (2 x bulk velocity).  The laminar
+ * flow is the Sexl-Womersley profile with bulk velocity
+ * u_b(t) = 1/2 [1 + A sin(2 pi t / T)], T = 2 pi Re / Wo^2 (Sec. 2).
+ *
+ * A "field" is a complex128 array [3][nr][M+1][2K+1] (interleaved re/im
+ * doubles) in device memory: components (u_r, u_theta, u_z), radial node j
+ * (r_j ascending, r_{nr-1} = 1 is the wall), azimuthal index m = 0..M and axial
+ * index kk in FFT order (k = 0..K, -K..-1), with M = (ntheta-1)/3 and
+ * K = (nz-1)/3 so that the ntheta x nz physical grid is the 3/2-rule
+ * dealiasing grid of the Fourier-Galerkin expansion (Sec. 2.3).  The m = 0
+ * column is a Hermitian series in k.  Inner products are the discrete form of
+ * the paper's volume integral <.> (Sec. 2):
+ *   <a,b>_W = 2 pi L_z sum_{k,m} c_m sum_j w_j Re(conj(a) . b), c_0 = 1, c_m = 2.
+ *
+ * Ownership: the caller owns every device buffer passed in (fields, the
+ * workspace, the checkpoint arena, device scalars).  A plan owns only its
+ * constant device tables, allocated by npo_plan_create and released by
+ * npo_plan_destroy.  No call after plan creation allocates device memory.
+ *
+ * Asynchrony: every call that takes `stream` (a hipStream_t; NULL is the
+ * default stream) only enqueues work on that stream unless stated otherwise;
+ * outputs are valid once the stream reaches that point.  Calls that return a
+ * host scalar say so and synchronise the stream.
+ *
+ * Errors: argument and shape errors return synchronously (NPO_EINVAL,
+ * NPO_EUNSUPPORTED) before anything is enqueued; launch and runtime errors
+ * return NPO_EHIP.  npo_last_error() gives a message for the calling thread.
+ */
+#ifndef NPO_H
+#define NPO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t npo_status;
+#define NPO_OK            0
+#define NPO_EINVAL       -1   /* bad argument or size                           */
+#define NPO_ENOMEM       -2   /* plan tables could not be allocated              */
+#define NPO_EHIP         -3   /* a HIP runtime or launch error                   */
+#define NPO_EUNSUPPORTED -4   /* grid outside the sizes the kernels support      */
+#define NPO_ESTATE       -5   /* call out of order (e.g. no forward sweep yet)   */
+
+/* Grid: nr radial nodes (8..64), ntheta and nz physical points (products of 2
+ * and 3, ntheta in 6..128, nz in 6..2048), pipe length lz in radii. */
+typedef struct { int32_t nr, ntheta, nz; double lz; } npo_grid;
+/* Flow: Re (diameter and mean bulk velocity), Womersley number Wo, pulsation
+ * amplitude A = U_max/U_bar - 1 (Sec. 1). A = 0 is steady Hagen-Poiseuille. */
+typedef struct { double re, wo, amp; } npo_flow;
+/* Time: step dt, initial time tau0 (the perturbation is introduced at t0,
+ * Sec. 2) and horizon nsteps, so the gain is evaluated at tau0 + nsteps*dt. */
+typedef struct { double dt, t0; int64_t nsteps; } npo_time;
+
+typedef struct npo_plan_s* npo_plan;
+
+typedef struct {
+    int32_t nr, ntheta, nz, M, K, nk;   /* nk = 2K+1                              */
+    int64_t field_elems;                /* complex elements per field = 3*nr*(M+1)*nk */
+    int64_t field_bytes;                /* 16 * field_elems                       */
+    int64_t workspace_bytes;            /* device workspace every run call needs  */
+    int64_t scalars_bytes;              /* device scalar block for npo_iterate    */
+    double period, k0, dt, t0;
+    int64_t nsteps;
+} npo_info;
+
+/* Message describing the last error on this thread ("" if none). */
+const char* npo_last_error(void);
+
+/* Build a plan: radial nodes r_j = cos(pi (nr-1-j)/(2 nr-1)), quadrature
+ * weights w_j (interpolatory in r^2), sixth-order 7-point FD weights with
+ * parity folding at the axis and one-sided wall rows (Sec. 2.3), Womersley
+ * profile tables (Sec. 2), FFT twiddles.  Allocates the plan's device tables
+ * on the current device.  flags must be 0. */
+npo_status npo_plan_create(const npo_grid* grid, const npo_flow* flow, const npo_time* time,
+                           uint32_t flags, npo_plan* out);
+npo_status npo_plan_destroy(npo_plan plan);
+npo_status npo_plan_info(npo_plan plan, npo_info* out);
+
+/* Host copies of the plan's radial tables: r[nr], w[nr], and the FD weights
+ * D1[2][nr][7], D2[2][nr][7] (parity index 0 = even, 1 = odd) acting on the
+ * nodes col0[j] .. col0[j]+6.  Any pointer may be NULL. */
+npo_status npo_plan_tables(npo_plan plan, double* r, double* w, double* D1, double* D2, int32_t* col0);
+
+/* Laminar Sexl-Womersley flow at time t (Sec. 2): U(r_j,t) and
+ * Omega_theta(r_j,t) = -dU/dr, written to host arrays of length nr. */
+npo_status npo_base_flow(npo_plan plan, double t, double* U, double* Om);
+
+/* Pieces of the step, exposed for testing each kernel (all device pointers,
+ * workspace ws of workspace_bytes):
+ *   npo_nonlinear:     out = P_K F[u x w] + U x w + u x Om at time t, w = curl u
+ *                      (dealiased convective term, Sec. 2 direct equations);
+ *   npo_nonlinear_adj: out = W-adjoint of the tangent of the above at u, applied to y;
+ *   npo_solve:         out = S(R): H out + grad p = R, div out = 0, out(1) = 0,
+ *                      with zero flux for the mean mode (Sec. 2.3);
+ *   npo_solve_adj:     out = W-adjoint of S applied to y. */
+npo_status npo_nonlinear(npo_plan plan, void* ws, const void* u, double t, void* out, void* stream);
+npo_status npo_nonlinear_adj(npo_plan plan, void* ws, const void* u, double t, const void* y,
+                             void* out, void* stream);
+npo_status npo_solve(npo_plan plan, void* ws, const void* R, void* out, void* stream);
+npo_status npo_solve_adj(npo_plan plan, void* ws, const void* y, void* out, void* stream);
+
+/* One predictor-corrector step u^n -> u^{n+1} at t_n = t0 + n dt (Sec. 2.3).
+ * u_n and u_np1 may alias. */
+npo_status npo_forward_step(npo_plan plan, void* ws, const void* u_n, void* u_np1, int64_t n,
+                            void* stream);
+/* Exact discrete adjoint of that step (W inner product): lam_n = Phi'(u_n)^dag lam_np1
+ * (Sec. 2 adjoint equations, integrated backward). lam_n may alias lam_np1. */
+npo_status npo_adjoint_step(npo_plan plan, void* ws, const void* u_n, const void* lam_np1,
+                            void* lam_n, int64_t n, void* stream);
+
+/* Forward sweep over the plan's nsteps from u0 to uN, storing binomial
+ * checkpoints (Sec. 2.4) into `ckpt`, an arena of n_ckpt fields (n_ckpt >= 1;
+ * slot 0 receives u0).  The arena must not be touched before the matching
+ * npo_adjoint_run. */
+npo_status npo_forward_run(npo_plan plan, void* ws, void* ckpt, int32_t n_ckpt, const void* u0,
+                           void* uN, void* stream);
+/* Backward adjoint sweep from lamN to lam0 using the checkpoints of the last
+ * npo_forward_run with the same arena and n_ckpt.  *n_recompute (host) receives
+ * the forward steps re-advanced from checkpoints; together with the nsteps-1
+ * advances of the forward sweep they equal S N - beta(N_G+1, S-1) (Sec. 2.4).
+ * The result does not depend on n_ckpt. */
+npo_status npo_adjoint_run(npo_plan plan, void* ws, void* ckpt, int32_t n_ckpt, const void* lamN,
+                           void* lam0, int64_t* n_recompute, void* stream);
+/* Host-side count of the checkpoint schedule without running it. */
+npo_status npo_ckpt_count(int64_t nsteps, int32_t n_ckpt, int64_t* n_recompute);
+
+/* out_dev[0] = <a,b>_W (deterministic fixed-order reduction). */
+npo_status npo_inner(npo_plan plan, void* ws, const void* a, const void* b, double* out_dev,
+                     void* stream);
+/* out = P_h u: W-orthogonal projection onto admissible perturbations (zero
+ * wall velocity, zero discrete divergence at every node, zero flux and u_r = 0
+ * for the mean mode); the normal equations are solved twice (one refinement).
+ * out may alias u. */
+npo_status npo_project(npo_plan plan, void* ws, const void* u, void* out, void* stream);
+/* Gradient step of Sec. 2.2: u_new = (1 + lambda_+ alpha) u0 - alpha udag with
+ * lambda_+ the '+' root of the energy constraint (E0dag = <udag,udag>/2,
+ * C0 = <u0,udag> given), then rescaled to energy e0 on the device. */
+npo_status npo_update(npo_plan plan, void* ws, const void* u0, const void* udag, double e0,
+                      double alpha, double e0dag, double c0, void* u_new, void* stream);
+
+/* One adjoint-looping iteration (Sec. 2.1-2.2) on the host: requires that the
+ * arena holds the forward sweep of u0 (npo_forward_run, or the accepted trial
+ * of the previous iterate) with u^N in uN.  Runs the adjoint sweep, projects
+ * the gradient, and does the backtracking line search (alpha = alpha_max,
+ * halve while G does not increase, stop when |dG/G| < tol or after
+ * max_halvings).  On acceptance u0 and uN hold the new iterate and the arena its
+ * sweep.  stats (host, 8 doubles): G_old, G_new, alpha, alpha_max, E0dag, C0,
+ * accepted (1/0), forward sweeps run.  Synchronises the stream. */
+npo_status npo_iterate(npo_plan plan, void* ws, void* ckpt, int32_t n_ckpt, void* u0, void* uN,
+                       double e0, double tol, int32_t max_halvings, double* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NPO_H */

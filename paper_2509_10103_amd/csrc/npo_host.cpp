@@ -1,0 +1,711 @@
+// Host side of the NLOP hot path: plan tables, workspace layout, step and
+// sweep drivers, binomial checkpoint schedule and the exported C ABI.
+#include "npo_internal.h"
+#include "../../include/npo.h"
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_err;
+
+npo_status fail(npo_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+npo_status hipfail(hipError_t e, const char* where) {
+    return fail(NPO_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+#define HIPCHK(expr)                                   \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return hipfail(e_, #expr); \
+    } while (0)
+
+using ld = long double;
+
+// ---------------------------------------------------------------- tables
+// Radial nodes: positive half of a 2N-point Chebyshev-Gauss-Lobatto grid.
+std::vector<ld> radial_nodes(int nr) {
+    std::vector<ld> r(nr);
+    const ld pi = acosl(-1.0L);
+    for (int j = 0; j < nr; ++j) r[j] = cosl(pi * (ld)(nr - 1 - j) / (ld)(2 * nr - 1));
+    r[nr - 1] = 1.0L;
+    return r;
+}
+
+// Gaussian elimination with partial pivoting (small dense, long double).
+std::vector<ld> dense_solve(std::vector<ld> A, std::vector<ld> b, int n) {
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < n; ++i)
+            if (fabsl(A[i * n + k]) > fabsl(A[piv * n + k])) piv = i;
+        if (piv != k) {
+            for (int c = 0; c < n; ++c) std::swap(A[k * n + c], A[piv * n + c]);
+            std::swap(b[k], b[piv]);
+        }
+        for (int i = k + 1; i < n; ++i) {
+            const ld l = A[i * n + k] / A[k * n + k];
+            for (int c = k; c < n; ++c) A[i * n + c] -= l * A[k * n + c];
+            b[i] -= l * b[k];
+        }
+    }
+    std::vector<ld> x(n);
+    for (int i = n - 1; i >= 0; --i) {
+        ld s = b[i];
+        for (int c = i + 1; c < n; ++c) s -= A[i * n + c] * x[c];
+        x[i] = s / A[i * n + i];
+    }
+    return x;
+}
+
+// Interpolatory weights of int_0^1 g(r) r dr on the nodes, exact for
+// polynomials of degree < nr in s = r^2 (Chebyshev-moment formulation).
+std::vector<ld> quad_weights(const std::vector<ld>& r) {
+    const int n = (int)r.size();
+    std::vector<ld> A(n * n), b(n);
+    for (int k = 0; k < n; ++k) {
+        for (int j = 0; j < n; ++j) {
+            const ld x = 2.0L * r[j] * r[j] - 1.0L;
+            // T_k(x) by recurrence
+            ld t0 = 1.0L, t1 = x, tk = (k == 0) ? t0 : t1;
+            for (int q = 2; q <= k; ++q) {
+                tk = 2.0L * x * t1 - t0;
+                t0 = t1;
+                t1 = tk;
+            }
+            A[k * n + j] = tk;
+        }
+        b[k] = (k % 2 == 0) ? 1.0L / (1.0L - (ld)k * (ld)k) : 0.0L;   // int_0^1 T_k(2s-1) ds
+    }
+    std::vector<ld> W = dense_solve(A, b, n);
+    for (auto& v : W) v *= 0.5L;
+    return W;
+}
+
+// Fornberg's recursion for FD weights at x0 on nodes x[0..n-1], derivative
+// orders 0..2; returns c[d][i].
+void fornberg(ld x0, const ld* x, int n, ld c[3][7]) {
+    ld c1 = 1.0L, c4 = x[0] - x0;
+    for (int d = 0; d < 3; ++d)
+        for (int i = 0; i < n; ++i) c[d][i] = 0.0L;
+    c[0][0] = 1.0L;
+    for (int i = 1; i < n; ++i) {
+        const int mn = std::min(i, 2);
+        ld c2 = 1.0L;
+        const ld c5 = c4;
+        c4 = x[i] - x0;
+        for (int j = 0; j < i; ++j) {
+            const ld c3 = x[i] - x[j];
+            c2 *= c3;
+            if (j == i - 1) {
+                for (int k = mn; k >= 1; --k) c[k][i] = c1 * (k * c[k - 1][i - 1] - c5 * c[k][i - 1]) / c2;
+                c[0][i] = -c1 * c5 * c[0][i - 1] / c2;
+            }
+            for (int k = mn; k >= 1; --k) c[k][j] = (c4 * c[k][j] - k * c[k - 1][j]) / c3;
+            c[0][j] = c4 * c[0][j] / c3;
+        }
+        c1 = c2;
+    }
+}
+
+// Complex Bessel J0, J1 by their power series (|z| <= ~25 in long double).
+void bessel01(std::complex<ld> z, std::complex<ld>& J0, std::complex<ld>& J1) {
+    const std::complex<ld> q = -0.25L * z * z;
+    std::complex<ld> t0 = 1.0L, t1 = 0.5L * z;
+    J0 = t0;
+    J1 = t1;
+    for (int k = 1; k < 200; ++k) {
+        t0 *= q / ((ld)k * (ld)k);
+        t1 *= q / ((ld)k * (ld)(k + 1));
+        J0 += t0;
+        J1 += t1;
+        if (std::abs(t0) < 1e-30L * std::abs(J0) && std::abs(t1) < 1e-30L * std::abs(J1) && k > 10) break;
+    }
+}
+
+std::vector<int> radix_factors(int n) {
+    std::vector<int> f;
+    while (n % 4 == 0) { f.push_back(4); n /= 4; }
+    while (n % 2 == 0) { f.push_back(2); n /= 2; }
+    while (n % 3 == 0) { f.push_back(3); n /= 3; }
+    if (n != 1) f.clear();
+    return f;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// --------------------------------------------------- binomial checkpointing
+// T(l, s): minimal forward advances to reverse l steps from a stored start
+// with s slots in total (Sec. 2.4 closed form).
+long long beta(long long n, long long s) {   // C(n + s, n), saturating
+    long double v = 1.0L;
+    for (long long i = 1; i <= s; ++i) {
+        v = v * (long double)(n + i) / (long double)i;
+        if (v > 9e18L) return (long long)9e18;
+    }
+    return (long long)(v + 0.5L);
+}
+long long adv_cost(long long l, long long s) {
+    if (l <= 1) return 0;
+    if (s <= 1) return l * (l - 1) / 2;
+    long long r = 0;
+    while (beta(s, r) < l) ++r;
+    return r * l - beta(s + 1, r - 1);
+}
+// argmin over m in [1, l-1] of m + T(l-m, s-1) + T(m, s); convex in m.
+long long best_split(long long l, long long s) {
+    auto f = [&](long long m) { return m + adv_cost(l - m, s - 1) + adv_cost(m, s); };
+    long long lo = 1, hi = l - 1;
+    while (lo < hi) {
+        const long long mid = lo + (hi - lo) / 2;
+        if (f(mid + 1) < f(mid)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+enum ActKind { A_RESTORE = 0, A_ADV = 1, A_STORE = 2, A_ADJ = 3 };
+struct Act { int kind; long long a, b; };
+
+void reverse_sched(long long start, long long end, int slot, std::vector<int>& freeslots, std::vector<Act>& acts) {
+    const long long l = end - start;
+    if (l == 1) {
+        acts.push_back({A_RESTORE, slot, start});
+        acts.push_back({A_ADJ, start, 0});
+        return;
+    }
+    const long long s = 1 + (long long)freeslots.size();
+    if (s == 1) {
+        for (long long i = end - 1; i >= start; --i) {
+            acts.push_back({A_RESTORE, slot, start});
+            if (i > start) acts.push_back({A_ADV, i - start, 0});
+            acts.push_back({A_ADJ, i, 0});
+        }
+        return;
+    }
+    const long long m = best_split(l, s);
+    acts.push_back({A_RESTORE, slot, start});
+    acts.push_back({A_ADV, m, 0});
+    const int sl = freeslots.back();
+    freeslots.pop_back();
+    acts.push_back({A_STORE, sl, start + m});
+    reverse_sched(start + m, end, sl, freeslots, acts);
+    freeslots.push_back(sl);
+    reverse_sched(start, start + m, slot, freeslots, acts);
+}
+
+std::vector<Act> schedule(long long nsteps, int nck) {
+    std::vector<Act> acts;
+    std::vector<int> freeslots;
+    for (int s = nck - 1; s >= 1; --s) freeslots.push_back(s);
+    reverse_sched(0, nsteps, 0, freeslots, acts);
+    return acts;
+}
+size_t first_adj(const std::vector<Act>& acts) {
+    for (size_t i = 0; i < acts.size(); ++i)
+        if (acts[i].kind == A_ADJ) return i;
+    return acts.size();
+}
+
+// -------------------------------------------------------------- step drivers
+struct WsPtrs {
+    double2 *aux0, *aux1, *nn, *ns, *us, *muC, *muP, *yb, *zb2, *fa, *fb, *fa2, *fb2, *cur, *lam, *tmp, *g,
+        *trial, *trialN;
+    double* red;
+};
+WsPtrs wsptrs(const npo_plan_s& p, void* ws) {
+    char* b = static_cast<char*>(ws);
+    auto F = [&](size_t off) { return reinterpret_cast<double2*>(b + off); };
+    WsPtrs w;
+    w.aux0 = F(p.ws.aux0); w.aux1 = F(p.ws.aux1); w.nn = F(p.ws.nn); w.ns = F(p.ws.ns); w.us = F(p.ws.us);
+    w.muC = F(p.ws.muC); w.muP = F(p.ws.muP); w.yb = F(p.ws.yb); w.zb2 = F(p.ws.zb2);
+    w.fa = F(p.ws.fa); w.fb = F(p.ws.fb); w.fa2 = F(p.ws.fa2); w.fb2 = F(p.ws.fb2);
+    w.cur = F(p.ws.cur); w.lam = F(p.ws.lam); w.tmp = F(p.ws.tmp); w.g = F(p.ws.g);
+    w.trial = F(p.ws.trial); w.trialN = F(p.ws.trialN);
+    w.red = reinterpret_cast<double*>(b + p.ws.red);
+    return w;
+}
+
+double time_of(const npo_plan_s& p, long long n) { return p.t0 + (double)n * p.dt; }
+
+// u_out = Phi(u_n).  If have_aux, w.aux0 already holds the vorticity parts of u_n.
+hipError_t fwd_step(const npo_plan_s& p, void* ws, const double2* un, double2* uout, long long n, bool have_aux,
+                    hipStream_t st) {
+    WsPtrs w = wsptrs(p, ws);
+    hipError_t e;
+    if (!have_aux && (e = npo::launch_curl_aux(p, un, w.aux0, st)) != hipSuccess) return e;
+    if ((e = npo::launch_nl(p, 0, un, w.aux0, nullptr, time_of(p, n), w.nn, nullptr, ws, st)) != hipSuccess) return e;
+    if ((e = npo::launch_solve(p, 1, un, w.nn, nullptr, w.us, w.aux1, st)) != hipSuccess) return e;
+    if ((e = npo::launch_nl(p, 0, w.us, w.aux1, nullptr, time_of(p, n + 1), w.ns, nullptr, ws, st)) != hipSuccess)
+        return e;
+    return npo::launch_solve(p, 2, un, w.nn, w.ns, uout, w.aux0, st);
+}
+
+// lam_out = Phi'(u_n)^dag lam_in
+hipError_t adj_step(const npo_plan_s& p, void* ws, const double2* un, const double2* lamin, double2* lamout,
+                    long long n, hipStream_t st) {
+    WsPtrs w = wsptrs(p, ws);
+    hipError_t e;
+    const double t0 = time_of(p, n), t1 = time_of(p, n + 1);
+    if ((e = npo::launch_curl_aux(p, un, w.aux0, st)) != hipSuccess) return e;
+    if ((e = npo::launch_nl(p, 0, un, w.aux0, nullptr, t0, w.nn, nullptr, ws, st)) != hipSuccess) return e;
+    if ((e = npo::launch_solve(p, 1, un, w.nn, nullptr, w.us, w.aux1, st)) != hipSuccess) return e;
+    if ((e = npo::launch_solve_adj(p, lamin, 1.0, nullptr, 0.0, nullptr, 0.0, 0.0, w.muC, nullptr, st)) != hipSuccess)
+        return e;
+    if ((e = npo::launch_nl(p, 1, w.us, w.aux1, w.muC, t1, w.fa, w.fb, ws, st)) != hipSuccess) return e;
+    // mu_P = S^dag(lambda*), lambda* = (A + curl^dag B)/2;  yb = mu_P + mu_C/2, zb2 = mu_P + mu_C
+    if ((e = npo::launch_solve_adj(p, w.fa, 0.5, w.fb, 0.5, w.muC, 0.5, 1.0, w.yb, w.zb2, st)) != hipSuccess)
+        return e;
+    if ((e = npo::launch_nl(p, 1, un, w.aux0, w.yb, t0, w.fa2, w.fb2, ws, st)) != hipSuccess) return e;
+    return npo::launch_final(p, w.zb2, w.fa2, w.fb2, lamout, st);
+}
+
+npo_status check_plan(npo_plan p) {
+    if (!p) return fail(NPO_EINVAL, "null plan");
+    return NPO_OK;
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+extern "C" {
+
+const char* npo_last_error(void) { return g_err.c_str(); }
+
+npo_status npo_plan_create(const npo_grid* grid, const npo_flow* flow, const npo_time* time, uint32_t flags,
+                           npo_plan* out) {
+    g_err.clear();
+    if (!grid || !flow || !time || !out) return fail(NPO_EINVAL, "null argument");
+    if (flags != 0) return fail(NPO_EINVAL, "flags must be 0");
+    const int nr = grid->nr, nt = grid->ntheta, nz = grid->nz;
+    if (nr < 8 || nr > npo::NR_MAX) return fail(NPO_EUNSUPPORTED, "nr must be in [8, 64]");
+    if (nt < 6 || nt > 128 || radix_factors(nt).empty()) return fail(NPO_EUNSUPPORTED, "ntheta must be 2^a 3^b in [6,128]");
+    if (nz < 6 || nz > 2048 || radix_factors(nz).empty()) return fail(NPO_EUNSUPPORTED, "nz must be 2^a 3^b in [6,2048]");
+    if (!(grid->lz > 0) || !(flow->re > 0) || !(flow->wo > 0) || !(time->dt > 0) || time->nsteps < 1)
+        return fail(NPO_EINVAL, "lz, re, wo, dt must be positive and nsteps >= 1");
+    if (flow->amp < 0) return fail(NPO_EINVAL, "amp must be >= 0");
+
+    auto* p = new npo_plan_s();
+    p->nr = nr; p->nt = nt; p->nz = nz;
+    p->M = (nt - 1) / 3; p->K = (nz - 1) / 3; p->nk = 2 * p->K + 1; p->mp1 = p->M + 1;
+    p->lz = grid->lz; p->k0 = 2.0 * M_PI / grid->lz;
+    p->re = flow->re; p->wo = flow->wo; p->amp = flow->amp;
+    p->dt = time->dt; p->t0 = time->t0; p->nsteps = time->nsteps;
+    p->omega = flow->wo * flow->wo / flow->re;
+    (void)hipGetDevice(&p->device);
+
+    // radial tables
+    std::vector<ld> r = radial_nodes(nr);
+    std::vector<ld> w = quad_weights(r);
+    p->r.resize(nr); p->w.resize(nr);
+    for (int j = 0; j < nr; ++j) { p->r[j] = (double)r[j]; p->w[j] = (double)w[j]; }
+    p->col0.resize(nr);
+    p->D1.assign(2 * nr * 7, 0.0);
+    p->D2.assign(2 * nr * 7, 0.0);
+    for (int j = 0; j < nr; ++j) {
+        const int c0 = std::min(std::max(j - 3, 0), nr - 7);
+        p->col0[j] = c0;
+        // stencil nodes in the mirrored numbering
+        int cols[7];
+        if (j >= nr - 3) for (int t = 0; t < 7; ++t) cols[t] = nr - 7 + t;
+        else for (int t = 0; t < 7; ++t) cols[t] = j - 3 + t;
+        ld xs[7];
+        for (int t = 0; t < 7; ++t) xs[t] = cols[t] >= 0 ? r[cols[t]] : -r[-cols[t] - 1];
+        ld c[3][7];
+        fornberg(r[j], xs, 7, c);
+        for (int pi = 0; pi < 2; ++pi) {
+            const ld par = pi == 0 ? 1.0L : -1.0L;
+            ld a1[7] = {0}, a2[7] = {0};
+            for (int t = 0; t < 7; ++t) {
+                const int cc = cols[t] >= 0 ? cols[t] : -cols[t] - 1;
+                const ld s = cols[t] >= 0 ? 1.0L : par;
+                a1[cc - c0] += s * c[1][t];
+                a2[cc - c0] += s * c[2][t];
+            }
+            for (int t = 0; t < 7; ++t) {
+                p->D1[(pi * nr + j) * 7 + t] = (double)a1[t];
+                p->D2[(pi * nr + j) * 7 + t] = (double)a2[t];
+            }
+        }
+    }
+    // Womersley profile: Ut = b [1 - J0(k r)/J0(k)] / [1 - 2 J1(k)/(k J0(k))], k = Wo e^{3 i pi/4}, b = -i A/2
+    p->ut_re.assign(nr, 0.0); p->ut_im.assign(nr, 0.0); p->dut_re.assign(nr, 0.0); p->dut_im.assign(nr, 0.0);
+    if (flow->amp != 0.0) {
+        const ld pi = acosl(-1.0L);
+        const std::complex<ld> kap = (ld)flow->wo * std::polar(1.0L, 0.75L * pi);
+        const std::complex<ld> b(0.0L, -0.5L * (ld)flow->amp);
+        std::complex<ld> J0k, J1k;
+        bessel01(kap, J0k, J1k);
+        const std::complex<ld> den = 1.0L - 2.0L * J1k / (kap * J0k);
+        for (int j = 0; j < nr; ++j) {
+            std::complex<ld> J0r, J1r;
+            bessel01(kap * r[j], J0r, J1r);
+            const std::complex<ld> ut = b * (1.0L - J0r / J0k) / den;
+            const std::complex<ld> dut = b * kap * J1r / J0k / den;
+            p->ut_re[j] = (double)ut.real(); p->ut_im[j] = (double)ut.imag();
+            p->dut_re[j] = (double)dut.real(); p->dut_im[j] = (double)dut.imag();
+        }
+    }
+    // FFT factors
+    std::vector<int> fz = radix_factors(nz), ft = radix_factors(nt);
+    if ((int)fz.size() > npo::NFAC_MAX || (int)ft.size() > npo::NFAC_MAX) {
+        delete p;
+        return fail(NPO_EUNSUPPORTED, "too many FFT factors");
+    }
+    // device tables: r, w, D1, D2 (doubles), Ut, dUt, twz, twt (double2), col0 (int)
+    const size_t nd = nr + nr + 2 * nr * 7 + 2 * nr * 7;
+    const size_t nc = nr + nr + nz + nt;
+    const size_t bytes = align256(nd * 8) + align256(nc * 16) + align256(nr * 4);
+    if (hipMalloc(&p->d_tables, bytes) != hipSuccess) {
+        delete p;
+        return fail(NPO_ENOMEM, "hipMalloc of plan tables failed");
+    }
+    std::vector<char> host(bytes, 0);
+    double* hd = reinterpret_cast<double*>(host.data());
+    size_t o = 0;
+    std::memcpy(hd + o, p->r.data(), nr * 8); const size_t o_r = o; o += nr;
+    std::memcpy(hd + o, p->w.data(), nr * 8); const size_t o_w = o; o += nr;
+    std::memcpy(hd + o, p->D1.data(), 2 * nr * 7 * 8); const size_t o_d1 = o; o += 2 * nr * 7;
+    std::memcpy(hd + o, p->D2.data(), 2 * nr * 7 * 8); const size_t o_d2 = o; o += 2 * nr * 7;
+    const size_t cbase = align256(nd * 8);
+    double2* hc = reinterpret_cast<double2*>(host.data() + cbase);
+    const ld pi = acosl(-1.0L);
+    for (int j = 0; j < nr; ++j) {
+        hc[j] = make_double2(p->ut_re[j], p->ut_im[j]);
+        hc[nr + j] = make_double2(p->dut_re[j], p->dut_im[j]);
+    }
+    for (int t = 0; t < nz; ++t) hc[2 * nr + t] = make_double2((double)cosl(2 * pi * t / nz), (double)-sinl(2 * pi * t / nz));
+    for (int t = 0; t < nt; ++t)
+        hc[2 * nr + nz + t] = make_double2((double)cosl(2 * pi * t / nt), (double)-sinl(2 * pi * t / nt));
+    const size_t ibase = cbase + align256(nc * 16);
+    std::memcpy(host.data() + ibase, p->col0.data(), nr * 4);
+    if (hipMemcpy(p->d_tables, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(p->d_tables);
+        delete p;
+        return fail(NPO_EHIP, "upload of plan tables failed");
+    }
+    const double* dd = reinterpret_cast<const double*>(p->d_tables);
+    const double2* dc = reinterpret_cast<const double2*>(reinterpret_cast<const char*>(p->d_tables) + cbase);
+    npo::KP& kp = p->kp;
+    kp.nr = nr; kp.nt = nt; kp.nz = nz; kp.M = p->M; kp.K = p->K; kp.nk = p->nk; kp.mp1 = p->mp1;
+    kp.k0 = p->k0; kp.re = p->re; kp.dt = p->dt; kp.lz = p->lz;
+    kp.r = dd + o_r; kp.w = dd + o_w; kp.D1 = dd + o_d1; kp.D2 = dd + o_d2;
+    kp.col0 = reinterpret_cast<const int*>(reinterpret_cast<const char*>(p->d_tables) + ibase);
+    kp.Ut = dc; kp.dUt = dc + nr; kp.twz = dc + 2 * nr; kp.twt = dc + 2 * nr + nz;
+    kp.nfz = (int)fz.size(); kp.nft = (int)ft.size();
+    for (int i = 0; i < npo::NFAC_MAX; ++i) {
+        kp.fz[i] = i < kp.nfz ? fz[i] : 1;
+        kp.ft[i] = i < kp.nft ? ft[i] : 1;
+    }
+    // launch shapes: LDS budget 64 KiB per block for the FFT kernels
+    const size_t lds = 64 * 1024;
+    p->zgroup = 1;
+    for (int g : {3, 2, 1})
+        if ((size_t)2 * g * nz * 16 <= lds) { p->zgroup = g; break; }
+    if ((size_t)2 * nz * 16 > 160 * 1024) {
+        (void)hipFree(p->d_tables);
+        delete p;
+        return fail(NPO_EUNSUPPORTED, "nz too large for one LDS-resident axial transform");
+    }
+    auto theta_lds = [&](int ZB, int adj) {
+        const int H = ZB / 2;
+        const int nin = adj ? 4 * ZB + H : 3 * ZB, nout = adj ? 3 * ZB : ZB + H;
+        return (size_t)2 * std::max(nin, nout) * nt * 16;
+    };
+    p->zb_theta_fwd = p->zb_theta_adj = 2;
+    for (int ZB : {8, 4, 2}) {
+        if (nz % ZB == 0 && theta_lds(ZB, 0) <= lds) { p->zb_theta_fwd = ZB; break; }
+    }
+    for (int ZB : {8, 4, 2}) {
+        if (nz % ZB == 0 && theta_lds(ZB, 1) <= lds) { p->zb_theta_adj = ZB; break; }
+    }
+    // workspace layout
+    const size_t fb = (size_t)3 * nr * p->mp1 * p->nk * 16;
+    const size_t f2 = (size_t)2 * nr * p->mp1 * p->nk * 16;
+    const size_t gb = (size_t)nr * p->mp1 * nz * 16;
+    size_t off = 0;
+    auto take = [&](size_t n) { size_t at = off; off += align256(n); return at; };
+    npo::WsLayout& L = p->ws;
+    L.aux0 = take(f2); L.aux1 = take(f2);
+    L.nn = take(fb); L.ns = take(fb); L.us = take(fb);
+    L.muC = take(fb); L.muP = take(fb); L.yb = take(fb); L.zb2 = take(fb);
+    L.fa = take(fb); L.fb = take(fb); L.fa2 = take(fb); L.fb2 = take(fb);
+    L.cur = take(fb); L.lam = take(fb); L.tmp = take(fb); L.g = take(fb);
+    L.trial = take(fb); L.trialN = take(fb);
+    L.zbuf = take(9 * gb); L.tbuf = take(6 * gb);
+    L.red = take((npo::NR_MAX * 4 + 512) * 8);
+    L.total = off;
+    *out = p;
+    return NPO_OK;
+}
+
+npo_status npo_plan_destroy(npo_plan p) {
+    if (!p) return NPO_OK;
+    if (p->d_tables) (void)hipFree(p->d_tables);
+    delete p;
+    return NPO_OK;
+}
+
+npo_status npo_plan_info(npo_plan p, npo_info* out) {
+    if (check_plan(p) || !out) return fail(NPO_EINVAL, "null argument");
+    out->nr = p->nr; out->ntheta = p->nt; out->nz = p->nz; out->M = p->M; out->K = p->K; out->nk = p->nk;
+    out->field_elems = (int64_t)3 * p->nr * p->mp1 * p->nk;
+    out->field_bytes = out->field_elems * 16;
+    out->workspace_bytes = (int64_t)p->ws.total;
+    out->scalars_bytes = 256;
+    out->period = 2.0 * M_PI * p->re / (p->wo * p->wo);
+    out->k0 = p->k0; out->dt = p->dt; out->t0 = p->t0; out->nsteps = p->nsteps;
+    return NPO_OK;
+}
+
+npo_status npo_plan_tables(npo_plan p, double* r, double* w, double* D1, double* D2, int32_t* col0) {
+    if (check_plan(p)) return NPO_EINVAL;
+    if (r) std::memcpy(r, p->r.data(), p->nr * 8);
+    if (w) std::memcpy(w, p->w.data(), p->nr * 8);
+    if (D1) std::memcpy(D1, p->D1.data(), p->D1.size() * 8);
+    if (D2) std::memcpy(D2, p->D2.data(), p->D2.size() * 8);
+    if (col0) for (int j = 0; j < p->nr; ++j) col0[j] = p->col0[j];
+    return NPO_OK;
+}
+
+npo_status npo_base_flow(npo_plan p, double t, double* U, double* Om) {
+    if (check_plan(p) || !U || !Om) return fail(NPO_EINVAL, "null argument");
+    const double cw = cos(p->omega * t), sw = sin(p->omega * t);
+    for (int j = 0; j < p->nr; ++j) {
+        const double r = p->r[j];
+        U[j] = 1.0 - r * r + (p->ut_re[j] * cw - p->ut_im[j] * sw);
+        Om[j] = 2.0 * r - (p->dut_re[j] * cw - p->dut_im[j] * sw);
+    }
+    return NPO_OK;
+}
+
+#define ST(s) reinterpret_cast<hipStream_t>(s)
+#define CF(x) reinterpret_cast<const double2*>(x)
+#define F(x) reinterpret_cast<double2*>(x)
+
+npo_status npo_nonlinear(npo_plan p, void* ws, const void* u, double t, void* out, void* stream) {
+    if (check_plan(p) || !ws || !u || !out) return fail(NPO_EINVAL, "null argument");
+    WsPtrs w = wsptrs(*p, ws);
+    HIPCHK(npo::launch_curl_aux(*p, CF(u), w.aux0, ST(stream)));
+    HIPCHK(npo::launch_nl(*p, 0, CF(u), w.aux0, nullptr, t, F(out), nullptr, ws, ST(stream)));
+    return NPO_OK;
+}
+
+npo_status npo_nonlinear_adj(npo_plan p, void* ws, const void* u, double t, const void* y, void* out, void* stream) {
+    if (check_plan(p) || !ws || !u || !y || !out) return fail(NPO_EINVAL, "null argument");
+    WsPtrs w = wsptrs(*p, ws);
+    HIPCHK(npo::launch_curl_aux(*p, CF(u), w.aux0, ST(stream)));
+    HIPCHK(npo::launch_nl(*p, 1, CF(u), w.aux0, CF(y), t, w.fa, w.fb, ws, ST(stream)));
+    HIPCHK(npo::launch_final(*p, nullptr, w.fa, w.fb, F(out), ST(stream)));
+    return NPO_OK;
+}
+
+npo_status npo_solve(npo_plan p, void* ws, const void* R, void* out, void* stream) {
+    if (check_plan(p) || !R || !out) return fail(NPO_EINVAL, "null argument");
+    (void)ws;
+    HIPCHK(npo::launch_solve(*p, 0, CF(R), nullptr, nullptr, F(out), nullptr, ST(stream)));
+    return NPO_OK;
+}
+
+npo_status npo_solve_adj(npo_plan p, void* ws, const void* y, void* out, void* stream) {
+    if (check_plan(p) || !y || !out) return fail(NPO_EINVAL, "null argument");
+    (void)ws;
+    HIPCHK(npo::launch_solve_adj(*p, CF(y), 1.0, nullptr, 0.0, nullptr, 0.0, 0.0, F(out), nullptr, ST(stream)));
+    return NPO_OK;
+}
+
+npo_status npo_forward_step(npo_plan p, void* ws, const void* un, void* unp1, int64_t n, void* stream) {
+    if (check_plan(p) || !ws || !un || !unp1) return fail(NPO_EINVAL, "null argument");
+    HIPCHK(fwd_step(*p, ws, CF(un), F(unp1), n, false, ST(stream)));
+    return NPO_OK;
+}
+
+npo_status npo_adjoint_step(npo_plan p, void* ws, const void* un, const void* lnp1, void* ln, int64_t n,
+                            void* stream) {
+    if (check_plan(p) || !ws || !un || !lnp1 || !ln) return fail(NPO_EINVAL, "null argument");
+    HIPCHK(adj_step(*p, ws, CF(un), CF(lnp1), F(ln), n, ST(stream)));
+    return NPO_OK;
+}
+
+npo_status npo_ckpt_count(int64_t nsteps, int32_t n_ckpt, int64_t* n_recompute) {
+    if (nsteps < 1 || n_ckpt < 1 || !n_recompute) return fail(NPO_EINVAL, "bad argument");
+    std::vector<Act> acts = schedule(nsteps, n_ckpt);
+    int64_t c = 0;
+    for (size_t i = first_adj(acts); i < acts.size(); ++i)
+        if (acts[i].kind == A_ADV) c += acts[i].a;
+    *n_recompute = c;
+    return NPO_OK;
+}
+
+npo_status npo_forward_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const void* u0, void* uN, void* stream) {
+    if (check_plan(p) || !ws || !ckpt || !u0 || !uN) return fail(NPO_EINVAL, "null argument");
+    if (nck < 1) return fail(NPO_EINVAL, "n_ckpt must be >= 1");
+    const hipStream_t st = ST(stream);
+    const size_t fb = (size_t)3 * p->nr * p->mp1 * p->nk * 16;
+    WsPtrs w = wsptrs(*p, ws);
+    auto slot = [&](long long s) { return reinterpret_cast<double2*>(static_cast<char*>(ckpt) + s * fb); };
+    std::vector<Act> acts = schedule(p->nsteps, nck);
+    const size_t fa = first_adj(acts);
+    HIPCHK(hipMemcpyAsync(slot(0), u0, fb, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(w.cur, u0, fb, hipMemcpyDeviceToDevice, st));
+    long long pos = 0;
+    bool aux = false;
+    for (size_t i = 0; i < fa; ++i) {
+        const Act& a = acts[i];
+        if (a.kind == A_ADV) {
+            for (long long k = 0; k < a.a; ++k) {
+                HIPCHK(fwd_step(*p, ws, w.cur, w.cur, pos, aux, st));
+                aux = true;
+                ++pos;
+            }
+        } else if (a.kind == A_STORE) {
+            if (a.b != pos) return fail(NPO_ESTATE, "schedule store position mismatch");
+            HIPCHK(hipMemcpyAsync(slot(a.a), w.cur, fb, hipMemcpyDeviceToDevice, st));
+        }
+    }
+    if (pos != p->nsteps - 1) return fail(NPO_ESTATE, "schedule descent did not reach the last step");
+    // u^{N-1} stays in cur for the first adjoint step; the last step goes to uN
+    HIPCHK(fwd_step(*p, ws, w.cur, F(uN), pos, aux, st));
+    return NPO_OK;
+}
+
+npo_status npo_adjoint_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const void* lamN, void* lam0,
+                           int64_t* n_recompute, void* stream) {
+    if (check_plan(p) || !ws || !ckpt || !lamN || !lam0) return fail(NPO_EINVAL, "null argument");
+    if (nck < 1) return fail(NPO_EINVAL, "n_ckpt must be >= 1");
+    const hipStream_t st = ST(stream);
+    const size_t fb = (size_t)3 * p->nr * p->mp1 * p->nk * 16;
+    WsPtrs w = wsptrs(*p, ws);
+    auto slot = [&](long long s) { return reinterpret_cast<double2*>(static_cast<char*>(ckpt) + s * fb); };
+    std::vector<Act> acts = schedule(p->nsteps, nck);
+    HIPCHK(hipMemcpyAsync(w.lam, lamN, fb, hipMemcpyDeviceToDevice, st));
+    long long pos = p->nsteps - 1, adv = 0;
+    bool aux = false;
+    for (size_t i = first_adj(acts); i < acts.size(); ++i) {
+        const Act& a = acts[i];
+        if (a.kind == A_RESTORE) {
+            HIPCHK(hipMemcpyAsync(w.cur, slot(a.a), fb, hipMemcpyDeviceToDevice, st));
+            pos = a.b;
+            aux = false;
+        } else if (a.kind == A_ADV) {
+            for (long long k = 0; k < a.a; ++k) {
+                HIPCHK(fwd_step(*p, ws, w.cur, w.cur, pos, aux, st));
+                aux = true;
+                ++pos;
+            }
+            adv += a.a;
+        } else if (a.kind == A_STORE) {
+            if (a.b != pos) return fail(NPO_ESTATE, "schedule store position mismatch");
+            HIPCHK(hipMemcpyAsync(slot(a.a), w.cur, fb, hipMemcpyDeviceToDevice, st));
+        } else {
+            if (a.a != pos) return fail(NPO_ESTATE, "schedule adjoint position mismatch");
+            HIPCHK(adj_step(*p, ws, w.cur, w.lam, w.lam, pos, st));
+            aux = false;   // the adjoint step reuses aux0 for its own work
+        }
+    }
+    HIPCHK(hipMemcpyAsync(lam0, w.lam, fb, hipMemcpyDeviceToDevice, st));
+    if (n_recompute) *n_recompute = adv;
+    return NPO_OK;
+}
+
+npo_status npo_inner(npo_plan p, void* ws, const void* a, const void* b, double* out_dev, void* stream) {
+    if (check_plan(p) || !ws || !a || !b || !out_dev) return fail(NPO_EINVAL, "null argument");
+    WsPtrs w = wsptrs(*p, ws);
+    HIPCHK(npo::launch_wdot(*p, CF(a), CF(b), w.red, out_dev, ST(stream)));
+    return NPO_OK;
+}
+
+npo_status npo_project(npo_plan p, void* ws, const void* u, void* out, void* stream) {
+    if (check_plan(p) || !u || !out) return fail(NPO_EINVAL, "null argument");
+    (void)ws;
+    HIPCHK(npo::launch_project(*p, CF(u), F(out), ST(stream)));
+    return NPO_OK;
+}
+
+static double lambda_plus(double al, double E0, double E0d, double C0) {
+    const double a = (al * C0 - 2.0 * E0) / (2.0 * al * E0);
+    const double q = (-al * C0 + 2.0 * E0) / (2.0 * al * E0);
+    const double disc = q * q - (al * E0d - C0) / (al * E0);
+    return a + std::sqrt(disc > 0.0 ? disc : 0.0);
+}
+
+npo_status npo_update(npo_plan p, void* ws, const void* u0, const void* udag, double e0, double alpha, double e0dag,
+                      double c0, void* u_new, void* stream) {
+    if (check_plan(p) || !ws || !u0 || !udag || !u_new) return fail(NPO_EINVAL, "null argument");
+    if (!(e0 > 0) || !(alpha > 0)) return fail(NPO_EINVAL, "e0 and alpha must be positive");
+    WsPtrs w = wsptrs(*p, ws);
+    const hipStream_t st = ST(stream);
+    const double lam = lambda_plus(alpha, e0, e0dag, c0);
+    HIPCHK(npo::launch_axpby(*p, 1.0 + lam * alpha, CF(u0), -alpha, CF(udag), F(u_new), st));
+    double* en = w.red + npo::NR_MAX * 4 + 256;
+    HIPCHK(npo::launch_wdot(*p, CF(u_new), CF(u_new), w.red, en, st));
+    // energy = <u,u>/2
+    HIPCHK(npo::launch_rescale(*p, F(u_new), en, 2.0 * e0, st));
+    return NPO_OK;
+}
+
+npo_status npo_iterate(npo_plan p, void* ws, void* ckpt, int32_t nck, void* u0, void* uN, double e0, double tol,
+                       int32_t max_halvings, double* stats, void* stream) {
+    if (check_plan(p) || !ws || !ckpt || !u0 || !uN || !stats) return fail(NPO_EINVAL, "null argument");
+    if (!(e0 > 0) || max_halvings < 0) return fail(NPO_EINVAL, "bad e0 or max_halvings");
+    const hipStream_t st = ST(stream);
+    const size_t fb = (size_t)3 * p->nr * p->mp1 * p->nk * 16;
+    WsPtrs w = wsptrs(*p, ws);
+    double* sc = w.red + npo::NR_MAX * 4 + 256 + 8;
+    auto read = [&](double* dev, double* host, int n) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(host, dev, n * 8, hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(st);
+    };
+    double h[4];
+    HIPCHK(npo::launch_wdot(*p, CF(uN), CF(uN), w.red, sc, st));
+    HIPCHK(read(sc, h, 1));
+    const double Gold = 0.5 * h[0] / e0;
+    int64_t nrec = 0;
+    npo_status s = npo_adjoint_run(p, ws, ckpt, nck, uN, w.g, &nrec, stream);
+    if (s) return s;
+    HIPCHK(npo::launch_project(*p, w.g, w.g, st));
+    // udag = -g:  E0dag = <g,g>/2, C0 = <u0, udag> = -<u0, g>
+    HIPCHK(npo::launch_wdot(*p, w.g, w.g, w.red, sc, st));
+    HIPCHK(npo::launch_wdot(*p, CF(u0), w.g, w.red, sc + 1, st));
+    HIPCHK(read(sc, h, 2));
+    const double E0d = 0.5 * h[0], C0 = -h[1];
+    const double q = E0d / e0 - C0 * C0 / (4.0 * e0 * e0);
+    const double amax = q > 0 ? 1.0 / std::sqrt(q) : std::numeric_limits<double>::infinity();
+    stats[0] = Gold; stats[1] = Gold; stats[2] = 0.0; stats[3] = amax; stats[4] = E0d; stats[5] = C0;
+    stats[6] = 0.0; stats[7] = 0.0;
+    if (!std::isfinite(amax)) return NPO_OK;
+    // udag into w.tmp
+    HIPCHK(npo::launch_axpby(*p, -1.0, w.g, 0.0, nullptr, w.tmp, st));
+    double al = amax;
+    for (int hv = 0; hv <= max_halvings; ++hv) {
+        s = npo_update(p, ws, u0, w.tmp, e0, al, E0d, C0, w.trial, stream);
+        if (s) return s;
+        s = npo_forward_run(p, ws, ckpt, nck, w.trial, w.trialN, stream);
+        if (s) return s;
+        stats[7] += 1.0;
+        HIPCHK(npo::launch_wdot(*p, w.trialN, w.trialN, w.red, sc, st));
+        HIPCHK(read(sc, h, 1));
+        const double Gn = 0.5 * h[0] / e0;
+        if (Gn > Gold) {
+            HIPCHK(hipMemcpyAsync(u0, w.trial, fb, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(uN, w.trialN, fb, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
+            stats[1] = Gn; stats[2] = al; stats[6] = 1.0;
+            return NPO_OK;
+        }
+        if (std::fabs((Gn - Gold) / Gn) < tol) break;
+        al *= 0.5;
+    }
+    return NPO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// Internal declarations shared by the host driver (npo_host.cpp) and the
+// device kernels (npo_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace npo {
+
+constexpr int NR_MAX = 64;     // radial nodes handled by one workgroup
+constexpr int NFAC_MAX = 8;    // radix factors of an FFT length
+
+// Per-plan constants handed to every kernel by value.
+struct KP {
+    int nr, nt, nz, M, K, nk, mp1;
+    double k0, re, dt;
+    double lz;
+    const double* r;      // [nr]
+    const double* w;      // [nr]
+    const double* D1;     // [2][nr][7] parity 0 = even, 1 = odd
+    const double* D2;     // [2][nr][7]
+    const int* col0;      // [nr] first column of each 7-point row
+    const double2* Ut;    // [nr] Womersley amplitude
+    const double2* dUt;   // [nr] its radial derivative
+    const double2* twz;   // [nz] exp(-2 pi i t / nz)
+    const double2* twt;   // [nt] exp(-2 pi i t / nt)
+    int nfz, nft;
+    int fz[NFAC_MAX];
+    int ft[NFAC_MAX];
+};
+
+// Workspace carve-up (byte offsets into the caller's workspace).
+struct WsLayout {
+    size_t aux0, aux1;          // 2-component vorticity parts of u^n and u*
+    size_t nn, ns;              // N(u^n), N(u*)
+    size_t us;                  // u*
+    size_t muC, muP, yb, zb2;   // adjoint temporaries
+    size_t fa, fb;              // adjoint convective outputs (A, B)
+    size_t fa2, fb2;
+    size_t cur, lam, tmp;       // checkpoint-run state buffers
+    size_t g, trial, trialN;    // iterate buffers
+    size_t zbuf, tbuf;          // z-transformed and theta-pass intermediates
+    size_t red;                 // reduction partials + scalars
+    size_t total;
+};
+
+}  // namespace npo
+
+struct npo_plan_s {
+    int nr, nt, nz, M, K, nk, mp1;
+    double lz, k0, re, wo, amp, dt, t0, omega;
+    int64_t nsteps;
+    std::vector<double> r, w, D1, D2;
+    std::vector<int> col0;
+    std::vector<double> ut_re, ut_im, dut_re, dut_im;
+    double* d_tables = nullptr;   // one device allocation for all tables
+    npo::KP kp;
+    npo::WsLayout ws;
+    int device = 0;
+    // launch shapes
+    int zb_theta_fwd = 4, zb_theta_adj = 4;
+    int zgroup = 1;
+};
+
+namespace npo {
+
+// Kernel launchers (npo_kernels.hip).  All enqueue on `st` and return the
+// hipGetLastError() of the launch.
+hipError_t launch_curl_aux(const npo_plan_s& p, const double2* u, double2* aux, hipStream_t st);
+hipError_t launch_nl(const npo_plan_s& p, int adjoint, const double2* u, const double2* aux,
+                     const double2* y, double t, double2* out0, double2* out1, void* ws, hipStream_t st);
+// solve kinds: 0 = out = S(R) with R = a (raw); 1 = predictor S(E a + b);
+// 2 = corrector S(E a + (b + c)/2).  aux_out may be null.
+hipError_t launch_solve(const npo_plan_s& p, int kind, const double2* a, const double2* b,
+                        const double2* c, double2* u_out, double2* aux_out, hipStream_t st);
+// mu = S^dag(ca*A + cb*curl^dag(B)); out0 = mu + q0*Q; out1 = mu + q1*Q (out1, Q optional).
+hipError_t launch_solve_adj(const npo_plan_s& p, const double2* A, double ca, const double2* B, double cb,
+                            const double2* Q, double q0, double q1, double2* out0, double2* out1,
+                            hipStream_t st);
+// out = E^dag Z + A + curl^dag B
+hipError_t launch_final(const npo_plan_s& p, const double2* Z, const double2* A, const double2* B,
+                        double2* out, hipStream_t st);
+hipError_t launch_wdot(const npo_plan_s& p, const double2* a, const double2* b, double* partial,
+                       double* out, hipStream_t st);
+hipError_t launch_project(const npo_plan_s& p, const double2* u, double2* out, hipStream_t st);
+// out = ca*a + cb*b
+hipError_t launch_axpby(const npo_plan_s& p, double ca, const double2* a, double cb, const double2* b,
+                        double2* out, hipStream_t st);
+// x *= sqrt(e0 / energy_dev[0])
+hipError_t launch_rescale(const npo_plan_s& p, double2* x, const double* energy_dev, double e0,
+                          hipStream_t st);
+
+}  // namespace npo

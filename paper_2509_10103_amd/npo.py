@@ -1,0 +1,239 @@
+"""ctypes binding of libnpo.so (C ABI in include/npo.h).
+
+Argument marshalling only: every numerical step runs in the HIP library.
+Fields are torch complex128 tensors of shape (3, nr, M+1, 2K+1) on the GPU;
+their data pointers and torch's current HIP stream are passed to the library.
+Loading fails loudly if the library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libnpo.so")
+_lib = None
+
+
+class NpoError(RuntimeError):
+    pass
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nr", ctypes.c_int32), ("ntheta", ctypes.c_int32), ("nz", ctypes.c_int32), ("lz", ctypes.c_double)]
+
+
+class Flow(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("wo", ctypes.c_double), ("amp", ctypes.c_double)]
+
+
+class Time(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("t0", ctypes.c_double), ("nsteps", ctypes.c_int64)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("nr", ctypes.c_int32), ("ntheta", ctypes.c_int32), ("nz", ctypes.c_int32), ("M", ctypes.c_int32),
+                ("K", ctypes.c_int32), ("nk", ctypes.c_int32), ("field_elems", ctypes.c_int64),
+                ("field_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+                ("scalars_bytes", ctypes.c_int64), ("period", ctypes.c_double), ("k0", ctypes.c_double),
+                ("dt", ctypes.c_double), ("t0", ctypes.c_double), ("nsteps", ctypes.c_int64)]
+
+
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_DP = ctypes.POINTER(ctypes.c_double)
+
+SIGNATURES = {
+    "npo_last_error": (ctypes.c_char_p, []),
+    "npo_plan_create": (_I32, [ctypes.POINTER(Grid), ctypes.POINTER(Flow), ctypes.POINTER(Time), ctypes.c_uint32,
+                               ctypes.POINTER(_P)]),
+    "npo_plan_destroy": (_I32, [_P]),
+    "npo_plan_info": (_I32, [_P, ctypes.POINTER(Info)]),
+    "npo_plan_tables": (_I32, [_P, _DP, _DP, _DP, _DP, ctypes.POINTER(_I32)]),
+    "npo_base_flow": (_I32, [_P, _D, _DP, _DP]),
+    "npo_nonlinear": (_I32, [_P, _P, _P, _D, _P, _P]),
+    "npo_nonlinear_adj": (_I32, [_P, _P, _P, _D, _P, _P, _P]),
+    "npo_solve": (_I32, [_P, _P, _P, _P, _P]),
+    "npo_solve_adj": (_I32, [_P, _P, _P, _P, _P]),
+    "npo_forward_step": (_I32, [_P, _P, _P, _P, _I64, _P]),
+    "npo_adjoint_step": (_I32, [_P, _P, _P, _P, _P, _I64, _P]),
+    "npo_forward_run": (_I32, [_P, _P, _P, _I32, _P, _P, _P]),
+    "npo_adjoint_run": (_I32, [_P, _P, _P, _I32, _P, _P, ctypes.POINTER(_I64), _P]),
+    "npo_ckpt_count": (_I32, [_I64, _I32, ctypes.POINTER(_I64)]),
+    "npo_inner": (_I32, [_P, _P, _P, _P, _P, _P]),
+    "npo_project": (_I32, [_P, _P, _P, _P, _P]),
+    "npo_update": (_I32, [_P, _P, _P, _P, _D, _D, _D, _D, _P, _P]),
+    "npo_iterate": (_I32, [_P, _P, _P, _I32, _P, _P, _D, _D, _I32, _DP, _P]),
+}
+
+
+def lib():
+    """Load libnpo.so once; raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise NpoError(f"{_LIB_PATH} not built; run paper_2509_10103_amd/build.py")
+        L = ctypes.CDLL(_LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise NpoError(f"npo error {status}: {lib().npo_last_error().decode()}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ------------------------------------------------------------------ plan
+def npo_plan_create(nr, ntheta, nz, lz, re, wo, amp, dt, t0, nsteps):
+    g = Grid(nr, ntheta, nz, lz)
+    f = Flow(re, wo, amp)
+    t = Time(dt, t0, nsteps)
+    h = _P()
+    _check(lib().npo_plan_create(ctypes.byref(g), ctypes.byref(f), ctypes.byref(t), 0, ctypes.byref(h)))
+    return h
+
+
+def npo_plan_destroy(plan):
+    _check(lib().npo_plan_destroy(plan))
+
+
+def npo_plan_info(plan):
+    i = Info()
+    _check(lib().npo_plan_info(plan, ctypes.byref(i)))
+    return {k: getattr(i, k) for k, _ in Info._fields_}
+
+
+def npo_plan_tables(plan, nr):
+    r, w = np.zeros(nr), np.zeros(nr)
+    D1, D2 = np.zeros((2, nr, 7)), np.zeros((2, nr, 7))
+    col0 = np.zeros(nr, dtype=np.int32)
+    dp = lambda a: a.ctypes.data_as(_DP)
+    _check(lib().npo_plan_tables(plan, dp(r), dp(w), dp(D1), dp(D2), col0.ctypes.data_as(ctypes.POINTER(_I32))))
+    return r, w, D1, D2, col0
+
+
+def npo_base_flow(plan, t, nr):
+    U, Om = np.zeros(nr), np.zeros(nr)
+    _check(lib().npo_base_flow(plan, t, U.ctypes.data_as(_DP), Om.ctypes.data_as(_DP)))
+    return U, Om
+
+
+# --------------------------------------------------------- device calls
+def npo_nonlinear(plan, ws, u, t, out, stream=None):
+    _check(lib().npo_nonlinear(plan, _ptr(ws), _ptr(u), t, _ptr(out), _stream(stream)))
+
+
+def npo_nonlinear_adj(plan, ws, u, t, y, out, stream=None):
+    _check(lib().npo_nonlinear_adj(plan, _ptr(ws), _ptr(u), t, _ptr(y), _ptr(out), _stream(stream)))
+
+
+def npo_solve(plan, ws, R, out, stream=None):
+    _check(lib().npo_solve(plan, _ptr(ws), _ptr(R), _ptr(out), _stream(stream)))
+
+
+def npo_solve_adj(plan, ws, y, out, stream=None):
+    _check(lib().npo_solve_adj(plan, _ptr(ws), _ptr(y), _ptr(out), _stream(stream)))
+
+
+def npo_forward_step(plan, ws, u_n, u_np1, n, stream=None):
+    _check(lib().npo_forward_step(plan, _ptr(ws), _ptr(u_n), _ptr(u_np1), n, _stream(stream)))
+
+
+def npo_adjoint_step(plan, ws, u_n, lam_np1, lam_n, n, stream=None):
+    _check(lib().npo_adjoint_step(plan, _ptr(ws), _ptr(u_n), _ptr(lam_np1), _ptr(lam_n), n, _stream(stream)))
+
+
+def npo_forward_run(plan, ws, ckpt, n_ckpt, u0, uN, stream=None):
+    _check(lib().npo_forward_run(plan, _ptr(ws), _ptr(ckpt), n_ckpt, _ptr(u0), _ptr(uN), _stream(stream)))
+
+
+def npo_adjoint_run(plan, ws, ckpt, n_ckpt, lamN, lam0, stream=None):
+    c = _I64()
+    _check(lib().npo_adjoint_run(plan, _ptr(ws), _ptr(ckpt), n_ckpt, _ptr(lamN), _ptr(lam0), ctypes.byref(c),
+                                 _stream(stream)))
+    return c.value
+
+
+def npo_ckpt_count(nsteps, n_ckpt):
+    c = _I64()
+    _check(lib().npo_ckpt_count(nsteps, n_ckpt, ctypes.byref(c)))
+    return c.value
+
+
+def npo_inner(plan, ws, a, b, out_dev, stream=None):
+    _check(lib().npo_inner(plan, _ptr(ws), _ptr(a), _ptr(b), _ptr(out_dev), _stream(stream)))
+
+
+def npo_project(plan, ws, u, out, stream=None):
+    _check(lib().npo_project(plan, _ptr(ws), _ptr(u), _ptr(out), _stream(stream)))
+
+
+def npo_update(plan, ws, u0, udag, e0, alpha, e0dag, c0, u_new, stream=None):
+    _check(lib().npo_update(plan, _ptr(ws), _ptr(u0), _ptr(udag), e0, alpha, e0dag, c0, _ptr(u_new),
+                            _stream(stream)))
+
+
+def npo_iterate(plan, ws, ckpt, n_ckpt, u0, uN, e0, tol=1e-8, max_halvings=30, stream=None):
+    st = np.zeros(8)
+    _check(lib().npo_iterate(plan, _ptr(ws), _ptr(ckpt), n_ckpt, _ptr(u0), _ptr(uN), e0, tol, max_halvings,
+                             st.ctypes.data_as(_DP), _stream(stream)))
+    keys = ("G_old", "G_new", "alpha", "alpha_max", "E0dag", "C0", "accepted", "forward_sweeps")
+    return dict(zip(keys, st.tolist()))
+
+
+# ------------------------------------------------------- convenience
+class Plan:
+    """A plan plus its device workspace (torch allocations)."""
+
+    def __init__(self, nr, ntheta, nz, lz, re, wo, amp, dt, t0=0.0, nsteps=1, device="cuda"):
+        import torch
+        self.handle = npo_plan_create(nr, ntheta, nz, lz, re, wo, amp, dt, t0, nsteps)
+        self.info = npo_plan_info(self.handle)
+        self.nr, self.M, self.K = nr, self.info["M"], self.info["K"]
+        self.shape = (3, nr, self.M + 1, 2 * self.K + 1)
+        self.device = device
+        self.ws = torch.empty(self.info["workspace_bytes"], dtype=torch.uint8, device=device)
+        self.scal = torch.zeros(8, dtype=torch.float64, device=device)
+
+    def field(self):
+        import torch
+        return torch.zeros(self.shape, dtype=torch.complex128, device=self.device)
+
+    def arena(self, n_ckpt):
+        import torch
+        return torch.empty((n_ckpt,) + self.shape, dtype=torch.complex128, device=self.device)
+
+    def inner(self, a, b):
+        npo_inner(self.handle, self.ws, a, b, self.scal)
+        return float(self.scal[0].item())
+
+    def energy(self, u):
+        return 0.5 * self.inner(u, u)
+
+    def close(self):
+        if self.handle:
+            npo_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

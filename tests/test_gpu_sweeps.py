@@ -1,0 +1,99 @@
+"""End-to-end parity at the plain single-instance workload (32 x 24 x 48,
+500 steps): forward sweep, adjoint sweep under several checkpoint budgets,
+projected gradient and one optimisation iteration, against oracle values
+stored by tests/golden/make_oracle_fixtures.py."""
+import ast
+import os
+
+import numpy as np
+import pytest
+
+from tests.gpu_common import to_dev, to_host, relerr
+from oracle.pipe import Pipe
+from oracle.checkpoint import closed_form
+
+pytestmark = pytest.mark.gpu
+FIX = os.path.join(os.path.dirname(__file__), "golden", "c1_oracle.npz")
+
+
+@pytest.fixture(scope="module")
+def c1():
+    if not os.path.exists(FIX):
+        pytest.skip("oracle fixture not generated")
+    d = np.load(FIX)
+    c = ast.literal_eval(str(d["config"]))
+    P = Pipe(c["nr"], c["nt"], c["nz"], c["lz"], c["re"], c["wo"], c["amp"], c["dt"], c["t0"])
+    from paper_2509_10103_amd import npo
+    G = npo.Plan(c["nr"], c["nt"], c["nz"], c["lz"], c["re"], c["wo"], c["amp"], c["dt"], c["t0"], c["nsteps"])
+    return c, d, P, G
+
+
+def test_forward_sweep_matches_oracle(c1):
+    c, d, P, G = c1
+    from paper_2509_10103_amd import npo
+    ck = G.arena(c["nsteps"])
+    uN = G.field()
+    npo.npo_forward_run(G.handle, G.ws, ck, c["nsteps"], to_dev(d["u0"]), uN)
+    assert relerr(P, to_host(uN), d["uN"]) < 1e-10
+    J = G.energy(uN)
+    assert abs(J - float(d["J"])) < 1e-10 * float(d["J"])
+
+
+def test_gradient_matches_oracle_and_is_independent_of_budget(c1):
+    c, d, P, G = c1
+    from paper_2509_10103_amd import npo
+    N = c["nsteps"]
+    u0 = to_dev(d["u0"])
+    res = {}
+    for nck in (3, 16, N):
+        ck = G.arena(nck)
+        uN = G.field()
+        lam0 = G.field()
+        npo.npo_forward_run(G.handle, G.ws, ck, nck, u0, uN)
+        nrec = npo.npo_adjoint_run(G.handle, G.ws, ck, nck, uN, lam0)
+        assert nrec + N - 1 == closed_form(N, nck)[0]
+        res[nck] = to_host(lam0)
+        del ck
+    assert np.array_equal(res[3], res[N]) and np.array_equal(res[16], res[N])
+    assert relerr(P, res[N], d["lam0"]) < 1e-8
+
+
+def test_projected_gradient(c1):
+    c, d, P, G = c1
+    from paper_2509_10103_amd import npo
+    g = G.field()
+    npo.npo_project(G.handle, G.ws, to_dev(d["lam0"]), g)
+    assert relerr(P, to_host(g), d["g"]) < 1e-10
+
+
+def test_one_iteration_with_line_search(c1):
+    c, d, P, G = c1
+    from paper_2509_10103_amd import npo
+    N = c["nsteps"]
+    ck = G.arena(N)
+    u0 = to_dev(d["u0"])
+    uN = G.field()
+    npo.npo_forward_run(G.handle, G.ws, ck, N, u0, uN)
+    st = npo.npo_iterate(G.handle, G.ws, ck, N, u0, uN, c["e0"])
+    assert abs(st["G_old"] / float(d["G0"]) - 1) < 1e-10
+    assert abs(st["alpha_max"] / float(d["alpha_max"]) - 1) < 1e-8
+    assert abs(st["E0dag"] / float(d["E0dag"]) - 1) < 1e-8
+    assert abs(st["C0"] - float(d["C0"])) < 1e-8 * np.sqrt(2 * float(d["E0dag"]) * 2 * c["e0"])
+    assert bool(st["accepted"]) == bool(d["accepted"])
+    assert int(st["forward_sweeps"]) == len(d["trials"])
+    if st["accepted"]:
+        assert abs(st["G_new"] / float(d["G1"]) - 1) < 1e-8
+        assert relerr(P, to_host(u0), d["u1"]) < 1e-8
+        # the new iterate keeps the energy constraint
+        assert abs(G.energy(u0) / c["e0"] - 1) < 1e-12
+
+
+def test_forward_sweep_is_deterministic(c1):
+    c, d, P, G = c1
+    from paper_2509_10103_amd import npo
+    ck = G.arena(4)
+    a, b = G.field(), G.field()
+    u0 = to_dev(d["u0"])
+    npo.npo_forward_run(G.handle, G.ws, ck, 4, u0, a)
+    npo.npo_forward_run(G.handle, G.ws, ck, 4, u0, b)
+    assert np.array_equal(to_host(a), to_host(b))
