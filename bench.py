@@ -1,0 +1,179 @@
+"""Benchmark: adjoint-looping iterations of the NLOP hot path on one MI355X.
+
+One benchmark step is one optimisation iteration of the paper's method
+(Sec. 2.1-2.2) on the paper-like workload: adjoint sweep over one pulsation
+period with binomial checkpoints (Sec. 2.4), solenoidal projection of the
+gradient, and the backtracking line search whose trial forward sweeps leave
+the next iterate's checkpoints in place.  The initial forward sweep is done
+before the timed region.  Metric: forward + adjoint grid-point-steps per
+second, counting one forward and one adjoint sweep of N_r*N_theta*N_z points
+per step per iteration; recomputation and extra trial sweeps are not counted.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2509_10103_amd import configs, synth  # noqa: E402
+
+PEAK_HBM_GBS = 8000.0
+
+
+def alg_bytes(cfg):
+    """Algorithmic HBM bytes per launch of each kernel family."""
+    nr, nz = cfg["nr"], cfg["nz"]
+    M, K = (cfg["nt"] - 1) // 3, (cfg["nz"] - 1) // 3
+    f1 = nr * (M + 1) * (2 * K + 1) * 16        # one scalar spectral field
+    g1 = nr * (M + 1) * nz * 16                 # one axially transformed scalar field
+    return {
+        "curl": 5 * f1, "zinv_fwd": 5 * f1 + 6 * g1, "theta_fwd": 9 * g1, "zfwd_fwd": 3 * g1 + 3 * f1,
+        "zinv_adj": 8 * f1 + 9 * g1, "theta_adj": 15 * g1, "zfwd_adj": 6 * g1 + 6 * f1,
+        "solve_pred": 11 * f1, "solve_corr": 14 * f1, "solve_raw": 6 * f1, "solve_adj": 6 * f1,
+        "solve_adj2": 15 * f1, "adj_combine": 12 * f1, "wdot": 6 * f1, "project": 6 * f1, "axpby": 9 * f1,
+    }
+
+
+def cpu_baseline(cfg, seed):
+    """Time the CPU oracle on a bounded sample: one forward and one adjoint
+    step of the same workload (one BLAS thread, single-threaded FFTs)."""
+    from threadpoolctl import threadpool_limits
+    from oracle.pipe import Pipe
+    from oracle import optimize as opt
+    with threadpool_limits(limits=1):
+        P = Pipe(cfg["nr"], cfg["nt"], cfg["nz"], cfg["lz"], cfg["re"], cfg["wo"], cfg["amp"], cfg["dt"], cfg["t0"])
+        P.cache_limit = 0
+        raw = make_raw(cfg, P.r, P.M, P.K, seed)
+        u = opt.normalise(P, opt.project(P, raw), cfg["e0"])
+        t = time.perf_counter()
+        u1 = P.step(u, 0)
+        tf = time.perf_counter() - t
+        t = time.perf_counter()
+        P.step_adj(u, 0, u1)
+        ta = time.perf_counter() - t
+    pts = cfg["nr"] * cfg["nt"] * cfg["nz"]
+    return {"value": 2 * pts / (tf + ta), "unit": "grid-point-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 forward step ({tf:.1f} s) + 1 adjoint step ({ta:.1f} s) of the same workload, "
+                      f"NumPy/SciPy oracle, 1 BLAS thread"}
+
+
+def make_raw(cfg, r, M, K, seed):
+    if cfg["gen"] == "oblique":
+        return synth.localized_oblique(r, M, K, cfg["lz"], cfg["nz"], seed)
+    return synth.solenoidal_modes(r, M, K, cfg["lz"], seed)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1, help="timed optimisation iterations")
+    ap.add_argument("--warmup", type=int, default=0, help="untimed optimisation iterations")
+    ap.add_argument("--workload", default="c2", choices=sorted(configs.WORKLOADS))
+    ap.add_argument("--nsteps", type=int, default=0, help="shorter horizon (development only)")
+    ap.add_argument("--ckpt", type=int, default=0, help="checkpoint slots (default: the workload's)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--stride", type=int, default=8, help="profiler sampling stride")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sharded design is described "
+              f"in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2509_10103_amd import npo
+
+    cfg = dict(configs.WORKLOADS[args.workload])
+    if args.nsteps:
+        cfg["nsteps"] = args.nsteps
+    nck = args.ckpt or min(cfg["n_ckpt"], cfg["nsteps"])
+    torch.cuda.set_device(0)
+    G = npo.Plan(cfg["nr"], cfg["nt"], cfg["nz"], cfg["lz"], cfg["re"], cfg["wo"], cfg["amp"], cfg["dt"],
+                 cfg["t0"], cfg["nsteps"])
+    r = npo.npo_plan_tables(G.handle, cfg["nr"])[0]
+    raw = make_raw(cfg, r, G.M, G.K, cfg["seed"])
+    u0 = torch.from_numpy(raw).to("cuda")
+    npo.npo_project(G.handle, G.ws, u0, u0)
+    npo.npo_normalize(G.handle, G.ws, u0, cfg["e0"])
+    arena = G.arena(nck)
+    uN = G.field()
+    print(f"[bench] {cfg['name']} nsteps={cfg['nsteps']} n_ckpt={nck} arena={arena.numel() * 16 / 2**30:.1f} GiB",
+          file=sys.stderr, flush=True)
+    t = time.perf_counter()
+    npo.npo_forward_run(G.handle, G.ws, arena, nck, u0, uN)
+    torch.cuda.synchronize()
+    print(f"[bench] initial forward sweep {time.perf_counter() - t:.2f} s", file=sys.stderr, flush=True)
+
+    def one_iter():
+        st = npo.npo_iterate(G.handle, G.ws, arena, nck, u0, uN, cfg["e0"])
+        if not st["accepted"]:
+            npo.npo_forward_run(G.handle, G.ws, arena, nck, u0, uN)
+        return st
+
+    for _ in range(args.warmup):
+        one_iter()
+    torch.cuda.synchronize()
+    npo.npo_profile_begin(G.handle, args.stride)
+    lat = []
+    hist = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ti = time.perf_counter()
+        st = one_iter()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ti)
+        hist.append(st)
+        print(f"[bench] iteration {i}: G {st['G_old']:.6g} -> {st['G_new']:.6g} accepted={int(st['accepted'])} "
+              f"sweeps={int(st['forward_sweeps'])} {lat[-1]:.2f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = npo.npo_profile_read(G.handle)
+    pts = cfg["nr"] * cfg["nt"] * cfg["nz"]
+    counted = args.steps * 2 * cfg["nsteps"] * pts
+    value = counted / elapsed
+    ab = alg_bytes(cfg)
+    tot = {k: v["launches"] * v["avg_ms"] for k, v in prof.items()}
+    dom = max(tot, key=tot.get)
+    avg_s = prof[dom]["avg_ms"] * 1e-3
+    achieved = ab[dom] / avg_s / 1e9 if avg_s > 0 else 0.0
+    kern = {k: {"launches": v["launches"], "avg_us": round(v["avg_ms"] * 1e3, 2),
+                "share": round(tot[k] / max(sum(tot.values()), 1e-30), 4),
+                "GBps_alg": round(ab[k] / (v["avg_ms"] * 1e-3) / 1e9, 1) if v["avg_ms"] > 0 else None}
+            for k, v in prof.items() if v["launches"]}
+    out = {
+        "metric": "fwd+adjoint grid-point-steps/s",
+        "value": value,
+        "unit": "grid-point-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "grid": [cfg["nr"], cfg["nt"], cfg["nz"]], "lz_radii": cfg["lz"],
+                   "re": cfg["re"], "wo": cfg["wo"], "amp": cfg["amp"], "dt": cfg["dt"], "t0": cfg["t0"],
+                   "nsteps": cfg["nsteps"], "n_ckpt": nck, "e0": cfg["e0"], "seed": cfg["seed"],
+                   "iteration_latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+                   "gains": [[h["G_old"], h["G_new"], int(h["accepted"]), int(h["forward_sweeps"])] for h in hist]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "alg_bytes_per_launch": ab[dom], "avg_launch_us": avg_s * 1e6},
+        "kernels": kern,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cfg, cfg["seed"])
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -159,6 +159,22 @@ npo_status npo_update(npo_plan plan, void* ws, const void* u0, const void* udag,
 npo_status npo_iterate(npo_plan plan, void* ws, void* ckpt, int32_t n_ckpt, void* u0, void* uN,
                        double e0, double tol, int32_t max_halvings, double* stats, void* stream);
 
+/* u *= sqrt(e0 / E(u)), E(u) = <u,u>_W / 2, on the device. */
+npo_status npo_normalize(npo_plan plan, void* ws, void* u, double e0, void* stream);
+
+/* Sampling profiler: from npo_profile_begin until npo_profile_read, every
+ * stride-th launch of each kernel family is bracketed by HIP events recorded
+ * on the stream it is launched on.  npo_profile_read (host arrays of
+ * NPO_KERNEL_FAMILIES entries) synchronises on the recorded events and returns
+ * launch counts, sampled counts and the mean sampled duration in ms.
+ * Families: 0 curl, 1-3 forward axial-inverse / azimuthal / axial-forward
+ * transforms, 4-6 the same for the adjoint, 7 predictor solve, 8 corrector
+ * solve, 9 plain solve, 10 adjoint solve, 11 adjoint combine, 12 reduction,
+ * 13 projection, 14 axpby, 15 adjoint solve of the composed input. */
+#define NPO_KERNEL_FAMILIES 16
+npo_status npo_profile_begin(npo_plan plan, int32_t stride);
+npo_status npo_profile_read(npo_plan plan, int64_t* launches, int64_t* sampled, double* avg_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -243,8 +243,14 @@ class Pipe:
             out[:, :, m, :] = np.einsum('kab,bk->ak', A, x).reshape(3, self.nr, self.nk)
         return out
 
+    def _fits(self):
+        """Whether one kind of per-mode matrix for all modes fits the cache."""
+        n3 = 3 * self.nr
+        return (self.M + 1) * self.nk * n3 * n3 * 16 <= self.cache_limit // 4
+
     def S(self, R):
-        return self.apply_modes(R, 'S')
+        # the same linear map either way: materialised when it fits in memory
+        return self.apply_modes(R, 'S') if self._fits() else self.S_direct(R)
 
     def S_direct(self, R):
         """S applied mode by mode through the literal solve (no matrices)."""
@@ -261,7 +267,13 @@ class Pipe:
         return out
 
     def E(self, u):
-        return self.apply_modes(u, 'E')
+        if self._fits():
+            return self.apply_modes(u, 'E')
+        out = np.empty_like(u)
+        for m in range(self.M + 1):
+            for kk in range(self.nk):
+                out[:, :, m, kk] = self.E_mode(m, self.alpha[kk], u[:, :, m, kk])
+        return out
 
     # ---------------------------------------------------------- transforms
     def to_phys(self, F):

@@ -275,6 +275,26 @@ npo_status check_plan(npo_plan p) {
 
 }  // namespace
 
+
+namespace npo {
+void prof_begin(const npo_plan_s& p, int kid, hipStream_t st) {
+    Profiler& f = p.prof;
+    if (!f.on) return;
+    const long long n = f.launches[kid];
+    if (n % f.stride == 0 && f.used[kid] < PROF_SLOTS)
+        (void)hipEventRecord(f.ev[(kid * PROF_SLOTS + f.used[kid]) * 2], st);
+}
+void prof_end(const npo_plan_s& p, int kid, hipStream_t st) {
+    Profiler& f = p.prof;
+    if (!f.on) return;
+    const long long n = f.launches[kid]++;
+    if (n % f.stride == 0 && f.used[kid] < PROF_SLOTS) {
+        (void)hipEventRecord(f.ev[(kid * PROF_SLOTS + f.used[kid]) * 2 + 1], st);
+        f.used[kid]++;
+    }
+}
+}  // namespace npo
+
 // ===================================================================== ABI
 extern "C" {
 
@@ -705,6 +725,49 @@ npo_status npo_iterate(npo_plan p, void* ws, void* ckpt, int32_t nck, void* u0, 
         if (std::fabs((Gn - Gold) / Gn) < tol) break;
         al *= 0.5;
     }
+    return NPO_OK;
+}
+
+npo_status npo_profile_begin(npo_plan p, int32_t stride) {
+    if (check_plan(p) || stride < 1) return fail(NPO_EINVAL, "bad argument");
+    npo::Profiler& f = p->prof;
+    if (f.ev.empty()) {
+        f.ev.resize((size_t)npo::KID_COUNT * npo::PROF_SLOTS * 2);
+        for (auto& e : f.ev) HIPCHK(hipEventCreate(&e));
+    }
+    for (int k = 0; k < npo::KID_COUNT; ++k) { f.launches[k] = 0; f.used[k] = 0; }
+    f.stride = stride;
+    f.on = true;
+    return NPO_OK;
+}
+
+npo_status npo_profile_read(npo_plan p, int64_t* launches, int64_t* sampled, double* avg_ms) {
+    if (check_plan(p) || !launches || !sampled || !avg_ms) return fail(NPO_EINVAL, "null argument");
+    npo::Profiler& f = p->prof;
+    for (int k = 0; k < npo::KID_COUNT; ++k) {
+        launches[k] = f.on || f.launches[k] ? f.launches[k] : 0;
+        sampled[k] = f.used[k];
+        double tot = 0.0;
+        for (int s = 0; s < f.used[k]; ++s) {
+            hipEvent_t a = f.ev[(k * npo::PROF_SLOTS + s) * 2], b = f.ev[(k * npo::PROF_SLOTS + s) * 2 + 1];
+            HIPCHK(hipEventSynchronize(b));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, a, b));
+            tot += ms;
+        }
+        avg_ms[k] = f.used[k] ? tot / f.used[k] : 0.0;
+    }
+    f.on = false;
+    return NPO_OK;
+}
+
+npo_status npo_normalize(npo_plan p, void* ws, void* u, double e0, void* stream) {
+    if (check_plan(p) || !ws || !u) return fail(NPO_EINVAL, "null argument");
+    if (!(e0 > 0)) return fail(NPO_EINVAL, "e0 must be positive");
+    WsPtrs w = wsptrs(*p, ws);
+    double* en = w.red + npo::NR_MAX * 4 + 256;
+    HIPCHK(npo::launch_wdot(*p, CF(u), CF(u), w.red, en, ST(stream)));
+    HIPCHK(npo::launch_rescale(*p, F(u), en, 2.0 * e0, ST(stream)));
     return NPO_OK;
 }
 

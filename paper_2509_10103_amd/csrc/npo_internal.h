@@ -8,6 +8,22 @@
 
 namespace npo {
 
+// Kernel families timed by the sampling profiler (ids of npo_profile_read).
+enum KernelId {
+    KID_CURL = 0, KID_ZINV_F, KID_THETA_F, KID_ZFWD_F, KID_ZINV_A, KID_THETA_A, KID_ZFWD_A,
+    KID_SOLVE_P, KID_SOLVE_C, KID_SOLVE_R, KID_SOLVE_ADJ, KID_FINAL, KID_WDOT, KID_PROJECT, KID_AXPBY,
+    KID_SOLVE_ADJ2, KID_COUNT
+};
+constexpr int PROF_SLOTS = 256;   // sampled launches kept per kernel family
+
+struct Profiler {
+    bool on = false;
+    int stride = 1;
+    long long launches[KID_COUNT] = {0};
+    int used[KID_COUNT] = {0};
+    std::vector<hipEvent_t> ev;   // KID_COUNT * PROF_SLOTS * 2
+};
+
 constexpr int NR_MAX = 64;     // radial nodes handled by one workgroup
 constexpr int NFAC_MAX = 8;    // radix factors of an FFT length
 
@@ -61,9 +77,14 @@ struct npo_plan_s {
     // launch shapes
     int zb_theta_fwd = 4, zb_theta_adj = 4;
     int zgroup = 1;
+    mutable npo::Profiler prof;
 };
 
 namespace npo {
+
+// Sampling profiler hooks around one launch on stream st.
+void prof_begin(const npo_plan_s& p, int kid, hipStream_t st);
+void prof_end(const npo_plan_s& p, int kid, hipStream_t st);
 
 // Kernel launchers (npo_kernels.hip).  All enqueue on `st` and return the
 // hipGetLastError() of the launch.

@@ -1175,7 +1175,9 @@ static inline size_t field_elems(const npo_plan_s& p) { return (size_t)3 * p.nr 
 
 hipError_t launch_curl_aux(const npo_plan_s& p, const double2* u, double2* aux, hipStream_t st) {
     const size_t per = (size_t)p.nr * p.mp1 * p.nk;
+    prof_begin(p, KID_CURL, st);
     hipLaunchKernelGGL(k_curl_aux, dim3((per + 255) / 256), dim3(256), 0, st, p.kp, u, aux);
+    prof_end(p, KID_CURL, st);
     return hipGetLastError();
 }
 
@@ -1187,53 +1189,71 @@ hipError_t launch_nl(const npo_plan_s& p, int adj, const double2* u, const doubl
     const int nf = adj ? 9 : 6, nfo = adj ? 6 : 3;
     const int G = p.zgroup;
     const size_t shz = (size_t)2 * G * p.nz * sizeof(double2);
+    prof_begin(p, adj ? KID_ZINV_A : KID_ZINV_F, st);
     hipLaunchKernelGGL(k_zinv, dim3(p.mp1, p.nr), dim3(256), shz, st, p.kp, nf, G, u, aux, y, zb);
+    prof_end(p, adj ? KID_ZINV_A : KID_ZINV_F, st);
     const int ZB = adj ? p.zb_theta_adj : p.zb_theta_fwd;
     const int H = ZB / 2;
     const int nin = adj ? 4 * ZB + H : 3 * ZB, nout = adj ? 3 * ZB : ZB + H;
     const size_t sht = (size_t)2 * (nin > nout ? nin : nout) * p.nt * sizeof(double2);
     const double cw = cos(p.omega * t), sw = sin(p.omega * t);
+    prof_begin(p, adj ? KID_THETA_A : KID_THETA_F, st);
     hipLaunchKernelGGL(k_theta, dim3(p.nz / ZB, p.nr), dim3(256), sht, st, p.kp, adj, ZB, zb, tb, cw, sw);
+    prof_end(p, adj ? KID_THETA_A : KID_THETA_F, st);
     const double scale = 1.0 / ((double)p.nt * p.nz);
+    prof_begin(p, adj ? KID_ZFWD_A : KID_ZFWD_F, st);
     hipLaunchKernelGGL(k_zfwd, dim3(p.mp1, p.nr), dim3(256), shz, st, p.kp, nfo, G, tb, out0, out1, scale);
+    prof_end(p, adj ? KID_ZFWD_A : KID_ZFWD_F, st);
     return hipGetLastError();
 }
 
 hipError_t launch_solve(const npo_plan_s& p, int kind, const double2* a, const double2* b, const double2* c,
                         double2* u_out, double2* aux_out, hipStream_t st) {
+    prof_begin(p, kind == 1 ? KID_SOLVE_P : (kind == 2 ? KID_SOLVE_C : KID_SOLVE_R), st);
     hipLaunchKernelGGL(k_solve, dim3(p.K + 1, p.mp1), dim3(64), 0, st, p.kp, kind, a, b, c, u_out, aux_out);
+    prof_end(p, kind == 1 ? KID_SOLVE_P : (kind == 2 ? KID_SOLVE_C : KID_SOLVE_R), st);
     return hipGetLastError();
 }
 
 hipError_t launch_solve_adj(const npo_plan_s& p, const double2* A, double ca, const double2* B, double cb,
                             const double2* Q, double q0, double q1, double2* out0, double2* out1, hipStream_t st) {
+    prof_begin(p, B ? KID_SOLVE_ADJ2 : KID_SOLVE_ADJ, st);
     hipLaunchKernelGGL(k_solve_adj, dim3(p.K + 1, p.mp1), dim3(64), 0, st, p.kp, A, ca, B, cb, Q, q0, q1, out0,
                        out1);
+    prof_end(p, B ? KID_SOLVE_ADJ2 : KID_SOLVE_ADJ, st);
     return hipGetLastError();
 }
 
 hipError_t launch_final(const npo_plan_s& p, const double2* Z, const double2* A, const double2* B, double2* out,
                         hipStream_t st) {
+    prof_begin(p, KID_FINAL, st);
     hipLaunchKernelGGL(k_final, dim3(p.K + 1, p.mp1), dim3(64), 0, st, p.kp, Z, A, B, out);
+    prof_end(p, KID_FINAL, st);
     return hipGetLastError();
 }
 
 hipError_t launch_wdot(const npo_plan_s& p, const double2* a, const double2* b, double* partial, double* out,
                        hipStream_t st) {
+    prof_begin(p, KID_WDOT, st);
     hipLaunchKernelGGL(k_wdot_partial, dim3(RED_BLOCKS), dim3(256), 0, st, p.kp, a, b, partial);
+    prof_end(p, KID_WDOT, st);
     hipLaunchKernelGGL(k_wdot_final, dim3(1), dim3(256), 0, st, partial, 2.0 * M_PI * p.lz, out);
     return hipGetLastError();
 }
 
 hipError_t launch_project(const npo_plan_s& p, const double2* u, double2* out, hipStream_t st) {
+    prof_begin(p, KID_PROJECT, st);
     hipLaunchKernelGGL(k_project, dim3(p.K + 1, p.mp1), dim3(64), 0, st, p.kp, u, out);
+    prof_end(p, KID_PROJECT, st);
     return hipGetLastError();
 }
 
 hipError_t launch_axpby(const npo_plan_s& p, double ca, const double2* a, double cb, const double2* b, double2* out,
                         hipStream_t st) {
     const size_t n = field_elems(p);
+    prof_begin(p, KID_AXPBY, st);
     hipLaunchKernelGGL(k_axpby, dim3((n + 255) / 256), dim3(256), 0, st, n, ca, a, cb, b, out);
+    prof_end(p, KID_AXPBY, st);
     return hipGetLastError();
 }
 

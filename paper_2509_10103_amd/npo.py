@@ -66,7 +66,14 @@ SIGNATURES = {
     "npo_project": (_I32, [_P, _P, _P, _P, _P]),
     "npo_update": (_I32, [_P, _P, _P, _P, _D, _D, _D, _D, _P, _P]),
     "npo_iterate": (_I32, [_P, _P, _P, _I32, _P, _P, _D, _D, _I32, _DP, _P]),
+    "npo_normalize": (_I32, [_P, _P, _P, _D, _P]),
+    "npo_profile_begin": (_I32, [_P, _I32]),
+    "npo_profile_read": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _DP]),
 }
+
+KERNEL_FAMILIES = ("curl", "zinv_fwd", "theta_fwd", "zfwd_fwd", "zinv_adj", "theta_adj", "zfwd_adj",
+                   "solve_pred", "solve_corr", "solve_raw", "solve_adj", "adj_combine", "wdot", "project", "axpby",
+                   "solve_adj2")
 
 
 def lib():
@@ -196,6 +203,23 @@ def npo_iterate(plan, ws, ckpt, n_ckpt, u0, uN, e0, tol=1e-8, max_halvings=30, s
                              st.ctypes.data_as(_DP), _stream(stream)))
     keys = ("G_old", "G_new", "alpha", "alpha_max", "E0dag", "C0", "accepted", "forward_sweeps")
     return dict(zip(keys, st.tolist()))
+
+
+def npo_normalize(plan, ws, u, e0, stream=None):
+    _check(lib().npo_normalize(plan, _ptr(ws), _ptr(u), e0, _stream(stream)))
+
+
+def npo_profile_begin(plan, stride=1):
+    _check(lib().npo_profile_begin(plan, stride))
+
+
+def npo_profile_read(plan):
+    n = len(KERNEL_FAMILIES)
+    la = (_I64 * n)()
+    sa = (_I64 * n)()
+    av = np.zeros(n)
+    _check(lib().npo_profile_read(plan, la, sa, av.ctypes.data_as(_DP)))
+    return {k: dict(launches=la[i], sampled=sa[i], avg_ms=float(av[i])) for i, k in enumerate(KERNEL_FAMILIES)}
 
 
 # ------------------------------------------------------- convenience
