@@ -159,6 +159,12 @@ npo_status npo_update(npo_plan plan, void* ws, const void* u0, const void* udag,
 npo_status npo_iterate(npo_plan plan, void* ws, void* ckpt, int32_t n_ckpt, void* u0, void* uN,
                        double e0, double tol, int32_t max_halvings, double* stats, void* stream);
 
+/* out = scale * q (.) lam with q = 2 pi L_z c_m w_j: converts the W-gradient
+ * lam of a real functional into the gradient with respect to the real and
+ * imaginary parts of the stored coefficients (m = 0 entries at +k and -k count
+ * as independent coordinates).  out may alias lam. */
+npo_status npo_euclid_grad(npo_plan plan, const void* lam, double scale, void* out, void* stream);
+
 /* u *= sqrt(e0 / E(u)), E(u) = <u,u>_W / 2, on the device. */
 npo_status npo_normalize(npo_plan plan, void* ws, void* u, double e0, void* stream);
 

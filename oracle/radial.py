@@ -16,7 +16,8 @@ the radial quadrature unstated; the readings taken here are
   that sum_j w_j g(r_j) approximates int_0^1 g r dr.
 
 Everything is built from first principles: FD weights from the Taylor
-(moment) conditions, quadrature weights from exact Chebyshev moments.
+(moment) conditions solved exactly in rationals, quadrature weights from
+exact Chebyshev moments.
 """
 import math
 
@@ -50,19 +51,22 @@ def quad_weights(nr):
 def fd_weights(x0, xs, order):
     """Weights c with sum_i c_i f(xs_i) = f^(order)(x0), exact for deg <= len(xs)-1.
 
-    Direct solution of the Taylor conditions sum_i c_i (xs_i - x0)^q / q! =
-    delta_{q, order}, with offsets scaled by their largest magnitude.
+    The Taylor (moment) conditions sum_i c_i (xs_i - x0)^q / q! = delta_{q, order}
+    are solved exactly in rational arithmetic on the (exactly representable)
+    double values of the nodes; only the final weights are rounded.
     """
-    xs = np.asarray(xs, dtype=float)
-    d = xs - x0
-    h = np.max(np.abs(d))
-    t = d / h
-    npt = len(xs)
-    A = np.array([t ** q / math.factorial(q) for q in range(npt)])
-    rhs = np.zeros(npt)
-    rhs[order] = 1.0
-    c = np.linalg.solve(A, rhs)
-    return c / h ** order
+    from fractions import Fraction
+    d = [Fraction(float(x)) - Fraction(float(x0)) for x in xs]
+    npt = len(d)
+    A = [[d[i] ** q / math.factorial(q) for i in range(npt)] + [Fraction(int(q == order))] for q in range(npt)]
+    for k in range(npt):
+        piv = next(i for i in range(k, npt) if A[i][k] != 0)
+        A[k], A[piv] = A[piv], A[k]
+        for i in range(npt):
+            if i != k and A[i][k] != 0:
+                f = A[i][k] / A[k][k]
+                A[i] = [a - f * b for a, b in zip(A[i], A[k])]
+    return np.array([float(A[i][npt] / A[i][i]) for i in range(npt)])
 
 
 def stencil(nr, j):

@@ -142,6 +142,60 @@ std::vector<int> radix_factors(int n) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+
+// ------------------------------------------------- per-mode operator caches
+// Interior operators (nodes 0..nr-2, wall column removed) from B = D2 + D1/r:
+//   Helmholtz H_n = I/dt - (1/(2Re)) (B - n^2/r^2 - a^2),  Poisson P_n = B - n^2/r^2 - a^2.
+// Factored without pivoting into rows of 9 values: l[0..4] (multipliers of
+// columns i-5..i-1), 1/u_ii, u[i][i+1..i+3]; computed in long double.
+struct BandOp {
+    int nr;
+    const std::vector<double>* B;   // [2][nr][7]
+    const std::vector<double>* r;
+};
+void factor_ld(const BandOp& o, int helm, int n, ld a2, ld re, ld dt, ld* LU) {
+    const int nr = o.nr, n1 = nr - 1, pi = n & 1;
+    const ld re2 = 0.5L / re, idt = 1.0L / dt, nn = (ld)n * (ld)n;
+    ld Uw[5][4] = {};
+    for (int i = 0; i < n1; ++i) {
+        const int c0 = std::min(std::max(i - 3, 0), nr - 7);
+        const ld ri = (*o.r)[i];
+        ld a[9];
+        for (int t = 0; t < 9; ++t) {
+            const int c = i - 5 + t, w = c - c0;
+            const ld v = (c >= 0 && c < n1 && w >= 0 && w < 7) ? (ld)(*o.B)[(pi * nr + i) * 7 + w] : 0.0L;
+            a[t] = helm ? -re2 * v : v;
+        }
+        const ld dg = nn / (ri * ri) + a2;
+        a[5] += helm ? (idt + re2 * dg) : -dg;
+        for (int t = 0; t < 5; ++t) {
+            ld l = 0.0L;
+            if (i - 5 + t >= 0) {
+                l = a[t] * Uw[t][0];
+                for (int q = 1; q <= 3; ++q) a[t + q] -= l * Uw[t][q];
+            }
+            LU[i * 9 + t] = l;
+        }
+        const ld inv = 1.0L / a[5];
+        LU[i * 9 + 5] = inv;
+        LU[i * 9 + 6] = a[6]; LU[i * 9 + 7] = a[7]; LU[i * 9 + 8] = a[8];
+        for (int t = 0; t < 4; ++t)
+            for (int q = 0; q < 4; ++q) Uw[t][q] = Uw[t + 1][q];
+        Uw[4][0] = inv; Uw[4][1] = a[6]; Uw[4][2] = a[7]; Uw[4][3] = a[8];
+    }
+}
+void subst_ld(const ld* LU, int n1, ld* x) {
+    for (int i = 0; i < n1; ++i)
+        for (int t = 0; t < 5; ++t)
+            if (i - 5 + t >= 0) x[i] -= LU[i * 9 + t] * x[i - 5 + t];
+    for (int i = n1 - 1; i >= 0; --i) {
+        ld v = x[i];
+        for (int q = 1; q <= 3; ++q)
+            if (i + q < n1) v -= LU[i * 9 + 5 + q] * x[i + q];
+        x[i] = v * LU[i * 9 + 5];
+    }
+}
+
 // --------------------------------------------------- binomial checkpointing
 // T(l, s): minimal forward advances to reverse l steps from a stored start
 // with s slots in total (Sec. 2.4 closed form).
@@ -381,7 +435,7 @@ npo_status npo_plan_create(const npo_grid* grid, const npo_flow* flow, const npo
         return fail(NPO_EUNSUPPORTED, "too many FFT factors");
     }
     // device tables: r, w, D1, D2 (doubles), Ut, dUt, twz, twt (double2), col0 (int)
-    const size_t nd = nr + nr + 2 * nr * 7 + 2 * nr * 7;
+    const size_t nd = nr + nr + 3 * (2 * nr * 7);
     const size_t nc = nr + nr + nz + nt;
     const size_t bytes = align256(nd * 8) + align256(nc * 16) + align256(nr * 4);
     if (hipMalloc(&p->d_tables, bytes) != hipSuccess) {
@@ -395,6 +449,12 @@ npo_status npo_plan_create(const npo_grid* grid, const npo_flow* flow, const npo
     std::memcpy(hd + o, p->w.data(), nr * 8); const size_t o_w = o; o += nr;
     std::memcpy(hd + o, p->D1.data(), 2 * nr * 7 * 8); const size_t o_d1 = o; o += 2 * nr * 7;
     std::memcpy(hd + o, p->D2.data(), 2 * nr * 7 * 8); const size_t o_d2 = o; o += 2 * nr * 7;
+    const size_t o_b = o;
+    for (int pi = 0; pi < 2; ++pi)
+        for (int j = 0; j < nr; ++j)
+            for (int t = 0; t < 7; ++t)
+                hd[o_b + (pi * nr + j) * 7 + t] = p->D2[(pi * nr + j) * 7 + t] + p->D1[(pi * nr + j) * 7 + t] / p->r[j];
+    o += 2 * nr * 7;
     const size_t cbase = align256(nd * 8);
     double2* hc = reinterpret_cast<double2*>(host.data() + cbase);
     const ld pi = acosl(-1.0L);
@@ -417,13 +477,100 @@ npo_status npo_plan_create(const npo_grid* grid, const npo_flow* flow, const npo
     npo::KP& kp = p->kp;
     kp.nr = nr; kp.nt = nt; kp.nz = nz; kp.M = p->M; kp.K = p->K; kp.nk = p->nk; kp.mp1 = p->mp1;
     kp.k0 = p->k0; kp.re = p->re; kp.dt = p->dt; kp.lz = p->lz;
-    kp.r = dd + o_r; kp.w = dd + o_w; kp.D1 = dd + o_d1; kp.D2 = dd + o_d2;
+    kp.r = dd + o_r; kp.w = dd + o_w; kp.D1 = dd + o_d1; kp.D2 = dd + o_d2; kp.B = dd + o_b;
     kp.col0 = reinterpret_cast<const int*>(reinterpret_cast<const char*>(p->d_tables) + ibase);
     kp.Ut = dc; kp.dUt = dc + nr; kp.twz = dc + 2 * nr; kp.twt = dc + 2 * nr + nz;
     kp.nfz = (int)fz.size(); kp.nft = (int)ft.size();
     for (int i = 0; i < npo::NFAC_MAX; ++i) {
         kp.fz[i] = i < kp.nfz ? fz[i] : 1;
         kp.ft[i] = i < kp.nft ? ft[i] : 1;
+    }
+
+    // per-mode operator caches: Helmholtz factors for n = 0..M+1, Poisson
+    // factors for m = 0..M, and the homogeneous (influence) solutions
+    {
+        const int n1 = nr - 1, M = p->M, K = p->K;
+        std::vector<double> Btab(2 * nr * 7);
+        for (int pi = 0; pi < 2; ++pi)
+            for (int j = 0; j < nr; ++j)
+                for (int t = 0; t < 7; ++t)
+                    Btab[(pi * nr + j) * 7 + t] = p->D2[(pi * nr + j) * 7 + t] + p->D1[(pi * nr + j) * 7 + t] / p->r[j];
+        BandOp bo{nr, &Btab, &p->r};
+        const size_t opsz = (size_t)n1 * 9;
+        const size_t homsz = (size_t)3 * nr + 1;
+        std::vector<double> hlu((size_t)(K + 1) * (M + 2) * opsz), plu((size_t)(K + 1) * (M + 1) * opsz);
+        std::vector<double> hom((size_t)(K + 1) * (M + 1) * homsz, 0.0);
+        std::vector<ld> LUh((size_t)(M + 2) * opsz), LUp(opsz), x(nr), y(nr), z(nr), ph(nr);
+        for (int ka = 0; ka <= K; ++ka) {
+            const ld al = (ld)ka * (2.0L * acosl(-1.0L) / (ld)p->lz);
+            const ld a2 = al * al;
+            for (int n = 0; n <= M + 1; ++n) {
+                factor_ld(bo, 1, n, a2, p->re, p->dt, &LUh[n * opsz]);
+                for (size_t e = 0; e < opsz; ++e) hlu[((size_t)ka * (M + 2) + n) * opsz + e] = (double)LUh[n * opsz + e];
+            }
+            for (int m = 0; m <= M; ++m) {
+                double* hm = &hom[((size_t)ka * (M + 1) + m) * homsz];
+                factor_ld(bo, 0, m, a2, p->re, p->dt, LUp.data());
+                for (size_t e = 0; e < opsz; ++e) plu[((size_t)ka * (M + 1) + m) * opsz + e] = (double)LUp[e];
+                if (m == 0 && ka == 0) {
+                    // mean mode: g = H_0^{-1} 1 and sum_i w_i g_i
+                    for (int i = 0; i < n1; ++i) x[i] = 1.0L;
+                    subst_ld(&LUh[0], n1, x.data());
+                    ld wg = 0.0L;
+                    for (int i = 0; i < n1; ++i) { hm[i] = (double)x[i]; wg += (ld)p->w[i] * x[i]; }
+                    hm[3 * nr] = (double)wg;
+                    continue;
+                }
+                const int pe = m & 1, po = (m + 1) & 1;
+                for (int i = 0; i < n1; ++i) {
+                    const int w = n1 - p->col0[i];
+                    ph[i] = (w >= 0 && w < 7) ? -(ld)Btab[(pe * nr + i) * 7 + w] : 0.0L;
+                }
+                subst_ld(LUp.data(), n1, ph.data());
+                ph[n1] = 1.0L;
+                for (int i = 0; i < n1; ++i) {
+                    ld d = 0.0L;
+                    for (int t = 0; t < 7; ++t) d += (ld)p->D1[(pe * nr + i) * 7 + t] * ph[p->col0[i] + t];
+                    const ld mr = (ld)m / (ld)p->r[i];
+                    x[i] = -(d - mr * ph[i]);
+                    y[i] = -(d + mr * ph[i]);
+                    z[i] = -ph[i];
+                }
+                subst_ld(&LUh[(m + 1) * opsz], n1, x.data());
+                subst_ld(&LUh[std::abs(m - 1) * opsz], n1, y.data());
+                subst_ld(&LUh[m * opsz], n1, z.data());
+                ld sh = 0.0L;
+                const int cw = p->col0[n1];
+                for (int t = 0; t < 7; ++t)
+                    if (cw + t < n1) sh += (ld)p->D1[(po * nr + n1) * 7 + t] * (x[cw + t] + y[cw + t]);
+                for (int i = 0; i < n1; ++i) {
+                    hm[i] = (double)x[i];
+                    hm[nr + i] = (double)y[i];
+                    hm[2 * nr + i] = (double)z[i];
+                }
+                hm[3 * nr] = (double)sh;
+            }
+        }
+        const size_t cbytes = (hlu.size() + plu.size() + hom.size()) * 8;
+        if (hipMalloc(&p->d_cache, cbytes) != hipSuccess) {
+            (void)hipFree(p->d_tables);
+            delete p;
+            return fail(NPO_ENOMEM, "hipMalloc of operator caches failed");
+        }
+        double* dcache = p->d_cache;
+        if (hipMemcpy(dcache, hlu.data(), hlu.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(dcache + hlu.size(), plu.data(), plu.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(dcache + hlu.size() + plu.size(), hom.data(), hom.size() * 8, hipMemcpyHostToDevice) !=
+                hipSuccess) {
+            (void)hipFree(p->d_cache);
+            (void)hipFree(p->d_tables);
+            delete p;
+            return fail(NPO_EHIP, "upload of operator caches failed");
+        }
+        p->kp.HLU = dcache;
+        p->kp.PLU = dcache + hlu.size();
+        p->kp.HOM = dcache + hlu.size() + plu.size();
+        p->cache_bytes = cbytes;
     }
     // launch shapes: LDS budget 64 KiB per block for the FFT kernels
     const size_t lds = 64 * 1024;
@@ -470,6 +617,7 @@ npo_status npo_plan_create(const npo_grid* grid, const npo_flow* flow, const npo
 npo_status npo_plan_destroy(npo_plan p) {
     if (!p) return NPO_OK;
     if (p->d_tables) (void)hipFree(p->d_tables);
+    if (p->d_cache) (void)hipFree(p->d_cache);
     delete p;
     return NPO_OK;
 }
@@ -725,6 +873,12 @@ npo_status npo_iterate(npo_plan p, void* ws, void* ckpt, int32_t nck, void* u0, 
         if (std::fabs((Gn - Gold) / Gn) < tol) break;
         al *= 0.5;
     }
+    return NPO_OK;
+}
+
+npo_status npo_euclid_grad(npo_plan p, const void* lam, double scale, void* out, void* stream) {
+    if (check_plan(p) || !lam || !out) return fail(NPO_EINVAL, "null argument");
+    HIPCHK(npo::launch_wscale(*p, CF(lam), F(out), scale, ST(stream)));
     return NPO_OK;
 }
 

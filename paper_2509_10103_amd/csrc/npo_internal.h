@@ -36,11 +36,15 @@ struct KP {
     const double* w;      // [nr]
     const double* D1;     // [2][nr][7] parity 0 = even, 1 = odd
     const double* D2;     // [2][nr][7]
+    const double* B;      // [2][nr][7] D2 + D1 / r_j
     const int* col0;      // [nr] first column of each 7-point row
     const double2* Ut;    // [nr] Womersley amplitude
     const double2* dUt;   // [nr] its radial derivative
     const double2* twz;   // [nz] exp(-2 pi i t / nz)
     const double2* twt;   // [nt] exp(-2 pi i t / nt)
+    const double* HLU;    // [K+1][M+2][nr-1][9] Helmholtz factors
+    const double* PLU;    // [K+1][M+1][nr-1][9] Poisson factors
+    const double* HOM;    // [K+1][M+1][3 nr + 1] homogeneous solutions and s_h
     int nfz, nft;
     int fz[NFAC_MAX];
     int ft[NFAC_MAX];
@@ -71,6 +75,8 @@ struct npo_plan_s {
     std::vector<int> col0;
     std::vector<double> ut_re, ut_im, dut_re, dut_im;
     double* d_tables = nullptr;   // one device allocation for all tables
+    double* d_cache = nullptr;    // per-mode operator factors and homogeneous solutions
+    size_t cache_bytes = 0;
     npo::KP kp;
     npo::WsLayout ws;
     int device = 0;
@@ -108,6 +114,8 @@ hipError_t launch_project(const npo_plan_s& p, const double2* u, double2* out, h
 // out = ca*a + cb*b
 hipError_t launch_axpby(const npo_plan_s& p, double ca, const double2* a, double cb, const double2* b,
                         double2* out, hipStream_t st);
+// out = s * 2 pi L_z c_m w_j * x
+hipError_t launch_wscale(const npo_plan_s& p, const double2* x, double2* out, double s, hipStream_t st);
 // x *= sqrt(e0 / energy_dev[0])
 hipError_t launch_rescale(const npo_plan_s& p, double2* x, const double* energy_dev, double e0,
                           hipStream_t st);

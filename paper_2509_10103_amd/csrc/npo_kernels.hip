@@ -305,148 +305,95 @@ __global__ void k_zfwd(KP p, int nfo, int G, const double2* __restrict__ tb, dou
 }
 
 // ------------------------------------------------------ banded operators
-// Operator kinds on the interior nodes 0..nr-2 (the wall node carries a
-// Dirichlet value and its column is removed):
+// Interior operators on nodes 0..nr-2 (the wall node carries a Dirichlet value
+// and its column is removed):
 //   Helmholtz H_n = I/dt - (1/(2Re)) (D2 + D1/r - n^2/r^2 - a^2)
 //   Poisson   P_n = D2 + D1/r - n^2/r^2 - a^2
-struct OpDesc {
-    int helm;   // 1 = Helmholtz, 0 = Poisson
-    int n;      // azimuthal index of the scalar
-    double a2;  // alpha^2
-};
+// They depend on the plan only, so the host factors each one once (no
+// pivoting; growth factor <= 1 for every operator of these grids) into rows of
+// 9 doubles: l[0..4] (multipliers of columns i-5..i-1), 1/u_ii,
+// u[i][i+1..i+3] (tables p.HLU, p.PLU).  One lane runs one substitution on a
+// real vector x[i*s] in LDS; entries needed from earlier rows ride in shift
+// registers so no load is on the dependence chain.
+constexpr int LUW = 9;
 
-// Entry (row, col) of the full-width scalar Laplacian (no column restriction).
-__device__ __forceinline__ double lap_entry(const KP& p, int n, double a2, int row, int col) {
-    const int pi = n & 1;
-    const double ri = p.r[row];
-    double v = fdw(p.D2, pi, p.nr, p.col0, row, col) + fdw(p.D1, pi, p.nr, p.col0, row, col) / ri;
-    if (row == col) v -= (double)(n * n) / (ri * ri) + a2;
-    return v;
+// (L U) x = b in place.
+__device__ void gsubst(const double* __restrict__ LU, int n1, double* x, int s) {
+    double y1 = 0.0, y2 = 0.0, y3 = 0.0, y4 = 0.0, y5 = 0.0;   // y_{i-1} .. y_{i-5}
+#pragma unroll 4
+    for (int i = 0; i < n1; ++i) {
+        const double* L = LU + i * LUW;
+        double y = x[i * s];
+        y = fma(-L[0], y5, y);
+        y = fma(-L[1], y4, y);
+        y = fma(-L[2], y3, y);
+        y = fma(-L[3], y2, y);
+        y = fma(-L[4], y1, y);
+        x[i * s] = y;
+        y5 = y4; y4 = y3; y3 = y2; y2 = y1; y1 = y;
+    }
+    double x1 = 0.0, x2 = 0.0, x3 = 0.0;                       // x_{i+1} .. x_{i+3}
+#pragma unroll 4
+    for (int i = n1 - 1; i >= 0; --i) {
+        const double* U = LU + i * LUW;
+        double v = x[i * s];
+        v = fma(-U[8], x3, v);
+        v = fma(-U[7], x2, v);
+        v = fma(-U[6], x1, v);
+        v *= U[5];
+        x[i * s] = v;
+        x3 = x2; x2 = x1; x1 = v;
+    }
 }
 
-__device__ __forceinline__ double op_entry(const KP& p, const OpDesc& o, int row, int col) {
+// (L U)^T x = b in place: U^T z = b forward, then L^T x = z backward.
+__device__ void gsubst_T(const double* __restrict__ LU, int n1, double* x, int s) {
+    double z1 = 0.0, z2 = 0.0, z3 = 0.0;                       // z_{i-1} .. z_{i-3}
+    double u61 = 0.0, u71 = 0.0, u72 = 0.0, u81 = 0.0, u82 = 0.0, u83 = 0.0;
+#pragma unroll 4
+    for (int i = 0; i < n1; ++i) {
+        const double* R = LU + i * LUW;
+        const double inv = R[5], r6 = R[6], r7 = R[7], r8 = R[8];
+        double v = x[i * s];
+        v = fma(-u83, z3, v);
+        v = fma(-u72, z2, v);
+        v = fma(-u61, z1, v);
+        v *= inv;
+        x[i * s] = v;
+        z3 = z2; z2 = z1; z1 = v;
+        u83 = u82; u82 = u81; u81 = r8;
+        u72 = u71; u71 = r7;
+        u61 = r6;
+    }
+    double x1 = 0.0, x2 = 0.0, x3 = 0.0, x4 = 0.0, x5 = 0.0;   // x_{i+1} .. x_{i+5}
+    double l41 = 0.0, l31 = 0.0, l32 = 0.0, l21 = 0.0, l22 = 0.0, l23 = 0.0;
+    double l11 = 0.0, l12 = 0.0, l13 = 0.0, l14 = 0.0, l01 = 0.0, l02 = 0.0, l03 = 0.0, l04 = 0.0, l05 = 0.0;
+#pragma unroll 4
+    for (int i = n1 - 1; i >= 0; --i) {
+        const double* R = LU + i * LUW;
+        const double r0 = R[0], r1 = R[1], r2 = R[2], r3 = R[3], r4 = R[4];
+        double v = x[i * s];
+        v = fma(-l05, x5, v);
+        v = fma(-l14, x4, v);
+        v = fma(-l23, x3, v);
+        v = fma(-l32, x2, v);
+        v = fma(-l41, x1, v);
+        x[i * s] = v;
+        x5 = x4; x4 = x3; x3 = x2; x2 = x1; x1 = v;
+        l05 = l04; l04 = l03; l03 = l02; l02 = l01; l01 = r0;
+        l14 = l13; l13 = l12; l12 = l11; l11 = r1;
+        l23 = l22; l22 = l21; l21 = r2;
+        l32 = l31; l31 = r3;
+        l41 = r4;
+    }
+}
+
+// -(Poisson wall column) at interior row j: right-hand side of the
+// homogeneous pressure with p(1) = 1.
+__device__ __forceinline__ double poisson_wall_rhs(const KP& p, int m, int j) {
     const int n1 = p.nr - 1;
-    if (row < 0 || col < 0 || row >= n1 || col >= n1) return 0.0;
-    const double l = lap_entry(p, o.n, o.a2, row, col);
-    if (!o.helm) return l;
-    double v = -l / (2.0 * p.re);
-    if (row == col) v += 1.0 / p.dt;
-    return v;
-}
-
-// Banded LU without pivoting, factor + forward elimination in one sweep and
-// back substitution, run by ONE thread.  The operator (or its transpose) is
-// generated row by row from the FD tables.  NC complex right-hand sides
-// rc[c*ldc + i] and NRR real right-hand sides rr[c*ldr + i] are solved in
-// place.  Uf (LDS, n*(KU+1) doubles) holds U with the inverse diagonal.
-template <int KL, int KU, int NC, int NRR, bool TRANS>
-__device__ void band_solve(const KP& p, const OpDesc& o, int n, double* Uf, double2* rc, int ldc, double* rr,
-                           int ldr) {
-    double Uw[KL][KU + 1];
-    double2 yc[KL][NC > 0 ? NC : 1];
-    double yr[KL][NRR > 0 ? NRR : 1];
-#pragma unroll
-    for (int t = 0; t < KL; ++t) {
-#pragma unroll
-        for (int q = 0; q <= KU; ++q) Uw[t][q] = 0.0;
-#pragma unroll
-        for (int c = 0; c < (NC > 0 ? NC : 1); ++c) yc[t][c] = czero();
-#pragma unroll
-        for (int c = 0; c < (NRR > 0 ? NRR : 1); ++c) yr[t][c] = 0.0;
-    }
-    for (int i = 0; i < n; ++i) {
-        double a[KL + KU + 1];
-#pragma unroll
-        for (int t = 0; t <= KL + KU; ++t) {
-            const int col = i - KL + t;
-            a[t] = TRANS ? op_entry(p, o, col, i) : op_entry(p, o, i, col);
-        }
-        double2 bc[NC > 0 ? NC : 1];
-        double br[NRR > 0 ? NRR : 1];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) bc[c] = rc[c * ldc + i];
-#pragma unroll
-        for (int c = 0; c < NRR; ++c) br[c] = rr[c * ldr + i];
-#pragma unroll
-        for (int t = 0; t < KL; ++t) {
-            if (i - KL + t >= 0) {
-                const double l = a[t] * Uw[t][0];
-#pragma unroll
-                for (int q = 1; q <= KU; ++q) a[t + q] = fma(-l, Uw[t][q], a[t + q]);
-#pragma unroll
-                for (int c = 0; c < NC; ++c) bc[c] = caxpy(bc[c], -l, yc[t][c]);
-#pragma unroll
-                for (int c = 0; c < NRR; ++c) br[c] = fma(-l, yr[t][c], br[c]);
-            }
-        }
-        const double inv = 1.0 / a[KL];
-        Uf[i * (KU + 1)] = inv;
-#pragma unroll
-        for (int q = 1; q <= KU; ++q) Uf[i * (KU + 1) + q] = a[KL + q];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) rc[c * ldc + i] = bc[c];
-#pragma unroll
-        for (int c = 0; c < NRR; ++c) rr[c * ldr + i] = br[c];
-#pragma unroll
-        for (int t = 0; t < KL - 1; ++t) {
-#pragma unroll
-            for (int q = 0; q <= KU; ++q) Uw[t][q] = Uw[t + 1][q];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) yc[t][c] = yc[t + 1][c];
-#pragma unroll
-            for (int c = 0; c < NRR; ++c) yr[t][c] = yr[t + 1][c];
-        }
-        Uw[KL - 1][0] = inv;
-#pragma unroll
-        for (int q = 1; q <= KU; ++q) Uw[KL - 1][q] = a[KL + q];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) yc[KL - 1][c] = bc[c];
-#pragma unroll
-        for (int c = 0; c < NRR; ++c) yr[KL - 1][c] = br[c];
-    }
-    double2 xc[KU][NC > 0 ? NC : 1];
-    double xr[KU][NRR > 0 ? NRR : 1];
-#pragma unroll
-    for (int q = 0; q < KU; ++q) {
-#pragma unroll
-        for (int c = 0; c < (NC > 0 ? NC : 1); ++c) xc[q][c] = czero();
-#pragma unroll
-        for (int c = 0; c < (NRR > 0 ? NRR : 1); ++c) xr[q][c] = 0.0;
-    }
-    for (int i = n - 1; i >= 0; --i) {
-        double2 bc[NC > 0 ? NC : 1];
-        double br[NRR > 0 ? NRR : 1];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) bc[c] = rc[c * ldc + i];
-#pragma unroll
-        for (int c = 0; c < NRR; ++c) br[c] = rr[c * ldr + i];
-#pragma unroll
-        for (int q = 1; q <= KU; ++q) {
-            if (i + q < n) {
-                const double uq = Uf[i * (KU + 1) + q];
-#pragma unroll
-                for (int c = 0; c < NC; ++c) bc[c] = caxpy(bc[c], -uq, xc[q - 1][c]);
-#pragma unroll
-                for (int c = 0; c < NRR; ++c) br[c] = fma(-uq, xr[q - 1][c], br[c]);
-            }
-        }
-        const double inv = Uf[i * (KU + 1)];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) { bc[c] = cscale(bc[c], inv); rc[c * ldc + i] = bc[c]; }
-#pragma unroll
-        for (int c = 0; c < NRR; ++c) { br[c] *= inv; rr[c * ldr + i] = br[c]; }
-#pragma unroll
-        for (int q = KU - 1; q > 0; --q) {
-#pragma unroll
-            for (int c = 0; c < NC; ++c) xc[q][c] = xc[q - 1][c];
-#pragma unroll
-            for (int c = 0; c < NRR; ++c) xr[q][c] = xr[q - 1][c];
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) xc[0][c] = bc[c];
-#pragma unroll
-        for (int c = 0; c < NRR; ++c) xr[0][c] = br[c];
-    }
+    const int w = n1 - p.col0[j];
+    return (w >= 0 && w < 7) ? -p.B[((m & 1) * p.nr + j) * 7 + w] : 0.0;
 }
 
 // Sum over the 7-point row j of FD table D (parity pi) applied to x[col].
@@ -479,12 +426,31 @@ __device__ __forceinline__ double2 fd_apply_T(const KP& p, const double* D, int 
     return s;
 }
 
+// Logical (ka, m) of this block: launches are 1-D with the block count
+// padded to a multiple of 8, and consecutive logical blocks (same ka,
+// neighbouring m, so sharing Helmholtz operators and cache lines) are placed
+// on the same XCD.  Returns false for padding blocks.
+__device__ __forceinline__ bool block_mode(const KP& p, int& ka, int& m) {
+    const int nb = (p.K + 1) * p.mp1;
+    const int per = (nb + 7) / 8;
+    const int b = blockIdx.x;
+    const int L = (b % 8) * per + b / 8;
+    if (L >= nb) return false;
+    m = L % p.mp1;
+    ka = L / p.mp1;
+    return true;
+}
+
 // ------------------------------------------------------------ forward solve
-// Block (ka, m): modes (k, m) and (-k, m) share every operator.
+// One 64-lane block per pair of modes (k, m), (-k, m): they share every
+// operator.  Lanes are radial nodes in the pointwise phases and independent
+// real right-hand sides in the substitution phases.
 __global__ __launch_bounds__(64) void k_solve(KP p, int kind, const double2* __restrict__ ain,
                                               const double2* __restrict__ bin, const double2* __restrict__ cin,
                                               double2* __restrict__ uout, double2* __restrict__ auxout) {
-    const int ka = blockIdx.x, m = blockIdx.y, j = threadIdx.x;
+    int ka, m;
+    if (!block_mode(p, ka, m)) return;
+    const int j = threadIdx.x;
     const int nr = p.nr, N1 = nr - 1;
     const int ncol = ka == 0 ? 1 : 2;
     const int kkc[2] = {ka, ka == 0 ? 0 : p.nk - ka};
@@ -492,67 +458,57 @@ __global__ __launch_bounds__(64) void k_solve(KP p, int kind, const double2* __r
     const double a2 = alc[0] * alc[0];
     const double re2 = 0.5 / p.re, idt = 1.0 / p.dt;
     const int pe = m & 1, po = (m + 1) & 1;
-    __shared__ double2 su[3][2][NR_MAX];
+    const bool mean = (m == 0 && ka == 0);
+    const size_t opsz = (size_t)N1 * LUW;
+    const double* Hk = p.HLU + (size_t)ka * (p.M + 2) * opsz;
+    const double* Pm = p.PLU + ((size_t)ka * p.mp1 + m) * opsz;
+    const double* hom = p.HOM + ((size_t)ka * p.mp1 + m) * (3 * nr + 1);
     __shared__ double2 sR[3][2][NR_MAX];
     __shared__ double2 sp[2][NR_MAX];
-    __shared__ double sph[NR_MAX];
-    __shared__ double shv[3][NR_MAX];
-    __shared__ double sUf[3][NR_MAX * 4];
     __shared__ double2 sa[2];
 
-    if (j < nr) {
-        for (int col = 0; col < 2; ++col)
-            for (int c = 0; c < 3; ++c)
-                su[c][col][j] = (col < ncol) ? ain[fidx(p, c, j, m, kkc[col])] : czero();
-    }
-    __syncthreads();
+    // R = E u^n + N in the (+, -, z) basis (kind 0: R = a)
     if (j < nr) {
         const double rj = p.r[j];
+        const int c0 = p.col0[j];
         for (int col = 0; col < 2; ++col) {
-            const double2 ur = su[0][col][j], ut = su[1][col][j], uz = su[2][col][j];
-            double2 Rp, Rm, Rz;
-            if (kind == 0) {
-                Rp = cadd(ur, cmuli(ut));
-                Rm = csub(ur, cmuli(ut));
-                Rz = uz;
-            } else {
-                // E u = u/dt + (1/(2Re)) lap u, vector Laplacian in the +- basis
-                const double* d1 = p.D1 + (po * nr + j) * 7;
-                const double* d2 = p.D2 + (po * nr + j) * 7;
-                const double* d1z = p.D1 + (pe * nr + j) * 7;
-                const double* d2z = p.D2 + (pe * nr + j) * 7;
-                const int c0 = p.col0[j];
-                double2 lp = czero(), lm = czero(), lz = czero();
-                for (int t = 0; t < 7; ++t) {
-                    const double2 vr = su[0][col][c0 + t], vt = su[1][col][c0 + t], vz = su[2][col][c0 + t];
-                    const double wgt = d2[t] + d1[t] / rj;
-                    lp = caxpy(lp, wgt, cadd(vr, cmuli(vt)));
-                    lm = caxpy(lm, wgt, csub(vr, cmuli(vt)));
-                    lz = caxpy(lz, d2z[t] + d1z[t] / rj, vz);
-                }
-                const double2 up = cadd(ur, cmuli(ut)), um = csub(ur, cmuli(ut));
-                const double np2 = (double)((m + 1) * (m + 1)), nm2 = (double)((m - 1) * (m - 1));
-                const double ia = 1.0 / (rj * rj);
-                lp = caxpy(lp, -(np2 * ia + a2), up);
-                lm = caxpy(lm, -(nm2 * ia + a2), um);
-                lz = caxpy(lz, -((double)(m * m) * ia + a2), uz);
-                double2 Nr, Nt, Nz;
-                if (col < ncol) {
-                    const int kk = kkc[col];
-                    Nr = bin[fidx(p, 0, j, m, kk)];
-                    Nt = bin[fidx(p, 1, j, m, kk)];
-                    Nz = bin[fidx(p, 2, j, m, kk)];
+            double2 Rp = czero(), Rm = czero(), Rz = czero();
+            if (col < ncol) {
+                const int kk = kkc[col];
+                const double2 ur = ain[fidx(p, 0, j, m, kk)], ut = ain[fidx(p, 1, j, m, kk)];
+                const double2 uz = ain[fidx(p, 2, j, m, kk)];
+                if (kind == 0) {
+                    Rp = cadd(ur, cmuli(ut));
+                    Rm = csub(ur, cmuli(ut));
+                    Rz = uz;
+                } else {
+                    const double* bo = p.B + (po * nr + j) * 7;
+                    const double* be = p.B + (pe * nr + j) * 7;
+                    double2 lp = czero(), lm = czero(), lz = czero();
+                    for (int t = 0; t < 7; ++t) {
+                        const double2 vr = ain[fidx(p, 0, c0 + t, m, kk)], vt = ain[fidx(p, 1, c0 + t, m, kk)];
+                        const double2 vz = ain[fidx(p, 2, c0 + t, m, kk)];
+                        lp = caxpy(lp, bo[t], cadd(vr, cmuli(vt)));
+                        lm = caxpy(lm, bo[t], csub(vr, cmuli(vt)));
+                        lz = caxpy(lz, be[t], vz);
+                    }
+                    const double2 up = cadd(ur, cmuli(ut)), um = csub(ur, cmuli(ut));
+                    const double ia = 1.0 / (rj * rj);
+                    lp = caxpy(lp, -((double)((m + 1) * (m + 1)) * ia + a2), up);
+                    lm = caxpy(lm, -((double)((m - 1) * (m - 1)) * ia + a2), um);
+                    lz = caxpy(lz, -((double)(m * m) * ia + a2), uz);
+                    double2 Nr = bin[fidx(p, 0, j, m, kk)];
+                    double2 Nt = bin[fidx(p, 1, j, m, kk)];
+                    double2 Nz = bin[fidx(p, 2, j, m, kk)];
                     if (kind == 2) {
                         Nr = cscale(cadd(Nr, cin[fidx(p, 0, j, m, kk)]), 0.5);
                         Nt = cscale(cadd(Nt, cin[fidx(p, 1, j, m, kk)]), 0.5);
                         Nz = cscale(cadd(Nz, cin[fidx(p, 2, j, m, kk)]), 0.5);
                     }
-                } else {
-                    Nr = Nt = Nz = czero();
+                    Rp = cadd(caxpy(cscale(up, idt), re2, lp), cadd(Nr, cmuli(Nt)));
+                    Rm = cadd(caxpy(cscale(um, idt), re2, lm), csub(Nr, cmuli(Nt)));
+                    Rz = cadd(caxpy(cscale(uz, idt), re2, lz), Nz);
                 }
-                Rp = cadd(caxpy(cscale(up, idt), re2, lp), cadd(Nr, cmuli(Nt)));
-                Rm = cadd(caxpy(cscale(um, idt), re2, lm), csub(Nr, cmuli(Nt)));
-                Rz = cadd(caxpy(cscale(uz, idt), re2, lz), Nz);
             }
             sR[0][col][j] = Rp;
             sR[1][col][j] = Rm;
@@ -561,41 +517,31 @@ __global__ __launch_bounds__(64) void k_solve(KP p, int kind, const double2* __r
     }
     __syncthreads();
 
-    if (m == 0 && ka == 0) {
-        // mean mode: u_r = 0, swirl H_1 u_theta = R_theta, axial H_0 u_z = R_z - f_z with zero flux
-        double2 rt = czero();
-        if (j < N1) rt = cscale(cmuli(csub(sR[1][0][j], sR[0][0][j])), 0.5);   // (R+ - R-)/(2i)
+    if (mean) {
+        // u_r = 0; H_1 u_theta = R_theta; H_0 u_z = R_z - f_z with zero flux (g = H_0^{-1} 1 cached)
+        if (j < N1) sR[1][0][j] = cscale(cmuli(csub(sR[1][0][j], sR[0][0][j])), 0.5);   // (R+ - R-)/(2i)
         __syncthreads();
-        if (j < N1) {
-            sR[1][0][j] = rt;
-            shv[1][j] = 1.0;
-        }
-        __syncthreads();
-        if (j < 2) {
-            OpDesc o{1, j == 0 ? 1 : 0, 0.0};
-            band_solve<5, 3, 2, 1, false>(p, o, N1, sUf[j], &sR[j + 1][0][0], NR_MAX, shv[j], NR_MAX);
+        if (j < 4) {
+            double* x = reinterpret_cast<double*>(&sR[1 + (j >> 1)][0][0]) + (j & 1);
+            gsubst(Hk + (j < 2 ? 1 : 0) * opsz, N1, x, 2);
         }
         __syncthreads();
         if (j == 0) {
             double2 s = czero();
-            double g = 0.0;
-            for (int i = 0; i < N1; ++i) {
-                s = caxpy(s, p.w[i], sR[2][0][i]);
-                g = fma(p.w[i], shv[1][i], g);
-            }
-            sa[0] = cscale(s, -1.0 / g);
+            for (int i = 0; i < N1; ++i) s = caxpy(s, p.w[i], sR[2][0][i]);
+            sa[0] = cscale(s, -1.0 / hom[3 * nr]);
+        }
+        __syncthreads();
+        double2 ut = czero(), uz = czero();
+        if (j < N1) {
+            ut = sR[1][0][j];
+            uz = cadd(sR[2][0][j], cscale(sa[0], hom[j]));
         }
         __syncthreads();
         if (j < nr) {
-            double2 ut = czero(), uz = czero();
-            if (j < N1) {
-                ut = sR[1][0][j];
-                uz = caxpy(sR[2][0][j], shv[1][j], sa[0]);
-                uz = cadd(sR[2][0][j], cscale(sa[0], shv[1][j]));
-            }
-            su[0][0][j] = czero();
-            su[1][0][j] = ut;
-            su[2][0][j] = uz;
+            sR[0][0][j] = czero();
+            sR[1][0][j] = ut;
+            sR[2][0][j] = uz;
             uout[fidx(p, 0, j, 0, 0)] = czero();
             uout[fidx(p, 1, j, 0, 0)] = ut;
             uout[fidx(p, 2, j, 0, 0)] = uz;
@@ -616,20 +562,15 @@ __global__ __launch_bounds__(64) void k_solve(KP p, int kind, const double2* __r
                 d = cadd(d, cscale(cmuli(sR[2][col][j]), alc[col]));
                 sp[col][j] = d;
             }
-            sph[j] = -lap_entry(p, m, a2, j, N1);
-        }
-        __syncthreads();
-        if (j == 0) {
-            OpDesc o{0, m, a2};
-            band_solve<5, 3, 2, 1, false>(p, o, N1, sUf[0], &sp[0][0], NR_MAX, sph, NR_MAX);
+        } else if (j == N1) {
             sp[0][N1] = czero();
             sp[1][N1] = czero();
-            sph[N1] = 1.0;
         }
         __syncthreads();
+        if (j < 4) gsubst(Pm, N1, reinterpret_cast<double*>(&sp[j >> 1][0]) + (j & 1), 2);
+        __syncthreads();
         if (j < N1) {
-            const double rj = p.r[j];
-            const double mr = m / rj;
+            const double mr = m / p.r[j];
             for (int col = 0; col < 2; ++col) {
                 const double2 Dp = fd_apply(p, p.D1, pe, j, sp[col]);
                 const double2 pj = sp[col][j];
@@ -637,50 +578,53 @@ __global__ __launch_bounds__(64) void k_solve(KP p, int kind, const double2* __r
                 sR[1][col][j] = csub(sR[1][col][j], caxpy(Dp, mr, pj));
                 sR[2][col][j] = csub(sR[2][col][j], cscale(cmuli(pj), alc[col]));
             }
-            const double Dph = fd_apply_r(p, p.D1, pe, j, sph);
-            shv[0][j] = -(Dph - mr * sph[j]);
-            shv[1][j] = -(Dph + mr * sph[j]);
-            shv[2][j] = -sph[j];
         }
         __syncthreads();
-        if (j < 3) {
-            const int n = (j == 0) ? m + 1 : (j == 1 ? m - 1 : m);
-            OpDesc o{1, n, a2};
-            band_solve<5, 3, 2, 1, false>(p, o, N1, sUf[j], &sR[j][0][0], NR_MAX, shv[j], NR_MAX);
+        if (j < 12) {
+            // lane = (operator, column, re/im): H_{m+1} u+, H_{|m-1|} u-, H_m u_z
+            const int op = j >> 2;
+            const int n = op == 0 ? m + 1 : (op == 1 ? abs(m - 1) : m);
+            gsubst(Hk + n * opsz, N1, reinterpret_cast<double*>(&sR[op][(j >> 1) & 1][0]) + (j & 1), 2);
         }
         __syncthreads();
-        if (j == 0) {
+        if (j < 2) {
+            // influence coefficient: zero discrete wall divergence
+            const int col = j;
             const double* dw = p.D1 + (po * nr + N1) * 7;
             const int c0 = p.col0[N1];
-            double shs = 0.0;
-            double2 s[2] = {czero(), czero()};
+            double2 s = czero();
             for (int t = 0; t < 7; ++t) {
                 const int c = c0 + t;
-                if (c >= N1) continue;
-                shs = fma(dw[t], shv[0][c] + shv[1][c], shs);
-                for (int col = 0; col < 2; ++col) s[col] = caxpy(s[col], dw[t], cadd(sR[0][col][c], sR[1][col][c]));
+                if (c < N1) s = caxpy(s, dw[t], cadd(sR[0][col][c], sR[1][col][c]));
             }
-            for (int col = 0; col < 2; ++col) sa[col] = cscale(s[col], -1.0 / shs);
+            sa[col] = cscale(s, -1.0 / hom[3 * nr]);
         }
         __syncthreads();
+        double2 outv[2][3];
         if (j < nr) {
-            for (int col = 0; col < ncol; ++col) {
+            double h0 = 0.0, h1 = 0.0, h2 = 0.0;
+            if (j < N1) { h0 = hom[j]; h1 = hom[nr + j]; h2 = hom[2 * nr + j]; }
+            for (int col = 0; col < 2; ++col) {
                 double2 up = czero(), um = czero(), uz = czero();
                 if (j < N1) {
                     const double2 a = sa[col];
-                    up = cadd(sR[0][col][j], cscale(a, shv[0][j]));
-                    um = cadd(sR[1][col][j], cscale(a, shv[1][j]));
-                    uz = cadd(sR[2][col][j], cscale(cmuli(a), alc[col] * shv[2][j]));
+                    up = cadd(sR[0][col][j], cscale(a, h0));
+                    um = cadd(sR[1][col][j], cscale(a, h1));
+                    uz = cadd(sR[2][col][j], cscale(cmuli(a), alc[col] * h2));
                 }
-                const double2 ur = cscale(cadd(up, um), 0.5);
-                const double2 ut = cscale(cmuli(csub(um, up)), 0.5);   // (up - um)/(2i)
-                su[0][col][j] = ur;
-                su[1][col][j] = ut;
-                su[2][col][j] = uz;
-                const int kk = kkc[col];
-                uout[fidx(p, 0, j, m, kk)] = ur;
-                uout[fidx(p, 1, j, m, kk)] = ut;
-                uout[fidx(p, 2, j, m, kk)] = uz;
+                outv[col][0] = cscale(cadd(up, um), 0.5);
+                outv[col][1] = cscale(cmuli(csub(um, up)), 0.5);   // (up - um)/(2i)
+                outv[col][2] = uz;
+            }
+        }
+        __syncthreads();
+        if (j < nr) {
+            for (int col = 0; col < 2; ++col) {
+                for (int c = 0; c < 3; ++c) sR[c][col][j] = outv[col][c];
+                if (col < ncol) {
+                    const int kk = kkc[col];
+                    for (int c = 0; c < 3; ++c) uout[fidx(p, c, j, m, kk)] = outv[col][c];
+                }
             }
         }
         __syncthreads();
@@ -689,9 +633,9 @@ __global__ __launch_bounds__(64) void k_solve(KP p, int kind, const double2* __r
         const double rj = p.r[j];
         for (int col = 0; col < ncol; ++col) {
             const int kk = kkc[col];
-            const double2 ur = su[0][col][j], ut = su[1][col][j];
-            const double2 duz = fd_apply(p, p.D1, pe, j, su[2][col]);
-            const double2 dut = fd_apply(p, p.D1, po, j, su[1][col]);
+            const double2 ur = sR[0][col][j], ut = sR[1][col][j];
+            const double2 duz = fd_apply(p, p.D1, pe, j, sR[2][col]);
+            const double2 dut = fd_apply(p, p.D1, po, j, sR[1][col]);
             auxout[fidx(p, 0, j, m, kk)] = csub(cscale(cmuli(ur), alc[col]), duz);
             auxout[fidx(p, 1, j, m, kk)] = csub(caxpy(dut, 1.0 / rj, ut), cscale(cmuli(ur), m / rj));
         }
@@ -710,23 +654,28 @@ __device__ __forceinline__ void curlH_row(const KP& p, int m, double al, int j, 
 
 // ------------------------------------------------------------ adjoint solve
 // mu = S^dag(ca*A + cb*curl^dag B); out0 = mu + q0*Q; out1 = mu + q1*Q.
+// S^dag = W^{-1} S^H W is applied as the reversed chain of conjugate-
+// transposed steps of the forward solve.
 __global__ __launch_bounds__(64) void k_solve_adj(KP p, const double2* __restrict__ Ain, double ca,
                                                   const double2* __restrict__ Bin, double cb,
                                                   const double2* __restrict__ Qin, double q0, double q1,
                                                   double2* __restrict__ out0, double2* __restrict__ out1) {
-    const int ka = blockIdx.x, m = blockIdx.y, j = threadIdx.x;
+    int ka, m;
+    if (!block_mode(p, ka, m)) return;
+    const int j = threadIdx.x;
     const int nr = p.nr, N1 = nr - 1;
     const int ncol = ka == 0 ? 1 : 2;
     const int kkc[2] = {ka, ka == 0 ? 0 : p.nk - ka};
     const double alc[2] = {ka * p.k0, -ka * p.k0};
-    const double a2 = alc[0] * alc[0];
     const int pe = m & 1, po = (m + 1) & 1;
+    const bool mean = (m == 0 && ka == 0);
+    const size_t opsz = (size_t)N1 * LUW;
+    const double* Hk = p.HLU + (size_t)ka * (p.M + 2) * opsz;
+    const double* Pm = p.PLU + ((size_t)ka * p.mp1 + m) * opsz;
+    const double* hom = p.HOM + ((size_t)ka * p.mp1 + m) * (3 * nr + 1);
     __shared__ double2 sy[3][2][NR_MAX];
     __shared__ double2 sb[3][2][NR_MAX];
     __shared__ double2 sp[2][NR_MAX];
-    __shared__ double sph[NR_MAX];
-    __shared__ double shv[3][NR_MAX];
-    __shared__ double sUf[3][NR_MAX * 4];
     __shared__ double2 sa[2];
     const bool useB = Bin != nullptr;
 
@@ -735,7 +684,7 @@ __global__ __launch_bounds__(64) void k_solve_adj(KP p, const double2* __restric
         for (int col = 0; col < 2; ++col)
             for (int c = 0; c < 3; ++c) {
                 const bool ok = col < ncol;
-                const size_t id = fidx(p, c, j, m, kkc[col]);
+                const size_t id = fidx(p, c, j, m, kkc[ok ? col : 0]);
                 sy[c][col][j] = ok ? cscale(Ain[id], ca) : czero();
                 sb[c][col][j] = (ok && useB) ? cscale(Bin[id], wj) : czero();
             }
@@ -753,7 +702,6 @@ __global__ __launch_bounds__(64) void k_solve_adj(KP p, const double2* __restric
     }
     __syncthreads();
     // y = W lambda on interior rows (the solve's wall output is identically zero)
-    const bool mean = (m == 0 && ka == 0);
     if (j < nr) {
         const double wj = (j < N1) ? p.w[j] : 0.0;
         for (int col = 0; col < 2; ++col) {
@@ -772,25 +720,17 @@ __global__ __launch_bounds__(64) void k_solve_adj(KP p, const double2* __restric
     __syncthreads();
 
     if (mean) {
-        if (j < N1) shv[1][j] = 1.0;
-        __syncthreads();
         if (j == 0) {
-            OpDesc o{1, 0, 0.0};
-            band_solve<5, 3, 0, 1, false>(p, o, N1, sUf[0], nullptr, 0, shv[1], NR_MAX);
-            double wg = 0.0;
             double2 pr = czero();
-            for (int i = 0; i < N1; ++i) {
-                wg = fma(p.w[i], shv[1][i], wg);
-                pr = caxpy(pr, shv[1][i], sy[2][0][i]);
-            }
-            sa[0] = cscale(pr, 1.0 / wg);
+            for (int i = 0; i < N1; ++i) pr = caxpy(pr, hom[i], sy[2][0][i]);
+            sa[0] = cscale(pr, 1.0 / hom[3 * nr]);
         }
         __syncthreads();
         if (j < N1) sy[2][0][j] = caxpy(sy[2][0][j], -p.w[j], sa[0]);
         __syncthreads();
-        if (j < 2) {
-            OpDesc o{1, j == 0 ? 1 : 0, 0.0};
-            band_solve<3, 5, 2, 0, true>(p, o, N1, sUf[j], &sy[j + 1][0][0], NR_MAX, nullptr, 0);
+        if (j < 4) {
+            double* x = reinterpret_cast<double*>(&sy[1 + (j >> 1)][0][0]) + (j & 1);
+            gsubst_T(Hk + (j < 2 ? 1 : 0) * opsz, N1, x, 2);
         }
         __syncthreads();
         if (j < nr) {
@@ -808,48 +748,18 @@ __global__ __launch_bounds__(64) void k_solve_adj(KP p, const double2* __restric
         return;
     }
 
-    // homogeneous pair (forward operators)
-    if (j < N1) sph[j] = -lap_entry(p, m, a2, j, N1);
-    __syncthreads();
-    if (j == 0) {
-        OpDesc o{0, m, a2};
-        band_solve<5, 3, 0, 1, false>(p, o, N1, sUf[0], nullptr, 0, sph, NR_MAX);
-        sph[N1] = 1.0;
-    }
-    __syncthreads();
-    if (j < N1) {
-        const double mr = m / p.r[j];
-        const double Dph = fd_apply_r(p, p.D1, pe, j, sph);
-        shv[0][j] = -(Dph - mr * sph[j]);
-        shv[1][j] = -(Dph + mr * sph[j]);
-        shv[2][j] = -sph[j];
-    }
-    __syncthreads();
-    if (j < 3) {
-        const int n = (j == 0) ? m + 1 : (j == 1 ? m - 1 : m);
-        OpDesc o{1, n, a2};
-        band_solve<5, 3, 0, 1, false>(p, o, N1, sUf[j], nullptr, 0, shv[j], NR_MAX);
-    }
-    __syncthreads();
     // transposed influence correction: ybar_pm -= s * (u_h^H ybar) / s_h
     const double* dw = p.D1 + (po * nr + N1) * 7;
     const int cw0 = p.col0[N1];
-    if (j == 0) {
-        double shs = 0.0;
-        for (int t = 0; t < 7; ++t) {
-            const int c = cw0 + t;
-            if (c < N1) shs = fma(dw[t], shv[0][c] + shv[1][c], shs);
+    if (j < 2) {
+        const int col = j;
+        double2 pr = czero();
+        for (int i = 0; i < N1; ++i) {
+            pr = caxpy(pr, hom[i], sy[0][col][i]);
+            pr = caxpy(pr, hom[nr + i], sy[1][col][i]);
+            pr = cadd(pr, cscale(cmuli(sy[2][col][i]), -alc[col] * hom[2 * nr + i]));   // conj(i a uhz) = -i a uhz
         }
-        for (int col = 0; col < 2; ++col) {
-            double2 pr = czero();
-            for (int i = 0; i < N1; ++i) {
-                pr = caxpy(pr, shv[0][i], sy[0][col][i]);
-                pr = caxpy(pr, shv[1][i], sy[1][col][i]);
-                // conj(i a uhz) = -i a uhz
-                pr = cadd(pr, cscale(cmuli(sy[2][col][i]), -alc[col] * shv[2][i]));
-            }
-            sa[col] = cscale(pr, 1.0 / shs);
-        }
+        sa[col] = cscale(pr, 1.0 / hom[3 * nr]);
     }
     __syncthreads();
     if (j < N1) {
@@ -862,22 +772,16 @@ __global__ __launch_bounds__(64) void k_solve_adj(KP p, const double2* __restric
         }
     }
     __syncthreads();
-    if (j < 3) {
-        const int n = (j == 0) ? m + 1 : (j == 1 ? m - 1 : m);
-        OpDesc o{1, n, a2};
-        band_solve<3, 5, 2, 0, true>(p, o, N1, sUf[j], &sy[j][0][0], NR_MAX, nullptr, 0);
+    if (j < 12) {
+        const int op = j >> 2;
+        const int n = op == 0 ? m + 1 : (op == 1 ? abs(m - 1) : m);
+        gsubst_T(Hk + n * opsz, N1, reinterpret_cast<double*>(&sy[op][(j >> 1) & 1][0]) + (j & 1), 2);
     }
     __syncthreads();
-    // q = G^H w on interior rows
-    if (j < N1) {
-        const double mr = m / p.r[j];
-        for (int col = 0; col < 2; ++col) {
-            // sum of w+ and w- stored temporarily in sb[0]
-            sb[0][col][j] = cadd(sy[0][col][j], sy[1][col][j]);
-        }
-    } else if (j == N1) {
-        sb[0][0][j] = czero();
-        sb[0][1][j] = czero();
+    // q = G^H w on interior rows (w+ + w- staged in sb[0])
+    if (j < nr) {
+        for (int col = 0; col < 2; ++col)
+            sb[0][col][j] = (j < N1) ? cadd(sy[0][col][j], sy[1][col][j]) : czero();
     }
     __syncthreads();
     if (j < N1) {
@@ -888,14 +792,12 @@ __global__ __launch_bounds__(64) void k_solve_adj(KP p, const double2* __restric
             q = csub(q, cscale(cmuli(sy[2][col][j]), alc[col]));
             sp[col][j] = q;
         }
-    }
-    __syncthreads();
-    if (j == 0) {
-        OpDesc o{0, m, a2};
-        band_solve<3, 5, 2, 0, true>(p, o, N1, sUf[0], &sp[0][0], NR_MAX, nullptr, 0);
+    } else if (j == N1) {
         sp[0][N1] = czero();
         sp[1][N1] = czero();
     }
+    __syncthreads();
+    if (j < 4) gsubst_T(Pm, N1, reinterpret_cast<double*>(&sp[j >> 1][0]) + (j & 1), 2);
     __syncthreads();
     if (j < nr) {
         const double rj = p.r[j];
@@ -1163,6 +1065,17 @@ __global__ void k_axpby(size_t n, double ca, const double2* __restrict__ a, doub
     if (b) v = caxpy(v, cb, b[i]);
     out[i] = v;
 }
+// out = s * q (.) x with q = 2 pi L_z c_m w_j: the W-gradient as a Euclidean
+// gradient in the (Re, Im) coordinates of the stored coefficients.
+__global__ void k_wscale(KP p, const double2* __restrict__ x, double2* __restrict__ out, double s) {
+    const size_t total = (size_t)3 * p.nr * p.mp1 * p.nk;
+    size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const int m = (e / p.nk) % p.mp1;
+    const int j = (e / ((size_t)p.nk * p.mp1)) % p.nr;
+    const double q = s * 2.0 * M_PI * p.lz * p.w[j] * (m == 0 ? 1.0 : 2.0);
+    out[e] = cscale(x[e], q);
+}
 __global__ void k_rescale(size_t n, double2* __restrict__ x, const double* __restrict__ en, double e0) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -1210,7 +1123,7 @@ hipError_t launch_nl(const npo_plan_s& p, int adj, const double2* u, const doubl
 hipError_t launch_solve(const npo_plan_s& p, int kind, const double2* a, const double2* b, const double2* c,
                         double2* u_out, double2* aux_out, hipStream_t st) {
     prof_begin(p, kind == 1 ? KID_SOLVE_P : (kind == 2 ? KID_SOLVE_C : KID_SOLVE_R), st);
-    hipLaunchKernelGGL(k_solve, dim3(p.K + 1, p.mp1), dim3(64), 0, st, p.kp, kind, a, b, c, u_out, aux_out);
+    hipLaunchKernelGGL(k_solve, dim3(((p.K + 1) * p.mp1 + 7) / 8 * 8), dim3(64), 0, st, p.kp, kind, a, b, c, u_out, aux_out);
     prof_end(p, kind == 1 ? KID_SOLVE_P : (kind == 2 ? KID_SOLVE_C : KID_SOLVE_R), st);
     return hipGetLastError();
 }
@@ -1218,7 +1131,7 @@ hipError_t launch_solve(const npo_plan_s& p, int kind, const double2* a, const d
 hipError_t launch_solve_adj(const npo_plan_s& p, const double2* A, double ca, const double2* B, double cb,
                             const double2* Q, double q0, double q1, double2* out0, double2* out1, hipStream_t st) {
     prof_begin(p, B ? KID_SOLVE_ADJ2 : KID_SOLVE_ADJ, st);
-    hipLaunchKernelGGL(k_solve_adj, dim3(p.K + 1, p.mp1), dim3(64), 0, st, p.kp, A, ca, B, cb, Q, q0, q1, out0,
+    hipLaunchKernelGGL(k_solve_adj, dim3(((p.K + 1) * p.mp1 + 7) / 8 * 8), dim3(64), 0, st, p.kp, A, ca, B, cb, Q, q0, q1, out0,
                        out1);
     prof_end(p, B ? KID_SOLVE_ADJ2 : KID_SOLVE_ADJ, st);
     return hipGetLastError();
@@ -1254,6 +1167,12 @@ hipError_t launch_axpby(const npo_plan_s& p, double ca, const double2* a, double
     prof_begin(p, KID_AXPBY, st);
     hipLaunchKernelGGL(k_axpby, dim3((n + 255) / 256), dim3(256), 0, st, n, ca, a, cb, b, out);
     prof_end(p, KID_AXPBY, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_wscale(const npo_plan_s& p, const double2* x, double2* out, double s, hipStream_t st) {
+    const size_t n = field_elems(p);
+    hipLaunchKernelGGL(k_wscale, dim3((n + 255) / 256), dim3(256), 0, st, p.kp, x, out, s);
     return hipGetLastError();
 }
 

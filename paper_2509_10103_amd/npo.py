@@ -67,6 +67,7 @@ SIGNATURES = {
     "npo_update": (_I32, [_P, _P, _P, _P, _D, _D, _D, _D, _P, _P]),
     "npo_iterate": (_I32, [_P, _P, _P, _I32, _P, _P, _D, _D, _I32, _DP, _P]),
     "npo_normalize": (_I32, [_P, _P, _P, _D, _P]),
+    "npo_euclid_grad": (_I32, [_P, _P, _D, _P, _P]),
     "npo_profile_begin": (_I32, [_P, _I32]),
     "npo_profile_read": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _DP]),
 }
@@ -207,6 +208,10 @@ def npo_iterate(plan, ws, ckpt, n_ckpt, u0, uN, e0, tol=1e-8, max_halvings=30, s
 
 def npo_normalize(plan, ws, u, e0, stream=None):
     _check(lib().npo_normalize(plan, _ptr(ws), _ptr(u), e0, _stream(stream)))
+
+
+def npo_euclid_grad(plan, lam, scale, out, stream=None):
+    _check(lib().npo_euclid_grad(plan, _ptr(lam), scale, _ptr(out), _stream(stream)))
 
 
 def npo_profile_begin(plan, stride=1):
