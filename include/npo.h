@@ -58,8 +58,10 @@ typedef struct { int32_t nr, ntheta, nz; double lz; } npo_grid;
  * amplitude A = U_max/U_bar - 1 (Sec. 1). A = 0 is steady Hagen-Poiseuille. */
 typedef struct { double re, wo, amp; } npo_flow;
 /* Time: step dt, initial time tau0 (the perturbation is introduced at t0,
- * Sec. 2) and horizon nsteps, so the gain is evaluated at tau0 + nsteps*dt. */
-typedef struct { double dt, t0; int64_t nsteps; } npo_time;
+ * Sec. 2), horizon nsteps (the gain is evaluated at tau0 + nsteps*dt) and the
+ * number of corrector passes of the predictor-corrector step (1..3; 2 keeps
+ * the explicit convective terms stable at axial CFL numbers up to ~2). */
+typedef struct { double dt, t0; int64_t nsteps; int32_t ncorr; } npo_time;
 
 typedef struct npo_plan_s* npo_plan;
 
@@ -109,7 +111,8 @@ npo_status npo_nonlinear_adj(npo_plan plan, void* ws, const void* u, double t, c
 npo_status npo_solve(npo_plan plan, void* ws, const void* R, void* out, void* stream);
 npo_status npo_solve_adj(npo_plan plan, void* ws, const void* y, void* out, void* stream);
 
-/* One predictor-corrector step u^n -> u^{n+1} at t_n = t0 + n dt (Sec. 2.3).
+/* One predictor-corrector step u^n -> u^{n+1} at t_n = t0 + n dt (Sec. 2.3):
+ * w_0 = S(E u^n + N(u^n)), w_c = S(E u^n + (N(u^n) + N(w_{c-1}))/2), c = 1..ncorr.
  * u_n and u_np1 may alias. */
 npo_status npo_forward_step(npo_plan plan, void* ws, const void* u_n, void* u_np1, int64_t n,
                             void* stream);

@@ -17,9 +17,14 @@ with w = curl u, U = U(r,t) e_z the Womersley flow and Om = curl U; the
 gradient of (|u|^2/2 + U.u) is absorbed in the pressure.  Time stepping is the
 second-order predictor-corrector of Sec. 2.3: Crank-Nicolson on the viscous
 term, explicit Euler predictor and trapezoidal corrector for the convective
-terms, the pressure and the flux-holding gradient f_z implicit in both stages:
-    u*      = S(E u^n + N(u^n, t_n))
-    u^{n+1} = S(E u^n + (N(u^n, t_n) + N(u*, t_{n+1})) / 2).
+terms, the pressure and the flux-holding gradient f_z implicit in every stage,
+the corrector iterated ncorr times (default 2):
+    w_0     = S(E u^n + N(u^n, t_n))
+    w_c     = S(E u^n + (N(u^n, t_n) + N(w_{c-1}, t_{n+1})) / 2),  c = 1..ncorr
+    u^{n+1} = w_ncorr.
+A single corrector pass is Heun's method on the convective terms, whose
+amplification on the imaginary axis exceeds one (by (a U dt)^4 / 8 per step);
+two passes are dissipative there for |a U dt| < 2.
 S is the per-mode solve of H u + grad p = R, div u = 0, u(1) = 0 with the
 influence-matrix correction for the wall (Sec. 2.3, wall boundary conditions)
 and, for the mean mode, the zero-flux constraint (Sec. 2, zero bulk velocity).
@@ -48,7 +53,10 @@ def sizes(ntheta, nz):
 class Pipe:
     """One discretised problem: grid, flow parameters, time step."""
 
-    def __init__(self, nr, ntheta, nz, lz, re, wo, amp, dt, tau0=0.0):
+    def __init__(self, nr, ntheta, nz, lz, re, wo, amp, dt, tau0=0.0, ncorr=2):
+        if ncorr < 1:
+            raise ValueError("at least one corrector pass")
+        self.ncorr = int(ncorr)
         self.nr, self.ntheta, self.nz = nr, ntheta, nz
         self.lz, self.re, self.wo, self.amp = float(lz), float(re), float(wo), float(amp)
         self.dt, self.tau0 = float(dt), float(tau0)
@@ -112,6 +120,11 @@ class Pipe:
         """Interior solve with wall column removed; b complex (nr-1, ...)."""
         f = self._factor(kind, n, alpha)
         return sl.lu_solve(f, b.real) + 1j * sl.lu_solve(f, b.imag)
+
+    def _inv_T(self, kind, n, alpha, b):
+        """Transposed interior solve A^T x = b (A real), b complex."""
+        f = self._factor(kind, n, alpha)
+        return sl.lu_solve(f, b.real, trans=1) + 1j * sl.lu_solve(f, b.imag, trans=1)
 
     def _par(self, n):
         return self.rad.parity(n)
@@ -260,6 +273,85 @@ class Pipe:
                 out[:, :, m, kk:kk + 1] = self.S_mode(m, self.alpha[kk], R[:, :, m, kk:kk + 1])
         return out
 
+    def S_adj_mode(self, m, alpha, Y):
+        """W^{-1} S^H W Y for one mode, applied as the reversed chain of
+        conjugate-transposed steps of S_mode (pinned against the materialised
+        W^{-1} S^H W in the tests).  Y has shape (3, nr, ncol)."""
+        nr = self.nr
+        r = self.r[:-1, None]
+        wi = self.w[:-1]
+        y = Y * self.w[None, :, None]
+        y[:, -1] = 0.0                                   # the solve's wall output is identically zero
+        out = np.zeros_like(Y)
+        if m == 0 and alpha == 0.0:
+            out[1, :-1] = self._inv_T('H', 1, 0.0, y[1, :-1])
+            g = self._inv('H', 0, 0.0, np.ones((nr - 1, 1), dtype=complex))[:, 0].real
+            yz = y[2, :-1] - wi[:, None] * (g @ y[2, :-1])[None, :] / (wi @ g)
+            out[2, :-1] = self._inv_T('H', 0, 0.0, yz)
+            return out / self.w[None, :, None]
+        D1o = self.rad.D1[self._par(m + 1)]
+        D1e = self.rad.D1[self._par(m)]
+        yp = 0.5 * (y[0, :-1] + 1j * y[1, :-1])
+        ym = 0.5 * (y[0, :-1] - 1j * y[1, :-1])
+        yz = y[2, :-1]
+        # homogeneous pair (forward operators)
+        L = self.lap(m, alpha)
+        ph = np.zeros(nr, dtype=complex)
+        ph[-1] = 1.0
+        ph[:-1] = -self._inv('P', m, alpha, L[:-1, -1:].astype(complex))[:, 0]
+        rr = self.r
+        hp = self._inv('H', m + 1, alpha, (-(D1e @ ph - m / rr * ph)[:-1])[:, None])[:, 0]
+        hm = self._inv('H', m - 1, alpha, (-(D1e @ ph + m / rr * ph)[:-1])[:, None])[:, 0]
+        hz = self._inv('H', m, alpha, (-(1j * alpha * ph)[:-1])[:, None])[:, 0]
+        s = D1o[-1, :-1]
+        sh = s @ (hp + hm)
+        c = (np.conj(hp) @ yp + np.conj(hm) @ ym + np.conj(hz) @ yz) / sh
+        yp = yp - s[:, None] * c[None, :]
+        ym = ym - s[:, None] * c[None, :]
+        wp = self._inv_T('H', m + 1, alpha, yp)
+        wm = self._inv_T('H', m - 1, alpha, ym)
+        wz = self._inv_T('H', m, alpha, yz)
+        q = D1e[:-1, :-1].T @ (wp + wm) - m / r * (wp - wm) - 1j * alpha * wz
+        phi = self._inv_T('P', m, alpha, q)
+        DT = D1o[:-1, :].T @ phi
+        Rp = -0.5 * DT
+        Rm = -0.5 * DT
+        Rp[:-1] += wp - 0.5 * (1 + m) / r * phi
+        Rm[:-1] += wm - 0.5 * (1 - m) / r * phi
+        out[0] = Rp + Rm
+        out[1] = -1j * (Rp - Rm)
+        out[2, :-1] = wz + 1j * alpha * phi
+        return out / self.w[None, :, None]
+
+    def S_adj_direct(self, Y):
+        out = np.empty_like(Y)
+        for m in range(self.M + 1):
+            for kk in range(self.nk):
+                out[:, :, m, kk:kk + 1] = self.S_adj_mode(m, self.alpha[kk], Y[:, :, m, kk:kk + 1])
+        return out
+
+    def E_adj_direct(self, Z):
+        """W^{-1} E^H W Z with E^H = C^H diag(E_{m+1}^T, E_{m-1}^T) (C/2) and E_m^T."""
+        out = np.empty_like(Z)
+        c = 1.0 / (2.0 * self.re)
+        for m in range(self.M + 1):
+            for kk in range(self.nk):
+                a = self.alpha[kk]
+                z = Z[:, :, m, kk] * self.w[None, :]
+                zp = 0.5 * (z[0] + 1j * z[1])
+                zm = 0.5 * (z[0] - 1j * z[1])
+                ep = zp / self.dt + c * self.lap(m + 1, a).T @ zp
+                em = zm / self.dt + c * self.lap(m - 1, a).T @ zm
+                ez = z[2] / self.dt + c * self.lap(m, a).T @ z[2]
+                out[:, :, m, kk] = np.stack([ep + em, -1j * (ep - em), ez]) / self.w[None, :]
+        return out
+
+    def S_adj(self, Y):
+        return self.apply_modes(Y, 'S', adjoint=True) if self._fits() else self.S_adj_direct(Y)
+
+    def E_adj(self, Z):
+        return self.apply_modes(Z, 'E', adjoint=True) if self._fits() else self.E_adj_direct(Z)
+
     def curl(self, u):
         out = np.empty_like(u)
         for m in range(self.M + 1):
@@ -336,36 +428,51 @@ class Pipe:
         return a + self.apply_modes(b, 'C', adjoint=True)
 
     # ------------------------------------------------------------ stepping
-    def step(self, u, n):
-        """u^n -> u^{n+1} (predictor-corrector)."""
+    def stages(self, u, n):
+        """Predictor and corrector iterates w_0..w_C of the step from u^n.
+
+        w_0 = S(E u + N(u, t_n)); w_c = S(E u + (N(u, t_n) + N(w_{c-1}, t_{n+1}))/2),
+        c = 1..C (C = ncorr corrector passes); w_C = u^{n+1}."""
         t0, t1 = self.time(n), self.time(n + 1)
         Nn = self.N(u, t0)
         Eu = self.E(u)
-        us = self.S(Eu + Nn)
-        Ns = self.N(us, t1)
-        return self.S(Eu + 0.5 * (Nn + Ns))
+        ws = [self.S(Eu + Nn)]
+        for _ in range(self.ncorr):
+            ws.append(self.S(Eu + 0.5 * (Nn + self.N(ws[-1], t1))))
+        return ws
+
+    def step(self, u, n):
+        """u^n -> u^{n+1} (predictor and ncorr corrector passes)."""
+        return self.stages(u, n)[-1]
 
     def predictor(self, u, n):
-        return self.S(self.E(u) + self.N(u, self.time(n)))
+        return self.stages(u, n)[0]
 
     def step_tan(self, u, n, v):
         """Tangent of the step at u^n in direction v."""
         t0, t1 = self.time(n), self.time(n + 1)
-        us = self.predictor(u, n)
+        ws = self.stages(u, n)
         Ev = self.E(v)
         Nv = self.N_tan(u, t0, v)
         vs = self.S(Ev + Nv)
-        return self.S(Ev + 0.5 * (Nv + self.N_tan(us, t1, vs)))
+        for c in range(self.ncorr):
+            vs = self.S(Ev + 0.5 * (Nv + self.N_tan(ws[c], t1, vs)))
+        return vs
 
     def step_adj(self, u, n, lam):
-        """W-adjoint of the step tangent at u^n applied to lam^{n+1}."""
+        """W-adjoint of the step tangent at u^n applied to lam^{n+1}:
+        mu_C = S^+ lam, mu_{c-1} = S^+ (N'(w_{c-1})^+ mu_c / 2),
+        lam^n = E^+ (sum_c mu_c) + N'(u^n)^+ (mu_0 + sum_{c>=1} mu_c / 2)."""
         t0, t1 = self.time(n), self.time(n + 1)
-        us = self.predictor(u, n)
-        muC = self.apply_modes(lam, 'S', adjoint=True)
-        lstar = 0.5 * self.N_adj(us, t1, muC)
-        muP = self.apply_modes(lstar, 'S', adjoint=True)
-        return (self.apply_modes(muC + muP, 'E', adjoint=True)
-                + self.N_adj(u, t0, 0.5 * muC + muP))
+        ws = self.stages(u, n)
+        mu = self.S_adj(lam)
+        Z = mu.copy()
+        Y = 0.5 * mu
+        for c in range(self.ncorr, 0, -1):
+            mu = self.S_adj(0.5 * self.N_adj(ws[c - 1], t1, mu))
+            Z = Z + mu
+            Y = Y + (mu if c == 1 else 0.5 * mu)
+        return self.E_adj(Z) + self.N_adj(u, t0, Y)
 
     def forward(self, u0, nsteps, keep=False):
         """Integrate nsteps; returns u^N (and all u^n, n < N, if keep)."""

@@ -271,15 +271,17 @@ size_t first_adj(const std::vector<Act>& acts) {
 
 // -------------------------------------------------------------- step drivers
 struct WsPtrs {
-    double2 *aux0, *aux1, *nn, *ns, *us, *muC, *muP, *yb, *zb2, *fa, *fb, *fa2, *fb2, *cur, *lam, *tmp, *g,
-        *trial, *trialN;
+    double2 *aux0, *nn, *ns, *muC, *muP, *yb, *zb2, *fa, *fb, *fa2, *fb2, *cur, *lam, *tmp, *g, *trial, *trialN;
+    double2* st[npo::NCORR_MAX];
+    double2* auxs[npo::NCORR_MAX];
     double* red;
 };
 WsPtrs wsptrs(const npo_plan_s& p, void* ws) {
     char* b = static_cast<char*>(ws);
     auto F = [&](size_t off) { return reinterpret_cast<double2*>(b + off); };
     WsPtrs w;
-    w.aux0 = F(p.ws.aux0); w.aux1 = F(p.ws.aux1); w.nn = F(p.ws.nn); w.ns = F(p.ws.ns); w.us = F(p.ws.us);
+    w.aux0 = F(p.ws.aux0); w.nn = F(p.ws.nn); w.ns = F(p.ws.ns);
+    for (int c = 0; c < npo::NCORR_MAX; ++c) { w.st[c] = F(p.ws.st[c]); w.auxs[c] = F(p.ws.auxs[c]); }
     w.muC = F(p.ws.muC); w.muP = F(p.ws.muP); w.yb = F(p.ws.yb); w.zb2 = F(p.ws.zb2);
     w.fa = F(p.ws.fa); w.fb = F(p.ws.fb); w.fa2 = F(p.ws.fa2); w.fb2 = F(p.ws.fb2);
     w.cur = F(p.ws.cur); w.lam = F(p.ws.lam); w.tmp = F(p.ws.tmp); w.g = F(p.ws.g);
@@ -291,33 +293,56 @@ WsPtrs wsptrs(const npo_plan_s& p, void* ws) {
 double time_of(const npo_plan_s& p, long long n) { return p.t0 + (double)n * p.dt; }
 
 // u_out = Phi(u_n).  If have_aux, w.aux0 already holds the vorticity parts of u_n.
+// Stages: w_0 = S(E u + N(u)), w_c = S(E u + (N(u) + N(w_{c-1}))/2), u_out = w_ncorr.
 hipError_t fwd_step(const npo_plan_s& p, void* ws, const double2* un, double2* uout, long long n, bool have_aux,
                     hipStream_t st) {
     WsPtrs w = wsptrs(p, ws);
     hipError_t e;
+    const double t0 = time_of(p, n), t1 = time_of(p, n + 1);
     if (!have_aux && (e = npo::launch_curl_aux(p, un, w.aux0, st)) != hipSuccess) return e;
-    if ((e = npo::launch_nl(p, 0, un, w.aux0, nullptr, time_of(p, n), w.nn, nullptr, ws, st)) != hipSuccess) return e;
-    if ((e = npo::launch_solve(p, 1, un, w.nn, nullptr, w.us, w.aux1, st)) != hipSuccess) return e;
-    if ((e = npo::launch_nl(p, 0, w.us, w.aux1, nullptr, time_of(p, n + 1), w.ns, nullptr, ws, st)) != hipSuccess)
-        return e;
-    return npo::launch_solve(p, 2, un, w.nn, w.ns, uout, w.aux0, st);
+    if ((e = npo::launch_nl(p, 0, un, w.aux0, nullptr, t0, w.nn, nullptr, ws, st)) != hipSuccess) return e;
+    if ((e = npo::launch_solve(p, 1, un, w.nn, nullptr, w.st[0], w.auxs[0], st)) != hipSuccess) return e;
+    for (int c = 1; c <= p.ncorr; ++c) {
+        if ((e = npo::launch_nl(p, 0, w.st[c - 1], w.auxs[c - 1], nullptr, t1, w.ns, nullptr, ws, st)) != hipSuccess)
+            return e;
+        const bool last = c == p.ncorr;
+        if ((e = npo::launch_solve(p, 2, un, w.nn, w.ns, last ? uout : w.st[c], last ? w.aux0 : w.auxs[c], st)) !=
+            hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
-// lam_out = Phi'(u_n)^dag lam_in
+// lam_out = Phi'(u_n)^dag lam_in:
+//   mu_C = S^+ lam; mu_{c-1} = S^+ (N'(w_{c-1})^+ mu_c / 2), c = C..1;
+//   lam_n = E^+ (sum mu_c) + N'(u_n)^+ (mu_0 + sum_{c>=1} mu_c / 2).
 hipError_t adj_step(const npo_plan_s& p, void* ws, const double2* un, const double2* lamin, double2* lamout,
                     long long n, hipStream_t st) {
     WsPtrs w = wsptrs(p, ws);
     hipError_t e;
     const double t0 = time_of(p, n), t1 = time_of(p, n + 1);
+    const int C = p.ncorr;
     if ((e = npo::launch_curl_aux(p, un, w.aux0, st)) != hipSuccess) return e;
     if ((e = npo::launch_nl(p, 0, un, w.aux0, nullptr, t0, w.nn, nullptr, ws, st)) != hipSuccess) return e;
-    if ((e = npo::launch_solve(p, 1, un, w.nn, nullptr, w.us, w.aux1, st)) != hipSuccess) return e;
-    if ((e = npo::launch_solve_adj(p, lamin, 1.0, nullptr, 0.0, nullptr, 0.0, 0.0, w.muC, nullptr, st)) != hipSuccess)
+    if ((e = npo::launch_solve(p, 1, un, w.nn, nullptr, w.st[0], w.auxs[0], st)) != hipSuccess) return e;
+    for (int c = 1; c < C; ++c) {
+        if ((e = npo::launch_nl(p, 0, w.st[c - 1], w.auxs[c - 1], nullptr, t1, w.ns, nullptr, ws, st)) != hipSuccess)
+            return e;
+        if ((e = npo::launch_solve(p, 2, un, w.nn, w.ns, w.st[c], w.auxs[c], st)) != hipSuccess) return e;
+    }
+    double2* mu[2] = {w.muC, w.muP};
+    // mu_C = S^+ lam;  Y = mu_C / 2;  Z = mu_C
+    if ((e = npo::launch_solve_adj(p, lamin, 1.0, nullptr, 0.0, mu[C & 1], nullptr, 0.5, w.yb, nullptr, 1.0, w.zb2,
+                                   st)) != hipSuccess)
         return e;
-    if ((e = npo::launch_nl(p, 1, w.us, w.aux1, w.muC, t1, w.fa, w.fb, ws, st)) != hipSuccess) return e;
-    // mu_P = S^dag(lambda*), lambda* = (A + curl^dag B)/2;  yb = mu_P + mu_C/2, zb2 = mu_P + mu_C
-    if ((e = npo::launch_solve_adj(p, w.fa, 0.5, w.fb, 0.5, w.muC, 0.5, 1.0, w.yb, w.zb2, st)) != hipSuccess)
-        return e;
+    for (int c = C; c >= 1; --c) {
+        if ((e = npo::launch_nl(p, 1, w.st[c - 1], w.auxs[c - 1], mu[c & 1], t1, w.fa, w.fb, ws, st)) != hipSuccess)
+            return e;
+        double2* next = (c > 1) ? mu[(c - 1) & 1] : nullptr;
+        if ((e = npo::launch_solve_adj(p, w.fa, 0.5, w.fb, 0.5, next, w.yb, c == 1 ? 1.0 : 0.5, w.yb, w.zb2, 1.0,
+                                       w.zb2, st)) != hipSuccess)
+            return e;
+    }
     if ((e = npo::launch_nl(p, 1, un, w.aux0, w.yb, t0, w.fa2, w.fb2, ws, st)) != hipSuccess) return e;
     return npo::launch_final(p, w.zb2, w.fa2, w.fb2, lamout, st);
 }
@@ -366,13 +391,14 @@ npo_status npo_plan_create(const npo_grid* grid, const npo_flow* flow, const npo
     if (!(grid->lz > 0) || !(flow->re > 0) || !(flow->wo > 0) || !(time->dt > 0) || time->nsteps < 1)
         return fail(NPO_EINVAL, "lz, re, wo, dt must be positive and nsteps >= 1");
     if (flow->amp < 0) return fail(NPO_EINVAL, "amp must be >= 0");
+    if (time->ncorr < 1 || time->ncorr > npo::NCORR_MAX) return fail(NPO_EINVAL, "ncorr must be in [1, 3]");
 
     auto* p = new npo_plan_s();
     p->nr = nr; p->nt = nt; p->nz = nz;
     p->M = (nt - 1) / 3; p->K = (nz - 1) / 3; p->nk = 2 * p->K + 1; p->mp1 = p->M + 1;
     p->lz = grid->lz; p->k0 = 2.0 * M_PI / grid->lz;
     p->re = flow->re; p->wo = flow->wo; p->amp = flow->amp;
-    p->dt = time->dt; p->t0 = time->t0; p->nsteps = time->nsteps;
+    p->dt = time->dt; p->t0 = time->t0; p->nsteps = time->nsteps; p->ncorr = time->ncorr;
     p->omega = flow->wo * flow->wo / flow->re;
     (void)hipGetDevice(&p->device);
 
@@ -601,8 +627,9 @@ npo_status npo_plan_create(const npo_grid* grid, const npo_flow* flow, const npo
     size_t off = 0;
     auto take = [&](size_t n) { size_t at = off; off += align256(n); return at; };
     npo::WsLayout& L = p->ws;
-    L.aux0 = take(f2); L.aux1 = take(f2);
-    L.nn = take(fb); L.ns = take(fb); L.us = take(fb);
+    L.aux0 = take(f2);
+    for (int c = 0; c < npo::NCORR_MAX; ++c) { L.auxs[c] = take(f2); L.st[c] = take(fb); }
+    L.nn = take(fb); L.ns = take(fb);
     L.muC = take(fb); L.muP = take(fb); L.yb = take(fb); L.zb2 = take(fb);
     L.fa = take(fb); L.fb = take(fb); L.fa2 = take(fb); L.fb2 = take(fb);
     L.cur = take(fb); L.lam = take(fb); L.tmp = take(fb); L.g = take(fb);
@@ -686,7 +713,8 @@ npo_status npo_solve(npo_plan p, void* ws, const void* R, void* out, void* strea
 npo_status npo_solve_adj(npo_plan p, void* ws, const void* y, void* out, void* stream) {
     if (check_plan(p) || !y || !out) return fail(NPO_EINVAL, "null argument");
     (void)ws;
-    HIPCHK(npo::launch_solve_adj(*p, CF(y), 1.0, nullptr, 0.0, nullptr, 0.0, 0.0, F(out), nullptr, ST(stream)));
+    HIPCHK(npo::launch_solve_adj(*p, CF(y), 1.0, nullptr, 0.0, F(out), nullptr, 0.0, nullptr, nullptr, 0.0, nullptr,
+                                 ST(stream)));
     return NPO_OK;
 }
 

@@ -51,10 +51,13 @@ struct KP {
 };
 
 // Workspace carve-up (byte offsets into the caller's workspace).
+constexpr int NCORR_MAX = 3;
+
 struct WsLayout {
-    size_t aux0, aux1;          // 2-component vorticity parts of u^n and u*
-    size_t nn, ns;              // N(u^n), N(u*)
-    size_t us;                  // u*
+    size_t aux0;                // 2-component vorticity parts of u^n
+    size_t auxs[NCORR_MAX];     // ... of the stage iterates w_c
+    size_t st[NCORR_MAX];       // stage iterates w_0 .. w_{ncorr-1}
+    size_t nn, ns;              // N(u^n), N(w_c)
     size_t muC, muP, yb, zb2;   // adjoint temporaries
     size_t fa, fb;              // adjoint convective outputs (A, B)
     size_t fa2, fb2;
@@ -71,6 +74,7 @@ struct npo_plan_s {
     int nr, nt, nz, M, K, nk, mp1;
     double lz, k0, re, wo, amp, dt, t0, omega;
     int64_t nsteps;
+    int ncorr = 2;
     std::vector<double> r, w, D1, D2;
     std::vector<int> col0;
     std::vector<double> ut_re, ut_im, dut_re, dut_im;
@@ -101,10 +105,11 @@ hipError_t launch_nl(const npo_plan_s& p, int adjoint, const double2* u, const d
 // 2 = corrector S(E a + (b + c)/2).  aux_out may be null.
 hipError_t launch_solve(const npo_plan_s& p, int kind, const double2* a, const double2* b,
                         const double2* c, double2* u_out, double2* aux_out, hipStream_t st);
-// mu = S^dag(ca*A + cb*curl^dag(B)); out0 = mu + q0*Q; out1 = mu + q1*Q (out1, Q optional).
+// mu = S^dag(ca*A + cb*curl^dag(B)); out0 = mu; Yout = Yin + qy*mu; Zout = Zin + qz*mu
+// (B, out0, Yin, Yout, Zin, Zout optional; Yin may alias Yout and Zin Zout).
 hipError_t launch_solve_adj(const npo_plan_s& p, const double2* A, double ca, const double2* B, double cb,
-                            const double2* Q, double q0, double q1, double2* out0, double2* out1,
-                            hipStream_t st);
+                            double2* out0, const double2* Yin, double qy, double2* Yout, const double2* Zin,
+                            double qz, double2* Zout, hipStream_t st);
 // out = E^dag Z + A + curl^dag B
 hipError_t launch_final(const npo_plan_s& p, const double2* Z, const double2* A, const double2* B,
                         double2* out, hipStream_t st);

@@ -653,13 +653,24 @@ __device__ __forceinline__ void curlH_row(const KP& p, int m, double al, int j, 
 }
 
 // ------------------------------------------------------------ adjoint solve
-// mu = S^dag(ca*A + cb*curl^dag B); out0 = mu + q0*Q; out1 = mu + q1*Q.
+// mu = S^dag(ca*A + cb*curl^dag B); out0 = mu; Yout = Yin + qy*mu; Zout = Zin + qz*mu.
 // S^dag = W^{-1} S^H W is applied as the reversed chain of conjugate-
 // transposed steps of the forward solve.
-__global__ __launch_bounds__(64) void k_solve_adj(KP p, const double2* __restrict__ Ain, double ca,
-                                                  const double2* __restrict__ Bin, double cb,
-                                                  const double2* __restrict__ Qin, double q0, double q1,
-                                                  double2* __restrict__ out0, double2* __restrict__ out1) {
+struct AdjOut {
+    double2* out0;
+    const double2* Yin;
+    double2* Yout;
+    const double2* Zin;
+    double2* Zout;
+    double qy, qz;
+};
+__device__ __forceinline__ void adj_store(const AdjOut& o, size_t id, double2 mu) {
+    if (o.out0) o.out0[id] = mu;
+    if (o.Yout) o.Yout[id] = caxpy(o.Yin ? o.Yin[id] : czero(), o.qy, mu);
+    if (o.Zout) o.Zout[id] = caxpy(o.Zin ? o.Zin[id] : czero(), o.qz, mu);
+}
+__global__ __launch_bounds__(64) void k_solve_adj(KP p, const double2* Ain, double ca, const double2* Bin,
+                                                  double cb, AdjOut ao) {
     int ka, m;
     if (!block_mode(p, ka, m)) return;
     const int j = threadIdx.x;
@@ -738,12 +749,7 @@ __global__ __launch_bounds__(64) void k_solve_adj(KP p, const double2* __restric
             const double2 mt = (j < N1) ? cscale(sy[1][0][j], iw) : czero();
             const double2 mz = (j < N1) ? cscale(sy[2][0][j], iw) : czero();
             const double2 mv[3] = {czero(), mt, mz};
-            for (int c = 0; c < 3; ++c) {
-                const size_t id = fidx(p, c, j, 0, 0);
-                const double2 qv = Qin ? Qin[id] : czero();
-                out0[id] = caxpy(mv[c], q0, qv);
-                if (out1) out1[id] = caxpy(mv[c], q1, qv);
-            }
+            for (int c = 0; c < 3; ++c) adj_store(ao, fidx(p, c, j, 0, 0), mv[c]);
         }
         return;
     }
@@ -813,12 +819,7 @@ __global__ __launch_bounds__(64) void k_solve_adj(KP p, const double2* __restric
             const double2 Rz = cadd(wz, cscale(cmuli(ph), alc[col]));
             const double2 mv[3] = {cscale(cadd(Rp, Rm), iw), cscale(cmuli(csub(Rm, Rp)), iw), cscale(Rz, iw)};
             const int kk = kkc[col];
-            for (int c = 0; c < 3; ++c) {
-                const size_t id = fidx(p, c, j, m, kk);
-                const double2 qv = Qin ? Qin[id] : czero();
-                out0[id] = caxpy(mv[c], q0, qv);
-                if (out1) out1[id] = caxpy(mv[c], q1, qv);
-            }
+            for (int c = 0; c < 3; ++c) adj_store(ao, fidx(p, c, j, m, kk), mv[c]);
         }
     }
 }
@@ -1129,10 +1130,11 @@ hipError_t launch_solve(const npo_plan_s& p, int kind, const double2* a, const d
 }
 
 hipError_t launch_solve_adj(const npo_plan_s& p, const double2* A, double ca, const double2* B, double cb,
-                            const double2* Q, double q0, double q1, double2* out0, double2* out1, hipStream_t st) {
+                            double2* out0, const double2* Yin, double qy, double2* Yout, const double2* Zin,
+                            double qz, double2* Zout, hipStream_t st) {
+    AdjOut ao{out0, Yin, Yout, Zin, Zout, qy, qz};
     prof_begin(p, B ? KID_SOLVE_ADJ2 : KID_SOLVE_ADJ, st);
-    hipLaunchKernelGGL(k_solve_adj, dim3(((p.K + 1) * p.mp1 + 7) / 8 * 8), dim3(64), 0, st, p.kp, A, ca, B, cb, Q, q0, q1, out0,
-                       out1);
+    hipLaunchKernelGGL(k_solve_adj, dim3(((p.K + 1) * p.mp1 + 7) / 8 * 8), dim3(64), 0, st, p.kp, A, ca, B, cb, ao);
     prof_end(p, B ? KID_SOLVE_ADJ2 : KID_SOLVE_ADJ, st);
     return hipGetLastError();
 }

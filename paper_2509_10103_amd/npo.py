@@ -28,7 +28,7 @@ class Flow(ctypes.Structure):
 
 
 class Time(ctypes.Structure):
-    _fields_ = [("dt", ctypes.c_double), ("t0", ctypes.c_double), ("nsteps", ctypes.c_int64)]
+    _fields_ = [("dt", ctypes.c_double), ("t0", ctypes.c_double), ("nsteps", ctypes.c_int64), ("ncorr", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -109,10 +109,10 @@ def _stream(stream=None):
 
 
 # ------------------------------------------------------------------ plan
-def npo_plan_create(nr, ntheta, nz, lz, re, wo, amp, dt, t0, nsteps):
+def npo_plan_create(nr, ntheta, nz, lz, re, wo, amp, dt, t0, nsteps, ncorr=2):
     g = Grid(nr, ntheta, nz, lz)
     f = Flow(re, wo, amp)
-    t = Time(dt, t0, nsteps)
+    t = Time(dt, t0, nsteps, ncorr)
     h = _P()
     _check(lib().npo_plan_create(ctypes.byref(g), ctypes.byref(f), ctypes.byref(t), 0, ctypes.byref(h)))
     return h
@@ -231,9 +231,9 @@ def npo_profile_read(plan):
 class Plan:
     """A plan plus its device workspace (torch allocations)."""
 
-    def __init__(self, nr, ntheta, nz, lz, re, wo, amp, dt, t0=0.0, nsteps=1, device="cuda"):
+    def __init__(self, nr, ntheta, nz, lz, re, wo, amp, dt, t0=0.0, nsteps=1, ncorr=2, device="cuda"):
         import torch
-        self.handle = npo_plan_create(nr, ntheta, nz, lz, re, wo, amp, dt, t0, nsteps)
+        self.handle = npo_plan_create(nr, ntheta, nz, lz, re, wo, amp, dt, t0, nsteps, ncorr)
         self.info = npo_plan_info(self.handle)
         self.nr, self.M, self.K = nr, self.info["M"], self.info["K"]
         self.shape = (3, nr, self.M + 1, 2 * self.K + 1)

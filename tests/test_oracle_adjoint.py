@@ -34,6 +34,16 @@ def test_materialised_solve_matches_literal_solve(prob):
     assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(a))
 
 
+def test_direct_adjoints_match_materialised_definition(prob):
+    P, u, v, y = prob
+    a = P.S_adj_direct(y)
+    b = P.apply_modes(y, 'S', adjoint=True)
+    assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(b))
+    a = P.E_adj_direct(y)
+    b = P.apply_modes(y, 'E', adjoint=True)
+    assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(b))
+
+
 def test_nonlinear_term_dot_product(prob):
     P, u, v, y = prob
     a = P.wdot(y, P.N_tan(u, 0.7, v))
@@ -47,6 +57,30 @@ def test_step_dot_product(prob):
     a = P.wdot(y, P.step_tan(u, 3, v))
     b = P.wdot(P.step_adj(u, 3, y), v)
     assert rel(a, b) < 1e-11
+
+
+@pytest.mark.parametrize("ncorr", [1, 3])
+def test_step_dot_product_other_corrector_counts(prob, ncorr):
+    P0, u, v, y = prob
+    P = Pipe(16, 12, 12, 2 * np.pi, 1500, 8, 1.0, 0.02, 0.3, ncorr=ncorr)
+    a = P.wdot(y, P.step_tan(u, 3, v))
+    b = P.wdot(P.step_adj(u, 3, y), v)
+    assert rel(a, b) < 1e-11
+
+
+def test_two_corrector_passes_damp_fast_axial_advection():
+    # one fast axial mode: with a single pass (Heun) the explicit advection
+    # grows by ~(a U dt)^4/8 per step, more than the viscous decay; two passes damp it
+    def radius(ncorr):
+        P = Pipe(24, 6, 6, 2 * np.pi / 40.0, 2000, 8, 0.0, 0.03, 0.0, ncorr=ncorr)
+        n3 = 3 * P.nr
+        A = np.zeros((n3, n3), dtype=complex)
+        for i in range(n3):
+            v = P.zeros()
+            v[:, :, 0, 1] = np.eye(n3)[i].reshape(3, P.nr)
+            A[:, i] = P.step_tan(P.zeros(), 0, v)[:, :, 0, 1].reshape(-1)
+        return np.max(np.abs(np.linalg.eigvals(A)))
+    assert radius(1) > 1.0 > radius(2)
 
 
 def test_tangent_matches_finite_differences(prob):
