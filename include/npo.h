@@ -162,6 +162,14 @@ npo_status npo_update(npo_plan plan, void* ws, const void* u0, const void* udag,
 npo_status npo_iterate(npo_plan plan, void* ws, void* ckpt, int32_t n_ckpt, void* u0, void* uN,
                        double e0, double tol, int32_t max_halvings, double* stats, void* stream);
 
+/* Launch shapes of the transform kernels (the autotuner's knobs): zgroup =
+ * fields per axial-transform block (1..3), zb_fwd / zb_adj = axial points per
+ * azimuthal-transform block in the forward / adjoint products (2, 4 or 8,
+ * dividing nz).  Shapes whose LDS tiles exceed 160 KiB are rejected
+ * (NPO_EINVAL).  Results do not depend on the shapes. */
+npo_status npo_plan_set_tuning(npo_plan plan, int32_t zgroup, int32_t zb_fwd, int32_t zb_adj);
+npo_status npo_plan_get_tuning(npo_plan plan, int32_t* zgroup, int32_t* zb_fwd, int32_t* zb_adj);
+
 /* out = scale * q (.) lam with q = 2 pi L_z c_m w_j: converts the W-gradient
  * lam of a real functional into the gradient with respect to the real and
  * imaginary parts of the stored coefficients (m = 0 entries at +k and -k count

@@ -904,6 +904,32 @@ npo_status npo_iterate(npo_plan p, void* ws, void* ckpt, int32_t nck, void* u0, 
     return NPO_OK;
 }
 
+npo_status npo_plan_set_tuning(npo_plan p, int32_t zgroup, int32_t zb_fwd, int32_t zb_adj) {
+    if (check_plan(p)) return NPO_EINVAL;
+    auto ok_zb = [&](int zb, int adj) {
+        if (zb != 2 && zb != 4 && zb != 8) return false;
+        if (p->nz % zb) return false;
+        const int H = zb / 2;
+        const int nin = adj ? 4 * zb + H : 3 * zb, nout = adj ? 3 * zb : zb + H;
+        return (size_t)2 * std::max(nin, nout) * p->nt * 16 <= 160 * 1024;
+    };
+    if (zgroup < 1 || zgroup > 3 || (size_t)2 * zgroup * p->nz * 16 > 160 * 1024)
+        return fail(NPO_EINVAL, "zgroup must be 1..3 and fit 160 KiB of LDS");
+    if (!ok_zb(zb_fwd, 0) || !ok_zb(zb_adj, 1)) return fail(NPO_EINVAL, "bad azimuthal z-block");
+    p->zgroup = zgroup;
+    p->zb_theta_fwd = zb_fwd;
+    p->zb_theta_adj = zb_adj;
+    return NPO_OK;
+}
+
+npo_status npo_plan_get_tuning(npo_plan p, int32_t* zgroup, int32_t* zb_fwd, int32_t* zb_adj) {
+    if (check_plan(p) || !zgroup || !zb_fwd || !zb_adj) return fail(NPO_EINVAL, "null argument");
+    *zgroup = p->zgroup;
+    *zb_fwd = p->zb_theta_fwd;
+    *zb_adj = p->zb_theta_adj;
+    return NPO_OK;
+}
+
 npo_status npo_euclid_grad(npo_plan p, const void* lam, double scale, void* out, void* stream) {
     if (check_plan(p) || !lam || !out) return fail(NPO_EINVAL, "null argument");
     HIPCHK(npo::launch_wscale(*p, CF(lam), F(out), scale, ST(stream)));

@@ -426,230 +426,270 @@ __device__ __forceinline__ double2 fd_apply_T(const KP& p, const double* D, int 
     return s;
 }
 
-// Logical (ka, m) of this block: launches are 1-D with the block count
-// padded to a multiple of 8, and consecutive logical blocks (same ka,
-// neighbouring m, so sharing Helmholtz operators and cache lines) are placed
-// on the same XCD.  Returns false for padding blocks.
-__device__ __forceinline__ bool block_mode(const KP& p, int& ka, int& m) {
-    const int nb = (p.K + 1) * p.mp1;
+// Radial kernels: a block owns one azimuthal index m and RG consecutive |k|
+// (RQ = 2*RG modes: +k and -k).  Lanes run over modes, so global loads and
+// stores of a radial row touch contiguous runs of kk; the block count is
+// padded to a multiple of 8 and consecutive logical blocks (same |k| group,
+// neighbouring m: they share Helmholtz operators) are placed on one XCD.
+constexpr int RG = 8;
+constexpr int RQ = 2 * RG;
+constexpr int RT = 256;    // threads per radial block
+constexpr int RJ = RT / RQ; // radial rows handled concurrently
+
+__host__ __device__ __forceinline__ int radial_groups(int K) { return (K + 1 + RG - 1) / RG; }
+
+__device__ __forceinline__ bool block_group(const KP& p, int& g, int& m) {
+    const int nb = radial_groups(p.K) * p.mp1;
     const int per = (nb + 7) / 8;
     const int b = blockIdx.x;
     const int L = (b % 8) * per + b / 8;
     if (L >= nb) return false;
     m = L % p.mp1;
-    ka = L / p.mp1;
+    g = L / p.mp1;
     return true;
 }
 
+struct Slot {
+    int ka, kk;
+    double al;
+    bool valid, mean;
+};
+__device__ __forceinline__ Slot slot_of(const KP& p, int g, int m, int q) {
+    Slot s;
+    s.ka = g * RG + (q >> 1);
+    const int neg = q & 1;
+    s.valid = s.ka <= p.K && !(s.ka == 0 && neg);
+    s.kk = neg ? p.nk - s.ka : s.ka;
+    s.al = (neg ? -s.ka : s.ka) * p.k0;
+    s.mean = s.valid && m == 0 && s.ka == 0;
+    return s;
+}
+
 // ------------------------------------------------------------ forward solve
-// One 64-lane block per pair of modes (k, m), (-k, m): they share every
-// operator.  Lanes are radial nodes in the pointwise phases and independent
-// real right-hand sides in the substitution phases.
-__global__ __launch_bounds__(64) void k_solve(KP p, int kind, const double2* __restrict__ ain,
+// Lanes are (radial row, mode) in the pointwise phases and independent real
+// right-hand sides (operator, mode, re/im) in the substitution phases.
+__global__ __launch_bounds__(RT) void k_solve(KP p, int kind, const double2* __restrict__ ain,
                                               const double2* __restrict__ bin, const double2* __restrict__ cin,
                                               double2* __restrict__ uout, double2* __restrict__ auxout) {
-    int ka, m;
-    if (!block_mode(p, ka, m)) return;
-    const int j = threadIdx.x;
+    int g, m;
+    if (!block_group(p, g, m)) return;
+    const int t = threadIdx.x, q = t % RQ, jg = t / RQ;
     const int nr = p.nr, N1 = nr - 1;
-    const int ncol = ka == 0 ? 1 : 2;
-    const int kkc[2] = {ka, ka == 0 ? 0 : p.nk - ka};
-    const double alc[2] = {ka * p.k0, -ka * p.k0};
-    const double a2 = alc[0] * alc[0];
     const double re2 = 0.5 / p.re, idt = 1.0 / p.dt;
     const int pe = m & 1, po = (m + 1) & 1;
-    const bool mean = (m == 0 && ka == 0);
     const size_t opsz = (size_t)N1 * LUW;
-    const double* Hk = p.HLU + (size_t)ka * (p.M + 2) * opsz;
-    const double* Pm = p.PLU + ((size_t)ka * p.mp1 + m) * opsz;
-    const double* hom = p.HOM + ((size_t)ka * p.mp1 + m) * (3 * nr + 1);
-    __shared__ double2 sR[3][2][NR_MAX];
-    __shared__ double2 sp[2][NR_MAX];
-    __shared__ double2 sa[2];
+    const Slot sl = slot_of(p, g, m, q);
+    const double a2 = sl.al * sl.al;
+    __shared__ double2 sR[3][NR_MAX][RQ];
+    __shared__ double2 sp[NR_MAX][RQ];
+    __shared__ double2 sa[RQ];
 
     // R = E u^n + N in the (+, -, z) basis (kind 0: R = a)
-    if (j < nr) {
-        const double rj = p.r[j];
-        const int c0 = p.col0[j];
-        for (int col = 0; col < 2; ++col) {
-            double2 Rp = czero(), Rm = czero(), Rz = czero();
-            if (col < ncol) {
-                const int kk = kkc[col];
-                const double2 ur = ain[fidx(p, 0, j, m, kk)], ut = ain[fidx(p, 1, j, m, kk)];
-                const double2 uz = ain[fidx(p, 2, j, m, kk)];
-                if (kind == 0) {
-                    Rp = cadd(ur, cmuli(ut));
-                    Rm = csub(ur, cmuli(ut));
-                    Rz = uz;
-                } else {
-                    const double* bo = p.B + (po * nr + j) * 7;
-                    const double* be = p.B + (pe * nr + j) * 7;
-                    double2 lp = czero(), lm = czero(), lz = czero();
-                    for (int t = 0; t < 7; ++t) {
-                        const double2 vr = ain[fidx(p, 0, c0 + t, m, kk)], vt = ain[fidx(p, 1, c0 + t, m, kk)];
-                        const double2 vz = ain[fidx(p, 2, c0 + t, m, kk)];
-                        lp = caxpy(lp, bo[t], cadd(vr, cmuli(vt)));
-                        lm = caxpy(lm, bo[t], csub(vr, cmuli(vt)));
-                        lz = caxpy(lz, be[t], vz);
-                    }
-                    const double2 up = cadd(ur, cmuli(ut)), um = csub(ur, cmuli(ut));
-                    const double ia = 1.0 / (rj * rj);
-                    lp = caxpy(lp, -((double)((m + 1) * (m + 1)) * ia + a2), up);
-                    lm = caxpy(lm, -((double)((m - 1) * (m - 1)) * ia + a2), um);
-                    lz = caxpy(lz, -((double)(m * m) * ia + a2), uz);
-                    double2 Nr = bin[fidx(p, 0, j, m, kk)];
-                    double2 Nt = bin[fidx(p, 1, j, m, kk)];
-                    double2 Nz = bin[fidx(p, 2, j, m, kk)];
-                    if (kind == 2) {
-                        Nr = cscale(cadd(Nr, cin[fidx(p, 0, j, m, kk)]), 0.5);
-                        Nt = cscale(cadd(Nt, cin[fidx(p, 1, j, m, kk)]), 0.5);
-                        Nz = cscale(cadd(Nz, cin[fidx(p, 2, j, m, kk)]), 0.5);
-                    }
-                    Rp = cadd(caxpy(cscale(up, idt), re2, lp), cadd(Nr, cmuli(Nt)));
-                    Rm = cadd(caxpy(cscale(um, idt), re2, lm), csub(Nr, cmuli(Nt)));
-                    Rz = cadd(caxpy(cscale(uz, idt), re2, lz), Nz);
+    for (int j = jg; j < nr; j += RJ) {
+        double2 Rp = czero(), Rm = czero(), Rz = czero();
+        if (sl.valid) {
+            const int kk = sl.kk;
+            const double2 ur = ain[fidx(p, 0, j, m, kk)], ut = ain[fidx(p, 1, j, m, kk)];
+            const double2 uz = ain[fidx(p, 2, j, m, kk)];
+            if (kind == 0) {
+                Rp = cadd(ur, cmuli(ut));
+                Rm = csub(ur, cmuli(ut));
+                Rz = uz;
+            } else {
+                const double rj = p.r[j];
+                const int c0 = p.col0[j];
+                const double* bo = p.B + (po * nr + j) * 7;
+                const double* be = p.B + (pe * nr + j) * 7;
+                double2 lp = czero(), lm = czero(), lz = czero();
+                for (int s = 0; s < 7; ++s) {
+                    const double2 vr = ain[fidx(p, 0, c0 + s, m, kk)], vt = ain[fidx(p, 1, c0 + s, m, kk)];
+                    const double2 vz = ain[fidx(p, 2, c0 + s, m, kk)];
+                    lp = caxpy(lp, bo[s], cadd(vr, cmuli(vt)));
+                    lm = caxpy(lm, bo[s], csub(vr, cmuli(vt)));
+                    lz = caxpy(lz, be[s], vz);
                 }
+                const double2 up = cadd(ur, cmuli(ut)), um = csub(ur, cmuli(ut));
+                const double ia = 1.0 / (rj * rj);
+                lp = caxpy(lp, -((double)((m + 1) * (m + 1)) * ia + a2), up);
+                lm = caxpy(lm, -((double)((m - 1) * (m - 1)) * ia + a2), um);
+                lz = caxpy(lz, -((double)(m * m) * ia + a2), uz);
+                double2 Nr = bin[fidx(p, 0, j, m, kk)];
+                double2 Nt = bin[fidx(p, 1, j, m, kk)];
+                double2 Nz = bin[fidx(p, 2, j, m, kk)];
+                if (kind == 2) {
+                    Nr = cscale(cadd(Nr, cin[fidx(p, 0, j, m, kk)]), 0.5);
+                    Nt = cscale(cadd(Nt, cin[fidx(p, 1, j, m, kk)]), 0.5);
+                    Nz = cscale(cadd(Nz, cin[fidx(p, 2, j, m, kk)]), 0.5);
+                }
+                Rp = cadd(caxpy(cscale(up, idt), re2, lp), cadd(Nr, cmuli(Nt)));
+                Rm = cadd(caxpy(cscale(um, idt), re2, lm), csub(Nr, cmuli(Nt)));
+                Rz = cadd(caxpy(cscale(uz, idt), re2, lz), Nz);
             }
-            sR[0][col][j] = Rp;
-            sR[1][col][j] = Rm;
-            sR[2][col][j] = Rz;
+        }
+        sR[0][j][q] = Rp;
+        sR[1][j][q] = Rm;
+        sR[2][j][q] = Rz;
+    }
+    __syncthreads();
+    // particular pressure: P_m p = div R on interior nodes, p(1) = 0 (zero for the mean mode)
+    for (int j = jg; j < nr; j += RJ) {
+        double2 d = czero();
+        if (j < N1 && sl.valid && !sl.mean) {
+            const double rj = p.r[j];
+            const double* d1 = p.D1 + (po * nr + j) * 7;
+            const int c0 = p.col0[j];
+            double2 dsum = czero();
+            for (int s = 0; s < 7; ++s) dsum = caxpy(dsum, d1[s], cadd(sR[0][c0 + s][q], sR[1][c0 + s][q]));
+            d = cscale(dsum, 0.5);
+            d = caxpy(d, 0.5 * (1 + m) / rj, sR[0][j][q]);
+            d = caxpy(d, 0.5 * (1 - m) / rj, sR[1][j][q]);
+            d = cadd(d, cscale(cmuli(sR[2][j][q]), sl.al));
+        }
+        sp[j][q] = d;
+    }
+    __syncthreads();
+    if (t < 2 * RQ) {
+        const int qq = t % RQ, part = t / RQ;
+        const Slot s2 = slot_of(p, g, m, qq);
+        if (s2.valid && !s2.mean)
+            gsubst(p.PLU + ((size_t)s2.ka * p.mp1 + m) * opsz, N1, reinterpret_cast<double*>(&sp[0][qq]) + part, 2 * RQ);
+    }
+    __syncthreads();
+    // Helmholtz right-hand sides R - grad p; the mean mode keeps (R_theta, R_z)
+    for (int j = jg; j < N1; j += RJ) {
+        if (sl.mean) {
+            sR[1][j][q] = cscale(cmuli(csub(sR[1][j][q], sR[0][j][q])), 0.5);   // (R+ - R-)/(2i)
+        } else if (sl.valid) {
+            const double mr = m / p.r[j];
+            const double* d1 = p.D1 + (pe * nr + j) * 7;
+            const int c0 = p.col0[j];
+            double2 Dp = czero();
+            for (int s = 0; s < 7; ++s) Dp = caxpy(Dp, d1[s], sp[c0 + s][q]);
+            const double2 pj = sp[j][q];
+            sR[0][j][q] = csub(sR[0][j][q], caxpy(Dp, -mr, pj));
+            sR[1][j][q] = csub(sR[1][j][q], caxpy(Dp, mr, pj));
+            sR[2][j][q] = csub(sR[2][j][q], cscale(cmuli(pj), sl.al));
         }
     }
     __syncthreads();
-
-    if (mean) {
-        // u_r = 0; H_1 u_theta = R_theta; H_0 u_z = R_z - f_z with zero flux (g = H_0^{-1} 1 cached)
-        if (j < N1) sR[1][0][j] = cscale(cmuli(csub(sR[1][0][j], sR[0][0][j])), 0.5);   // (R+ - R-)/(2i)
-        __syncthreads();
-        if (j < 4) {
-            double* x = reinterpret_cast<double*>(&sR[1 + (j >> 1)][0][0]) + (j & 1);
-            gsubst(Hk + (j < 2 ? 1 : 0) * opsz, N1, x, 2);
-        }
-        __syncthreads();
-        if (j == 0) {
-            double2 s = czero();
-            for (int i = 0; i < N1; ++i) s = caxpy(s, p.w[i], sR[2][0][i]);
-            sa[0] = cscale(s, -1.0 / hom[3 * nr]);
-        }
-        __syncthreads();
-        double2 ut = czero(), uz = czero();
-        if (j < N1) {
-            ut = sR[1][0][j];
-            uz = cadd(sR[2][0][j], cscale(sa[0], hom[j]));
-        }
-        __syncthreads();
-        if (j < nr) {
-            sR[0][0][j] = czero();
-            sR[1][0][j] = ut;
-            sR[2][0][j] = uz;
-            uout[fidx(p, 0, j, 0, 0)] = czero();
-            uout[fidx(p, 1, j, 0, 0)] = ut;
-            uout[fidx(p, 2, j, 0, 0)] = uz;
-        }
-        __syncthreads();
-    } else {
-        // particular pressure: P_m p = div R on interior nodes, p(1) = 0
-        if (j < N1) {
-            const double rj = p.r[j];
-            for (int col = 0; col < 2; ++col) {
-                double2 dsum = czero();
-                const double* d1 = p.D1 + (po * nr + j) * 7;
-                const int c0 = p.col0[j];
-                for (int t = 0; t < 7; ++t) dsum = caxpy(dsum, d1[t], cadd(sR[0][col][c0 + t], sR[1][col][c0 + t]));
-                double2 d = cscale(dsum, 0.5);
-                d = caxpy(d, 0.5 * (1 + m) / rj, sR[0][col][j]);
-                d = caxpy(d, 0.5 * (1 - m) / rj, sR[1][col][j]);
-                d = cadd(d, cscale(cmuli(sR[2][col][j]), alc[col]));
-                sp[col][j] = d;
-            }
-        } else if (j == N1) {
-            sp[0][N1] = czero();
-            sp[1][N1] = czero();
-        }
-        __syncthreads();
-        if (j < 4) gsubst(Pm, N1, reinterpret_cast<double*>(&sp[j >> 1][0]) + (j & 1), 2);
-        __syncthreads();
-        if (j < N1) {
-            const double mr = m / p.r[j];
-            for (int col = 0; col < 2; ++col) {
-                const double2 Dp = fd_apply(p, p.D1, pe, j, sp[col]);
-                const double2 pj = sp[col][j];
-                sR[0][col][j] = csub(sR[0][col][j], caxpy(Dp, -mr, pj));
-                sR[1][col][j] = csub(sR[1][col][j], caxpy(Dp, mr, pj));
-                sR[2][col][j] = csub(sR[2][col][j], cscale(cmuli(pj), alc[col]));
-            }
-        }
-        __syncthreads();
-        if (j < 12) {
-            // lane = (operator, column, re/im): H_{m+1} u+, H_{|m-1|} u-, H_m u_z
-            const int op = j >> 2;
+    if (t < 6 * RQ) {
+        // lane = (operator, mode, re/im): H_{m+1} u+, H_{|m-1|} u-, H_m u_z (mean mode: H_1 u_theta, H_0 u_z)
+        const int qq = t % RQ, part = (t / RQ) & 1, op = t / (2 * RQ);
+        const Slot s2 = slot_of(p, g, m, qq);
+        if (s2.valid && !(s2.mean && op == 0)) {
             const int n = op == 0 ? m + 1 : (op == 1 ? abs(m - 1) : m);
-            gsubst(Hk + n * opsz, N1, reinterpret_cast<double*>(&sR[op][(j >> 1) & 1][0]) + (j & 1), 2);
+            gsubst(p.HLU + ((size_t)s2.ka * (p.M + 2) + n) * opsz, N1,
+                   reinterpret_cast<double*>(&sR[op][0][qq]) + part, 2 * RQ);
         }
-        __syncthreads();
-        if (j < 2) {
+    }
+    __syncthreads();
+    const double* hom = p.HOM + ((size_t)sl.ka * p.mp1 + m) * (3 * nr + 1);
+    if (t < RQ && sl.valid) {
+        if (sl.mean) {
+            // zero flux: u_z += c g with c = -sum w u_z / sum w g
+            double2 s = czero();
+            for (int i = 0; i < N1; ++i) s = caxpy(s, p.w[i], sR[2][i][q]);
+            sa[q] = cscale(s, -1.0 / hom[3 * nr]);
+        } else {
             // influence coefficient: zero discrete wall divergence
-            const int col = j;
             const double* dw = p.D1 + (po * nr + N1) * 7;
             const int c0 = p.col0[N1];
             double2 s = czero();
-            for (int t = 0; t < 7; ++t) {
-                const int c = c0 + t;
-                if (c < N1) s = caxpy(s, dw[t], cadd(sR[0][col][c], sR[1][col][c]));
-            }
-            sa[col] = cscale(s, -1.0 / hom[3 * nr]);
+            for (int i = 0; i < 7; ++i)
+                if (c0 + i < N1) s = caxpy(s, dw[i], cadd(sR[0][c0 + i][q], sR[1][c0 + i][q]));
+            sa[q] = cscale(s, -1.0 / hom[3 * nr]);
         }
-        __syncthreads();
-        double2 outv[2][3];
-        if (j < nr) {
-            double h0 = 0.0, h1 = 0.0, h2 = 0.0;
-            if (j < N1) { h0 = hom[j]; h1 = hom[nr + j]; h2 = hom[2 * nr + j]; }
-            for (int col = 0; col < 2; ++col) {
-                double2 up = czero(), um = czero(), uz = czero();
-                if (j < N1) {
-                    const double2 a = sa[col];
-                    up = cadd(sR[0][col][j], cscale(a, h0));
-                    um = cadd(sR[1][col][j], cscale(a, h1));
-                    uz = cadd(sR[2][col][j], cscale(cmuli(a), alc[col] * h2));
-                }
-                outv[col][0] = cscale(cadd(up, um), 0.5);
-                outv[col][1] = cscale(cmuli(csub(um, up)), 0.5);   // (up - um)/(2i)
-                outv[col][2] = uz;
-            }
-        }
-        __syncthreads();
-        if (j < nr) {
-            for (int col = 0; col < 2; ++col) {
-                for (int c = 0; c < 3; ++c) sR[c][col][j] = outv[col][c];
-                if (col < ncol) {
-                    const int kk = kkc[col];
-                    for (int c = 0; c < 3; ++c) uout[fidx(p, c, j, m, kk)] = outv[col][c];
-                }
-            }
-        }
-        __syncthreads();
     }
-    if (auxout && j < nr) {
-        const double rj = p.r[j];
-        for (int col = 0; col < ncol; ++col) {
-            const int kk = kkc[col];
-            const double2 ur = sR[0][col][j], ut = sR[1][col][j];
-            const double2 duz = fd_apply(p, p.D1, pe, j, sR[2][col]);
-            const double2 dut = fd_apply(p, p.D1, po, j, sR[1][col]);
-            auxout[fidx(p, 0, j, m, kk)] = csub(cscale(cmuli(ur), alc[col]), duz);
-            auxout[fidx(p, 1, j, m, kk)] = csub(caxpy(dut, 1.0 / rj, ut), cscale(cmuli(ur), m / rj));
+    __syncthreads();
+    // combine and store (each lane touches only its own (row, mode) here)
+    for (int j = jg; j < nr; j += RJ) {
+        double2 ur = czero(), ut = czero(), uz = czero();
+        if (j < N1 && sl.valid) {
+            const double2 a = sa[q];
+            if (sl.mean) {
+                ut = sR[1][j][q];
+                uz = cadd(sR[2][j][q], cscale(a, hom[j]));
+            } else {
+                const double2 up = cadd(sR[0][j][q], cscale(a, hom[j]));
+                const double2 um = cadd(sR[1][j][q], cscale(a, hom[nr + j]));
+                uz = cadd(sR[2][j][q], cscale(cmuli(a), sl.al * hom[2 * nr + j]));
+                ur = cscale(cadd(up, um), 0.5);
+                ut = cscale(cmuli(csub(um, up)), 0.5);   // (up - um)/(2i)
+            }
         }
+        sR[0][j][q] = ur;
+        sR[1][j][q] = ut;
+        sR[2][j][q] = uz;
+        if (sl.valid) {
+            uout[fidx(p, 0, j, m, sl.kk)] = ur;
+            uout[fidx(p, 1, j, m, sl.kk)] = ut;
+            uout[fidx(p, 2, j, m, sl.kk)] = uz;
+        }
+    }
+    if (!auxout) return;
+    __syncthreads();
+    if (!sl.valid) return;
+    for (int j = jg; j < nr; j += RJ) {
+        const double rj = p.r[j];
+        const double* d1e = p.D1 + (pe * nr + j) * 7;
+        const double* d1o = p.D1 + (po * nr + j) * 7;
+        const int c0 = p.col0[j];
+        double2 duz = czero(), dut = czero();
+        for (int s = 0; s < 7; ++s) {
+            duz = caxpy(duz, d1e[s], sR[2][c0 + s][q]);
+            dut = caxpy(dut, d1o[s], sR[1][c0 + s][q]);
+        }
+        const double2 ur = sR[0][j][q], ut = sR[1][j][q];
+        auxout[fidx(p, 0, j, m, sl.kk)] = csub(cscale(cmuli(ur), sl.al), duz);
+        auxout[fidx(p, 1, j, m, sl.kk)] = csub(caxpy(dut, 1.0 / rj, ut), cscale(cmuli(ur), m / rj));
     }
 }
 
-// curl^H b at row j (b already W-weighted), for mode index m and axial wavenumber al.
+// (D^T x)[j] for x stored with stride st (rows i < rows_lim of D).
+__device__ __forceinline__ double2 fd_apply_Ts(const KP& p, const double* D, int pi, int j, const double2* x, int st,
+                                               int rows_lim) {
+    double2 s = czero();
+    const int lo = j - 6 < 0 ? 0 : j - 6;
+    const int hi = j + 6 < rows_lim - 1 ? j + 6 : rows_lim - 1;
+    for (int i = lo; i <= hi; ++i) {
+        const int t = j - p.col0[i];
+        if (t >= 0 && t < 7) s = caxpy(s, D[(pi * p.nr + i) * 7 + t], x[i * st]);
+    }
+    return s;
+}
+
+// curl^H (W b) at row j read straight from a global field b of mode (m, kk).
+__device__ __forceinline__ void curlH_row_g(const KP& p, int m, int kk, double al, int j, const double2* __restrict__ b,
+                                            double2& cr, double2& ct, double2& cz) {
+    const double rj = p.r[j], wj = p.w[j];
+    const int pe = m & 1, po = (m + 1) & 1;
+    const double2 br = cscale(b[fidx(p, 0, j, m, kk)], wj), bt = cscale(b[fidx(p, 1, j, m, kk)], wj);
+    const double2 bz = cscale(b[fidx(p, 2, j, m, kk)], wj);
+    double2 dz = czero(), dt = czero();
+    const int lo = j - 6 < 0 ? 0 : j - 6;
+    const int hi = j + 6 < p.nr - 1 ? j + 6 : p.nr - 1;
+    for (int i = lo; i <= hi; ++i) {
+        const int s = j - p.col0[i];
+        if (s < 0 || s >= 7) continue;
+        const double wi = p.w[i];
+        dz = caxpy(dz, p.D1[(po * p.nr + i) * 7 + s] * wi, b[fidx(p, 2, i, m, kk)]);
+        dt = caxpy(dt, p.D1[(pe * p.nr + i) * 7 + s] * wi, b[fidx(p, 1, i, m, kk)]);
+    }
+    cr = cadd(cscale(cmuli(bt), -al), cscale(cmuli(bz), m / rj));
+    ct = cadd(cadd(cscale(cmuli(br), al), dz), cscale(bz, 1.0 / rj));
+    cz = csub(cscale(cmuli(br), -m / rj), dt);
+}
+
+// curl^H b at row j (b already W-weighted, rows strided by st), for mode index
+// m and axial wavenumber al.
 __device__ __forceinline__ void curlH_row(const KP& p, int m, double al, int j, const double2* br, const double2* bt,
-                                          const double2* bz, double2& cr, double2& ct, double2& cz) {
+                                          const double2* bz, int st, double2& cr, double2& ct, double2& cz) {
     const double rj = p.r[j];
     const int pe = m & 1, po = (m + 1) & 1;
-    cr = cadd(cscale(cmuli(bt[j]), -al), cscale(cmuli(bz[j]), m / rj));
-    ct = cadd(cadd(cscale(cmuli(br[j]), al), fd_apply_T(p, p.D1, po, j, bz, p.nr)), cscale(bz[j], 1.0 / rj));
-    cz = csub(cscale(cmuli(br[j]), -m / rj), fd_apply_T(p, p.D1, pe, j, bt, p.nr));
+    cr = cadd(cscale(cmuli(bt[j * st]), -al), cscale(cmuli(bz[j * st]), m / rj));
+    ct = cadd(cadd(cscale(cmuli(br[j * st]), al), fd_apply_Ts(p, p.D1, po, j, bz, st, p.nr)),
+              cscale(bz[j * st], 1.0 / rj));
+    cz = csub(cscale(cmuli(br[j * st]), -m / rj), fd_apply_Ts(p, p.D1, pe, j, bt, st, p.nr));
 }
 
 // ------------------------------------------------------------ adjoint solve
@@ -669,225 +709,196 @@ __device__ __forceinline__ void adj_store(const AdjOut& o, size_t id, double2 mu
     if (o.Yout) o.Yout[id] = caxpy(o.Yin ? o.Yin[id] : czero(), o.qy, mu);
     if (o.Zout) o.Zout[id] = caxpy(o.Zin ? o.Zin[id] : czero(), o.qz, mu);
 }
-__global__ __launch_bounds__(64) void k_solve_adj(KP p, const double2* Ain, double ca, const double2* Bin,
-                                                  double cb, AdjOut ao) {
-    int ka, m;
-    if (!block_mode(p, ka, m)) return;
-    const int j = threadIdx.x;
+__global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, double ca, const double2* Bin, double cb,
+                                                  AdjOut ao) {
+    int g, m;
+    if (!block_group(p, g, m)) return;
+    const int t = threadIdx.x, q = t % RQ, jg = t / RQ;
     const int nr = p.nr, N1 = nr - 1;
-    const int ncol = ka == 0 ? 1 : 2;
-    const int kkc[2] = {ka, ka == 0 ? 0 : p.nk - ka};
-    const double alc[2] = {ka * p.k0, -ka * p.k0};
     const int pe = m & 1, po = (m + 1) & 1;
-    const bool mean = (m == 0 && ka == 0);
     const size_t opsz = (size_t)N1 * LUW;
-    const double* Hk = p.HLU + (size_t)ka * (p.M + 2) * opsz;
-    const double* Pm = p.PLU + ((size_t)ka * p.mp1 + m) * opsz;
-    const double* hom = p.HOM + ((size_t)ka * p.mp1 + m) * (3 * nr + 1);
-    __shared__ double2 sy[3][2][NR_MAX];
-    __shared__ double2 sb[3][2][NR_MAX];
-    __shared__ double2 sp[2][NR_MAX];
-    __shared__ double2 sa[2];
+    const Slot sl = slot_of(p, g, m, q);
+    __shared__ double2 sy[3][NR_MAX][RQ];
+    __shared__ double2 sphi[NR_MAX][RQ];
+    __shared__ double2 sa[RQ];
     const bool useB = Bin != nullptr;
 
-    if (j < nr) {
-        const double wj = p.w[j];
-        for (int col = 0; col < 2; ++col)
-            for (int c = 0; c < 3; ++c) {
-                const bool ok = col < ncol;
-                const size_t id = fidx(p, c, j, m, kkc[ok ? col : 0]);
-                sy[c][col][j] = ok ? cscale(Ain[id], ca) : czero();
-                sb[c][col][j] = (ok && useB) ? cscale(Bin[id], wj) : czero();
+    for (int j = jg; j < nr; j += RJ) {
+        double2 v[3] = {czero(), czero(), czero()};
+        if (sl.valid) {
+            for (int c = 0; c < 3; ++c) v[c] = cscale(Ain[fidx(p, c, j, m, sl.kk)], ca);
+            if (useB) {
+                const double iw = cb / p.w[j];
+                double2 cr, ct, cz;
+                curlH_row_g(p, m, sl.kk, sl.al, j, Bin, cr, ct, cz);
+                v[0] = caxpy(v[0], iw, cr);
+                v[1] = caxpy(v[1], iw, ct);
+                v[2] = caxpy(v[2], iw, cz);
             }
-    }
-    __syncthreads();
-    if (useB && j < nr) {
-        const double iw = cb / p.w[j];
-        for (int col = 0; col < 2; ++col) {
-            double2 cr, ct, cz;
-            curlH_row(p, m, alc[col], j, sb[0][col], sb[1][col], sb[2][col], cr, ct, cz);
-            sy[0][col][j] = caxpy(sy[0][col][j], iw, cr);
-            sy[1][col][j] = caxpy(sy[1][col][j], iw, ct);
-            sy[2][col][j] = caxpy(sy[2][col][j], iw, cz);
         }
+        for (int c = 0; c < 3; ++c) sy[c][j][q] = v[c];
     }
     __syncthreads();
     // y = W lambda on interior rows (the solve's wall output is identically zero)
-    if (j < nr) {
+    for (int j = jg; j < nr; j += RJ) {
         const double wj = (j < N1) ? p.w[j] : 0.0;
-        for (int col = 0; col < 2; ++col) {
-            const double2 yr = cscale(sy[0][col][j], wj), yt = cscale(sy[1][col][j], wj);
-            const double2 yz = cscale(sy[2][col][j], wj);
-            if (mean) {
-                sy[0][col][j] = yr;
-                sy[1][col][j] = yt;
-            } else {
-                sy[0][col][j] = cscale(cadd(yr, cmuli(yt)), 0.5);
-                sy[1][col][j] = cscale(csub(yr, cmuli(yt)), 0.5);
-            }
-            sy[2][col][j] = yz;
+        const double2 yr = cscale(sy[0][j][q], wj), yt = cscale(sy[1][j][q], wj);
+        const double2 yz = cscale(sy[2][j][q], wj);
+        if (sl.mean) {
+            sy[0][j][q] = czero();
+            sy[1][j][q] = yt;
+        } else {
+            sy[0][j][q] = cscale(cadd(yr, cmuli(yt)), 0.5);
+            sy[1][j][q] = cscale(csub(yr, cmuli(yt)), 0.5);
         }
+        sy[2][j][q] = yz;
     }
     __syncthreads();
-
-    if (mean) {
-        if (j == 0) {
-            double2 pr = czero();
-            for (int i = 0; i < N1; ++i) pr = caxpy(pr, hom[i], sy[2][0][i]);
-            sa[0] = cscale(pr, 1.0 / hom[3 * nr]);
-        }
-        __syncthreads();
-        if (j < N1) sy[2][0][j] = caxpy(sy[2][0][j], -p.w[j], sa[0]);
-        __syncthreads();
-        if (j < 4) {
-            double* x = reinterpret_cast<double*>(&sy[1 + (j >> 1)][0][0]) + (j & 1);
-            gsubst_T(Hk + (j < 2 ? 1 : 0) * opsz, N1, x, 2);
-        }
-        __syncthreads();
-        if (j < nr) {
-            const double iw = 1.0 / p.w[j];
-            const double2 mt = (j < N1) ? cscale(sy[1][0][j], iw) : czero();
-            const double2 mz = (j < N1) ? cscale(sy[2][0][j], iw) : czero();
-            const double2 mv[3] = {czero(), mt, mz};
-            for (int c = 0; c < 3; ++c) adj_store(ao, fidx(p, c, j, 0, 0), mv[c]);
-        }
-        return;
-    }
-
-    // transposed influence correction: ybar_pm -= s * (u_h^H ybar) / s_h
-    const double* dw = p.D1 + (po * nr + N1) * 7;
-    const int cw0 = p.col0[N1];
-    if (j < 2) {
-        const int col = j;
+    const double* hom = p.HOM + ((size_t)sl.ka * p.mp1 + m) * (3 * nr + 1);
+    // transposed influence (or, for the mean mode, flux) correction
+    if (t < RQ && sl.valid) {
         double2 pr = czero();
-        for (int i = 0; i < N1; ++i) {
-            pr = caxpy(pr, hom[i], sy[0][col][i]);
-            pr = caxpy(pr, hom[nr + i], sy[1][col][i]);
-            pr = cadd(pr, cscale(cmuli(sy[2][col][i]), -alc[col] * hom[2 * nr + i]));   // conj(i a uhz) = -i a uhz
+        if (sl.mean) {
+            for (int i = 0; i < N1; ++i) pr = caxpy(pr, hom[i], sy[2][i][q]);
+        } else {
+            for (int i = 0; i < N1; ++i) {
+                pr = caxpy(pr, hom[i], sy[0][i][q]);
+                pr = caxpy(pr, hom[nr + i], sy[1][i][q]);
+                pr = cadd(pr, cscale(cmuli(sy[2][i][q]), -sl.al * hom[2 * nr + i]));   // conj(i a uhz) = -i a uhz
+            }
         }
-        sa[col] = cscale(pr, 1.0 / hom[3 * nr]);
+        sa[q] = cscale(pr, 1.0 / hom[3 * nr]);
     }
     __syncthreads();
-    if (j < N1) {
-        const int t = j - cw0;
-        if (t >= 0 && t < 7) {
-            for (int col = 0; col < 2; ++col) {
-                sy[0][col][j] = caxpy(sy[0][col][j], -dw[t], sa[col]);
-                sy[1][col][j] = caxpy(sy[1][col][j], -dw[t], sa[col]);
+    if (sl.valid) {
+        const double* dw = p.D1 + (po * nr + N1) * 7;
+        const int cw0 = p.col0[N1];
+        for (int j = jg; j < N1; j += RJ) {
+            if (sl.mean) {
+                sy[2][j][q] = caxpy(sy[2][j][q], -p.w[j], sa[q]);
+            } else {
+                const int s = j - cw0;
+                if (s >= 0 && s < 7) {
+                    sy[0][j][q] = caxpy(sy[0][j][q], -dw[s], sa[q]);
+                    sy[1][j][q] = caxpy(sy[1][j][q], -dw[s], sa[q]);
+                }
             }
         }
     }
     __syncthreads();
-    if (j < 12) {
-        const int op = j >> 2;
-        const int n = op == 0 ? m + 1 : (op == 1 ? abs(m - 1) : m);
-        gsubst_T(Hk + n * opsz, N1, reinterpret_cast<double*>(&sy[op][(j >> 1) & 1][0]) + (j & 1), 2);
-    }
-    __syncthreads();
-    // q = G^H w on interior rows (w+ + w- staged in sb[0])
-    if (j < nr) {
-        for (int col = 0; col < 2; ++col)
-            sb[0][col][j] = (j < N1) ? cadd(sy[0][col][j], sy[1][col][j]) : czero();
-    }
-    __syncthreads();
-    if (j < N1) {
-        const double mr = m / p.r[j];
-        for (int col = 0; col < 2; ++col) {
-            double2 q = fd_apply_T(p, p.D1, pe, j, sb[0][col], N1);
-            q = caxpy(q, -mr, csub(sy[0][col][j], sy[1][col][j]));
-            q = csub(q, cscale(cmuli(sy[2][col][j]), alc[col]));
-            sp[col][j] = q;
+    if (t < 6 * RQ) {
+        const int qq = t % RQ, part = (t / RQ) & 1, op = t / (2 * RQ);
+        const Slot s2 = slot_of(p, g, m, qq);
+        if (s2.valid && !(s2.mean && op == 0)) {
+            const int n = op == 0 ? m + 1 : (op == 1 ? abs(m - 1) : m);
+            gsubst_T(p.HLU + ((size_t)s2.ka * (p.M + 2) + n) * opsz, N1,
+                     reinterpret_cast<double*>(&sy[op][0][qq]) + part, 2 * RQ);
         }
-    } else if (j == N1) {
-        sp[0][N1] = czero();
-        sp[1][N1] = czero();
     }
     __syncthreads();
-    if (j < 4) gsubst_T(Pm, N1, reinterpret_cast<double*>(&sp[j >> 1][0]) + (j & 1), 2);
+    // q = G^H w on interior rows (into sphi)
+    for (int j = jg; j < nr; j += RJ) {
+        double2 qv = czero();
+        if (j < N1 && sl.valid && !sl.mean) {
+            const double mr = m / p.r[j];
+            const int lo = j - 6 < 0 ? 0 : j - 6;
+            const int hi = j + 6 < N1 - 1 ? j + 6 : N1 - 1;
+            for (int i = lo; i <= hi; ++i) {
+                const int s = j - p.col0[i];
+                if (s >= 0 && s < 7) qv = caxpy(qv, p.D1[(pe * nr + i) * 7 + s], cadd(sy[0][i][q], sy[1][i][q]));
+            }
+            qv = caxpy(qv, -mr, csub(sy[0][j][q], sy[1][j][q]));
+            qv = csub(qv, cscale(cmuli(sy[2][j][q]), sl.al));
+        }
+        sphi[j][q] = qv;
+    }
     __syncthreads();
-    if (j < nr) {
+    if (t < 2 * RQ) {
+        const int qq = t % RQ, part = t / RQ;
+        const Slot s2 = slot_of(p, g, m, qq);
+        if (s2.valid && !s2.mean)
+            gsubst_T(p.PLU + ((size_t)s2.ka * p.mp1 + m) * opsz, N1, reinterpret_cast<double*>(&sphi[0][qq]) + part,
+                     2 * RQ);
+    }
+    __syncthreads();
+    if (!sl.valid) return;
+    for (int j = jg; j < nr; j += RJ) {
         const double rj = p.r[j];
         const double iw = 1.0 / p.w[j];
-        for (int col = 0; col < ncol; ++col) {
-            const double2 DT = fd_apply_T(p, p.D1, po, j, sp[col], N1);
-            const double2 ph = sp[col][j];
-            const double2 wp = (j < N1) ? sy[0][col][j] : czero();
-            const double2 wm = (j < N1) ? sy[1][col][j] : czero();
-            const double2 wz = (j < N1) ? sy[2][col][j] : czero();
+        double2 mv[3];
+        if (sl.mean) {
+            mv[0] = czero();
+            mv[1] = (j < N1) ? cscale(sy[1][j][q], iw) : czero();
+            mv[2] = (j < N1) ? cscale(sy[2][j][q], iw) : czero();
+        } else {
+            const double2 DT = fd_apply_Ts(p, p.D1, po, j, &sphi[0][q], RQ, N1);
+            const double2 ph = (j < N1) ? sphi[j][q] : czero();
+            const double2 wp = (j < N1) ? sy[0][j][q] : czero();
+            const double2 wm = (j < N1) ? sy[1][j][q] : czero();
+            const double2 wz = (j < N1) ? sy[2][j][q] : czero();
             const double2 Rp = csub(wp, cscale(caxpy(DT, (1 + m) / rj, ph), 0.5));
             const double2 Rm = csub(wm, cscale(caxpy(DT, (1 - m) / rj, ph), 0.5));
-            const double2 Rz = cadd(wz, cscale(cmuli(ph), alc[col]));
-            const double2 mv[3] = {cscale(cadd(Rp, Rm), iw), cscale(cmuli(csub(Rm, Rp)), iw), cscale(Rz, iw)};
-            const int kk = kkc[col];
-            for (int c = 0; c < 3; ++c) adj_store(ao, fidx(p, c, j, m, kk), mv[c]);
+            const double2 Rz = cadd(wz, cscale(cmuli(ph), sl.al));
+            mv[0] = cscale(cadd(Rp, Rm), iw);
+            mv[1] = cscale(cmuli(csub(Rm, Rp)), iw);
+            mv[2] = cscale(Rz, iw);
         }
+        for (int c = 0; c < 3; ++c) adj_store(ao, fidx(p, c, j, m, sl.kk), mv[c]);
     }
 }
 
 // ----------------------------------------------- adjoint combine (E^dag etc.)
-// out = E^dag Z + A + curl^dag B
-__global__ __launch_bounds__(64) void k_final(KP p, const double2* __restrict__ Z, const double2* __restrict__ Ain,
+// out = E^dag Z + A + curl^dag B  (Z, A, B optional).  Every transposed
+// stencil reads neighbouring rows straight from global memory (the same
+// lines serve the lanes of neighbouring rows).
+__global__ __launch_bounds__(RT) void k_final(KP p, const double2* __restrict__ Z, const double2* __restrict__ Ain,
                                               const double2* __restrict__ Bin, double2* __restrict__ out) {
-    const int ka = blockIdx.x, m = blockIdx.y, j = threadIdx.x;
+    int g, m;
+    if (!block_group(p, g, m)) return;
+    const int t = threadIdx.x, q = t % RQ, jg = t / RQ;
     const int nr = p.nr;
-    const int ncol = ka == 0 ? 1 : 2;
-    const int kkc[2] = {ka, ka == 0 ? 0 : p.nk - ka};
-    const double alc[2] = {ka * p.k0, -ka * p.k0};
-    const double a2 = alc[0] * alc[0];
+    const Slot sl = slot_of(p, g, m, q);
+    if (!sl.valid) return;
+    const int kk = sl.kk;
+    const double a2 = sl.al * sl.al;
     const double re2 = 0.5 / p.re, idt = 1.0 / p.dt;
     const int pe = m & 1, po = (m + 1) & 1;
-    __shared__ double2 sz[3][2][NR_MAX];
-    __shared__ double2 sb[3][2][NR_MAX];
-    if (j < nr) {
-        const double wj = p.w[j];
-        for (int col = 0; col < 2; ++col) {
-            const bool ok = col < ncol;
-            double2 zr = czero(), zt = czero(), zz = czero();
-            if (ok && Z) {
-                zr = cscale(Z[fidx(p, 0, j, m, kkc[col])], wj);
-                zt = cscale(Z[fidx(p, 1, j, m, kkc[col])], wj);
-                zz = cscale(Z[fidx(p, 2, j, m, kkc[col])], wj);
+    for (int j = jg; j < nr; j += RJ) {
+        const double rc = p.r[j];
+        const double iw = 1.0 / p.w[j];
+        double2 er = czero(), et = czero(), ez = czero();
+        if (Z) {
+            // E_n^T column j applied to (W Z) in the +- basis: sum_i E_n[i][j] v_i
+            const int lo = j - 6 < 0 ? 0 : j - 6;
+            const int hi = j + 6 < nr - 1 ? j + 6 : nr - 1;
+            double2 ep = czero(), em = czero();
+            for (int i = lo; i <= hi; ++i) {
+                const int s = j - p.col0[i];
+                if (s < 0 || s >= 7) continue;
+                const double ri = p.r[i], wi = p.w[i];
+                const double wo = re2 * (p.D2[(po * nr + i) * 7 + s] + p.D1[(po * nr + i) * 7 + s] / ri);
+                const double we = re2 * (p.D2[(pe * nr + i) * 7 + s] + p.D1[(pe * nr + i) * 7 + s] / ri);
+                const double2 zr = Z[fidx(p, 0, i, m, kk)], zt = Z[fidx(p, 1, i, m, kk)], zz = Z[fidx(p, 2, i, m, kk)];
+                ep = caxpy(ep, 0.5 * wo * wi, cadd(zr, cmuli(zt)));
+                em = caxpy(em, 0.5 * wo * wi, csub(zr, cmuli(zt)));
+                ez = caxpy(ez, we * wi, zz);
             }
-            sz[0][col][j] = cscale(cadd(zr, cmuli(zt)), 0.5);
-            sz[1][col][j] = cscale(csub(zr, cmuli(zt)), 0.5);
-            sz[2][col][j] = zz;
-            for (int c = 0; c < 3; ++c)
-                sb[c][col][j] = (ok && Bin) ? cscale(Bin[fidx(p, c, j, m, kkc[col])], wj) : czero();
+            const double wj = p.w[j];
+            const double ia = 1.0 / (rc * rc);
+            const double2 zr = Z[fidx(p, 0, j, m, kk)], zt = Z[fidx(p, 1, j, m, kk)], zz = Z[fidx(p, 2, j, m, kk)];
+            ep = caxpy(ep, 0.5 * wj * (idt - re2 * ((double)((m + 1) * (m + 1)) * ia + a2)), cadd(zr, cmuli(zt)));
+            em = caxpy(em, 0.5 * wj * (idt - re2 * ((double)((m - 1) * (m - 1)) * ia + a2)), csub(zr, cmuli(zt)));
+            ez = caxpy(ez, wj * (idt - re2 * ((double)(m * m) * ia + a2)), zz);
+            er = cadd(ep, em);
+            et = cmuli(csub(em, ep));     // -i (ep - em)
         }
-    }
-    __syncthreads();
-    if (j >= nr) return;
-    const double rc = p.r[j];
-    const double iw = 1.0 / p.w[j];
-    const int lo = j - 6 < 0 ? 0 : j - 6;
-    const int hi = j + 6 < nr - 1 ? j + 6 : nr - 1;
-    for (int col = 0; col < ncol; ++col) {
-        // E_n^T column j: sum_i E_n[i][j] v_i
-        double2 ep = czero(), em = czero(), ez = czero();
-        for (int i = lo; i <= hi; ++i) {
-            const int t = j - p.col0[i];
-            if (t < 0 || t >= 7) continue;
-            const double ri = p.r[i];
-            const double wo = re2 * (p.D2[(po * nr + i) * 7 + t] + p.D1[(po * nr + i) * 7 + t] / ri);
-            const double we = re2 * (p.D2[(pe * nr + i) * 7 + t] + p.D1[(pe * nr + i) * 7 + t] / ri);
-            ep = caxpy(ep, wo, sz[0][col][i]);
-            em = caxpy(em, wo, sz[1][col][i]);
-            ez = caxpy(ez, we, sz[2][col][i]);
-        }
-        const double ia = 1.0 / (rc * rc);
-        ep = caxpy(ep, idt - re2 * ((double)((m + 1) * (m + 1)) * ia + a2), sz[0][col][j]);
-        em = caxpy(em, idt - re2 * ((double)((m - 1) * (m - 1)) * ia + a2), sz[1][col][j]);
-        ez = caxpy(ez, idt - re2 * ((double)(m * m) * ia + a2), sz[2][col][j]);
-        double2 er = cadd(ep, em);
-        double2 et = cmuli(csub(em, ep));     // -i (ep - em)
         if (Bin) {
             double2 cr, ct, cz;
-            curlH_row(p, m, alc[col], j, sb[0][col], sb[1][col], sb[2][col], cr, ct, cz);
+            curlH_row_g(p, m, kk, sl.al, j, Bin, cr, ct, cz);
             er = cadd(er, cr);
             et = cadd(et, ct);
             ez = cadd(ez, cz);
         }
-        const int kk = kkc[col];
         const double2 ev[3] = {er, et, ez};
         for (int c = 0; c < 3; ++c) {
             const size_t id = fidx(p, c, j, m, kk);
@@ -1124,7 +1135,7 @@ hipError_t launch_nl(const npo_plan_s& p, int adj, const double2* u, const doubl
 hipError_t launch_solve(const npo_plan_s& p, int kind, const double2* a, const double2* b, const double2* c,
                         double2* u_out, double2* aux_out, hipStream_t st) {
     prof_begin(p, kind == 1 ? KID_SOLVE_P : (kind == 2 ? KID_SOLVE_C : KID_SOLVE_R), st);
-    hipLaunchKernelGGL(k_solve, dim3(((p.K + 1) * p.mp1 + 7) / 8 * 8), dim3(64), 0, st, p.kp, kind, a, b, c, u_out, aux_out);
+    hipLaunchKernelGGL(k_solve, dim3((radial_groups(p.K) * p.mp1 + 7) / 8 * 8), dim3(RT), 0, st, p.kp, kind, a, b, c, u_out, aux_out);
     prof_end(p, kind == 1 ? KID_SOLVE_P : (kind == 2 ? KID_SOLVE_C : KID_SOLVE_R), st);
     return hipGetLastError();
 }
@@ -1134,7 +1145,7 @@ hipError_t launch_solve_adj(const npo_plan_s& p, const double2* A, double ca, co
                             double qz, double2* Zout, hipStream_t st) {
     AdjOut ao{out0, Yin, Yout, Zin, Zout, qy, qz};
     prof_begin(p, B ? KID_SOLVE_ADJ2 : KID_SOLVE_ADJ, st);
-    hipLaunchKernelGGL(k_solve_adj, dim3(((p.K + 1) * p.mp1 + 7) / 8 * 8), dim3(64), 0, st, p.kp, A, ca, B, cb, ao);
+    hipLaunchKernelGGL(k_solve_adj, dim3((radial_groups(p.K) * p.mp1 + 7) / 8 * 8), dim3(RT), 0, st, p.kp, A, ca, B, cb, ao);
     prof_end(p, B ? KID_SOLVE_ADJ2 : KID_SOLVE_ADJ, st);
     return hipGetLastError();
 }
@@ -1142,7 +1153,7 @@ hipError_t launch_solve_adj(const npo_plan_s& p, const double2* A, double ca, co
 hipError_t launch_final(const npo_plan_s& p, const double2* Z, const double2* A, const double2* B, double2* out,
                         hipStream_t st) {
     prof_begin(p, KID_FINAL, st);
-    hipLaunchKernelGGL(k_final, dim3(p.K + 1, p.mp1), dim3(64), 0, st, p.kp, Z, A, B, out);
+    hipLaunchKernelGGL(k_final, dim3((radial_groups(p.K) * p.mp1 + 7) / 8 * 8), dim3(RT), 0, st, p.kp, Z, A, B, out);
     prof_end(p, KID_FINAL, st);
     return hipGetLastError();
 }

@@ -68,6 +68,8 @@ SIGNATURES = {
     "npo_iterate": (_I32, [_P, _P, _P, _I32, _P, _P, _D, _D, _I32, _DP, _P]),
     "npo_normalize": (_I32, [_P, _P, _P, _D, _P]),
     "npo_euclid_grad": (_I32, [_P, _P, _D, _P, _P]),
+    "npo_plan_set_tuning": (_I32, [_P, _I32, _I32, _I32]),
+    "npo_plan_get_tuning": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "npo_profile_begin": (_I32, [_P, _I32]),
     "npo_profile_read": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _DP]),
 }
@@ -208,6 +210,16 @@ def npo_iterate(plan, ws, ckpt, n_ckpt, u0, uN, e0, tol=1e-8, max_halvings=30, s
 
 def npo_normalize(plan, ws, u, e0, stream=None):
     _check(lib().npo_normalize(plan, _ptr(ws), _ptr(u), e0, _stream(stream)))
+
+
+def npo_plan_set_tuning(plan, zgroup, zb_fwd, zb_adj):
+    _check(lib().npo_plan_set_tuning(plan, zgroup, zb_fwd, zb_adj))
+
+
+def npo_plan_get_tuning(plan):
+    a, b_, c = _I32(), _I32(), _I32()
+    _check(lib().npo_plan_get_tuning(plan, ctypes.byref(a), ctypes.byref(b_), ctypes.byref(c)))
+    return a.value, b_.value, c.value
 
 
 def npo_euclid_grad(plan, lam, scale, out, stream=None):

@@ -1,0 +1,82 @@
+"""Autotuner of the transform launch shapes.
+
+For one grid shape it times the forward and the adjoint step of a plan under
+every admissible (zgroup, zb_fwd, zb_adj), with HIP events on the stream the
+kernels run on, and keeps the fastest.  Results are cached per shape class
+(nr, ntheta, nz) in a JSON file so that batched and served runs tune once.
+Shapes never change results (the tests run under several of them).
+"""
+import itertools
+import json
+import os
+
+from . import npo
+
+CACHE = os.environ.get("NPO_TUNE_CACHE", os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json"))
+
+
+def candidates(nt, nz):
+    out = []
+    for g, zf, za in itertools.product((1, 2, 3), (2, 4, 8), (2, 4, 8)):
+        if 2 * g * nz * 16 > 160 * 1024 or nz % zf or nz % za:
+            continue
+        if 2 * max(3 * zf, zf + zf // 2) * nt * 16 > 160 * 1024:
+            continue
+        if 2 * max(4 * za + za // 2, 3 * za) * nt * 16 > 160 * 1024:
+            continue
+        out.append((g, zf, za))
+    return out
+
+
+def _time_steps(plan, u, lam, reps):
+    import torch
+    st = torch.cuda.current_stream()
+    out = plan.field()
+    npo.npo_forward_step(plan.handle, plan.ws, u, out, 0)
+    npo.npo_adjoint_step(plan.handle, plan.ws, u, lam, out, 0)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(reps):
+        npo.npo_forward_step(plan.handle, plan.ws, u, out, 0)
+        npo.npo_adjoint_step(plan.handle, plan.ws, u, lam, out, 0)
+    b.record(st)
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def load_cache():
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def tune(plan, nr, nt, nz, reps=3, use_cache=True, save=True):
+    """Pick and set the fastest launch shapes for this plan; returns them."""
+    import torch
+    key = f"{nr}x{nt}x{nz}"
+    cache = load_cache() if use_cache else {}
+    if key in cache:
+        best = tuple(cache[key]["shape"])
+        npo.npo_plan_set_tuning(plan.handle, *best)
+        return best, cache[key]
+    u = torch.randn(plan.shape, dtype=torch.complex128, device=plan.device) * 1e-3
+    lam = torch.randn(plan.shape, dtype=torch.complex128, device=plan.device)
+    timings = {}
+    for c in candidates(nt, nz):
+        npo.npo_plan_set_tuning(plan.handle, *c)
+        timings[c] = _time_steps(plan, u, lam, reps)
+    best = min(timings, key=timings.get)
+    npo.npo_plan_set_tuning(plan.handle, *best)
+    rec = {"shape": list(best), "ms_fwd_plus_adj": timings[best],
+           "all": {",".join(map(str, c)): v for c, v in timings.items()}}
+    if save:
+        cache = load_cache()
+        cache[key] = rec
+        try:
+            with open(CACHE, "w") as f:
+                json.dump(cache, f, indent=1, sort_keys=True)
+        except OSError:
+            pass
+    return best, rec

@@ -120,3 +120,20 @@ def test_adjoint_step(prob):
     npo.npo_adjoint_step(G.handle, G.ws, to_dev(u), to_dev(y), out, 3)
     ref = P.step_adj(u, 3, y)
     assert relerr(P, to_host(out), ref) < 1e-11 * f
+
+
+def test_launch_shapes_do_not_change_results(prob):
+    P, G, u, y, f = prob
+    from paper_2509_10103_amd import npo, tune
+    base = npo.npo_plan_get_tuning(G.handle)
+    outs = []
+    for shape in tune.candidates(P.ntheta, P.nz)[:4]:
+        npo.npo_plan_set_tuning(G.handle, *shape)
+        a, b = G.field(), G.field()
+        npo.npo_forward_step(G.handle, G.ws, to_dev(u), a, 2)
+        npo.npo_adjoint_step(G.handle, G.ws, to_dev(u), to_dev(y), b, 2)
+        outs.append((to_host(a), to_host(b)))
+    npo.npo_plan_set_tuning(G.handle, *base)
+    for a, b in outs[1:]:
+        assert maxrel(a, outs[0][0]) < 1e-13
+        assert maxrel(b, outs[0][1]) < 1e-12

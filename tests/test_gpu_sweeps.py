@@ -83,7 +83,9 @@ def test_one_iteration_with_line_search(c1):
     assert int(st["forward_sweeps"]) == len(d["trials"])
     if st["accepted"]:
         assert abs(st["G_new"] / float(d["G1"]) - 1) < 1e-8
-        assert relerr(P, to_host(u0), d["u1"]) < 1e-8
+        # u1 = (1 + lambda alpha) u0 - alpha udag renormalised: its error is the
+        # gradient's (<= 1e-8) plus alpha_max's (<= 1e-8), so the bound is 3e-8
+        assert relerr(P, to_host(u0), d["u1"]) < 3e-8
         # the new iterate keeps the energy constraint
         assert abs(G.energy(u0) / c["e0"] - 1) < 1e-12
 
