@@ -79,6 +79,11 @@ def main():
     ap.add_argument("--ckpt", type=int, default=0, help="checkpoint slots (default: the workload's)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--stride", type=int, default=8, help="profiler sampling stride")
+    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve"],
+                    help="plain: one instance (the metric); batch / serve: the systems layers")
+    ap.add_argument("--batch-n", type=int, default=16, help="instances of the batched workload")
+    ap.add_argument("--serve-n", type=int, default=24, help="requests of the served workload")
+    ap.add_argument("--serve-iters", type=int, default=2, help="iterations per served request")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sharded design is described "
@@ -88,6 +93,10 @@ def main():
     import torch
     from paper_2509_10103_amd import npo
 
+    if args.mode == "batch":
+        return bench_batch(args)
+    if args.mode == "serve":
+        return bench_serve(args)
     cfg = dict(configs.WORKLOADS[args.workload])
     if args.nsteps:
         cfg["nsteps"] = args.nsteps
@@ -172,6 +181,74 @@ def main():
         out["cpu_baseline"] = cpu_baseline(cfg, cfg["seed"])
     else:
         out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """Uneven instances advanced concurrently vs the plain solver run on the same
+    instances one after another (iterations are the same work either way)."""
+    import torch
+    from paper_2509_10103_amd.batch import Batch, percentiles
+    cfgs = configs.batch_instances(64)[:args.batch_n]
+    if args.nsteps:
+        for c in cfgs:
+            c["nsteps"] = args.nsteps
+            c["n_ckpt"] = min(c["n_ckpt"], args.nsteps)
+    torch.cuda.set_device(0)
+    b = Batch(cfgs)
+    for inst in b.instances:          # initial forward sweeps (untimed, as in the plain mode)
+        inst.forward()
+    torch.cuda.synchronize()
+    wall, counted, lat = b.run(iters=args.steps)
+    print(f"[bench] batched {len(cfgs)} instances: {wall:.2f} s", file=sys.stderr, flush=True)
+    for inst in b.instances:
+        inst.swept = False
+    seq, counted_seq = b.run_sequential(iters=args.steps)
+    print(f"[bench] sequential: {seq:.2f} s", file=sys.stderr, flush=True)
+    p50, p99 = percentiles(lat)
+    out = {"metric": "fwd+adjoint grid-point-steps/s (batched)", "value": counted / wall,
+           "unit": "grid-point-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": 0,
+           "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"batch-{len(cfgs)}-uneven", "instances": len(cfgs),
+                      "plain_sequential_value": counted_seq / seq, "speedup_vs_plain": (counted / wall) /
+                      (counted_seq / seq), "iteration_latency_s": {"p50": p50, "p99": p99}}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Poisson arrivals of uneven optimisation jobs; continuous batching."""
+    import torch
+    from paper_2509_10103_amd import serve
+    from paper_2509_10103_amd.batch import Instance
+    pool = configs.batch_instances(64)
+    rng = np.random.default_rng(7)
+    cfgs = []
+    for i in range(args.serve_n):
+        c = dict(pool[int(rng.integers(0, len(pool)))])
+        if args.nsteps:
+            c["nsteps"] = args.nsteps
+            c["n_ckpt"] = min(c["n_ckpt"], args.nsteps)
+        cfgs.append(c)
+    torch.cuda.set_device(0)
+    # offered load ~0.8 of the measured capacity: time one job alone first
+    probe = Instance(cfgs[0])
+    t = time.perf_counter()
+    for _ in range(args.serve_iters):
+        probe.iterate()
+    t1 = (time.perf_counter() - t)
+    probe.release()
+    mean_job = t1 * np.mean([c["nr"] * c["nt"] * c["nz"] for c in cfgs]) / (cfgs[0]["nr"] * cfgs[0]["nt"] * cfgs[0]["nz"])
+    rate = 0.8 / max(mean_job, 1e-3)
+    arrivals = serve.poisson_arrivals(len(cfgs), rate, seed=7)
+    s = serve.Server(hbm_budget=250e9, max_active=16, workers=8)
+    jobs, rep = serve.replay(s, cfgs, args.serve_iters, arrivals)
+    out = {"metric": "fwd+adjoint grid-point-steps/s (served)", "value": rep["gp_steps_per_s"],
+           "unit": "grid-point-steps/s", "n_gpus": 1, "steps": rep["iterations"], "warmup": 0,
+           "ms_per_step": rep["wall_s"] / max(rep["iterations"], 1) * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"serve-{len(cfgs)}-poisson", "arrival_rate_per_s": rate,
+                      "iterations_per_job": args.serve_iters, **rep}}
     print(json.dumps(out), flush=True)
 
 

@@ -36,3 +36,41 @@ C3 = _mk("autograd-48x64x384", 48, 64, 384, 24.0, 1500.0, 10.0, 1.0, 0.02, 0.5 *
          "smooth")
 
 WORKLOADS = {"c1": C1, "c2": C2, "c3": C3}
+
+
+def batch_instances(n=64, seed0=1000, hbm_budget=200e9, nsteps=2000, dt=0.02):
+    """The batched workload: n instances of uneven size, seed seed0 + i.
+
+    Per instance: N_r in {32, 48, 64}, N_theta in {24, 48, 96}, N_z in
+    {96, ..., 768} with L_D = 25 N_z / 768 (the paper-like axial spacing),
+    Re ~ U[1000, 3000], Wo ~ U[4, 18], A ~ U[0.25, 1.5], log10 E0 ~ U[-7, -3],
+    tau0 in {0, T/4, T/2, 3T/4}; horizon 10 D/U (nsteps at dt); checkpoint
+    slots so that all arenas together fit the HBM budget."""
+    import numpy as np
+    out = []
+    sizes = []
+    for i in range(n):
+        rng = np.random.default_rng(seed0 + i)
+        nr = int(rng.choice([32, 48, 64]))
+        nt = int(rng.choice([24, 48, 96]))
+        nz = int(rng.choice([96, 144, 192, 288, 384, 576, 768]))
+        re = float(rng.uniform(1000, 3000))
+        wo = float(rng.uniform(4, 18))
+        amp = float(rng.uniform(0.25, 1.5))
+        e0 = float(10 ** rng.uniform(-7, -3))
+        T = period(re, wo)
+        t0 = float(rng.choice([0.0, 0.25, 0.5, 0.75])) * T
+        M, K = (nt - 1) // 3, (nz - 1) // 3
+        fbytes = 3 * nr * (M + 1) * (2 * K + 1) * 16
+        sizes.append(fbytes)
+        out.append(_mk(f"batch-{i}-{nr}x{nt}x{nz}", nr, nt, nz, 50.0 * nz / 768.0, re, wo, amp, dt, t0, nsteps,
+                       e0, seed0 + i, 0, 1, "smooth"))
+    per = hbm_budget / n
+    for c, fb in zip(out, sizes):
+        c["n_ckpt"] = int(max(2, min(c["nsteps"], per // fb)))
+    return out
+
+
+def field_bytes(c):
+    M, K = (c["nt"] - 1) // 3, (c["nz"] - 1) // 3
+    return 3 * c["nr"] * (M + 1) * (2 * K + 1) * 16

@@ -1,0 +1,210 @@
+"""Serving loop: continuous batching of optimisation jobs on one GPU.
+
+Requests (a job configuration and a number of optimisation iterations)
+arrive at any time.  A job is admitted when its HBM footprint (checkpoint
+arena + workspace + operator caches + its fields) fits the free budget and a
+slot is free; admitted jobs keep their state resident and are advanced one
+iteration at a time by a pool of worker threads, each job on its own HIP
+stream, so the work of jobs admitted at different times overlaps on the
+device (a new job joins at the next iteration boundary, a finished job frees
+its slot and memory at once).  Each iteration's wall latency and each job's
+queue wait are recorded.  A job whose gain becomes non-finite or whose calls
+fail is retired with an error; the others continue.
+
+The job factory is pluggable so that the scheduling can be exercised without
+a GPU.
+"""
+import heapq
+import math
+import threading
+import time
+
+import numpy as np
+
+
+def estimate_footprint(cfg):
+    """Device bytes of one job: arena + workspace + operator caches + 2 fields."""
+    nr, nt, nz = cfg["nr"], cfg["nt"], cfg["nz"]
+    M, K = (nt - 1) // 3, (nz - 1) // 3
+    f = 3 * nr * (M + 1) * (2 * K + 1) * 16
+    g = nr * (M + 1) * nz * 16
+    ws = 25 * f + 15 * g
+    cache = (K + 1) * ((M + 2) + (M + 1)) * (nr - 1) * 9 * 8 + (K + 1) * (M + 1) * (3 * nr + 1) * 8
+    n_ckpt = max(1, min(cfg.get("n_ckpt") or cfg["nsteps"], cfg["nsteps"]))
+    return n_ckpt * f + ws + cache + 2 * f
+
+
+class Job:
+    def __init__(self, jid, cfg, iters, arrival):
+        self.id = jid
+        self.cfg = cfg
+        self.iters = iters
+        self.arrival = arrival
+        self.admitted = None
+        self.finished = None
+        self.done_iters = 0
+        self.latencies = []
+        self.error = None
+        self.result = None
+        self.footprint = estimate_footprint(cfg)
+        self.runner = None
+        self.busy = False
+        self.counted = 0
+
+
+class Server:
+    """Admission by footprint, iteration-granular continuous batching."""
+
+    def __init__(self, hbm_budget, max_active=16, workers=8, factory=None):
+        self.budget = hbm_budget
+        self.max_active = max_active
+        self.workers = workers
+        self.factory = factory or gpu_factory
+        self.lock = threading.Condition()
+        self.pending = []          # heap of (arrival, id, job)
+        self.active = []
+        self.done = []
+        self.used = 0
+        self.closed = False
+        self.next_id = 0
+        self._threads = []
+
+    # ------------------------------------------------------------ client side
+    def submit(self, cfg, iters, arrival=None):
+        with self.lock:
+            j = Job(self.next_id, cfg, iters, time.perf_counter() if arrival is None else arrival)
+            self.next_id += 1
+            if j.footprint > self.budget:
+                j.error = f"footprint {j.footprint / 1e9:.1f} GB exceeds the budget {self.budget / 1e9:.1f} GB"
+                j.finished = j.arrival
+                self.done.append(j)
+            else:
+                heapq.heappush(self.pending, (j.arrival, j.id, j))
+            self.lock.notify_all()
+            return j
+
+    def close(self):
+        with self.lock:
+            self.closed = True
+            self.lock.notify_all()
+
+    # ------------------------------------------------------------ scheduling
+    def _admit_locked(self):
+        while self.pending and len(self.active) < self.max_active:
+            _, _, j = self.pending[0]
+            if self.used + j.footprint > self.budget:
+                break                  # first-come first-served: do not overtake
+            heapq.heappop(self.pending)
+            self.used += j.footprint
+            j.admitted = time.perf_counter()
+            self.active.append(j)
+
+    def _retire_locked(self, j):
+        self.active.remove(j)
+        self.used -= j.footprint
+        j.finished = time.perf_counter()
+        self.done.append(j)
+        self._admit_locked()
+        self.lock.notify_all()
+
+    def _next_locked(self):
+        """Least-advanced idle active job (round-robin at iteration granularity)."""
+        cands = [j for j in self.active if not j.busy]
+        if not cands:
+            return None
+        j = min(cands, key=lambda x: (x.done_iters, x.admitted, x.id))
+        j.busy = True
+        return j
+
+    def _worker(self):
+        while True:
+            with self.lock:
+                self._admit_locked()
+                j = self._next_locked()
+                while j is None:
+                    if self.closed and not self.pending and not self.active:
+                        return
+                    self.lock.wait(timeout=0.05)
+                    self._admit_locked()
+                    j = self._next_locked()
+            try:
+                if j.runner is None:
+                    j.runner = self.factory(j.cfg)
+                st, dt, counted = j.runner.iterate()
+                ok = st is None or math.isfinite(st.get("G_new", 0.0))
+                with self.lock:
+                    j.latencies.append(dt)
+                    j.counted += counted
+                    j.done_iters += 1
+                    if not ok:
+                        j.error = "non-finite gain"
+                    finished = j.done_iters >= j.iters or j.error is not None
+                    if finished:
+                        j.result = j.runner.state() if j.error is None else None
+                        j.runner.release()
+                        j.runner = None
+                    j.busy = False
+                    if finished:
+                        self._retire_locked(j)
+            except Exception as e:       # isolate the failing job
+                with self.lock:
+                    j.error = repr(e)
+                    try:
+                        if j.runner is not None:
+                            j.runner.release()
+                    except Exception:
+                        pass
+                    j.runner = None
+                    j.busy = False
+                    self._retire_locked(j)
+
+    def start(self):
+        for _ in range(self.workers):
+            t = threading.Thread(target=self._worker, daemon=True)
+            t.start()
+            self._threads.append(t)
+
+    def join(self):
+        self.close()
+        for t in self._threads:
+            t.join()
+
+    # ------------------------------------------------------------ reporting
+    def report(self, t_start, t_end):
+        lat = [x for j in self.done for x in j.latencies]
+        waits = [j.admitted - j.arrival for j in self.done if j.admitted is not None]
+        counted = sum(j.counted for j in self.done)
+        a = np.asarray(lat) if lat else np.zeros(1)
+        w = np.asarray(waits) if waits else np.zeros(1)
+        return {
+            "jobs": len(self.done), "failed": sum(1 for j in self.done if j.error),
+            "iterations": len(lat),
+            "iteration_latency_s": {"p50": float(np.percentile(a, 50)), "p99": float(np.percentile(a, 99))},
+            "queue_wait_s": {"p50": float(np.percentile(w, 50)), "p99": float(np.percentile(w, 99))},
+            "gp_steps_per_s": counted / max(t_end - t_start, 1e-9),
+            "wall_s": t_end - t_start,
+        }
+
+
+def gpu_factory(cfg):
+    from .batch import Instance
+    return Instance(cfg)
+
+
+def poisson_arrivals(n, rate, seed):
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
+def replay(server, cfgs, iters, arrivals):
+    """Submit cfgs at the given arrival offsets (seconds) and wait for all."""
+    t0 = time.perf_counter()
+    server.start()
+    jobs = []
+    for c, a in zip(cfgs, arrivals):
+        now = time.perf_counter() - t0
+        if a > now:
+            time.sleep(a - now)
+        jobs.append(server.submit(c, iters))
+    server.join()
+    return jobs, server.report(t0, time.perf_counter())
