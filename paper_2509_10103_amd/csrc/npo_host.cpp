@@ -387,7 +387,8 @@ npo_status npo_plan_create(const npo_grid* grid, const npo_flow* flow, const npo
     const int nr = grid->nr, nt = grid->ntheta, nz = grid->nz;
     if (nr < 8 || nr > npo::NR_MAX) return fail(NPO_EUNSUPPORTED, "nr must be in [8, 64]");
     if (nt < 6 || nt > 128 || radix_factors(nt).empty()) return fail(NPO_EUNSUPPORTED, "ntheta must be 2^a 3^b in [6,128]");
-    if (nz < 6 || nz > 2048 || radix_factors(nz).empty()) return fail(NPO_EUNSUPPORTED, "nz must be 2^a 3^b in [6,2048]");
+    if (nz < 6 || nz > 2048 || nz % 2 || radix_factors(nz).empty())
+        return fail(NPO_EUNSUPPORTED, "nz must be even and 2^a 3^b in [6,2048]");
     if (!(grid->lz > 0) || !(flow->re > 0) || !(flow->wo > 0) || !(time->dt > 0) || time->nsteps < 1)
         return fail(NPO_EINVAL, "lz, re, wo, dt must be positive and nsteps >= 1");
     if (flow->amp < 0) return fail(NPO_EINVAL, "amp must be >= 0");
@@ -600,25 +601,21 @@ npo_status npo_plan_create(const npo_grid* grid, const npo_flow* flow, const npo
     }
     // launch shapes: LDS budget 64 KiB per block for the FFT kernels
     const size_t lds = 64 * 1024;
-    p->zgroup = 1;
-    for (int g : {3, 2, 1})
-        if ((size_t)2 * g * nz * 16 <= lds) { p->zgroup = g; break; }
-    if ((size_t)2 * nz * 16 > 160 * 1024) {
+    if (npo::zpass_lds(*p, 1) > 160 * 1024) {
+        (void)hipFree(p->d_cache);
         (void)hipFree(p->d_tables);
         delete p;
         return fail(NPO_EUNSUPPORTED, "nz too large for one LDS-resident axial transform");
     }
-    auto theta_lds = [&](int ZB, int adj) {
-        const int H = ZB / 2;
-        const int nin = adj ? 4 * ZB + H : 3 * ZB, nout = adj ? 3 * ZB : ZB + H;
-        return (size_t)2 * std::max(nin, nout) * nt * 16;
-    };
+    p->zgroup = 1;
+    for (int g : {3, 2, 1})
+        if (npo::zpass_lds(*p, g) <= lds) { p->zgroup = g; break; }
     p->zb_theta_fwd = p->zb_theta_adj = 2;
     for (int ZB : {8, 4, 2}) {
-        if (nz % ZB == 0 && theta_lds(ZB, 0) <= lds) { p->zb_theta_fwd = ZB; break; }
+        if (nz % ZB == 0 && npo::theta_lds(*p, ZB, 0) <= lds) { p->zb_theta_fwd = ZB; break; }
     }
     for (int ZB : {8, 4, 2}) {
-        if (nz % ZB == 0 && theta_lds(ZB, 1) <= lds) { p->zb_theta_adj = ZB; break; }
+        if (nz % ZB == 0 && npo::theta_lds(*p, ZB, 1) <= lds) { p->zb_theta_adj = ZB; break; }
     }
     // workspace layout
     const size_t fb = (size_t)3 * nr * p->mp1 * p->nk * 16;
@@ -909,11 +906,9 @@ npo_status npo_plan_set_tuning(npo_plan p, int32_t zgroup, int32_t zb_fwd, int32
     auto ok_zb = [&](int zb, int adj) {
         if (zb != 2 && zb != 4 && zb != 8) return false;
         if (p->nz % zb) return false;
-        const int H = zb / 2;
-        const int nin = adj ? 4 * zb + H : 3 * zb, nout = adj ? 3 * zb : zb + H;
-        return (size_t)2 * std::max(nin, nout) * p->nt * 16 <= 160 * 1024;
+        return npo::theta_lds(*p, zb, adj) <= 160 * 1024;
     };
-    if (zgroup < 1 || zgroup > 3 || (size_t)2 * zgroup * p->nz * 16 > 160 * 1024)
+    if (zgroup < 1 || zgroup > 3 || npo::zpass_lds(*p, zgroup) > 160 * 1024)
         return fail(NPO_EINVAL, "zgroup must be 1..3 and fit 160 KiB of LDS");
     if (!ok_zb(zb_fwd, 0) || !ok_zb(zb_adj, 1)) return fail(NPO_EINVAL, "bad azimuthal z-block");
     p->zgroup = zgroup;

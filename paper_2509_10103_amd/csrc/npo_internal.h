@@ -98,6 +98,10 @@ void prof_end(const npo_plan_s& p, int kid, hipStream_t st);
 
 // Kernel launchers (npo_kernels.hip).  All enqueue on `st` and return the
 // hipGetLastError() of the launch.
+// Dynamic LDS bytes of the axial passes (G fields per round) and of the
+// azimuthal pass (z-block ZB) for this plan's transform lengths.
+size_t zpass_lds(const npo_plan_s& p, int G);
+size_t theta_lds(const npo_plan_s& p, int ZB, int adj);
 hipError_t launch_curl_aux(const npo_plan_s& p, const double2* u, double2* aux, hipStream_t st);
 hipError_t launch_nl(const npo_plan_s& p, int adjoint, const double2* u, const double2* aux,
                      const double2* y, double t, double2* out0, double2* out1, void* ws, hipStream_t st);

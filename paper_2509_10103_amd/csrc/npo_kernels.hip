@@ -10,111 +10,9 @@
 //
 // Spectral field layout: complex [c][j][m][kk], kk in FFT order.
 // Intermediate layout (after the axial transform): complex [j][f][m][z].
-#include "npo_internal.h"
+#include "npo_device.h"
 
 namespace npo {
-
-// ------------------------------------------------------------------ complex
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
-__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
-__device__ __forceinline__ double2 cmuli(double2 a) { return make_double2(-a.y, a.x); }   // i*a
-__device__ __forceinline__ double2 czero() { return make_double2(0.0, 0.0); }
-// a + s*b (s real)
-__device__ __forceinline__ double2 caxpy(double2 a, double s, double2 b) {
-    return make_double2(fma(s, b.x, a.x), fma(s, b.y, a.y));
-}
-
-__device__ __forceinline__ double alpha_of(const KP& p, int kk) {
-    return (kk <= p.K ? kk : kk - p.nk) * p.k0;
-}
-__device__ __forceinline__ size_t fidx(const KP& p, int c, int j, int m, int kk) {
-    return ((size_t)(c * p.nr + j) * p.mp1 + m) * p.nk + kk;
-}
-// 7-point FD weight of row `row` at column `col` (0 outside the stencil).
-__device__ __forceinline__ double fdw(const double* D, int pi, int nr, const int* col0, int row, int col) {
-    int t = col - col0[row];
-    return (t >= 0 && t < 7) ? D[(pi * nr + row) * 7 + t] : 0.0;
-}
-
-// Base flow at node j: U and Omega_theta = -dU/dr, with (cw, sw) = (cos wt, sin wt).
-__device__ __forceinline__ void base_at(const KP& p, int j, double cw, double sw, double& U, double& Om) {
-    double r = p.r[j];
-    double2 a = p.Ut[j], b = p.dUt[j];
-    U = 1.0 - r * r + (a.x * cw - a.y * sw);
-    Om = 2.0 * r - (b.x * cw - b.y * sw);
-}
-
-// ---------------------------------------------------------------- LDS FFTs
-// Batched Stockham autosort FFT of B transforms of length n held in LDS
-// (a: input, b: scratch); radices 2, 3, 4.  sg = -1 forward, +1 inverse,
-// no scaling.  tw[t] = exp(-2 pi i t / n).  Returns the buffer with the result.
-__device__ double2* fft_lds(double2* a, double2* b, int B, int n, const int* fac, int nfac,
-                            const double2* __restrict__ tw, double sg) {
-    int Ns = 1;
-    for (int s = 0; s < nfac; ++s) {
-        const int R = fac[s];
-        const int nb = n / R;
-        const int total = B * nb;
-        const int tws = n / (Ns * R);
-        for (int t = threadIdx.x; t < total; t += blockDim.x) {
-            const int bi = t / nb;
-            const int jj = t - bi * nb;
-            const double2* x = a + bi * n;
-            double2* y = b + bi * n;
-            const int k = jj % Ns;
-            const int base = (jj / Ns) * Ns * R + k;
-            if (R == 4) {
-                double2 v0 = x[jj], v1 = x[jj + nb], v2 = x[jj + 2 * nb], v3 = x[jj + 3 * nb];
-                if (k) {
-                    double2 w1 = tw[k * tws], w2 = tw[2 * k * tws], w3 = tw[3 * k * tws];
-                    if (sg > 0) { w1.y = -w1.y; w2.y = -w2.y; w3.y = -w3.y; }
-                    v1 = cmul(v1, w1); v2 = cmul(v2, w2); v3 = cmul(v3, w3);
-                }
-                double2 s02 = cadd(v0, v2), d02 = csub(v0, v2);
-                double2 s13 = cadd(v1, v3), d13 = csub(v1, v3);
-                // w = exp(sg * 2 pi i / 4) = sg * i
-                double2 wd = cmuli(d13);
-                if (sg < 0) wd = make_double2(-wd.x, -wd.y);
-                y[base] = cadd(s02, s13);
-                y[base + Ns] = cadd(d02, wd);
-                y[base + 2 * Ns] = csub(s02, s13);
-                y[base + 3 * Ns] = csub(d02, wd);
-            } else if (R == 2) {
-                double2 v0 = x[jj], v1 = x[jj + nb];
-                if (k) {
-                    double2 w1 = tw[k * tws];
-                    if (sg > 0) w1.y = -w1.y;
-                    v1 = cmul(v1, w1);
-                }
-                y[base] = cadd(v0, v1);
-                y[base + Ns] = csub(v0, v1);
-            } else {  // R == 3
-                double2 v0 = x[jj], v1 = x[jj + nb], v2 = x[jj + 2 * nb];
-                if (k) {
-                    double2 w1 = tw[k * tws], w2 = tw[2 * k * tws];
-                    if (sg > 0) { w1.y = -w1.y; w2.y = -w2.y; }
-                    v1 = cmul(v1, w1); v2 = cmul(v2, w2);
-                }
-                const double c = -0.5, s3 = 0.86602540378443864676 * sg;
-                double2 s12 = cadd(v1, v2), d12 = csub(v1, v2);
-                double2 t0 = caxpy(v0, c, s12);
-                double2 t1 = cscale(cmuli(d12), s3);
-                y[base] = cadd(v0, s12);
-                y[base + Ns] = cadd(t0, t1);
-                y[base + 2 * Ns] = csub(t0, t1);
-            }
-        }
-        __syncthreads();
-        double2* tmp = a; a = b; b = tmp;
-        Ns *= R;
-    }
-    return a;
-}
 
 // ------------------------------------------------------------ vorticity aux
 // aux[0] = w_theta = i a u_r - D1 u_z ; aux[1] = w_z = D1 u_theta + u_theta/r - (i m / r) u_r
@@ -137,171 +35,6 @@ __global__ void k_curl_aux(KP p, const double2* __restrict__ u, double2* __restr
     const double2 ur = u[fidx(p, 0, j, m, kk)], ut = u[fidx(p, 1, j, m, kk)];
     aux[fidx(p, 0, j, m, kk)] = csub(cscale(cmuli(ur), a), duz);
     aux[fidx(p, 1, j, m, kk)] = csub(caxpy(dut, 1.0 / r, ut), cscale(cmuli(ur), m / r));
-}
-
-// ------------------------------------------------------ axial inverse FFT
-// Block (m, j).  Fields: 0..2 u, 3 w_r (built from u), 4..5 aux, 6..8 y.
-__global__ void k_zinv(KP p, int nf, int G, const double2* __restrict__ u, const double2* __restrict__ aux,
-                       const double2* __restrict__ y, double2* __restrict__ zb) {
-    extern __shared__ double2 sh[];
-    const int m = blockIdx.x, j = blockIdx.y;
-    const int nz = p.nz, nk = p.nk, K = p.K;
-    const double r = p.r[j];
-    double2* A = sh;
-    double2* Bf = sh + G * nz;
-    for (int f0 = 0; f0 < nf; f0 += G) {
-        const int g = min(G, nf - f0);
-        for (int t = threadIdx.x; t < g * nz; t += blockDim.x) A[t] = czero();
-        __syncthreads();
-        for (int t = threadIdx.x; t < g * nk; t += blockDim.x) {
-            const int fi = t / nk, kk = t - fi * nk, f = f0 + fi;
-            double2 v;
-            if (f < 3) {
-                v = u[fidx(p, f, j, m, kk)];
-            } else if (f == 3) {
-                const double a = alpha_of(p, kk);
-                v = csub(cscale(cmuli(u[fidx(p, 2, j, m, kk)]), m / r), cscale(cmuli(u[fidx(p, 1, j, m, kk)]), a));
-            } else if (f < 6) {
-                v = aux[fidx(p, f - 4, j, m, kk)];
-            } else {
-                v = y[fidx(p, f - 6, j, m, kk)];
-            }
-            const int pos = kk <= K ? kk : nz - (nk - kk);
-            A[fi * nz + pos] = v;
-        }
-        __syncthreads();
-        double2* res = fft_lds(A, Bf, g, nz, p.fz, p.nfz, p.twz, 1.0);
-        for (int t = threadIdx.x; t < g * nz; t += blockDim.x) {
-            const int fi = t / nz, z = t - fi * nz;
-            zb[((size_t)(j * nf + f0 + fi) * p.mp1 + m) * nz + z] = res[t];
-        }
-        __syncthreads();
-    }
-}
-
-// ------------------------------------------- azimuthal FFTs and products
-// Block (z-block, j).  Forward (adj = 0): 6 inputs (u, w) -> 3 outputs N.
-// Adjoint (adj = 1): 9 inputs (u, w, y) -> 6 outputs A = (Om + w) x Y, B = Y x (U + u).
-__device__ __forceinline__ void place_pair(double2* s, int nt, int m, double2 xa, double2 xb) {
-    if (m == 0) {
-        s[0] = make_double2(xa.x, xb.x);
-    } else {
-        s[m] = make_double2(xa.x - xb.y, xa.y + xb.x);          // xa + i xb
-        s[nt - m] = make_double2(xa.x + xb.y, -xa.y + xb.x);    // conj(xa) + i conj(xb)
-    }
-}
-
-__global__ void k_theta(KP p, int adj, int ZB, const double2* __restrict__ zb, double2* __restrict__ tb,
-                        double cw, double sw) {
-    extern __shared__ double2 sh[];
-    const int j = blockIdx.y, z0 = blockIdx.x * ZB;
-    const int nt = p.nt, mp1 = p.mp1, nz = p.nz;
-    const int nf = adj ? 9 : 6, nfo = adj ? 6 : 3;
-    const int H = ZB / 2;
-    const int nin = adj ? 4 * ZB + H : 3 * ZB;
-    const int nout = adj ? 3 * ZB : ZB + H;
-    const int nseq = nin > nout ? nin : nout;
-    double2* A = sh;
-    double2* Bf = sh + nseq * nt;
-    for (int t = threadIdx.x; t < nin * nt; t += blockDim.x) A[t] = czero();
-    __syncthreads();
-    const int npair = adj ? 4 : 3;
-    for (int t = threadIdx.x; t < npair * ZB * mp1; t += blockDim.x) {
-        const int zi = t % ZB, m = (t / ZB) % mp1, pi = t / (ZB * mp1);
-        const double2 xa = zb[((size_t)(j * nf + 2 * pi) * mp1 + m) * nz + z0 + zi];
-        const double2 xb = zb[((size_t)(j * nf + 2 * pi + 1) * mp1 + m) * nz + z0 + zi];
-        place_pair(A + (pi * ZB + zi) * nt, nt, m, xa, xb);
-    }
-    if (adj) {
-        for (int t = threadIdx.x; t < H * mp1; t += blockDim.x) {
-            const int zi = t % H, m = t / H;
-            const double2 xa = zb[((size_t)(j * nf + 8) * mp1 + m) * nz + z0 + zi];
-            const double2 xb = zb[((size_t)(j * nf + 8) * mp1 + m) * nz + z0 + zi + H];
-            place_pair(A + (4 * ZB + zi) * nt, nt, m, xa, xb);
-        }
-    }
-    __syncthreads();
-    double2* R1 = fft_lds(A, Bf, nin, nt, p.ft, p.nft, p.twt, 1.0);
-    double2* O = (R1 == A) ? Bf : A;
-    double* Od = reinterpret_cast<double*>(O);
-    double U, Om;
-    base_at(p, j, cw, sw, U, Om);
-    for (int t = threadIdx.x; t < ZB * nt; t += blockDim.x) {
-        const int zi = t / nt, th = t - zi * nt;
-        const double2 s0 = R1[(0 * ZB + zi) * nt + th];
-        const double2 s1 = R1[(1 * ZB + zi) * nt + th];
-        const double2 s2 = R1[(2 * ZB + zi) * nt + th];
-        const double ur = s0.x, ut = s0.y, uz = s1.x, wr = s1.y, wt = s2.x, wz = s2.y;
-        if (!adj) {
-            const double uzU = uz + U;
-            const double Nr = ut * wz - uzU * wt - uz * Om;
-            const double Nt = uzU * wr - ur * wz;
-            const double Nz = ur * (wt + Om) - ut * wr;
-            O[zi * nt + th] = make_double2(Nr, Nt);
-            const int q = ZB + (zi < H ? zi : zi - H);
-            Od[2 * (q * nt + th) + (zi < H ? 0 : 1)] = Nz;
-        } else {
-            const double2 s3 = R1[(3 * ZB + zi) * nt + th];
-            const double2 s4 = R1[(4 * ZB + (zi < H ? zi : zi - H)) * nt + th];
-            const double yr = s3.x, yt = s3.y, yz = (zi < H) ? s4.x : s4.y;
-            const double wtO = wt + Om, uzU = uz + U;
-            const double Ar = wtO * yz - wz * yt;
-            const double At = wz * yr - wr * yz;
-            const double Az = wr * yt - wtO * yr;
-            const double Br = yt * uzU - yz * ut;
-            const double Bt = yz * ur - yr * uzU;
-            const double Bz = yr * ut - yt * ur;
-            O[zi * nt + th] = make_double2(Ar, At);
-            O[(ZB + zi) * nt + th] = make_double2(Az, Br);
-            O[(2 * ZB + zi) * nt + th] = make_double2(Bt, Bz);
-        }
-    }
-    __syncthreads();
-    double2* R2 = fft_lds(O, R1, nout, nt, p.ft, p.nft, p.twt, -1.0);
-    for (int t = threadIdx.x; t < nfo * mp1 * ZB; t += blockDim.x) {
-        const int zi = t % ZB, m = (t / ZB) % mp1, f = t / (ZB * mp1);
-        int q, half;
-        if (!adj) {
-            if (f < 2) { q = zi; half = f; }
-            else { q = ZB + (zi < H ? zi : zi - H); half = (zi < H) ? 0 : 1; }
-        } else {
-            q = (f >> 1) * ZB + zi;
-            half = f & 1;
-        }
-        const double2 a = R2[q * nt + m];
-        const double2 b = cconj(R2[q * nt + (m == 0 ? 0 : nt - m)]);
-        double2 v;
-        if (half == 0) v = cscale(cadd(a, b), 0.5);
-        else v = cscale(cmuli(csub(b, a)), 0.5);          // (a - b) / (2i)
-        tb[((size_t)(j * nfo + f) * mp1 + m) * nz + z0 + zi] = v;
-    }
-}
-
-// ------------------------------------------------------ axial forward FFT
-__global__ void k_zfwd(KP p, int nfo, int G, const double2* __restrict__ tb, double2* __restrict__ out0,
-                       double2* __restrict__ out1, double scale) {
-    extern __shared__ double2 sh[];
-    const int m = blockIdx.x, j = blockIdx.y;
-    const int nz = p.nz, nk = p.nk, K = p.K;
-    double2* A = sh;
-    double2* Bf = sh + G * nz;
-    for (int f0 = 0; f0 < nfo; f0 += G) {
-        const int g = min(G, nfo - f0);
-        for (int t = threadIdx.x; t < g * nz; t += blockDim.x) {
-            const int fi = t / nz, z = t - fi * nz;
-            A[t] = tb[((size_t)(j * nfo + f0 + fi) * p.mp1 + m) * nz + z];
-        }
-        __syncthreads();
-        double2* res = fft_lds(A, Bf, g, nz, p.fz, p.nfz, p.twz, -1.0);
-        for (int t = threadIdx.x; t < g * nk; t += blockDim.x) {
-            const int fi = t / nk, kk = t - fi * nk, f = f0 + fi;
-            const int pos = kk <= K ? kk : nz - (nk - kk);
-            const double2 v = cscale(res[fi * nz + pos], scale);
-            if (f < 3) out0[fidx(p, f, j, m, kk)] = v;
-            else out1[fidx(p, f - 3, j, m, kk)] = v;
-        }
-        __syncthreads();
-    }
 }
 
 // ------------------------------------------------------ banded operators
@@ -1103,32 +836,6 @@ hipError_t launch_curl_aux(const npo_plan_s& p, const double2* u, double2* aux, 
     prof_begin(p, KID_CURL, st);
     hipLaunchKernelGGL(k_curl_aux, dim3((per + 255) / 256), dim3(256), 0, st, p.kp, u, aux);
     prof_end(p, KID_CURL, st);
-    return hipGetLastError();
-}
-
-hipError_t launch_nl(const npo_plan_s& p, int adj, const double2* u, const double2* aux, const double2* y,
-                     double t, double2* out0, double2* out1, void* ws, hipStream_t st) {
-    char* base = static_cast<char*>(ws);
-    double2* zb = reinterpret_cast<double2*>(base + p.ws.zbuf);
-    double2* tb = reinterpret_cast<double2*>(base + p.ws.tbuf);
-    const int nf = adj ? 9 : 6, nfo = adj ? 6 : 3;
-    const int G = p.zgroup;
-    const size_t shz = (size_t)2 * G * p.nz * sizeof(double2);
-    prof_begin(p, adj ? KID_ZINV_A : KID_ZINV_F, st);
-    hipLaunchKernelGGL(k_zinv, dim3(p.mp1, p.nr), dim3(256), shz, st, p.kp, nf, G, u, aux, y, zb);
-    prof_end(p, adj ? KID_ZINV_A : KID_ZINV_F, st);
-    const int ZB = adj ? p.zb_theta_adj : p.zb_theta_fwd;
-    const int H = ZB / 2;
-    const int nin = adj ? 4 * ZB + H : 3 * ZB, nout = adj ? 3 * ZB : ZB + H;
-    const size_t sht = (size_t)2 * (nin > nout ? nin : nout) * p.nt * sizeof(double2);
-    const double cw = cos(p.omega * t), sw = sin(p.omega * t);
-    prof_begin(p, adj ? KID_THETA_A : KID_THETA_F, st);
-    hipLaunchKernelGGL(k_theta, dim3(p.nz / ZB, p.nr), dim3(256), sht, st, p.kp, adj, ZB, zb, tb, cw, sw);
-    prof_end(p, adj ? KID_THETA_A : KID_THETA_F, st);
-    const double scale = 1.0 / ((double)p.nt * p.nz);
-    prof_begin(p, adj ? KID_ZFWD_A : KID_ZFWD_F, st);
-    hipLaunchKernelGGL(k_zfwd, dim3(p.mp1, p.nr), dim3(256), shz, st, p.kp, nfo, G, tb, out0, out1, scale);
-    prof_end(p, adj ? KID_ZFWD_A : KID_ZFWD_F, st);
     return hipGetLastError();
 }
 

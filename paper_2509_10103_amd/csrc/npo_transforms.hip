@@ -1,0 +1,677 @@
+// Nonlinear-term kernels: axial FFTs, azimuthal FFTs and the pointwise
+// products of the rotational form (Sec. 2.3: pseudo-spectral evaluation with
+// 3/2-rule dealiasing), for gfx950 in FP64.
+//
+// Three kernels per evaluation, one per data grouping:
+//   k_zinv   block (m, j): inverse axial FFTs of the spectral inputs, zero
+//            padded from 2K+1 retained modes to N_z points;
+//   k_theta  block (z-block, j): inverse azimuthal FFTs (two real fields packed
+//            per complex transform), products, forward azimuthal FFTs;
+//   k_zfwd   block (m, j): forward axial FFTs, truncation to the retained band.
+// Intermediates live in HBM as complex [j][f][m][z].
+//
+// Each kernel exists in two forms: a compile-time-sized one for the common
+// transform lengths (radix sequence, loop bounds and index arithmetic fixed at
+// compile time, twiddles staged in LDS, LDS index padded against bank
+// conflicts) and a generic one with run-time radices for every other length.
+#include "npo_device.h"
+
+namespace npo {
+
+// ====================================================== generic transforms
+// Run-time radices (factors p.fz / p.ft), for lengths without a compiled size.
+// ---------------------------------------------------------------- LDS FFTs
+// Batched Stockham autosort FFT of B transforms of length n held in LDS
+// (a: input, b: scratch); radices 2, 3, 4.  sg = -1 forward, +1 inverse,
+// no scaling.  tw[t] = exp(-2 pi i t / n).  Returns the buffer with the result.
+__device__ double2* fft_lds(double2* a, double2* b, int B, int n, const int* fac, int nfac,
+                            const double2* __restrict__ tw, double sg) {
+    int Ns = 1;
+    for (int s = 0; s < nfac; ++s) {
+        const int R = fac[s];
+        const int nb = n / R;
+        const int total = B * nb;
+        const int tws = n / (Ns * R);
+        for (int t = threadIdx.x; t < total; t += blockDim.x) {
+            const int bi = t / nb;
+            const int jj = t - bi * nb;
+            const double2* x = a + bi * n;
+            double2* y = b + bi * n;
+            const int k = jj % Ns;
+            const int base = (jj / Ns) * Ns * R + k;
+            if (R == 4) {
+                double2 v0 = x[jj], v1 = x[jj + nb], v2 = x[jj + 2 * nb], v3 = x[jj + 3 * nb];
+                if (k) {
+                    double2 w1 = tw[k * tws], w2 = tw[2 * k * tws], w3 = tw[3 * k * tws];
+                    if (sg > 0) { w1.y = -w1.y; w2.y = -w2.y; w3.y = -w3.y; }
+                    v1 = cmul(v1, w1); v2 = cmul(v2, w2); v3 = cmul(v3, w3);
+                }
+                double2 s02 = cadd(v0, v2), d02 = csub(v0, v2);
+                double2 s13 = cadd(v1, v3), d13 = csub(v1, v3);
+                // w = exp(sg * 2 pi i / 4) = sg * i
+                double2 wd = cmuli(d13);
+                if (sg < 0) wd = make_double2(-wd.x, -wd.y);
+                y[base] = cadd(s02, s13);
+                y[base + Ns] = cadd(d02, wd);
+                y[base + 2 * Ns] = csub(s02, s13);
+                y[base + 3 * Ns] = csub(d02, wd);
+            } else if (R == 2) {
+                double2 v0 = x[jj], v1 = x[jj + nb];
+                if (k) {
+                    double2 w1 = tw[k * tws];
+                    if (sg > 0) w1.y = -w1.y;
+                    v1 = cmul(v1, w1);
+                }
+                y[base] = cadd(v0, v1);
+                y[base + Ns] = csub(v0, v1);
+            } else {  // R == 3
+                double2 v0 = x[jj], v1 = x[jj + nb], v2 = x[jj + 2 * nb];
+                if (k) {
+                    double2 w1 = tw[k * tws], w2 = tw[2 * k * tws];
+                    if (sg > 0) { w1.y = -w1.y; w2.y = -w2.y; }
+                    v1 = cmul(v1, w1); v2 = cmul(v2, w2);
+                }
+                const double c = -0.5, s3 = 0.86602540378443864676 * sg;
+                double2 s12 = cadd(v1, v2), d12 = csub(v1, v2);
+                double2 t0 = caxpy(v0, c, s12);
+                double2 t1 = cscale(cmuli(d12), s3);
+                y[base] = cadd(v0, s12);
+                y[base + Ns] = cadd(t0, t1);
+                y[base + 2 * Ns] = csub(t0, t1);
+            }
+        }
+        __syncthreads();
+        double2* tmp = a; a = b; b = tmp;
+        Ns *= R;
+    }
+    return a;
+}
+
+// ------------------------------------------------------ axial inverse FFT
+// Block (m, j).  Fields: 0..2 u, 3 w_r (built from u), 4..5 aux, 6..8 y.
+__global__ void k_zinv(KP p, int nf, int G, const double2* __restrict__ u, const double2* __restrict__ aux,
+                       const double2* __restrict__ y, double2* __restrict__ zb) {
+    extern __shared__ double2 sh[];
+    const int m = blockIdx.x, j = blockIdx.y;
+    const int nz = p.nz, nk = p.nk, K = p.K;
+    const double r = p.r[j];
+    double2* A = sh;
+    double2* Bf = sh + G * nz;
+    for (int f0 = 0; f0 < nf; f0 += G) {
+        const int g = min(G, nf - f0);
+        for (int t = threadIdx.x; t < g * nz; t += blockDim.x) A[t] = czero();
+        __syncthreads();
+        for (int t = threadIdx.x; t < g * nk; t += blockDim.x) {
+            const int fi = t / nk, kk = t - fi * nk, f = f0 + fi;
+            double2 v;
+            if (f < 3) {
+                v = u[fidx(p, f, j, m, kk)];
+            } else if (f == 3) {
+                const double a = alpha_of(p, kk);
+                v = csub(cscale(cmuli(u[fidx(p, 2, j, m, kk)]), m / r), cscale(cmuli(u[fidx(p, 1, j, m, kk)]), a));
+            } else if (f < 6) {
+                v = aux[fidx(p, f - 4, j, m, kk)];
+            } else {
+                v = y[fidx(p, f - 6, j, m, kk)];
+            }
+            const int pos = kk <= K ? kk : nz - (nk - kk);
+            A[fi * nz + pos] = v;
+        }
+        __syncthreads();
+        double2* res = fft_lds(A, Bf, g, nz, p.fz, p.nfz, p.twz, 1.0);
+        for (int t = threadIdx.x; t < g * nz; t += blockDim.x) {
+            const int fi = t / nz, z = t - fi * nz;
+            zb[((size_t)(j * nf + f0 + fi) * p.mp1 + m) * nz + z] = res[t];
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------- azimuthal FFTs and products
+// Block (z-block, j).  Forward (adj = 0): 6 inputs (u, w) -> 3 outputs N.
+// Adjoint (adj = 1): 9 inputs (u, w, y) -> 6 outputs A = (Om + w) x Y, B = Y x (U + u).
+__device__ __forceinline__ void place_pair(double2* s, int nt, int m, double2 xa, double2 xb) {
+    if (m == 0) {
+        s[0] = make_double2(xa.x, xb.x);
+    } else {
+        s[m] = make_double2(xa.x - xb.y, xa.y + xb.x);          // xa + i xb
+        s[nt - m] = make_double2(xa.x + xb.y, -xa.y + xb.x);    // conj(xa) + i conj(xb)
+    }
+}
+
+__global__ void k_theta(KP p, int adj, int ZB, const double2* __restrict__ zb, double2* __restrict__ tb,
+                        double cw, double sw) {
+    extern __shared__ double2 sh[];
+    const int j = blockIdx.y, z0 = blockIdx.x * ZB;
+    const int nt = p.nt, mp1 = p.mp1, nz = p.nz;
+    const int nf = adj ? 9 : 6, nfo = adj ? 6 : 3;
+    const int H = ZB / 2;
+    const int nin = adj ? 4 * ZB + H : 3 * ZB;
+    const int nout = adj ? 3 * ZB : ZB + H;
+    const int nseq = nin > nout ? nin : nout;
+    double2* A = sh;
+    double2* Bf = sh + nseq * nt;
+    for (int t = threadIdx.x; t < nin * nt; t += blockDim.x) A[t] = czero();
+    __syncthreads();
+    const int npair = adj ? 4 : 3;
+    for (int t = threadIdx.x; t < npair * ZB * mp1; t += blockDim.x) {
+        const int zi = t % ZB, m = (t / ZB) % mp1, pi = t / (ZB * mp1);
+        const double2 xa = zb[((size_t)(j * nf + 2 * pi) * mp1 + m) * nz + z0 + zi];
+        const double2 xb = zb[((size_t)(j * nf + 2 * pi + 1) * mp1 + m) * nz + z0 + zi];
+        place_pair(A + (pi * ZB + zi) * nt, nt, m, xa, xb);
+    }
+    if (adj) {
+        for (int t = threadIdx.x; t < H * mp1; t += blockDim.x) {
+            const int zi = t % H, m = t / H;
+            const double2 xa = zb[((size_t)(j * nf + 8) * mp1 + m) * nz + z0 + zi];
+            const double2 xb = zb[((size_t)(j * nf + 8) * mp1 + m) * nz + z0 + zi + H];
+            place_pair(A + (4 * ZB + zi) * nt, nt, m, xa, xb);
+        }
+    }
+    __syncthreads();
+    double2* R1 = fft_lds(A, Bf, nin, nt, p.ft, p.nft, p.twt, 1.0);
+    double2* O = (R1 == A) ? Bf : A;
+    double* Od = reinterpret_cast<double*>(O);
+    double U, Om;
+    base_at(p, j, cw, sw, U, Om);
+    for (int t = threadIdx.x; t < ZB * nt; t += blockDim.x) {
+        const int zi = t / nt, th = t - zi * nt;
+        const double2 s0 = R1[(0 * ZB + zi) * nt + th];
+        const double2 s1 = R1[(1 * ZB + zi) * nt + th];
+        const double2 s2 = R1[(2 * ZB + zi) * nt + th];
+        const double ur = s0.x, ut = s0.y, uz = s1.x, wr = s1.y, wt = s2.x, wz = s2.y;
+        if (!adj) {
+            const double uzU = uz + U;
+            const double Nr = ut * wz - uzU * wt - uz * Om;
+            const double Nt = uzU * wr - ur * wz;
+            const double Nz = ur * (wt + Om) - ut * wr;
+            O[zi * nt + th] = make_double2(Nr, Nt);
+            const int q = ZB + (zi < H ? zi : zi - H);
+            Od[2 * (q * nt + th) + (zi < H ? 0 : 1)] = Nz;
+        } else {
+            const double2 s3 = R1[(3 * ZB + zi) * nt + th];
+            const double2 s4 = R1[(4 * ZB + (zi < H ? zi : zi - H)) * nt + th];
+            const double yr = s3.x, yt = s3.y, yz = (zi < H) ? s4.x : s4.y;
+            const double wtO = wt + Om, uzU = uz + U;
+            const double Ar = wtO * yz - wz * yt;
+            const double At = wz * yr - wr * yz;
+            const double Az = wr * yt - wtO * yr;
+            const double Br = yt * uzU - yz * ut;
+            const double Bt = yz * ur - yr * uzU;
+            const double Bz = yr * ut - yt * ur;
+            O[zi * nt + th] = make_double2(Ar, At);
+            O[(ZB + zi) * nt + th] = make_double2(Az, Br);
+            O[(2 * ZB + zi) * nt + th] = make_double2(Bt, Bz);
+        }
+    }
+    __syncthreads();
+    double2* R2 = fft_lds(O, R1, nout, nt, p.ft, p.nft, p.twt, -1.0);
+    for (int t = threadIdx.x; t < nfo * mp1 * ZB; t += blockDim.x) {
+        const int zi = t % ZB, m = (t / ZB) % mp1, f = t / (ZB * mp1);
+        int q, half;
+        if (!adj) {
+            if (f < 2) { q = zi; half = f; }
+            else { q = ZB + (zi < H ? zi : zi - H); half = (zi < H) ? 0 : 1; }
+        } else {
+            q = (f >> 1) * ZB + zi;
+            half = f & 1;
+        }
+        const double2 a = R2[q * nt + m];
+        const double2 b = cconj(R2[q * nt + (m == 0 ? 0 : nt - m)]);
+        double2 v;
+        if (half == 0) v = cscale(cadd(a, b), 0.5);
+        else v = cscale(cmuli(csub(b, a)), 0.5);          // (a - b) / (2i)
+        tb[((size_t)(j * nfo + f) * mp1 + m) * nz + z0 + zi] = v;
+    }
+}
+
+// ------------------------------------------------------ axial forward FFT
+__global__ void k_zfwd(KP p, int nfo, int G, const double2* __restrict__ tb, double2* __restrict__ out0,
+                       double2* __restrict__ out1, double scale) {
+    extern __shared__ double2 sh[];
+    const int m = blockIdx.x, j = blockIdx.y;
+    const int nz = p.nz, nk = p.nk, K = p.K;
+    double2* A = sh;
+    double2* Bf = sh + G * nz;
+    for (int f0 = 0; f0 < nfo; f0 += G) {
+        const int g = min(G, nfo - f0);
+        for (int t = threadIdx.x; t < g * nz; t += blockDim.x) {
+            const int fi = t / nz, z = t - fi * nz;
+            A[t] = tb[((size_t)(j * nfo + f0 + fi) * p.mp1 + m) * nz + z];
+        }
+        __syncthreads();
+        double2* res = fft_lds(A, Bf, g, nz, p.fz, p.nfz, p.twz, -1.0);
+        for (int t = threadIdx.x; t < g * nk; t += blockDim.x) {
+            const int fi = t / nk, kk = t - fi * nk, f = f0 + fi;
+            const int pos = kk <= K ? kk : nz - (nk - kk);
+            const double2 v = cscale(res[fi * nz + pos], scale);
+            if (f < 3) out0[fidx(p, f, j, m, kk)] = v;
+            else out1[fidx(p, f - 3, j, m, kk)] = v;
+        }
+        __syncthreads();
+    }
+}
+
+
+// ============================================ compile-time-sized transforms
+constexpr int TB = 256;   // threads per block of the transform kernels
+
+// Padded LDS index: one complex of padding per 16, so that the strided
+// accesses of the early Stockham passes spread over the LDS banks.
+__device__ __forceinline__ int lp(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int lp_size(int n) { return n + (n >> 4) + 1; }
+
+__host__ __device__ constexpr int pick_radix(int rem) {
+    return rem % 8 == 0 ? 8 : (rem % 4 == 0 ? 4 : (rem % 3 == 0 ? 3 : 2));
+}
+
+// a * w (forward) or a * conj(w) (inverse)
+template <bool INV>
+__device__ __forceinline__ double2 tw_mul(double2 a, double2 w) {
+    if (INV) return make_double2(a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y);
+    return make_double2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
+}
+// a * (-i) forward, a * i inverse: the quarter-turn of the length-4 DFT
+template <bool INV>
+__device__ __forceinline__ double2 qturn(double2 a) {
+    return INV ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft2(double2& a, double2& b) {
+    const double2 s = cadd(a, b), d = csub(a, b);
+    a = s; b = d;
+}
+template <bool INV>
+__device__ __forceinline__ void dft3(double2& a, double2& b, double2& c) {
+    constexpr double h = 0.86602540378443864676;   // sin(pi/3)
+    const double2 s = cadd(b, c), d = csub(b, c);
+    const double2 t0 = caxpy(a, -0.5, s);
+    const double2 t1 = cscale(qturn<INV>(d), h);     // -+ i sqrt(3)/2 (b - c)
+    a = cadd(a, s); b = cadd(t0, t1); c = csub(t0, t1);
+}
+template <bool INV>
+__device__ __forceinline__ void dft4(double2& a, double2& b, double2& c, double2& d) {
+    const double2 s02 = cadd(a, c), d02 = csub(a, c);
+    const double2 s13 = cadd(b, d), t13 = qturn<INV>(csub(b, d));
+    a = cadd(s02, s13); c = csub(s02, s13);
+    b = cadd(d02, t13); d = csub(d02, t13);
+}
+// length-8 DFT: two length-4 DFTs of the even and odd samples, odd half
+// rotated by w8^k = exp(-+ i pi k / 4)
+template <bool INV>
+__device__ __forceinline__ void dft8(double2* v) {
+    constexpr double s = 0.70710678118654752440;
+    dft4<INV>(v[0], v[2], v[4], v[6]);
+    dft4<INV>(v[1], v[3], v[5], v[7]);
+    const double2 o1 = v[3], o2 = v[5], o3 = v[7];
+    const double2 r1 = INV ? make_double2((o1.x - o1.y) * s, (o1.x + o1.y) * s)
+                           : make_double2((o1.x + o1.y) * s, (o1.y - o1.x) * s);
+    const double2 r2 = qturn<INV>(o2);
+    const double2 r3 = INV ? make_double2(-(o3.x + o3.y) * s, (o3.x - o3.y) * s)
+                           : make_double2((o3.y - o3.x) * s, -(o3.x + o3.y) * s);
+    const double2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6], o0 = v[1];
+    v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+    v[1] = cadd(e1, r1); v[5] = csub(e1, r1);
+    v[2] = cadd(e2, r2); v[6] = csub(e2, r2);
+    v[3] = cadd(e3, r3); v[7] = csub(e3, r3);
+}
+template <int R, bool INV>
+__device__ __forceinline__ void dft(double2* v) {
+    if constexpr (R == 2) dft2<INV>(v[0], v[1]);
+    else if constexpr (R == 3) dft3<INV>(v[0], v[1], v[2]);
+    else if constexpr (R == 4) dft4<INV>(v[0], v[1], v[2], v[3]);
+    else dft8<INV>(v);
+}
+
+// One Stockham autosort pass of radix R over B sequences of length N stored
+// back to back (padded index); NS = product of the radices already applied.
+// tw[t] = exp(-2 pi i t / N) in LDS.
+template <int N, int R, int NS, bool INV>
+__device__ __forceinline__ void stockham_pass(const double2* __restrict__ x, double2* __restrict__ y, int B,
+                                              const double2* __restrict__ tw) {
+    constexpr int nb = N / R;
+    constexpr int tws = N / (NS * R);
+    const int total = B * nb;
+    for (int t = threadIdx.x; t < total; t += TB) {
+        const int bi = t / nb;
+        const int jj = t - bi * nb;
+        const int k = jj % NS;
+        const int ib = bi * N + jj;
+        const int ob = bi * N + (jj - k) * R + k;
+        double2 v[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) v[q] = x[lp(ib + q * nb)];
+        if constexpr (NS > 1) {
+#pragma unroll
+            for (int q = 1; q < R; ++q) v[q] = tw_mul<INV>(v[q], tw[q * k * tws]);
+        }
+        dft<R, INV>(v);
+#pragma unroll
+        for (int q = 0; q < R; ++q) y[lp(ob + q * NS)] = v[q];
+    }
+}
+
+// B transforms of length N in LDS (a: data, b: scratch, both padded); the
+// passes end with a barrier.  Returns the buffer holding the result.
+template <int N, bool INV, int NS = 1>
+__device__ __forceinline__ double2* fft_ct(double2* a, double2* b, int B, const double2* tw) {
+    if constexpr (NS == N) {
+        return a;
+    } else {
+        constexpr int R = pick_radix(N / NS);
+        stockham_pass<N, R, NS, INV>(a, b, B, tw);
+        __syncthreads();
+        return fft_ct<N, INV, NS * R>(b, a, B, tw);
+    }
+}
+
+// Inverse axial transforms.  Fields: 0..2 u, 3 w_r (built from u), 4..5 aux,
+// 6..8 y; NF = 6 (forward term) or 9 (adjoint term).  G fields per round.
+template <int NZ, int NF>
+__global__ __launch_bounds__(TB) void k_zinv_t(KP p, int G, const double2* __restrict__ u,
+                                              const double2* __restrict__ aux, const double2* __restrict__ y,
+                                              double2* __restrict__ zb) {
+    constexpr int K = (NZ - 1) / 3, NK = 2 * K + 1;
+    extern __shared__ double2 sh[];
+    double2* tw = sh;
+    double2* A = sh + NZ;
+    double2* Bf = A + lp_size(G * NZ);
+    const int m = blockIdx.x, j = blockIdx.y, mp1 = p.mp1;
+    const double r = p.r[j];
+    for (int t = threadIdx.x; t < NZ; t += TB) tw[t] = p.twz[t];
+    for (int f0 = 0; f0 < NF; f0 += G) {
+        const int g = min(G, NF - f0);
+        for (int t = threadIdx.x; t < g * NZ; t += TB) {
+            const int fi = t / NZ, z = t - fi * NZ, f = f0 + fi;
+            const int kk = z <= K ? z : (z >= NZ - K ? z - NZ + NK : -1);
+            double2 v = czero();
+            if (kk >= 0) {
+                if (f < 3) {
+                    v = u[fidx(p, f, j, m, kk)];
+                } else if (f == 3) {
+                    const double a = alpha_of(p, kk);
+                    v = csub(cscale(cmuli(u[fidx(p, 2, j, m, kk)]), m / r),
+                             cscale(cmuli(u[fidx(p, 1, j, m, kk)]), a));
+                } else if (f < 6) {
+                    v = aux[fidx(p, f - 4, j, m, kk)];
+                } else {
+                    v = y[fidx(p, f - 6, j, m, kk)];
+                }
+            }
+            A[lp(t)] = v;
+        }
+        __syncthreads();
+        const double2* res = fft_ct<NZ, true>(A, Bf, g, tw);
+        for (int t = threadIdx.x; t < g * NZ; t += TB) {
+            const int fi = t / NZ, z = t - fi * NZ;
+            zb[((size_t)(j * NF + f0 + fi) * mp1 + m) * NZ + z] = res[lp(t)];
+        }
+        __syncthreads();
+    }
+}
+
+// Forward axial transforms of NFO theta-pass outputs, truncated to the band.
+template <int NZ, int NFO>
+__global__ __launch_bounds__(TB) void k_zfwd_t(KP p, int G, const double2* __restrict__ tb,
+                                              double2* __restrict__ out0, double2* __restrict__ out1, double scale) {
+    constexpr int K = (NZ - 1) / 3, NK = 2 * K + 1;
+    extern __shared__ double2 sh[];
+    double2* tw = sh;
+    double2* A = sh + NZ;
+    double2* Bf = A + lp_size(G * NZ);
+    const int m = blockIdx.x, j = blockIdx.y, mp1 = p.mp1;
+    for (int t = threadIdx.x; t < NZ; t += TB) tw[t] = p.twz[t];
+    for (int f0 = 0; f0 < NFO; f0 += G) {
+        const int g = min(G, NFO - f0);
+        for (int t = threadIdx.x; t < g * NZ; t += TB) {
+            const int fi = t / NZ, z = t - fi * NZ;
+            A[lp(t)] = tb[((size_t)(j * NFO + f0 + fi) * mp1 + m) * NZ + z];
+        }
+        __syncthreads();
+        const double2* res = fft_ct<NZ, false>(A, Bf, g, tw);
+        for (int t = threadIdx.x; t < g * NK; t += TB) {
+            const int fi = t / NK, kk = t - fi * NK, f = f0 + fi;
+            const int pos = kk <= K ? kk : NZ - (NK - kk);
+            const double2 v = cscale(res[lp(fi * NZ + pos)], scale);
+            if (f < 3) out0[fidx(p, f, j, m, kk)] = v;
+            else out1[fidx(p, f - 3, j, m, kk)] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// Azimuthal transforms and products for a block of ZB = 2^lzb consecutive z
+// at node j.  Blocks are placed so that consecutive z-blocks of one j run on
+// the same XCD (hardware round-robin over 8 XCDs by workgroup id), where they
+// share L2 lines of the [j][f][m][z] intermediates.
+template <int NT, int ADJ>
+__global__ __launch_bounds__(TB) void k_theta_t(KP p, int lzb, int nzb, const double2* __restrict__ zb,
+                                               double2* __restrict__ tb, double cw, double sw) {
+    constexpr int M = (NT - 1) / 3, MP1 = M + 1;
+    constexpr int NF = ADJ ? 9 : 6, NFO = ADJ ? 6 : 3;
+    const int nblk = nzb * p.nr;
+    const int per = (nblk + 7) >> 3;
+    const int L = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (L >= nblk) return;
+    const int j = L / nzb, z0 = (L - j * nzb) << lzb;
+    const int ZB = 1 << lzb, H = ZB >> 1, nz = p.nz;
+    const int nin = ADJ ? 4 * ZB + H : 3 * ZB;
+    const int nout = ADJ ? 3 * ZB : ZB + H;
+    const int nseq = nin > nout ? nin : nout;
+    extern __shared__ double2 sh[];
+    double2* tw = sh;
+    double2* A = sh + NT;
+    double2* Bf = A + lp_size(nseq * NT);
+    for (int t = threadIdx.x; t < NT; t += TB) tw[t] = p.twt[t];
+    // zero the unretained azimuthal band of every input sequence
+    constexpr int NGAP = NT - 2 * M - 1;
+    if constexpr (NGAP > 0) {
+        for (int t = threadIdx.x; t < nin * NGAP; t += TB) {
+            const int s = t / NGAP, q = t - s * NGAP;
+            A[lp(s * NT + M + 1 + q)] = czero();
+        }
+    }
+    // pairs of real fields packed as xa + i xb
+    constexpr int NPAIR = ADJ ? 4 : 3;
+    for (int t = threadIdx.x; t < (NPAIR * MP1) << lzb; t += TB) {
+        const int zi = t & (ZB - 1), q = t >> lzb;
+        const int pi = q / MP1, m = q - pi * MP1;
+        const double2 xa = zb[((size_t)(j * NF + 2 * pi) * MP1 + m) * nz + z0 + zi];
+        const double2 xb = zb[((size_t)(j * NF + 2 * pi + 1) * MP1 + m) * nz + z0 + zi];
+        const int s = (pi * ZB + zi) * NT;
+        if (m == 0) {
+            A[lp(s)] = make_double2(xa.x, xb.x);
+        } else {
+            A[lp(s + m)] = make_double2(xa.x - xb.y, xa.y + xb.x);
+            A[lp(s + NT - m)] = make_double2(xa.x + xb.y, -xa.y + xb.x);
+        }
+    }
+    if constexpr (ADJ) {   // y_z: pairs of z columns (zi, zi + H)
+        for (int t = threadIdx.x; t < H * MP1; t += TB) {
+            const int m = t / H, zi = t - m * H;
+            const double2 xa = zb[((size_t)(j * NF + 8) * MP1 + m) * nz + z0 + zi];
+            const double2 xb = zb[((size_t)(j * NF + 8) * MP1 + m) * nz + z0 + zi + H];
+            const int s = (4 * ZB + zi) * NT;
+            if (m == 0) {
+                A[lp(s)] = make_double2(xa.x, xb.x);
+            } else {
+                A[lp(s + m)] = make_double2(xa.x - xb.y, xa.y + xb.x);
+                A[lp(s + NT - m)] = make_double2(xa.x + xb.y, -xa.y + xb.x);
+            }
+        }
+    }
+    __syncthreads();
+    double2* R1 = fft_ct<NT, true>(A, Bf, nin, tw);
+    double2* O = (R1 == A) ? Bf : A;
+    double U, Om;
+    base_at(p, j, cw, sw, U, Om);
+    for (int t = threadIdx.x; t < ZB * NT; t += TB) {
+        const int zi = t / NT, th = t - zi * NT;
+        const double2 s0 = R1[lp((0 * ZB + zi) * NT + th)];
+        const double2 s1 = R1[lp((1 * ZB + zi) * NT + th)];
+        const double2 s2 = R1[lp((2 * ZB + zi) * NT + th)];
+        const double ur = s0.x, ut = s0.y, uz = s1.x, wr = s1.y, wt = s2.x, wz = s2.y;
+        if constexpr (!ADJ) {
+            const double uzU = uz + U;
+            const double Nr = ut * wz - uzU * wt - uz * Om;
+            const double Nt = uzU * wr - ur * wz;
+            const double Nz = ur * (wt + Om) - ut * wr;
+            O[lp(zi * NT + th)] = make_double2(Nr, Nt);
+            // N_z of columns zi and zi + H share one complex sequence
+            const int q = ZB + (zi < H ? zi : zi - H);
+            double* slot = reinterpret_cast<double*>(&O[lp(q * NT + th)]);
+            slot[zi < H ? 0 : 1] = Nz;
+        } else {
+            const double2 s3 = R1[lp((3 * ZB + zi) * NT + th)];
+            const double2 s4 = R1[lp((4 * ZB + (zi < H ? zi : zi - H)) * NT + th)];
+            const double yr = s3.x, yt = s3.y, yz = (zi < H) ? s4.x : s4.y;
+            const double wtO = wt + Om, uzU = uz + U;
+            const double Ar = wtO * yz - wz * yt;
+            const double At = wz * yr - wr * yz;
+            const double Az = wr * yt - wtO * yr;
+            const double Br = yt * uzU - yz * ut;
+            const double Bt = yz * ur - yr * uzU;
+            const double Bz = yr * ut - yt * ur;
+            O[lp(zi * NT + th)] = make_double2(Ar, At);
+            O[lp((ZB + zi) * NT + th)] = make_double2(Az, Br);
+            O[lp((2 * ZB + zi) * NT + th)] = make_double2(Bt, Bz);
+        }
+    }
+    __syncthreads();
+    const double2* R2 = fft_ct<NT, false>(O, R1, nout, tw);
+    for (int t = threadIdx.x; t < (NFO * MP1) << lzb; t += TB) {
+        const int zi = t & (ZB - 1), q0 = t >> lzb;
+        const int f = q0 / MP1, m = q0 - f * MP1;
+        int q, half;
+        if constexpr (!ADJ) {
+            if (f < 2) { q = zi; half = f; }
+            else { q = ZB + (zi < H ? zi : zi - H); half = (zi < H) ? 0 : 1; }
+        } else {
+            q = (f >> 1) * ZB + zi;
+            half = f & 1;
+        }
+        // unpack the two real transforms sharing sequence q
+        const double2 a = R2[lp(q * NT + m)];
+        const double2 b = cconj(R2[lp(q * NT + (m == 0 ? 0 : NT - m))]);
+        const double2 v = half == 0 ? cscale(cadd(a, b), 0.5) : cscale(cmuli(csub(b, a)), 0.5);
+        tb[((size_t)(j * NFO + f) * MP1 + m) * nz + z0 + zi] = v;
+    }
+}
+
+// ---------------------------------------------------------------- dispatch
+#define NPO_NZ_SIZES(X) X(24) X(48) X(96) X(144) X(192) X(288) X(384) X(576) X(768) X(1024) X(1536)
+#define NPO_NT_SIZES(X) X(12) X(24) X(48) X(64) X(96) X(128)
+
+bool fast_nz(int nz) {
+    switch (nz) {
+#define NPO_CASE(N) case N:
+        NPO_NZ_SIZES(NPO_CASE)
+#undef NPO_CASE
+        return true;
+    default:
+        return false;
+    }
+}
+bool fast_nt(int nt) {
+    switch (nt) {
+#define NPO_CASE(N) case N:
+        NPO_NT_SIZES(NPO_CASE)
+#undef NPO_CASE
+        return true;
+    default:
+        return false;
+    }
+}
+
+size_t zpass_lds(const npo_plan_s& p, int G) {
+    if (fast_nz(p.nz)) return ((size_t)p.nz + 2 * lp_size(G * p.nz)) * sizeof(double2);
+    return (size_t)2 * G * p.nz * sizeof(double2);
+}
+size_t theta_lds(const npo_plan_s& p, int ZB, int adj) {
+    const int H = ZB / 2;
+    const int nin = adj ? 4 * ZB + H : 3 * ZB, nout = adj ? 3 * ZB : ZB + H;
+    const int nseq = nin > nout ? nin : nout;
+    if (fast_nt(p.nt)) return ((size_t)p.nt + 2 * lp_size(nseq * p.nt)) * sizeof(double2);
+    return (size_t)2 * nseq * p.nt * sizeof(double2);
+}
+
+static void launch_zinv(const npo_plan_s& p, int adj, const double2* u, const double2* aux, const double2* y,
+                        double2* zb, hipStream_t st) {
+    const int G = p.zgroup;
+    const size_t sh = zpass_lds(p, G);
+    const dim3 grid(p.mp1, p.nr);
+    switch (p.nz) {
+#define NPO_CASE(N)                                                                                  \
+    case N:                                                                                          \
+        if (adj) hipLaunchKernelGGL((k_zinv_t<N, 9>), grid, dim3(TB), sh, st, p.kp, G, u, aux, y, zb); \
+        else hipLaunchKernelGGL((k_zinv_t<N, 6>), grid, dim3(TB), sh, st, p.kp, G, u, aux, y, zb);      \
+        return;
+        NPO_NZ_SIZES(NPO_CASE)
+#undef NPO_CASE
+    default:
+        hipLaunchKernelGGL(k_zinv, grid, dim3(256), sh, st, p.kp, adj ? 9 : 6, G, u, aux, y, zb);
+    }
+}
+
+static void launch_zfwd(const npo_plan_s& p, int adj, const double2* tb, double2* out0, double2* out1,
+                        double scale, hipStream_t st) {
+    const int G = p.zgroup;
+    const size_t sh = zpass_lds(p, G);
+    const dim3 grid(p.mp1, p.nr);
+    switch (p.nz) {
+#define NPO_CASE(N)                                                                                         \
+    case N:                                                                                                 \
+        if (adj) hipLaunchKernelGGL((k_zfwd_t<N, 6>), grid, dim3(TB), sh, st, p.kp, G, tb, out0, out1, scale); \
+        else hipLaunchKernelGGL((k_zfwd_t<N, 3>), grid, dim3(TB), sh, st, p.kp, G, tb, out0, out1, scale);     \
+        return;
+        NPO_NZ_SIZES(NPO_CASE)
+#undef NPO_CASE
+    default:
+        hipLaunchKernelGGL(k_zfwd, grid, dim3(256), sh, st, p.kp, adj ? 6 : 3, G, tb, out0, out1, scale);
+    }
+}
+
+static void launch_theta(const npo_plan_s& p, int adj, const double2* zb, double2* tb, double cw, double sw,
+                         hipStream_t st) {
+    const int ZB = adj ? p.zb_theta_adj : p.zb_theta_fwd;
+    const size_t sh = theta_lds(p, ZB, adj);
+    int lzb = 0;
+    while ((1 << lzb) < ZB) ++lzb;
+    const int nzb = p.nz / ZB;
+    const int nblk = nzb * p.nr;
+    const dim3 grid((nblk + 7) / 8 * 8);
+    switch (p.nt) {
+#define NPO_CASE(N)                                                                                          \
+    case N:                                                                                                  \
+        if (adj) hipLaunchKernelGGL((k_theta_t<N, 1>), grid, dim3(TB), sh, st, p.kp, lzb, nzb, zb, tb, cw, sw); \
+        else hipLaunchKernelGGL((k_theta_t<N, 0>), grid, dim3(TB), sh, st, p.kp, lzb, nzb, zb, tb, cw, sw);     \
+        return;
+        NPO_NT_SIZES(NPO_CASE)
+#undef NPO_CASE
+    default:
+        hipLaunchKernelGGL(k_theta, dim3(nzb, p.nr), dim3(256), sh, st, p.kp, adj, ZB, zb, tb, cw, sw);
+    }
+}
+
+// ---------------------------------------------------------------- launcher
+hipError_t launch_nl(const npo_plan_s& p, int adj, const double2* u, const double2* aux, const double2* y,
+                     double t, double2* out0, double2* out1, void* ws, hipStream_t st) {
+    char* base = static_cast<char*>(ws);
+    double2* zb = reinterpret_cast<double2*>(base + p.ws.zbuf);
+    double2* tb = reinterpret_cast<double2*>(base + p.ws.tbuf);
+    prof_begin(p, adj ? KID_ZINV_A : KID_ZINV_F, st);
+    launch_zinv(p, adj, u, aux, y, zb, st);
+    prof_end(p, adj ? KID_ZINV_A : KID_ZINV_F, st);
+    const double cw = cos(p.omega * t), sw = sin(p.omega * t);
+    prof_begin(p, adj ? KID_THETA_A : KID_THETA_F, st);
+    launch_theta(p, adj, zb, tb, cw, sw, st);
+    prof_end(p, adj ? KID_THETA_A : KID_THETA_F, st);
+    const double scale = 1.0 / ((double)p.nt * p.nz);
+    prof_begin(p, adj ? KID_ZFWD_A : KID_ZFWD_F, st);
+    launch_zfwd(p, adj, tb, out0, out1, scale, st);
+    prof_end(p, adj ? KID_ZFWD_A : KID_ZFWD_F, st);
+    return hipGetLastError();
+}
+
+}  // namespace npo
