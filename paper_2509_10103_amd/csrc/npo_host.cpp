@@ -461,8 +461,9 @@ npo_status npo_plan_create(const npo_grid* grid, const npo_flow* flow, const npo
         delete p;
         return fail(NPO_EUNSUPPORTED, "too many FFT factors");
     }
-    // device tables: r, w, D1, D2 (doubles), Ut, dUt, twz, twt (double2), col0 (int)
-    const size_t nd = nr + nr + 3 * (2 * nr * 7);
+    // device tables: r, w, D1, D2, B (doubles), their transposed 13-tap forms,
+    // Ut, dUt, twz, twt (double2), col0 (int)
+    const size_t nd = nr + nr + 3 * (2 * nr * 7) + 3 * (2 * nr * npo::TAPS);
     const size_t nc = nr + nr + nz + nt;
     const size_t bytes = align256(nd * 8) + align256(nc * 16) + align256(nr * 4);
     if (hipMalloc(&p->d_tables, bytes) != hipSuccess) {
@@ -482,6 +483,28 @@ npo_status npo_plan_create(const npo_grid* grid, const npo_flow* flow, const npo
             for (int t = 0; t < 7; ++t)
                 hd[o_b + (pi * nr + j) * 7 + t] = p->D2[(pi * nr + j) * 7 + t] + p->D1[(pi * nr + j) * 7 + t] / p->r[j];
     o += 2 * nr * 7;
+    // transposed stencils: entry s of column j is the weight of row i = j - 6 + s
+    // (zero where row i's stencil does not reach j); D1T plain, D1WT and BWT
+    // with the row's quadrature weight w_i folded in.
+    const size_t o_d1t = o, o_d1wt = o + 2 * nr * npo::TAPS, o_bwt = o + 4 * nr * npo::TAPS;
+    for (int pi = 0; pi < 2; ++pi)
+        for (int j = 0; j < nr; ++j)
+            for (int s = 0; s < npo::TAPS; ++s) {
+                const int i = j - 6 + s;
+                double d1 = 0.0, bb = 0.0;
+                if (i >= 0 && i < nr) {
+                    const int t = j - p->col0[i];
+                    if (t >= 0 && t < 7) {
+                        d1 = p->D1[(pi * nr + i) * 7 + t];
+                        bb = hd[o_b + (pi * nr + i) * 7 + t];
+                    }
+                }
+                const size_t e = (size_t)(pi * nr + j) * npo::TAPS + s;
+                hd[o_d1t + e] = d1;
+                hd[o_d1wt + e] = (i >= 0 && i < nr) ? d1 * p->w[i] : 0.0;
+                hd[o_bwt + e] = (i >= 0 && i < nr) ? bb * p->w[i] : 0.0;
+            }
+    o += 6 * nr * npo::TAPS;
     const size_t cbase = align256(nd * 8);
     double2* hc = reinterpret_cast<double2*>(host.data() + cbase);
     const ld pi = acosl(-1.0L);
@@ -505,6 +528,7 @@ npo_status npo_plan_create(const npo_grid* grid, const npo_flow* flow, const npo
     kp.nr = nr; kp.nt = nt; kp.nz = nz; kp.M = p->M; kp.K = p->K; kp.nk = p->nk; kp.mp1 = p->mp1;
     kp.k0 = p->k0; kp.re = p->re; kp.dt = p->dt; kp.lz = p->lz;
     kp.r = dd + o_r; kp.w = dd + o_w; kp.D1 = dd + o_d1; kp.D2 = dd + o_d2; kp.B = dd + o_b;
+    kp.D1T = dd + o_d1t; kp.D1WT = dd + o_d1wt; kp.BWT = dd + o_bwt;
     kp.col0 = reinterpret_cast<const int*>(reinterpret_cast<const char*>(p->d_tables) + ibase);
     kp.Ut = dc; kp.dUt = dc + nr; kp.twz = dc + 2 * nr; kp.twt = dc + 2 * nr + nz;
     kp.nfz = (int)fz.size(); kp.nft = (int)ft.size();

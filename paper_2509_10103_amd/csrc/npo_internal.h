@@ -26,6 +26,7 @@ struct Profiler {
 
 constexpr int NR_MAX = 64;     // radial nodes handled by one workgroup
 constexpr int NFAC_MAX = 8;    // radix factors of an FFT length
+constexpr int TAPS = 13;       // taps of a transposed 7-point stencil (rows j-6 .. j+6)
 
 // Per-plan constants handed to every kernel by value.
 struct KP {
@@ -37,6 +38,9 @@ struct KP {
     const double* D1;     // [2][nr][7] parity 0 = even, 1 = odd
     const double* D2;     // [2][nr][7]
     const double* B;      // [2][nr][7] D2 + D1 / r_j
+    const double* D1T;    // [2][nr][TAPS] D1 transposed: tap s of column j = D1[i][j], i = j - 6 + s
+    const double* D1WT;   // [2][nr][TAPS] the same with w_i folded in
+    const double* BWT;    // [2][nr][TAPS] B transposed with w_i folded in
     const int* col0;      // [nr] first column of each 7-point row
     const double2* Ut;    // [nr] Womersley amplitude
     const double2* dUt;   // [nr] its radial derivative

@@ -146,16 +146,15 @@ __device__ __forceinline__ double fd_apply_r(const KP& p, const double* D, int p
     for (int t = 0; t < 7; ++t) s = fma(d[t], x[c0 + t], s);
     return s;
 }
-// (D^T x)[j] restricted to rows i < rows_lim of D.
-__device__ __forceinline__ double2 fd_apply_T(const KP& p, const double* D, int pi, int j, const double2* x,
-                                              int rows_lim) {
+
+// Transposed stencil from a 13-tap table T ([2][nr][TAPS]): sum over rows
+// i = j - 6 + s inside [0, nr) of T[pi][j][s] * x[i * st].
+__device__ __forceinline__ double2 taps13(const KP& p, const double* T, int pi, int j, const double2* x, int st) {
+    const double* t = T + (size_t)(pi * p.nr + j) * TAPS;
+    const int lo = j < 6 ? 6 - j : 0;
+    const int hi = j + 6 >= p.nr ? p.nr + 5 - j : TAPS - 1;
     double2 s = czero();
-    const int lo = j - 6 < 0 ? 0 : j - 6;
-    const int hi = j + 6 < rows_lim - 1 ? j + 6 : rows_lim - 1;
-    for (int i = lo; i <= hi; ++i) {
-        const int t = j - p.col0[i];
-        if (t >= 0 && t < 7) s = caxpy(s, D[(pi * p.nr + i) * 7 + t], x[i]);
-    }
+    for (int k = lo; k <= hi; ++k) s = caxpy(s, t[k], x[(j - 6 + k) * st]);
     return s;
 }
 
@@ -217,31 +216,42 @@ __global__ __launch_bounds__(RT) void k_solve(KP p, int kind, const double2* __r
     __shared__ double2 sp[NR_MAX][RQ];
     __shared__ double2 sa[RQ];
 
-    // R = E u^n + N in the (+, -, z) basis (kind 0: R = a)
+    // u (kind 0: R) in the (+, -, z) basis, staged in LDS
     for (int j = jg; j < nr; j += RJ) {
-        double2 Rp = czero(), Rm = czero(), Rz = czero();
+        double2 up = czero(), um = czero(), uz = czero();
         if (sl.valid) {
-            const int kk = sl.kk;
-            const double2 ur = ain[fidx(p, 0, j, m, kk)], ut = ain[fidx(p, 1, j, m, kk)];
-            const double2 uz = ain[fidx(p, 2, j, m, kk)];
-            if (kind == 0) {
-                Rp = cadd(ur, cmuli(ut));
-                Rm = csub(ur, cmuli(ut));
-                Rz = uz;
-            } else {
+            const double2 ur = ain[fidx(p, 0, j, m, sl.kk)], ut = ain[fidx(p, 1, j, m, sl.kk)];
+            uz = ain[fidx(p, 2, j, m, sl.kk)];
+            up = cadd(ur, cmuli(ut));
+            um = csub(ur, cmuli(ut));
+        }
+        sR[0][j][q] = up;
+        sR[1][j][q] = um;
+        sR[2][j][q] = uz;
+    }
+    __syncthreads();
+    if (kind != 0) {
+        // R = E u^n + N: stencils read from LDS, results held in registers
+        // until every lane has read its neighbours
+        double2 Rv[NR_MAX / RJ][3];
+#pragma unroll
+        for (int jj = 0; jj < NR_MAX / RJ; ++jj) {
+            const int j = jg + jj * RJ;
+            Rv[jj][0] = Rv[jj][1] = Rv[jj][2] = czero();
+            if (j < nr && sl.valid) {
+                const int kk = sl.kk;
                 const double rj = p.r[j];
                 const int c0 = p.col0[j];
                 const double* bo = p.B + (po * nr + j) * 7;
                 const double* be = p.B + (pe * nr + j) * 7;
                 double2 lp = czero(), lm = czero(), lz = czero();
+#pragma unroll
                 for (int s = 0; s < 7; ++s) {
-                    const double2 vr = ain[fidx(p, 0, c0 + s, m, kk)], vt = ain[fidx(p, 1, c0 + s, m, kk)];
-                    const double2 vz = ain[fidx(p, 2, c0 + s, m, kk)];
-                    lp = caxpy(lp, bo[s], cadd(vr, cmuli(vt)));
-                    lm = caxpy(lm, bo[s], csub(vr, cmuli(vt)));
-                    lz = caxpy(lz, be[s], vz);
+                    lp = caxpy(lp, bo[s], sR[0][c0 + s][q]);
+                    lm = caxpy(lm, bo[s], sR[1][c0 + s][q]);
+                    lz = caxpy(lz, be[s], sR[2][c0 + s][q]);
                 }
-                const double2 up = cadd(ur, cmuli(ut)), um = csub(ur, cmuli(ut));
+                const double2 up = sR[0][j][q], um = sR[1][j][q], uz = sR[2][j][q];
                 const double ia = 1.0 / (rj * rj);
                 lp = caxpy(lp, -((double)((m + 1) * (m + 1)) * ia + a2), up);
                 lm = caxpy(lm, -((double)((m - 1) * (m - 1)) * ia + a2), um);
@@ -254,16 +264,23 @@ __global__ __launch_bounds__(RT) void k_solve(KP p, int kind, const double2* __r
                     Nt = cscale(cadd(Nt, cin[fidx(p, 1, j, m, kk)]), 0.5);
                     Nz = cscale(cadd(Nz, cin[fidx(p, 2, j, m, kk)]), 0.5);
                 }
-                Rp = cadd(caxpy(cscale(up, idt), re2, lp), cadd(Nr, cmuli(Nt)));
-                Rm = cadd(caxpy(cscale(um, idt), re2, lm), csub(Nr, cmuli(Nt)));
-                Rz = cadd(caxpy(cscale(uz, idt), re2, lz), Nz);
+                Rv[jj][0] = cadd(caxpy(cscale(up, idt), re2, lp), cadd(Nr, cmuli(Nt)));
+                Rv[jj][1] = cadd(caxpy(cscale(um, idt), re2, lm), csub(Nr, cmuli(Nt)));
+                Rv[jj][2] = cadd(caxpy(cscale(uz, idt), re2, lz), Nz);
             }
         }
-        sR[0][j][q] = Rp;
-        sR[1][j][q] = Rm;
-        sR[2][j][q] = Rz;
+        __syncthreads();
+#pragma unroll
+        for (int jj = 0; jj < NR_MAX / RJ; ++jj) {
+            const int j = jg + jj * RJ;
+            if (j < nr) {
+                sR[0][j][q] = Rv[jj][0];
+                sR[1][j][q] = Rv[jj][1];
+                sR[2][j][q] = Rv[jj][2];
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
     // particular pressure: P_m p = div R on interior nodes, p(1) = 0 (zero for the mean mode)
     for (int j = jg; j < nr; j += RJ) {
         double2 d = czero();
@@ -378,51 +395,18 @@ __global__ __launch_bounds__(RT) void k_solve(KP p, int kind, const double2* __r
     }
 }
 
-// (D^T x)[j] for x stored with stride st (rows i < rows_lim of D).
-__device__ __forceinline__ double2 fd_apply_Ts(const KP& p, const double* D, int pi, int j, const double2* x, int st,
-                                               int rows_lim) {
-    double2 s = czero();
-    const int lo = j - 6 < 0 ? 0 : j - 6;
-    const int hi = j + 6 < rows_lim - 1 ? j + 6 : rows_lim - 1;
-    for (int i = lo; i <= hi; ++i) {
-        const int t = j - p.col0[i];
-        if (t >= 0 && t < 7) s = caxpy(s, D[(pi * p.nr + i) * 7 + t], x[i * st]);
-    }
-    return s;
-}
 
-// curl^H (W b) at row j read straight from a global field b of mode (m, kk).
-__device__ __forceinline__ void curlH_row_g(const KP& p, int m, int kk, double al, int j, const double2* __restrict__ b,
-                                            double2& cr, double2& ct, double2& cz) {
-    const double rj = p.r[j], wj = p.w[j];
-    const int pe = m & 1, po = (m + 1) & 1;
-    const double2 br = cscale(b[fidx(p, 0, j, m, kk)], wj), bt = cscale(b[fidx(p, 1, j, m, kk)], wj);
-    const double2 bz = cscale(b[fidx(p, 2, j, m, kk)], wj);
-    double2 dz = czero(), dt = czero();
-    const int lo = j - 6 < 0 ? 0 : j - 6;
-    const int hi = j + 6 < p.nr - 1 ? j + 6 : p.nr - 1;
-    for (int i = lo; i <= hi; ++i) {
-        const int s = j - p.col0[i];
-        if (s < 0 || s >= 7) continue;
-        const double wi = p.w[i];
-        dz = caxpy(dz, p.D1[(po * p.nr + i) * 7 + s] * wi, b[fidx(p, 2, i, m, kk)]);
-        dt = caxpy(dt, p.D1[(pe * p.nr + i) * 7 + s] * wi, b[fidx(p, 1, i, m, kk)]);
-    }
-    cr = cadd(cscale(cmuli(bt), -al), cscale(cmuli(bz), m / rj));
-    ct = cadd(cadd(cscale(cmuli(br), al), dz), cscale(bz, 1.0 / rj));
-    cz = csub(cscale(cmuli(br), -m / rj), dt);
-}
 
-// curl^H b at row j (b already W-weighted, rows strided by st), for mode index
-// m and axial wavenumber al.
+// curl^H (W b) at row j for b in LDS (rows strided by st), mode index m and
+// axial wavenumber al.
 __device__ __forceinline__ void curlH_row(const KP& p, int m, double al, int j, const double2* br, const double2* bt,
                                           const double2* bz, int st, double2& cr, double2& ct, double2& cz) {
-    const double rj = p.r[j];
+    const double rj = p.r[j], wj = p.w[j];
     const int pe = m & 1, po = (m + 1) & 1;
-    cr = cadd(cscale(cmuli(bt[j * st]), -al), cscale(cmuli(bz[j * st]), m / rj));
-    ct = cadd(cadd(cscale(cmuli(br[j * st]), al), fd_apply_Ts(p, p.D1, po, j, bz, st, p.nr)),
-              cscale(bz[j * st], 1.0 / rj));
-    cz = csub(cscale(cmuli(br[j * st]), -m / rj), fd_apply_Ts(p, p.D1, pe, j, bt, st, p.nr));
+    const double2 wr = cscale(br[j * st], wj), wt = cscale(bt[j * st], wj), wz = cscale(bz[j * st], wj);
+    cr = cadd(cscale(cmuli(wt), -al), cscale(cmuli(wz), m / rj));
+    ct = cadd(cadd(cscale(cmuli(wr), al), taps13(p, p.D1WT, po, j, bz, st)), cscale(wz, 1.0 / rj));
+    cz = csub(cscale(cmuli(wr), -m / rj), taps13(p, p.D1WT, pe, j, bt, st));
 }
 
 // ------------------------------------------------------------ adjoint solve
@@ -456,20 +440,35 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
     __shared__ double2 sa[RQ];
     const bool useB = Bin != nullptr;
 
-    for (int j = jg; j < nr; j += RJ) {
-        double2 v[3] = {czero(), czero(), czero()};
-        if (sl.valid) {
-            for (int c = 0; c < 3; ++c) v[c] = cscale(Ain[fidx(p, c, j, m, sl.kk)], ca);
+    // v = ca A + cb W^{-1} curl^H (W B); B staged in LDS for the stencils
+    if (useB) {
+        for (int j = jg; j < nr; j += RJ)
+            for (int c = 0; c < 3; ++c) sy[c][j][q] = sl.valid ? Bin[fidx(p, c, j, m, sl.kk)] : czero();
+        __syncthreads();
+    }
+    double2 V[NR_MAX / RJ][3];
+#pragma unroll
+    for (int jj = 0; jj < NR_MAX / RJ; ++jj) {
+        const int j = jg + jj * RJ;
+        V[jj][0] = V[jj][1] = V[jj][2] = czero();
+        if (j < nr && sl.valid) {
+            for (int c = 0; c < 3; ++c) V[jj][c] = cscale(Ain[fidx(p, c, j, m, sl.kk)], ca);
             if (useB) {
-                const double iw = cb / p.w[j];
                 double2 cr, ct, cz;
-                curlH_row_g(p, m, sl.kk, sl.al, j, Bin, cr, ct, cz);
-                v[0] = caxpy(v[0], iw, cr);
-                v[1] = caxpy(v[1], iw, ct);
-                v[2] = caxpy(v[2], iw, cz);
+                curlH_row(p, m, sl.al, j, &sy[0][0][q], &sy[1][0][q], &sy[2][0][q], RQ, cr, ct, cz);
+                const double iw = cb / p.w[j];
+                V[jj][0] = caxpy(V[jj][0], iw, cr);
+                V[jj][1] = caxpy(V[jj][1], iw, ct);
+                V[jj][2] = caxpy(V[jj][2], iw, cz);
             }
         }
-        for (int c = 0; c < 3; ++c) sy[c][j][q] = v[c];
+    }
+    if (useB) __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < NR_MAX / RJ; ++jj) {
+        const int j = jg + jj * RJ;
+        if (j < nr)
+            for (int c = 0; c < 3; ++c) sy[c][j][q] = V[jj][c];
     }
     __syncthreads();
     // y = W lambda on interior rows (the solve's wall output is identically zero)
@@ -534,12 +533,8 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
         double2 qv = czero();
         if (j < N1 && sl.valid && !sl.mean) {
             const double mr = m / p.r[j];
-            const int lo = j - 6 < 0 ? 0 : j - 6;
-            const int hi = j + 6 < N1 - 1 ? j + 6 : N1 - 1;
-            for (int i = lo; i <= hi; ++i) {
-                const int s = j - p.col0[i];
-                if (s >= 0 && s < 7) qv = caxpy(qv, p.D1[(pe * nr + i) * 7 + s], cadd(sy[0][i][q], sy[1][i][q]));
-            }
+            // rows >= N1 of sy are zero, so the full transposed stencil applies
+            qv = cadd(taps13(p, p.D1T, pe, j, &sy[0][0][q], RQ), taps13(p, p.D1T, pe, j, &sy[1][0][q], RQ));
             qv = caxpy(qv, -mr, csub(sy[0][j][q], sy[1][j][q]));
             qv = csub(qv, cscale(cmuli(sy[2][j][q]), sl.al));
         }
@@ -564,7 +559,7 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
             mv[1] = (j < N1) ? cscale(sy[1][j][q], iw) : czero();
             mv[2] = (j < N1) ? cscale(sy[2][j][q], iw) : czero();
         } else {
-            const double2 DT = fd_apply_Ts(p, p.D1, po, j, &sphi[0][q], RQ, N1);
+            const double2 DT = taps13(p, p.D1T, po, j, &sphi[0][q], RQ);   // sphi[N1] = 0
             const double2 ph = (j < N1) ? sphi[j][q] : czero();
             const double2 wp = (j < N1) ? sy[0][j][q] : czero();
             const double2 wm = (j < N1) ? sy[1][j][q] : czero();
@@ -581,9 +576,8 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
 }
 
 // ----------------------------------------------- adjoint combine (E^dag etc.)
-// out = E^dag Z + A + curl^dag B  (Z, A, B optional).  Every transposed
-// stencil reads neighbouring rows straight from global memory (the same
-// lines serve the lanes of neighbouring rows).
+// out = E^dag Z + A + curl^dag B  (Z, A, B optional).  Z, then B, is staged in
+// LDS and every transposed stencil reads it there through the 13-tap tables.
 __global__ __launch_bounds__(RT) void k_final(KP p, const double2* __restrict__ Z, const double2* __restrict__ Ain,
                                               const double2* __restrict__ Bin, double2* __restrict__ out) {
     int g, m;
@@ -591,52 +585,74 @@ __global__ __launch_bounds__(RT) void k_final(KP p, const double2* __restrict__ 
     const int t = threadIdx.x, q = t % RQ, jg = t / RQ;
     const int nr = p.nr;
     const Slot sl = slot_of(p, g, m, q);
-    if (!sl.valid) return;
     const int kk = sl.kk;
     const double a2 = sl.al * sl.al;
     const double re2 = 0.5 / p.re, idt = 1.0 / p.dt;
     const int pe = m & 1, po = (m + 1) & 1;
-    for (int j = jg; j < nr; j += RJ) {
-        const double rc = p.r[j];
-        const double iw = 1.0 / p.w[j];
-        double2 er = czero(), et = czero(), ez = czero();
-        if (Z) {
-            // E_n^T column j applied to (W Z) in the +- basis: sum_i E_n[i][j] v_i
-            const int lo = j - 6 < 0 ? 0 : j - 6;
-            const int hi = j + 6 < nr - 1 ? j + 6 : nr - 1;
-            double2 ep = czero(), em = czero();
-            for (int i = lo; i <= hi; ++i) {
-                const int s = j - p.col0[i];
-                if (s < 0 || s >= 7) continue;
-                const double ri = p.r[i], wi = p.w[i];
-                const double wo = re2 * (p.D2[(po * nr + i) * 7 + s] + p.D1[(po * nr + i) * 7 + s] / ri);
-                const double we = re2 * (p.D2[(pe * nr + i) * 7 + s] + p.D1[(pe * nr + i) * 7 + s] / ri);
-                const double2 zr = Z[fidx(p, 0, i, m, kk)], zt = Z[fidx(p, 1, i, m, kk)], zz = Z[fidx(p, 2, i, m, kk)];
-                ep = caxpy(ep, 0.5 * wo * wi, cadd(zr, cmuli(zt)));
-                em = caxpy(em, 0.5 * wo * wi, csub(zr, cmuli(zt)));
-                ez = caxpy(ez, we * wi, zz);
+    __shared__ double2 s3[3][NR_MAX][RQ];
+    double2 E[NR_MAX / RJ][3];
+#pragma unroll
+    for (int jj = 0; jj < NR_MAX / RJ; ++jj) E[jj][0] = E[jj][1] = E[jj][2] = czero();
+    if (Z) {
+        // E_n^T applied to W Z in the (+, -, z) basis
+        for (int j = jg; j < nr; j += RJ) {
+            double2 zp = czero(), zm = czero(), zz = czero();
+            if (sl.valid) {
+                const double2 zr = Z[fidx(p, 0, j, m, kk)], zt = Z[fidx(p, 1, j, m, kk)];
+                zz = Z[fidx(p, 2, j, m, kk)];
+                zp = cadd(zr, cmuli(zt));
+                zm = csub(zr, cmuli(zt));
             }
-            const double wj = p.w[j];
-            const double ia = 1.0 / (rc * rc);
-            const double2 zr = Z[fidx(p, 0, j, m, kk)], zt = Z[fidx(p, 1, j, m, kk)], zz = Z[fidx(p, 2, j, m, kk)];
-            ep = caxpy(ep, 0.5 * wj * (idt - re2 * ((double)((m + 1) * (m + 1)) * ia + a2)), cadd(zr, cmuli(zt)));
-            em = caxpy(em, 0.5 * wj * (idt - re2 * ((double)((m - 1) * (m - 1)) * ia + a2)), csub(zr, cmuli(zt)));
-            ez = caxpy(ez, wj * (idt - re2 * ((double)(m * m) * ia + a2)), zz);
-            er = cadd(ep, em);
-            et = cmuli(csub(em, ep));     // -i (ep - em)
+            s3[0][j][q] = zp;
+            s3[1][j][q] = zm;
+            s3[2][j][q] = zz;
         }
-        if (Bin) {
-            double2 cr, ct, cz;
-            curlH_row_g(p, m, kk, sl.al, j, Bin, cr, ct, cz);
-            er = cadd(er, cr);
-            et = cadd(et, ct);
-            ez = cadd(ez, cz);
+        __syncthreads();
+#pragma unroll
+        for (int jj = 0; jj < NR_MAX / RJ; ++jj) {
+            const int j = jg + jj * RJ;
+            if (j < nr && sl.valid) {
+                const double rc = p.r[j], wj = p.w[j];
+                const double ia = 1.0 / (rc * rc);
+                double2 ep = cscale(taps13(p, p.BWT, po, j, &s3[0][0][q], RQ), 0.5 * re2);
+                double2 em = cscale(taps13(p, p.BWT, po, j, &s3[1][0][q], RQ), 0.5 * re2);
+                double2 ez = cscale(taps13(p, p.BWT, pe, j, &s3[2][0][q], RQ), re2);
+                ep = caxpy(ep, 0.5 * wj * (idt - re2 * ((double)((m + 1) * (m + 1)) * ia + a2)), s3[0][j][q]);
+                em = caxpy(em, 0.5 * wj * (idt - re2 * ((double)((m - 1) * (m - 1)) * ia + a2)), s3[1][j][q]);
+                ez = caxpy(ez, wj * (idt - re2 * ((double)(m * m) * ia + a2)), s3[2][j][q]);
+                E[jj][0] = cadd(ep, em);
+                E[jj][1] = cmuli(csub(em, ep));     // -i (ep - em)
+                E[jj][2] = ez;
+            }
         }
-        const double2 ev[3] = {er, et, ez};
+        if (Bin) __syncthreads();
+    }
+    if (Bin) {
+        for (int j = jg; j < nr; j += RJ)
+            for (int c = 0; c < 3; ++c) s3[c][j][q] = sl.valid ? Bin[fidx(p, c, j, m, kk)] : czero();
+        __syncthreads();
+#pragma unroll
+        for (int jj = 0; jj < NR_MAX / RJ; ++jj) {
+            const int j = jg + jj * RJ;
+            if (j < nr && sl.valid) {
+                double2 cr, ct, cz;
+                curlH_row(p, m, sl.al, j, &s3[0][0][q], &s3[1][0][q], &s3[2][0][q], RQ, cr, ct, cz);
+                E[jj][0] = cadd(E[jj][0], cr);
+                E[jj][1] = cadd(E[jj][1], ct);
+                E[jj][2] = cadd(E[jj][2], cz);
+            }
+        }
+    }
+    if (!sl.valid) return;
+#pragma unroll
+    for (int jj = 0; jj < NR_MAX / RJ; ++jj) {
+        const int j = jg + jj * RJ;
+        if (j >= nr) continue;
+        const double iw = 1.0 / p.w[j];
         for (int c = 0; c < 3; ++c) {
             const size_t id = fidx(p, c, j, m, kk);
             const double2 av = Ain ? Ain[id] : czero();
-            out[id] = caxpy(av, iw, ev[c]);
+            out[id] = caxpy(av, iw, E[jj][c]);
         }
     }
 }

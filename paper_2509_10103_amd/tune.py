@@ -15,16 +15,16 @@ from . import npo
 CACHE = os.environ.get("NPO_TUNE_CACHE", os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json"))
 
 
-def candidates(nt, nz):
+def candidates(plan):
+    """Launch shapes the library accepts for this plan (it checks LDS fit and
+    divisibility itself)."""
     out = []
-    for g, zf, za in itertools.product((1, 2, 3), (2, 4, 8), (2, 4, 8)):
-        if 2 * g * nz * 16 > 160 * 1024 or nz % zf or nz % za:
+    for c in itertools.product((1, 2, 3), (2, 4, 8), (2, 4, 8)):
+        try:
+            npo.npo_plan_set_tuning(plan.handle, *c)
+        except npo.NpoError:
             continue
-        if 2 * max(3 * zf, zf + zf // 2) * nt * 16 > 160 * 1024:
-            continue
-        if 2 * max(4 * za + za // 2, 3 * za) * nt * 16 > 160 * 1024:
-            continue
-        out.append((g, zf, za))
+        out.append(c)
     return out
 
 
@@ -64,7 +64,7 @@ def tune(plan, nr, nt, nz, reps=3, use_cache=True, save=True):
     u = torch.randn(plan.shape, dtype=torch.complex128, device=plan.device) * 1e-3
     lam = torch.randn(plan.shape, dtype=torch.complex128, device=plan.device)
     timings = {}
-    for c in candidates(nt, nz):
+    for c in candidates(plan):
         npo.npo_plan_set_tuning(plan.handle, *c)
         timings[c] = _time_steps(plan, u, lam, reps)
     best = min(timings, key=timings.get)
