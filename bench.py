@@ -126,6 +126,9 @@ def main():
     torch.cuda.set_device(0)
     G = npo.Plan(cfg["nr"], cfg["nt"], cfg["nz"], cfg["lz"], cfg["re"], cfg["wo"], cfg["amp"], cfg["dt"],
                  cfg["t0"], cfg["nsteps"])
+    from paper_2509_10103_amd import tune
+    shapes, _ = tune.tune(G, cfg["nr"], cfg["nt"], cfg["nz"], use_cache=False, save=False)
+    shapes = list(shapes)
     r = npo.npo_plan_tables(G.handle, cfg["nr"])[0]
     raw = make_raw(cfg, r, G.M, G.K, cfg["seed"])
     u0 = torch.from_numpy(raw).to("cuda")
@@ -133,7 +136,8 @@ def main():
     npo.npo_normalize(G.handle, G.ws, u0, cfg["e0"])
     arena = G.arena(nck)
     uN = G.field()
-    print(f"[bench] {cfg['name']} nsteps={cfg['nsteps']} n_ckpt={nck} arena={arena.numel() * 16 / 2**30:.1f} GiB",
+    print(f"[bench] {cfg['name']} nsteps={cfg['nsteps']} n_ckpt={nck} arena={arena.numel() * 16 / 2**30:.1f} GiB "
+          f"launch shapes {shapes}",
           file=sys.stderr, flush=True)
     t = time.perf_counter()
     npo.npo_forward_run(G.handle, G.ws, arena, nck, u0, uN)
@@ -172,6 +176,12 @@ def main():
     dom = max(tot, key=tot.get)
     avg_s = prof[dom]["avg_ms"] * 1e-3
     achieved = ab[dom] / avg_s / 1e9 if avg_s > 0 else 0.0
+    # HBM traffic of the dominant kernel from the committed counter summary
+    # (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-calibrated), only while it was
+    # taken on these kernel sources
+    from paper_2509_10103_amd import profsum
+    tr = profsum.load_traffic(os.path.join(ROOT, "profiles", f"{cfg['name']}_hbm_bytes.md"), cfg["nt"], cfg["nz"])
+    traffic = tr[dom]["fetch"] + tr[dom]["write"] if tr and dom in tr else None
     kern = {k: {"launches": v["launches"], "avg_us": round(v["avg_ms"] * 1e3, 2),
                 "share": round(tot[k] / max(sum(tot.values()), 1e-30), 4),
                 "GBps_alg": round(ab[k] / (v["avg_ms"] * 1e-3) / 1e9, 1) if v["avg_ms"] > 0 else None}
@@ -191,11 +201,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["name"], "grid": [cfg["nr"], cfg["nt"], cfg["nz"]], "lz_radii": cfg["lz"],
                    "re": cfg["re"], "wo": cfg["wo"], "amp": cfg["amp"], "dt": cfg["dt"], "t0": cfg["t0"],
-                   "nsteps": cfg["nsteps"], "n_ckpt": nck, "e0": cfg["e0"], "seed": cfg["seed"],
+                   "nsteps": cfg["nsteps"], "n_ckpt": nck, "launch_shapes": shapes, "e0": cfg["e0"], "seed": cfg["seed"],
                    "iteration_latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
                    "gains": [[h["G_old"], h["G_new"], int(h["accepted"]), int(h["forward_sweeps"])] for h in hist]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": ab[dom], "avg_launch_us": avg_s * 1e6},
         "kernels": kern,
     }

@@ -200,7 +200,8 @@ __device__ __forceinline__ Slot slot_of(const KP& p, int g, int m, int q) {
 // ------------------------------------------------------------ forward solve
 // Lanes are (radial row, mode) in the pointwise phases and independent real
 // right-hand sides (operator, mode, re/im) in the substitution phases.
-__global__ __launch_bounds__(RT) void k_solve(KP p, int kind, const double2* __restrict__ ain,
+template <int kind>
+__global__ __launch_bounds__(RT) void k_solve(KP p, const double2* __restrict__ ain,
                                               const double2* __restrict__ bin, const double2* __restrict__ cin,
                                               double2* __restrict__ uout, double2* __restrict__ auxout) {
     int g, m;
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(RT) void k_solve(KP p, int kind, const double2* __r
         sR[2][j][q] = uz;
     }
     __syncthreads();
-    if (kind != 0) {
+    if constexpr (kind != 0) {
         // R = E u^n + N: stencils read from LDS, results held in registers
         // until every lane has read its neighbours
         double2 Rv[NR_MAX / RJ][3];
@@ -259,7 +260,7 @@ __global__ __launch_bounds__(RT) void k_solve(KP p, int kind, const double2* __r
                 double2 Nr = bin[fidx(p, 0, j, m, kk)];
                 double2 Nt = bin[fidx(p, 1, j, m, kk)];
                 double2 Nz = bin[fidx(p, 2, j, m, kk)];
-                if (kind == 2) {
+                if constexpr (kind == 2) {
                     Nr = cscale(cadd(Nr, cin[fidx(p, 0, j, m, kk)]), 0.5);
                     Nt = cscale(cadd(Nt, cin[fidx(p, 1, j, m, kk)]), 0.5);
                     Nz = cscale(cadd(Nz, cin[fidx(p, 2, j, m, kk)]), 0.5);
@@ -426,6 +427,7 @@ __device__ __forceinline__ void adj_store(const AdjOut& o, size_t id, double2 mu
     if (o.Yout) o.Yout[id] = caxpy(o.Yin ? o.Yin[id] : czero(), o.qy, mu);
     if (o.Zout) o.Zout[id] = caxpy(o.Zin ? o.Zin[id] : czero(), o.qz, mu);
 }
+template <bool useB>
 __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, double ca, const double2* Bin, double cb,
                                                   AdjOut ao) {
     int g, m;
@@ -438,10 +440,9 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
     __shared__ double2 sy[3][NR_MAX][RQ];
     __shared__ double2 sphi[NR_MAX][RQ];
     __shared__ double2 sa[RQ];
-    const bool useB = Bin != nullptr;
 
     // v = ca A + cb W^{-1} curl^H (W B); B staged in LDS for the stencils
-    if (useB) {
+    if constexpr (useB) {
         for (int j = jg; j < nr; j += RJ)
             for (int c = 0; c < 3; ++c) sy[c][j][q] = sl.valid ? Bin[fidx(p, c, j, m, sl.kk)] : czero();
         __syncthreads();
@@ -453,7 +454,7 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
         V[jj][0] = V[jj][1] = V[jj][2] = czero();
         if (j < nr && sl.valid) {
             for (int c = 0; c < 3; ++c) V[jj][c] = cscale(Ain[fidx(p, c, j, m, sl.kk)], ca);
-            if (useB) {
+            if constexpr (useB) {
                 double2 cr, ct, cz;
                 curlH_row(p, m, sl.al, j, &sy[0][0][q], &sy[1][0][q], &sy[2][0][q], RQ, cr, ct, cz);
                 const double iw = cb / p.w[j];
@@ -463,7 +464,7 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
             }
         }
     }
-    if (useB) __syncthreads();
+    if constexpr (useB) __syncthreads();
 #pragma unroll
     for (int jj = 0; jj < NR_MAX / RJ; ++jj) {
         const int j = jg + jj * RJ;
@@ -858,7 +859,10 @@ hipError_t launch_curl_aux(const npo_plan_s& p, const double2* u, double2* aux, 
 hipError_t launch_solve(const npo_plan_s& p, int kind, const double2* a, const double2* b, const double2* c,
                         double2* u_out, double2* aux_out, hipStream_t st) {
     prof_begin(p, kind == 1 ? KID_SOLVE_P : (kind == 2 ? KID_SOLVE_C : KID_SOLVE_R), st);
-    hipLaunchKernelGGL(k_solve, dim3((radial_groups(p.K) * p.mp1 + 7) / 8 * 8), dim3(RT), 0, st, p.kp, kind, a, b, c, u_out, aux_out);
+    const dim3 grid((radial_groups(p.K) * p.mp1 + 7) / 8 * 8);
+    if (kind == 1) hipLaunchKernelGGL(k_solve<1>, grid, dim3(RT), 0, st, p.kp, a, b, c, u_out, aux_out);
+    else if (kind == 2) hipLaunchKernelGGL(k_solve<2>, grid, dim3(RT), 0, st, p.kp, a, b, c, u_out, aux_out);
+    else hipLaunchKernelGGL(k_solve<0>, grid, dim3(RT), 0, st, p.kp, a, b, c, u_out, aux_out);
     prof_end(p, kind == 1 ? KID_SOLVE_P : (kind == 2 ? KID_SOLVE_C : KID_SOLVE_R), st);
     return hipGetLastError();
 }
@@ -868,7 +872,9 @@ hipError_t launch_solve_adj(const npo_plan_s& p, const double2* A, double ca, co
                             double qz, double2* Zout, hipStream_t st) {
     AdjOut ao{out0, Yin, Yout, Zin, Zout, qy, qz};
     prof_begin(p, B ? KID_SOLVE_ADJ2 : KID_SOLVE_ADJ, st);
-    hipLaunchKernelGGL(k_solve_adj, dim3((radial_groups(p.K) * p.mp1 + 7) / 8 * 8), dim3(RT), 0, st, p.kp, A, ca, B, cb, ao);
+    const dim3 grid((radial_groups(p.K) * p.mp1 + 7) / 8 * 8);
+    if (B) hipLaunchKernelGGL(k_solve_adj<true>, grid, dim3(RT), 0, st, p.kp, A, ca, B, cb, ao);
+    else hipLaunchKernelGGL(k_solve_adj<false>, grid, dim3(RT), 0, st, p.kp, A, ca, B, cb, ao);
     prof_end(p, B ? KID_SOLVE_ADJ2 : KID_SOLVE_ADJ, st);
     return hipGetLastError();
 }
