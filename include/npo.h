@@ -52,7 +52,7 @@ typedef int32_t npo_status;
 #define NPO_ESTATE       -5   /* call out of order (e.g. no forward sweep yet)   */
 
 /* Grid: nr radial nodes (8..64), ntheta and nz physical points (products of 2
- * and 3, ntheta in 6..128, nz in 6..2048), pipe length lz in radii. */
+ * and 3, ntheta in 6..128, nz even in 6..2048), pipe length lz in radii. */
 typedef struct { int32_t nr, ntheta, nz; double lz; } npo_grid;
 /* Flow: Re (diameter and mean bulk velocity), Womersley number Wo, pulsation
  * amplitude A = U_max/U_bar - 1 (Sec. 1). A = 0 is steady Hagen-Poiseuille. */
@@ -169,6 +169,16 @@ npo_status npo_iterate(npo_plan plan, void* ws, void* ckpt, int32_t n_ckpt, void
  * (NPO_EINVAL).  Results do not depend on the shapes. */
 npo_status npo_plan_set_tuning(npo_plan plan, int32_t zgroup, int32_t zb_fwd, int32_t zb_adj);
 npo_status npo_plan_get_tuning(npo_plan plan, int32_t* zgroup, int32_t* zb_fwd, int32_t* zb_adj);
+
+/* Step graphs for the checkpointed sweeps (enable = 1): npo_forward_run and
+ * npo_adjoint_run (and so npo_iterate) replay one captured HIP graph per
+ * forward advance and per adjoint step (Sec. 2.3 step, Sec. 2.4 sweeps)
+ * instead of launching each step's kernels; the step index the time depends on
+ * is read from the workspace.  Graphs are captured on first use for a
+ * workspace (a new workspace, new launch shapes or enable = 0 drop them) and
+ * are not used while the sampling profiler runs.  Results are bitwise those of
+ * enable = 0.  Default 0. */
+npo_status npo_plan_set_graphs(npo_plan plan, int32_t enable);
 
 /* out = scale * q (.) lam with q = 2 pi L_z c_m w_j: converts the W-gradient
  * lam of a real functional into the gradient with respect to the real and

@@ -2,7 +2,8 @@
 
 Each instance owns a plan (its constant tables and operator caches), a
 workspace, a checkpoint arena and a HIP stream; launch shapes come from the
-autotuner, cached per grid shape.  ``Batch.run`` advances every instance by
+autotuner, cached per grid shape, and the sweeps replay captured step graphs
+(one graph launch per forward advance or adjoint step).  ``Batch.run`` advances every instance by
 optimisation iterations (Sec. 2.1-2.2) concurrently: one host thread per
 instance group issues that group's work on its own streams (the library
 calls release the GIL), so kernels of small instances overlap on the device
@@ -18,7 +19,7 @@ from . import npo, synth, tune as tuner
 
 
 class Instance:
-    def __init__(self, cfg, device="cuda", autotune=True):
+    def __init__(self, cfg, device="cuda", autotune=True, graphs=True):
         import torch
         self.cfg = cfg
         self.stream = torch.cuda.Stream(device=device)
@@ -27,6 +28,9 @@ class Instance:
                                  cfg["dt"], cfg["t0"], cfg["nsteps"], cfg.get("ncorr", 2), device=device)
             if autotune:
                 tuner.tune(self.plan, cfg["nr"], cfg["nt"], cfg["nz"])
+            # sweeps replay captured step graphs: one launch per step instead
+            # of one per kernel (small instances are launch-bound)
+            npo.npo_plan_set_graphs(self.plan.handle, int(graphs))
             self.n_ckpt = int(max(1, min(cfg["n_ckpt"] or cfg["nsteps"], cfg["nsteps"])))
             self.arena = self.plan.arena(self.n_ckpt)
             r = npo.npo_plan_tables(self.plan.handle, cfg["nr"])[0]
@@ -73,8 +77,8 @@ class Instance:
 
 
 class Batch:
-    def __init__(self, cfgs, device="cuda", autotune=True):
-        self.instances = [Instance(c, device, autotune) for c in cfgs]
+    def __init__(self, cfgs, device="cuda", autotune=True, graphs=True):
+        self.instances = [Instance(c, device, autotune, graphs) for c in cfgs]
 
     def run(self, iters=1, workers=None):
         """Advance every instance by ``iters`` iterations concurrently.

@@ -275,6 +275,7 @@ struct WsPtrs {
     double2* st[npo::NCORR_MAX];
     double2* auxs[npo::NCORR_MAX];
     double* red;
+    long long* step;
 };
 WsPtrs wsptrs(const npo_plan_s& p, void* ws) {
     char* b = static_cast<char*>(ws);
@@ -283,6 +284,7 @@ WsPtrs wsptrs(const npo_plan_s& p, void* ws) {
     w.aux0 = F(p.ws.aux0); w.nn = F(p.ws.nn); w.ns = F(p.ws.ns);
     for (int c = 0; c < npo::NCORR_MAX; ++c) { w.st[c] = F(p.ws.st[c]); w.auxs[c] = F(p.ws.auxs[c]); }
     w.muC = F(p.ws.muC); w.muP = F(p.ws.muP); w.yb = F(p.ws.yb); w.zb2 = F(p.ws.zb2);
+    w.step = reinterpret_cast<long long*>(b + p.ws.step);
     w.fa = F(p.ws.fa); w.fb = F(p.ws.fb); w.fa2 = F(p.ws.fa2); w.fb2 = F(p.ws.fb2);
     w.cur = F(p.ws.cur); w.lam = F(p.ws.lam); w.tmp = F(p.ws.tmp); w.g = F(p.ws.g);
     w.trial = F(p.ws.trial); w.trialN = F(p.ws.trialN);
@@ -290,15 +292,17 @@ WsPtrs wsptrs(const npo_plan_s& p, void* ws) {
     return w;
 }
 
-double time_of(const npo_plan_s& p, long long n) { return p.t0 + (double)n * p.dt; }
+// Evaluation time t0 + (n + off) dt, with n from the device step index when
+// dstep is given (captured graphs) and by value otherwise.
+npo::TimeArg at_step(const long long* dstep, long long n, int off) { return npo::TimeArg{dstep, n, off, 0, 0.0}; }
 
 // u_out = Phi(u_n).  If have_aux, w.aux0 already holds the vorticity parts of u_n.
 // Stages: w_0 = S(E u + N(u)), w_c = S(E u + (N(u) + N(w_{c-1}))/2), u_out = w_ncorr.
 hipError_t fwd_step(const npo_plan_s& p, void* ws, const double2* un, double2* uout, long long n, bool have_aux,
-                    hipStream_t st) {
+                    hipStream_t st, const long long* dstep = nullptr) {
     WsPtrs w = wsptrs(p, ws);
     hipError_t e;
-    const double t0 = time_of(p, n), t1 = time_of(p, n + 1);
+    const npo::TimeArg t0 = at_step(dstep, n, 0), t1 = at_step(dstep, n, 1);
     if (!have_aux && (e = npo::launch_curl_aux(p, un, w.aux0, st)) != hipSuccess) return e;
     if ((e = npo::launch_nl(p, 0, un, w.aux0, nullptr, t0, w.nn, nullptr, ws, st)) != hipSuccess) return e;
     if ((e = npo::launch_solve(p, 1, un, w.nn, nullptr, w.st[0], w.auxs[0], st)) != hipSuccess) return e;
@@ -317,10 +321,10 @@ hipError_t fwd_step(const npo_plan_s& p, void* ws, const double2* un, double2* u
 //   mu_C = S^+ lam; mu_{c-1} = S^+ (N'(w_{c-1})^+ mu_c / 2), c = C..1;
 //   lam_n = E^+ (sum mu_c) + N'(u_n)^+ (mu_0 + sum_{c>=1} mu_c / 2).
 hipError_t adj_step(const npo_plan_s& p, void* ws, const double2* un, const double2* lamin, double2* lamout,
-                    long long n, hipStream_t st) {
+                    long long n, hipStream_t st, const long long* dstep = nullptr) {
     WsPtrs w = wsptrs(p, ws);
     hipError_t e;
-    const double t0 = time_of(p, n), t1 = time_of(p, n + 1);
+    const npo::TimeArg t0 = at_step(dstep, n, 0), t1 = at_step(dstep, n, 1);
     const int C = p.ncorr;
     if ((e = npo::launch_curl_aux(p, un, w.aux0, st)) != hipSuccess) return e;
     if ((e = npo::launch_nl(p, 0, un, w.aux0, nullptr, t0, w.nn, nullptr, ws, st)) != hipSuccess) return e;
@@ -345,6 +349,49 @@ hipError_t adj_step(const npo_plan_s& p, void* ws, const double2* un, const doub
     }
     if ((e = npo::launch_nl(p, 1, un, w.aux0, w.yb, t0, w.fa2, w.fb2, ws, st)) != hipSuccess) return e;
     return npo::launch_final(p, w.zb2, w.fa2, w.fb2, lamout, st);
+}
+
+// ------------------------------------------------------- captured step graphs
+// The forward advance (cur -> cur, vorticity parts of cur present, then
+// step += 1) and the adjoint step (lam -> lam at u = cur) read their step
+// index from the workspace, so one capture per workspace serves every step.
+void drop_graphs(npo_plan_s& p) {
+    if (p.g_fwd) (void)hipGraphExecDestroy(p.g_fwd);
+    if (p.g_adj) (void)hipGraphExecDestroy(p.g_adj);
+    p.g_fwd = p.g_adj = nullptr;
+    p.graph_ws = nullptr;
+}
+
+hipError_t capture(npo_plan_s& p, void* ws, bool adjoint, hipGraphExec_t* exec) {
+    WsPtrs w = wsptrs(p, ws);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(p.graph_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t e1 = adjoint ? adj_step(p, ws, w.cur, w.lam, w.lam, 0, p.graph_stream, w.step)
+                            : fwd_step(p, ws, w.cur, w.cur, 0, true, p.graph_stream, w.step);
+    if (e1 == hipSuccess && !adjoint) e1 = npo::launch_step_index(w.step, 1, 1, p.graph_stream);
+    e = hipStreamEndCapture(p.graph_stream, &g);
+    if (e == hipSuccess) e = e1;
+    if (e == hipSuccess) e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+}
+
+hipError_t build_graphs(npo_plan_s& p, void* ws) {
+    drop_graphs(p);
+    hipError_t e = hipSuccess;
+    if (!p.graph_stream) e = hipStreamCreateWithFlags(&p.graph_stream, hipStreamNonBlocking);
+    const bool prof = p.prof.on;
+    p.prof.on = false;                    // no profiler events inside a graph
+    if (e == hipSuccess) e = capture(p, ws, false, &p.g_fwd);
+    if (e == hipSuccess) e = capture(p, ws, true, &p.g_adj);
+    p.prof.on = prof;
+    if (e != hipSuccess) {
+        drop_graphs(p);
+        return e;
+    }
+    p.graph_ws = ws;
+    return hipSuccess;
 }
 
 npo_status check_plan(npo_plan p) {
@@ -526,7 +573,7 @@ npo_status npo_plan_create(const npo_grid* grid, const npo_flow* flow, const npo
     const double2* dc = reinterpret_cast<const double2*>(reinterpret_cast<const char*>(p->d_tables) + cbase);
     npo::KP& kp = p->kp;
     kp.nr = nr; kp.nt = nt; kp.nz = nz; kp.M = p->M; kp.K = p->K; kp.nk = p->nk; kp.mp1 = p->mp1;
-    kp.k0 = p->k0; kp.re = p->re; kp.dt = p->dt; kp.lz = p->lz;
+    kp.k0 = p->k0; kp.re = p->re; kp.dt = p->dt; kp.lz = p->lz; kp.t0 = p->t0; kp.omega = p->omega;
     kp.r = dd + o_r; kp.w = dd + o_w; kp.D1 = dd + o_d1; kp.D2 = dd + o_d2; kp.B = dd + o_b;
     kp.D1T = dd + o_d1t; kp.D1WT = dd + o_d1wt; kp.BWT = dd + o_bwt;
     kp.col0 = reinterpret_cast<const int*>(reinterpret_cast<const char*>(p->d_tables) + ibase);
@@ -657,6 +704,7 @@ npo_status npo_plan_create(const npo_grid* grid, const npo_flow* flow, const npo
     L.trial = take(fb); L.trialN = take(fb);
     L.zbuf = take(9 * gb); L.tbuf = take(6 * gb);
     L.red = take((npo::NR_MAX * 4 + 512) * 8);
+    L.step = take(256);
     L.total = off;
     *out = p;
     return NPO_OK;
@@ -664,6 +712,8 @@ npo_status npo_plan_create(const npo_grid* grid, const npo_flow* flow, const npo
 
 npo_status npo_plan_destroy(npo_plan p) {
     if (!p) return NPO_OK;
+    drop_graphs(*p);
+    if (p->graph_stream) (void)hipStreamDestroy(p->graph_stream);
     if (p->d_tables) (void)hipFree(p->d_tables);
     if (p->d_cache) (void)hipFree(p->d_cache);
     delete p;
@@ -711,7 +761,8 @@ npo_status npo_nonlinear(npo_plan p, void* ws, const void* u, double t, void* ou
     if (check_plan(p) || !ws || !u || !out) return fail(NPO_EINVAL, "null argument");
     WsPtrs w = wsptrs(*p, ws);
     HIPCHK(npo::launch_curl_aux(*p, CF(u), w.aux0, ST(stream)));
-    HIPCHK(npo::launch_nl(*p, 0, CF(u), w.aux0, nullptr, t, F(out), nullptr, ws, ST(stream)));
+    HIPCHK(npo::launch_nl(*p, 0, CF(u), w.aux0, nullptr, npo::TimeArg{nullptr, 0, 0, 1, t}, F(out), nullptr, ws,
+                          ST(stream)));
     return NPO_OK;
 }
 
@@ -719,7 +770,8 @@ npo_status npo_nonlinear_adj(npo_plan p, void* ws, const void* u, double t, cons
     if (check_plan(p) || !ws || !u || !y || !out) return fail(NPO_EINVAL, "null argument");
     WsPtrs w = wsptrs(*p, ws);
     HIPCHK(npo::launch_curl_aux(*p, CF(u), w.aux0, ST(stream)));
-    HIPCHK(npo::launch_nl(*p, 1, CF(u), w.aux0, CF(y), t, w.fa, w.fb, ws, ST(stream)));
+    HIPCHK(npo::launch_nl(*p, 1, CF(u), w.aux0, CF(y), npo::TimeArg{nullptr, 0, 0, 1, t}, w.fa, w.fb, ws,
+                          ST(stream)));
     HIPCHK(npo::launch_final(*p, nullptr, w.fa, w.fb, F(out), ST(stream)));
     return NPO_OK;
 }
@@ -771,15 +823,24 @@ npo_status npo_forward_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const 
     auto slot = [&](long long s) { return reinterpret_cast<double2*>(static_cast<char*>(ckpt) + s * fb); };
     std::vector<Act> acts = schedule(p->nsteps, nck);
     const size_t fa = first_adj(acts);
+    const bool gr = p->use_graphs && !p->prof.on;
+    if (gr && p->graph_ws != ws) HIPCHK(build_graphs(*p, ws));
     HIPCHK(hipMemcpyAsync(slot(0), u0, fb, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(w.cur, u0, fb, hipMemcpyDeviceToDevice, st));
     long long pos = 0;
-    bool aux = false;
+    bool aux = false, synced = false;   // synced: the device step index equals pos
     for (size_t i = 0; i < fa; ++i) {
         const Act& a = acts[i];
         if (a.kind == A_ADV) {
             for (long long k = 0; k < a.a; ++k) {
-                HIPCHK(fwd_step(*p, ws, w.cur, w.cur, pos, aux, st));
+                if (gr && aux) {
+                    if (!synced) HIPCHK(npo::launch_step_index(w.step, pos, 0, st));
+                    HIPCHK(hipGraphLaunch(p->g_fwd, st));
+                    synced = true;
+                } else {
+                    HIPCHK(fwd_step(*p, ws, w.cur, w.cur, pos, aux, st));
+                    synced = false;
+                }
                 aux = true;
                 ++pos;
             }
@@ -803,18 +864,28 @@ npo_status npo_adjoint_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const 
     WsPtrs w = wsptrs(*p, ws);
     auto slot = [&](long long s) { return reinterpret_cast<double2*>(static_cast<char*>(ckpt) + s * fb); };
     std::vector<Act> acts = schedule(p->nsteps, nck);
+    const bool gr = p->use_graphs && !p->prof.on;
+    if (gr && p->graph_ws != ws) HIPCHK(build_graphs(*p, ws));
     HIPCHK(hipMemcpyAsync(w.lam, lamN, fb, hipMemcpyDeviceToDevice, st));
     long long pos = p->nsteps - 1, adv = 0;
-    bool aux = false;
+    bool aux = false, synced = false;   // synced: the device step index equals pos
     for (size_t i = first_adj(acts); i < acts.size(); ++i) {
         const Act& a = acts[i];
         if (a.kind == A_RESTORE) {
             HIPCHK(hipMemcpyAsync(w.cur, slot(a.a), fb, hipMemcpyDeviceToDevice, st));
             pos = a.b;
             aux = false;
+            synced = false;
         } else if (a.kind == A_ADV) {
             for (long long k = 0; k < a.a; ++k) {
-                HIPCHK(fwd_step(*p, ws, w.cur, w.cur, pos, aux, st));
+                if (gr && aux) {
+                    if (!synced) HIPCHK(npo::launch_step_index(w.step, pos, 0, st));
+                    HIPCHK(hipGraphLaunch(p->g_fwd, st));
+                    synced = true;
+                } else {
+                    HIPCHK(fwd_step(*p, ws, w.cur, w.cur, pos, aux, st));
+                    synced = false;
+                }
                 aux = true;
                 ++pos;
             }
@@ -824,7 +895,13 @@ npo_status npo_adjoint_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const 
             HIPCHK(hipMemcpyAsync(slot(a.a), w.cur, fb, hipMemcpyDeviceToDevice, st));
         } else {
             if (a.a != pos) return fail(NPO_ESTATE, "schedule adjoint position mismatch");
-            HIPCHK(adj_step(*p, ws, w.cur, w.lam, w.lam, pos, st));
+            if (gr) {
+                if (!synced) HIPCHK(npo::launch_step_index(w.step, pos, 0, st));
+                HIPCHK(hipGraphLaunch(p->g_adj, st));
+                synced = true;
+            } else {
+                HIPCHK(adj_step(*p, ws, w.cur, w.lam, w.lam, pos, st));
+            }
             aux = false;   // the adjoint step reuses aux0 for its own work
         }
     }
@@ -938,6 +1015,15 @@ npo_status npo_plan_set_tuning(npo_plan p, int32_t zgroup, int32_t zb_fwd, int32
     p->zgroup = zgroup;
     p->zb_theta_fwd = zb_fwd;
     p->zb_theta_adj = zb_adj;
+    drop_graphs(*p);          // launch shapes are baked into captured graphs
+    return NPO_OK;
+}
+
+npo_status npo_plan_set_graphs(npo_plan p, int32_t enable) {
+    if (check_plan(p)) return NPO_EINVAL;
+    if (enable != 0 && enable != 1) return fail(NPO_EINVAL, "enable must be 0 or 1");
+    p->use_graphs = enable != 0;
+    if (!p->use_graphs) drop_graphs(*p);
     return NPO_OK;
 }
 

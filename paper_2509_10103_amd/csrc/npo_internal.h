@@ -33,6 +33,7 @@ struct KP {
     int nr, nt, nz, M, K, nk, mp1;
     double k0, re, dt;
     double lz;
+    double t0, omega;     // start time and base-flow angular frequency
     const double* r;      // [nr]
     const double* w;      // [nr]
     const double* D1;     // [2][nr][7] parity 0 = even, 1 = odd
@@ -54,6 +55,17 @@ struct KP {
     int ft[NFAC_MAX];
 };
 
+// Time of a nonlinear-term evaluation: either `t` itself (direct), or
+// t0 + (n + off) dt with the step index n read from device memory (`dstep`,
+// when not null: captured graphs replay at any step) or given by value.
+struct TimeArg {
+    const long long* dstep;
+    long long n;
+    int off;
+    int direct;
+    double t;
+};
+
 // Workspace carve-up (byte offsets into the caller's workspace).
 constexpr int NCORR_MAX = 3;
 
@@ -69,6 +81,7 @@ struct WsLayout {
     size_t g, trial, trialN;    // iterate buffers
     size_t zbuf, tbuf;          // z-transformed and theta-pass intermediates
     size_t red;                 // reduction partials + scalars
+    size_t step;                // device step index read by captured step graphs
     size_t total;
 };
 
@@ -92,6 +105,12 @@ struct npo_plan_s {
     int zb_theta_fwd = 4, zb_theta_adj = 4;
     int zgroup = 1;
     mutable npo::Profiler prof;
+    // captured step graphs (see npo_plan_set_graphs); rebuilt for a new workspace
+    bool use_graphs = false;
+    void* graph_ws = nullptr;
+    hipStream_t graph_stream = nullptr;
+    hipGraphExec_t g_fwd = nullptr;   // forward advance cur -> cur (aux of cur present), then step += 1
+    hipGraphExec_t g_adj = nullptr;   // adjoint step lam -> lam at u = cur
 };
 
 namespace npo {
@@ -108,7 +127,9 @@ size_t zpass_lds(const npo_plan_s& p, int G);
 size_t theta_lds(const npo_plan_s& p, int ZB, int adj);
 hipError_t launch_curl_aux(const npo_plan_s& p, const double2* u, double2* aux, hipStream_t st);
 hipError_t launch_nl(const npo_plan_s& p, int adjoint, const double2* u, const double2* aux,
-                     const double2* y, double t, double2* out0, double2* out1, void* ws, hipStream_t st);
+                     const double2* y, const TimeArg& ta, double2* out0, double2* out1, void* ws, hipStream_t st);
+// *d = v (set) or *d += v (add), one thread.
+hipError_t launch_step_index(long long* d, long long v, int add, hipStream_t st);
 // solve kinds: 0 = out = S(R) with R = a (raw); 1 = predictor S(E a + b);
 // 2 = corrector S(E a + (b + c)/2).  aux_out may be null.
 hipError_t launch_solve(const npo_plan_s& p, int kind, const double2* a, const double2* b,

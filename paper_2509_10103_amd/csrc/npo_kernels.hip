@@ -845,8 +845,18 @@ __global__ void k_rescale(size_t n, double2* __restrict__ x, const double* __res
     x[i] = cscale(x[i], s);
 }
 
+// Device step index of captured step graphs: *d = v or *d += v.
+__global__ void k_step_index(long long* d, long long v, int add) {
+    if (threadIdx.x == 0) *d = add ? *d + v : v;
+}
+
 // ---------------------------------------------------------------- launchers
 static inline size_t field_elems(const npo_plan_s& p) { return (size_t)3 * p.nr * p.mp1 * p.nk; }
+
+hipError_t launch_step_index(long long* d, long long v, int add, hipStream_t st) {
+    hipLaunchKernelGGL(k_step_index, dim3(1), dim3(64), 0, st, d, v, add);
+    return hipGetLastError();
+}
 
 hipError_t launch_curl_aux(const npo_plan_s& p, const double2* u, double2* aux, hipStream_t st) {
     const size_t per = (size_t)p.nr * p.mp1 * p.nk;

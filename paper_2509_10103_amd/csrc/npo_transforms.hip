@@ -139,8 +139,14 @@ __device__ __forceinline__ void place_pair(double2* s, int nt, int m, double2 xa
     }
 }
 
+// cos and sin of the base-flow phase at the evaluation time
+__device__ __forceinline__ void phase_of(const KP& p, const TimeArg& ta, double& cw, double& sw) {
+    const double t = ta.direct ? ta.t : p.t0 + (double)((ta.dstep ? *ta.dstep : ta.n) + ta.off) * p.dt;
+    sincos(p.omega * t, &sw, &cw);
+}
+
 __global__ void k_theta(KP p, int adj, int ZB, const double2* __restrict__ zb, double2* __restrict__ tb,
-                        double cw, double sw) {
+                        TimeArg ta) {
     extern __shared__ double2 sh[];
     const int j = blockIdx.y, z0 = blockIdx.x * ZB;
     const int nt = p.nt, mp1 = p.mp1, nz = p.nz;
@@ -172,7 +178,8 @@ __global__ void k_theta(KP p, int adj, int ZB, const double2* __restrict__ zb, d
     double2* R1 = fft_lds(A, Bf, nin, nt, p.ft, p.nft, p.twt, 1.0);
     double2* O = (R1 == A) ? Bf : A;
     double* Od = reinterpret_cast<double*>(O);
-    double U, Om;
+    double U, Om, cw, sw;
+    phase_of(p, ta, cw, sw);
     base_at(p, j, cw, sw, U, Om);
     for (int t = threadIdx.x; t < ZB * nt; t += blockDim.x) {
         const int zi = t / nt, th = t - zi * nt;
@@ -447,7 +454,7 @@ __global__ __launch_bounds__(TB) void k_zfwd_t(KP p, int G, const double2* __res
 // share L2 lines of the [j][f][m][z] intermediates.
 template <int NT, int ADJ>
 __global__ __launch_bounds__(TB) void k_theta_t(KP p, int lzb, int nzb, const double2* __restrict__ zb,
-                                               double2* __restrict__ tb, double cw, double sw) {
+                                               double2* __restrict__ tb, TimeArg ta) {
     constexpr int M = (NT - 1) / 3, MP1 = M + 1;
     constexpr int NF = ADJ ? 9 : 6, NFO = ADJ ? 6 : 3;
     const int nblk = nzb * p.nr;
@@ -504,7 +511,8 @@ __global__ __launch_bounds__(TB) void k_theta_t(KP p, int lzb, int nzb, const do
     __syncthreads();
     double2* R1 = fft_ct<NT, true>(A, Bf, nin, tw);
     double2* O = (R1 == A) ? Bf : A;
-    double U, Om;
+    double U, Om, cw, sw;
+    phase_of(p, ta, cw, sw);
     base_at(p, j, cw, sw, U, Om);
     for (int t = threadIdx.x; t < ZB * NT; t += TB) {
         const int zi = t / NT, th = t - zi * NT;
@@ -632,7 +640,7 @@ static void launch_zfwd(const npo_plan_s& p, int adj, const double2* tb, double2
     }
 }
 
-static void launch_theta(const npo_plan_s& p, int adj, const double2* zb, double2* tb, double cw, double sw,
+static void launch_theta(const npo_plan_s& p, int adj, const double2* zb, double2* tb, const TimeArg& ta,
                          hipStream_t st) {
     const int ZB = adj ? p.zb_theta_adj : p.zb_theta_fwd;
     const size_t sh = theta_lds(p, ZB, adj);
@@ -644,28 +652,27 @@ static void launch_theta(const npo_plan_s& p, int adj, const double2* zb, double
     switch (p.nt) {
 #define NPO_CASE(N)                                                                                          \
     case N:                                                                                                  \
-        if (adj) hipLaunchKernelGGL((k_theta_t<N, 1>), grid, dim3(TB), sh, st, p.kp, lzb, nzb, zb, tb, cw, sw); \
-        else hipLaunchKernelGGL((k_theta_t<N, 0>), grid, dim3(TB), sh, st, p.kp, lzb, nzb, zb, tb, cw, sw);     \
+        if (adj) hipLaunchKernelGGL((k_theta_t<N, 1>), grid, dim3(TB), sh, st, p.kp, lzb, nzb, zb, tb, ta); \
+        else hipLaunchKernelGGL((k_theta_t<N, 0>), grid, dim3(TB), sh, st, p.kp, lzb, nzb, zb, tb, ta);     \
         return;
         NPO_NT_SIZES(NPO_CASE)
 #undef NPO_CASE
     default:
-        hipLaunchKernelGGL(k_theta, dim3(nzb, p.nr), dim3(256), sh, st, p.kp, adj, ZB, zb, tb, cw, sw);
+        hipLaunchKernelGGL(k_theta, dim3(nzb, p.nr), dim3(256), sh, st, p.kp, adj, ZB, zb, tb, ta);
     }
 }
 
 // ---------------------------------------------------------------- launcher
 hipError_t launch_nl(const npo_plan_s& p, int adj, const double2* u, const double2* aux, const double2* y,
-                     double t, double2* out0, double2* out1, void* ws, hipStream_t st) {
+                     const TimeArg& ta, double2* out0, double2* out1, void* ws, hipStream_t st) {
     char* base = static_cast<char*>(ws);
     double2* zb = reinterpret_cast<double2*>(base + p.ws.zbuf);
     double2* tb = reinterpret_cast<double2*>(base + p.ws.tbuf);
     prof_begin(p, adj ? KID_ZINV_A : KID_ZINV_F, st);
     launch_zinv(p, adj, u, aux, y, zb, st);
     prof_end(p, adj ? KID_ZINV_A : KID_ZINV_F, st);
-    const double cw = cos(p.omega * t), sw = sin(p.omega * t);
     prof_begin(p, adj ? KID_THETA_A : KID_THETA_F, st);
-    launch_theta(p, adj, zb, tb, cw, sw, st);
+    launch_theta(p, adj, zb, tb, ta, st);
     prof_end(p, adj ? KID_THETA_A : KID_THETA_F, st);
     const double scale = 1.0 / ((double)p.nt * p.nz);
     prof_begin(p, adj ? KID_ZFWD_A : KID_ZFWD_F, st);

@@ -70,6 +70,7 @@ SIGNATURES = {
     "npo_euclid_grad": (_I32, [_P, _P, _D, _P, _P]),
     "npo_plan_set_tuning": (_I32, [_P, _I32, _I32, _I32]),
     "npo_plan_get_tuning": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "npo_plan_set_graphs": (_I32, [_P, _I32]),
     "npo_profile_begin": (_I32, [_P, _I32]),
     "npo_profile_read": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _DP]),
 }
@@ -214,6 +215,10 @@ def npo_normalize(plan, ws, u, e0, stream=None):
 
 def npo_plan_set_tuning(plan, zgroup, zb_fwd, zb_adj):
     _check(lib().npo_plan_set_tuning(plan, zgroup, zb_fwd, zb_adj))
+
+
+def npo_plan_set_graphs(plan, enable):
+    _check(lib().npo_plan_set_graphs(plan, int(bool(enable))))
 
 
 def npo_plan_get_tuning(plan):

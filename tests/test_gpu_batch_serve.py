@@ -24,8 +24,10 @@ def small_cfgs(n, nsteps=24):
 
 
 def alone(cfg, iters):
+    """The instance alone, launching every kernel itself (no step graphs), so
+    that the batched runs, which replay graphs, are checked against it too."""
     from paper_2509_10103_amd.batch import Instance
-    inst = Instance(cfg, autotune=False)
+    inst = Instance(cfg, autotune=False, graphs=False)
     for _ in range(iters):
         inst.iterate()
     u0, uN = inst.state()

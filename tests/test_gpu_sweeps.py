@@ -99,3 +99,32 @@ def test_forward_sweep_is_deterministic(c1):
     npo.npo_forward_run(G.handle, G.ws, ck, 4, u0, a)
     npo.npo_forward_run(G.handle, G.ws, ck, 4, u0, b)
     assert np.array_equal(to_host(a), to_host(b))
+
+
+def test_step_graphs_replay_bitwise(c1):
+    """Sweeps replaying the captured step graphs equal the launched sweeps
+    bitwise, on every replay, with eager work and synchronisations between."""
+    import torch
+    c, d, P, G = c1
+    from paper_2509_10103_amd import npo
+    nck = 16
+    u0 = to_dev(d["u0"])
+    ck = G.arena(nck)
+    ref_uN, ref_lam = G.field(), G.field()
+    npo.npo_forward_run(G.handle, G.ws, ck, nck, u0, ref_uN)
+    npo.npo_adjoint_run(G.handle, G.ws, ck, nck, ref_uN, ref_lam)
+    ref_uN, ref_lam = to_host(ref_uN), to_host(ref_lam)
+    npo.npo_plan_set_graphs(G.handle, 1)
+    try:
+        for rep in range(3):
+            uN, lam = G.field(), G.field()
+            npo.npo_forward_run(G.handle, G.ws, ck, nck, u0, uN)
+            torch.cuda.synchronize()
+            y = G.field()
+            npo.npo_forward_step(G.handle, G.ws, u0, y, rep)      # eager work between replays
+            torch.cuda.synchronize()
+            npo.npo_adjoint_run(G.handle, G.ws, ck, nck, uN, lam)
+            assert np.array_equal(to_host(uN), ref_uN), rep
+            assert np.array_equal(to_host(lam), ref_lam), rep
+    finally:
+        npo.npo_plan_set_graphs(G.handle, 0)
