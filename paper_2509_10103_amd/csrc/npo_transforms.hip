@@ -374,196 +374,242 @@ __device__ __forceinline__ double2* fft_ct(double2* a, double2* b, int B, const 
 }
 
 // Inverse axial transforms.  Fields: 0..2 u, 3 w_r (built from u), 4..5 aux,
-// 6..8 y; NF = 6 (forward term) or 9 (adjoint term).  G fields per round.
+// 6..8 y; NF = 6 (forward term) or 9 (adjoint term).  One field per round;
+// the next field's inputs are loaded into registers while the current one is
+// transformed, so the global-load latency overlaps the LDS passes.
 template <int NZ, int NF>
-__global__ __launch_bounds__(TB) void k_zinv_t(KP p, int G, const double2* __restrict__ u,
-                                              const double2* __restrict__ aux, const double2* __restrict__ y,
-                                              double2* __restrict__ zb) {
+__global__ __launch_bounds__(TB) void k_zinv_t(KP p, const double2* __restrict__ u, const double2* __restrict__ aux,
+                                              const double2* __restrict__ y, double2* __restrict__ zb) {
     constexpr int K = (NZ - 1) / 3, NK = 2 * K + 1;
+    constexpr int PER = (NZ + TB - 1) / TB;
     extern __shared__ double2 sh[];
     double2* tw = sh;
     double2* A = sh + NZ;
-    double2* Bf = A + lp_size(G * NZ);
+    double2* Bf = A + lp_size(NZ);
     const int m = blockIdx.x, j = blockIdx.y, mp1 = p.mp1;
-    const double r = p.r[j];
+    const double mr = m / p.r[j];
     for (int t = threadIdx.x; t < NZ; t += TB) tw[t] = p.twz[t];
-    for (int f0 = 0; f0 < NF; f0 += G) {
-        const int g = min(G, NF - f0);
-        for (int t = threadIdx.x; t < g * NZ; t += TB) {
-            const int fi = t / NZ, z = t - fi * NZ, f = f0 + fi;
+    double2 v[PER];
+    auto fetch = [&](int f) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int z = threadIdx.x + i * TB;
             const int kk = z <= K ? z : (z >= NZ - K ? z - NZ + NK : -1);
-            double2 v = czero();
-            if (kk >= 0) {
+            v[i] = czero();
+            if (z < NZ && kk >= 0) {
                 if (f < 3) {
-                    v = u[fidx(p, f, j, m, kk)];
+                    v[i] = u[fidx(p, f, j, m, kk)];
                 } else if (f == 3) {
-                    const double a = alpha_of(p, kk);
-                    v = csub(cscale(cmuli(u[fidx(p, 2, j, m, kk)]), m / r),
-                             cscale(cmuli(u[fidx(p, 1, j, m, kk)]), a));
+                    v[i] = csub(cscale(cmuli(u[fidx(p, 2, j, m, kk)]), mr),
+                                cscale(cmuli(u[fidx(p, 1, j, m, kk)]), alpha_of(p, kk)));
                 } else if (f < 6) {
-                    v = aux[fidx(p, f - 4, j, m, kk)];
+                    v[i] = aux[fidx(p, f - 4, j, m, kk)];
                 } else {
-                    v = y[fidx(p, f - 6, j, m, kk)];
+                    v[i] = y[fidx(p, f - 6, j, m, kk)];
                 }
             }
-            A[lp(t)] = v;
+        }
+    };
+    fetch(0);
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int z = threadIdx.x + i * TB;
+            if (z < NZ) A[lp(z)] = v[i];
         }
         __syncthreads();
-        const double2* res = fft_ct<NZ, true>(A, Bf, g, tw);
-        for (int t = threadIdx.x; t < g * NZ; t += TB) {
-            const int fi = t / NZ, z = t - fi * NZ;
-            zb[((size_t)(j * NF + f0 + fi) * mp1 + m) * NZ + z] = res[lp(t)];
-        }
+        if (f + 1 < NF) fetch(f + 1);
+        const double2* res = fft_ct<NZ, true>(A, Bf, 1, tw);
+        double2* row = zb + ((size_t)(j * NF + f) * mp1 + m) * NZ;
+        for (int z = threadIdx.x; z < NZ; z += TB) row[z] = res[lp(z)];
         __syncthreads();
     }
 }
 
-// Forward axial transforms of NFO theta-pass outputs, truncated to the band.
+// Forward axial transforms of NFO theta-pass outputs, truncated to the band;
+// one field per round with the next field prefetched into registers.
 template <int NZ, int NFO>
-__global__ __launch_bounds__(TB) void k_zfwd_t(KP p, int G, const double2* __restrict__ tb,
-                                              double2* __restrict__ out0, double2* __restrict__ out1, double scale) {
+__global__ __launch_bounds__(TB) void k_zfwd_t(KP p, const double2* __restrict__ tb, double2* __restrict__ out0,
+                                              double2* __restrict__ out1, double scale) {
     constexpr int K = (NZ - 1) / 3, NK = 2 * K + 1;
+    constexpr int PER = (NZ + TB - 1) / TB;
     extern __shared__ double2 sh[];
     double2* tw = sh;
     double2* A = sh + NZ;
-    double2* Bf = A + lp_size(G * NZ);
+    double2* Bf = A + lp_size(NZ);
     const int m = blockIdx.x, j = blockIdx.y, mp1 = p.mp1;
     for (int t = threadIdx.x; t < NZ; t += TB) tw[t] = p.twz[t];
-    for (int f0 = 0; f0 < NFO; f0 += G) {
-        const int g = min(G, NFO - f0);
-        for (int t = threadIdx.x; t < g * NZ; t += TB) {
-            const int fi = t / NZ, z = t - fi * NZ;
-            A[lp(t)] = tb[((size_t)(j * NFO + f0 + fi) * mp1 + m) * NZ + z];
+    double2 v[PER];
+    auto fetch = [&](int f) {
+        const double2* row = tb + ((size_t)(j * NFO + f) * mp1 + m) * NZ;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int z = threadIdx.x + i * TB;
+            v[i] = z < NZ ? row[z] : czero();
+        }
+    };
+    fetch(0);
+    for (int f = 0; f < NFO; ++f) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int z = threadIdx.x + i * TB;
+            if (z < NZ) A[lp(z)] = v[i];
         }
         __syncthreads();
-        const double2* res = fft_ct<NZ, false>(A, Bf, g, tw);
-        for (int t = threadIdx.x; t < g * NK; t += TB) {
-            const int fi = t / NK, kk = t - fi * NK, f = f0 + fi;
+        if (f + 1 < NFO) fetch(f + 1);
+        const double2* res = fft_ct<NZ, false>(A, Bf, 1, tw);
+        double2* out = f < 3 ? out0 : out1;
+        const int c = f < 3 ? f : f - 3;
+        for (int kk = threadIdx.x; kk < NK; kk += TB) {
             const int pos = kk <= K ? kk : NZ - (NK - kk);
-            const double2 v = cscale(res[lp(fi * NZ + pos)], scale);
-            if (f < 3) out0[fidx(p, f, j, m, kk)] = v;
-            else out1[fidx(p, f - 3, j, m, kk)] = v;
+            out[fidx(p, c, j, m, kk)] = cscale(res[lp(pos)], scale);
         }
         __syncthreads();
     }
 }
 
-// Azimuthal transforms and products for a block of ZB = 2^lzb consecutive z
-// at node j.  Blocks are placed so that consecutive z-blocks of one j run on
-// the same XCD (hardware round-robin over 8 XCDs by workgroup id), where they
-// share L2 lines of the [j][f][m][z] intermediates.
-template <int NT, int ADJ>
-__global__ __launch_bounds__(TB) void k_theta_t(KP p, int lzb, int nzb, const double2* __restrict__ zb,
+// Azimuthal transforms and products.  A block owns Q consecutive tiles of ZB
+// axial points at node j and walks through them, loading the next tile's
+// inputs into registers while the current one is transformed.  Blocks are
+// placed so that consecutive tiles of one j run on the same XCD (hardware
+// round-robin over 8 XCDs by workgroup id), where they share L2 lines of the
+// [j][f][m][z] intermediates.
+template <int NT, int ADJ, int ZB>
+__global__ __launch_bounds__(TB) void k_theta_t(KP p, int nq, int Q, const double2* __restrict__ zb,
                                                double2* __restrict__ tb, TimeArg ta) {
     constexpr int M = (NT - 1) / 3, MP1 = M + 1;
     constexpr int NF = ADJ ? 9 : 6, NFO = ADJ ? 6 : 3;
-    const int nblk = nzb * p.nr;
+    constexpr int H = ZB / 2;
+    constexpr int NIN = ADJ ? 4 * ZB + H : 3 * ZB;
+    constexpr int NOUT = ADJ ? 3 * ZB : ZB + H;
+    constexpr int NSEQ = NIN > NOUT ? NIN : NOUT;
+    constexpr int NPAIR = ADJ ? 4 : 3;
+    constexpr int NP = NPAIR * MP1 * ZB;              // paired-field loads per tile
+    constexpr int NL = NP + (ADJ ? H * MP1 : 0);       // + paired z columns of y_z
+    constexpr int PER = (NL + TB - 1) / TB;
+    constexpr int NGAP = NT - 2 * M - 1;
+    const int nblk = nq * p.nr;
     const int per = (nblk + 7) >> 3;
     const int L = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (L >= nblk) return;
-    const int j = L / nzb, z0 = (L - j * nzb) << lzb;
-    const int ZB = 1 << lzb, H = ZB >> 1, nz = p.nz;
-    const int nin = ADJ ? 4 * ZB + H : 3 * ZB;
-    const int nout = ADJ ? 3 * ZB : ZB + H;
-    const int nseq = nin > nout ? nin : nout;
+    const int j = L / nq, zq = L - j * nq, nz = p.nz;
     extern __shared__ double2 sh[];
     double2* tw = sh;
     double2* A = sh + NT;
-    double2* Bf = A + lp_size(nseq * NT);
+    double2* Bf = A + lp_size(NSEQ * NT);
     for (int t = threadIdx.x; t < NT; t += TB) tw[t] = p.twt[t];
-    // zero the unretained azimuthal band of every input sequence
-    constexpr int NGAP = NT - 2 * M - 1;
-    if constexpr (NGAP > 0) {
-        for (int t = threadIdx.x; t < nin * NGAP; t += TB) {
-            const int s = t / NGAP, q = t - s * NGAP;
-            A[lp(s * NT + M + 1 + q)] = czero();
-        }
-    }
-    // pairs of real fields packed as xa + i xb
-    constexpr int NPAIR = ADJ ? 4 : 3;
-    for (int t = threadIdx.x; t < (NPAIR * MP1) << lzb; t += TB) {
-        const int zi = t & (ZB - 1), q = t >> lzb;
-        const int pi = q / MP1, m = q - pi * MP1;
-        const double2 xa = zb[((size_t)(j * NF + 2 * pi) * MP1 + m) * nz + z0 + zi];
-        const double2 xb = zb[((size_t)(j * NF + 2 * pi + 1) * MP1 + m) * nz + z0 + zi];
-        const int s = (pi * ZB + zi) * NT;
-        if (m == 0) {
-            A[lp(s)] = make_double2(xa.x, xb.x);
-        } else {
-            A[lp(s + m)] = make_double2(xa.x - xb.y, xa.y + xb.x);
-            A[lp(s + NT - m)] = make_double2(xa.x + xb.y, -xa.y + xb.x);
-        }
-    }
-    if constexpr (ADJ) {   // y_z: pairs of z columns (zi, zi + H)
-        for (int t = threadIdx.x; t < H * MP1; t += TB) {
-            const int m = t / H, zi = t - m * H;
-            const double2 xa = zb[((size_t)(j * NF + 8) * MP1 + m) * nz + z0 + zi];
-            const double2 xb = zb[((size_t)(j * NF + 8) * MP1 + m) * nz + z0 + zi + H];
-            const int s = (4 * ZB + zi) * NT;
-            if (m == 0) {
-                A[lp(s)] = make_double2(xa.x, xb.x);
-            } else {
-                A[lp(s + m)] = make_double2(xa.x - xb.y, xa.y + xb.x);
-                A[lp(s + NT - m)] = make_double2(xa.x + xb.y, -xa.y + xb.x);
-            }
-        }
-    }
-    __syncthreads();
-    double2* R1 = fft_ct<NT, true>(A, Bf, nin, tw);
-    double2* O = (R1 == A) ? Bf : A;
     double U, Om, cw, sw;
     phase_of(p, ta, cw, sw);
     base_at(p, j, cw, sw, U, Om);
-    for (int t = threadIdx.x; t < ZB * NT; t += TB) {
-        const int zi = t / NT, th = t - zi * NT;
-        const double2 s0 = R1[lp((0 * ZB + zi) * NT + th)];
-        const double2 s1 = R1[lp((1 * ZB + zi) * NT + th)];
-        const double2 s2 = R1[lp((2 * ZB + zi) * NT + th)];
-        const double ur = s0.x, ut = s0.y, uz = s1.x, wr = s1.y, wt = s2.x, wz = s2.y;
-        if constexpr (!ADJ) {
-            const double uzU = uz + U;
-            const double Nr = ut * wz - uzU * wt - uz * Om;
-            const double Nt = uzU * wr - ur * wz;
-            const double Nz = ur * (wt + Om) - ut * wr;
-            O[lp(zi * NT + th)] = make_double2(Nr, Nt);
-            // N_z of columns zi and zi + H share one complex sequence
-            const int q = ZB + (zi < H ? zi : zi - H);
-            double* slot = reinterpret_cast<double*>(&O[lp(q * NT + th)]);
-            slot[zi < H ? 0 : 1] = Nz;
-        } else {
-            const double2 s3 = R1[lp((3 * ZB + zi) * NT + th)];
-            const double2 s4 = R1[lp((4 * ZB + (zi < H ? zi : zi - H)) * NT + th)];
-            const double yr = s3.x, yt = s3.y, yz = (zi < H) ? s4.x : s4.y;
-            const double wtO = wt + Om, uzU = uz + U;
-            const double Ar = wtO * yz - wz * yt;
-            const double At = wz * yr - wr * yz;
-            const double Az = wr * yt - wtO * yr;
-            const double Br = yt * uzU - yz * ut;
-            const double Bt = yz * ur - yr * uzU;
-            const double Bz = yr * ut - yt * ur;
-            O[lp(zi * NT + th)] = make_double2(Ar, At);
-            O[lp((ZB + zi) * NT + th)] = make_double2(Az, Br);
-            O[lp((2 * ZB + zi) * NT + th)] = make_double2(Bt, Bz);
+    const double2* base = zb + (size_t)j * NF * MP1 * nz;
+    double2 xa[PER], xb[PER];
+    auto fetch = [&](int z0) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = threadIdx.x + i * TB;
+            if (e < NP) {
+                const int zi = e % ZB, q = e / ZB;
+                const int pi = q / MP1, m = q - pi * MP1;
+                xa[i] = base[(size_t)(2 * pi * MP1 + m) * nz + z0 + zi];
+                xb[i] = base[(size_t)((2 * pi + 1) * MP1 + m) * nz + z0 + zi];
+            } else if (ADJ && e < NL) {
+                const int e2 = e - NP, m = e2 / H, zi = e2 - m * H;
+                xa[i] = base[(size_t)(8 * MP1 + m) * nz + z0 + zi];
+                xb[i] = base[(size_t)(8 * MP1 + m) * nz + z0 + zi + H];
+            }
         }
-    }
-    __syncthreads();
-    const double2* R2 = fft_ct<NT, false>(O, R1, nout, tw);
-    for (int t = threadIdx.x; t < (NFO * MP1) << lzb; t += TB) {
-        const int zi = t & (ZB - 1), q0 = t >> lzb;
-        const int f = q0 / MP1, m = q0 - f * MP1;
-        int q, half;
-        if constexpr (!ADJ) {
-            if (f < 2) { q = zi; half = f; }
-            else { q = ZB + (zi < H ? zi : zi - H); half = (zi < H) ? 0 : 1; }
-        } else {
-            q = (f >> 1) * ZB + zi;
-            half = f & 1;
+    };
+    // pairs of real fields packed as xa + i xb into the Hermitian halves
+    auto place = [&]() {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = threadIdx.x + i * TB;
+            if (e >= NL) continue;
+            int s, m;
+            if (e < NP) {
+                const int zi = e % ZB, q = e / ZB;
+                const int pi = q / MP1;
+                m = q - pi * MP1;
+                s = (pi * ZB + zi) * NT;
+            } else {
+                const int e2 = e - NP;
+                m = e2 / H;
+                s = (4 * ZB + (e2 - m * H)) * NT;
+            }
+            if (m == 0) {
+                A[lp(s)] = make_double2(xa[i].x, xb[i].x);
+            } else {
+                A[lp(s + m)] = make_double2(xa[i].x - xb[i].y, xa[i].y + xb[i].x);
+                A[lp(s + NT - m)] = make_double2(xa[i].x + xb[i].y, -xa[i].y + xb[i].x);
+            }
         }
-        // unpack the two real transforms sharing sequence q
-        const double2 a = R2[lp(q * NT + m)];
-        const double2 b = cconj(R2[lp(q * NT + (m == 0 ? 0 : NT - m))]);
-        const double2 v = half == 0 ? cscale(cadd(a, b), 0.5) : cscale(cmuli(csub(b, a)), 0.5);
-        tb[((size_t)(j * NFO + f) * MP1 + m) * nz + z0 + zi] = v;
+    };
+    int z0 = zq * Q * ZB;
+    fetch(z0);
+    for (int tile = 0; tile < Q; ++tile, z0 += ZB) {
+        if constexpr (NGAP > 0) {
+            for (int t = threadIdx.x; t < NIN * NGAP; t += TB) {
+                const int s = t / NGAP, q = t - s * NGAP;
+                A[lp(s * NT + M + 1 + q)] = czero();
+            }
+        }
+        place();
+        __syncthreads();
+        if (tile + 1 < Q) fetch(z0 + ZB);
+        double2* R1 = fft_ct<NT, true>(A, Bf, NIN, tw);
+        double2* O = (R1 == A) ? Bf : A;
+        for (int t = threadIdx.x; t < ZB * NT; t += TB) {
+            const int zi = t / NT, th = t - zi * NT;
+            const double2 s0 = R1[lp((0 * ZB + zi) * NT + th)];
+            const double2 s1 = R1[lp((1 * ZB + zi) * NT + th)];
+            const double2 s2 = R1[lp((2 * ZB + zi) * NT + th)];
+            const double ur = s0.x, ut = s0.y, uz = s1.x, wr = s1.y, wt = s2.x, wz = s2.y;
+            if constexpr (!ADJ) {
+                const double uzU = uz + U;
+                const double Nr = ut * wz - uzU * wt - uz * Om;
+                const double Nt = uzU * wr - ur * wz;
+                const double Nz = ur * (wt + Om) - ut * wr;
+                O[lp(zi * NT + th)] = make_double2(Nr, Nt);
+                // N_z of columns zi and zi + H share one complex sequence
+                const int q = ZB + (zi < H ? zi : zi - H);
+                double* slot = reinterpret_cast<double*>(&O[lp(q * NT + th)]);
+                slot[zi < H ? 0 : 1] = Nz;
+            } else {
+                const double2 s3 = R1[lp((3 * ZB + zi) * NT + th)];
+                const double2 s4 = R1[lp((4 * ZB + (zi < H ? zi : zi - H)) * NT + th)];
+                const double yr = s3.x, yt = s3.y, yz = (zi < H) ? s4.x : s4.y;
+                const double wtO = wt + Om, uzU = uz + U;
+                const double Ar = wtO * yz - wz * yt;
+                const double At = wz * yr - wr * yz;
+                const double Az = wr * yt - wtO * yr;
+                const double Br = yt * uzU - yz * ut;
+                const double Bt = yz * ur - yr * uzU;
+                const double Bz = yr * ut - yt * ur;
+                O[lp(zi * NT + th)] = make_double2(Ar, At);
+                O[lp((ZB + zi) * NT + th)] = make_double2(Az, Br);
+                O[lp((2 * ZB + zi) * NT + th)] = make_double2(Bt, Bz);
+            }
+        }
+        __syncthreads();
+        const double2* R2 = fft_ct<NT, false>(O, R1, NOUT, tw);
+        for (int t = threadIdx.x; t < NFO * MP1 * ZB; t += TB) {
+            const int zi = t % ZB, q0 = t / ZB;
+            const int f = q0 / MP1, m = q0 - f * MP1;
+            int q, half;
+            if constexpr (!ADJ) {
+                if (f < 2) { q = zi; half = f; }
+                else { q = ZB + (zi < H ? zi : zi - H); half = (zi < H) ? 0 : 1; }
+            } else {
+                q = (f >> 1) * ZB + zi;
+                half = f & 1;
+            }
+            // unpack the two real transforms sharing sequence q
+            const double2 a = R2[lp(q * NT + m)];
+            const double2 b = cconj(R2[lp(q * NT + (m == 0 ? 0 : NT - m))]);
+            const double2 v = half == 0 ? cscale(cadd(a, b), 0.5) : cscale(cmuli(csub(b, a)), 0.5);
+            tb[((size_t)(j * NFO + f) * MP1 + m) * nz + z0 + zi] = v;
+        }
+        __syncthreads();
     }
 }
 
@@ -593,7 +639,7 @@ bool fast_nt(int nt) {
 }
 
 size_t zpass_lds(const npo_plan_s& p, int G) {
-    if (fast_nz(p.nz)) return ((size_t)p.nz + 2 * lp_size(G * p.nz)) * sizeof(double2);
+    if (fast_nz(p.nz)) return ((size_t)p.nz + 2 * lp_size(p.nz)) * sizeof(double2);   // one field per round
     return (size_t)2 * G * p.nz * sizeof(double2);
 }
 size_t theta_lds(const npo_plan_s& p, int ZB, int adj) {
@@ -610,10 +656,10 @@ static void launch_zinv(const npo_plan_s& p, int adj, const double2* u, const do
     const size_t sh = zpass_lds(p, G);
     const dim3 grid(p.mp1, p.nr);
     switch (p.nz) {
-#define NPO_CASE(N)                                                                                  \
-    case N:                                                                                          \
-        if (adj) hipLaunchKernelGGL((k_zinv_t<N, 9>), grid, dim3(TB), sh, st, p.kp, G, u, aux, y, zb); \
-        else hipLaunchKernelGGL((k_zinv_t<N, 6>), grid, dim3(TB), sh, st, p.kp, G, u, aux, y, zb);      \
+#define NPO_CASE(N)                                                                                \
+    case N:                                                                                        \
+        if (adj) hipLaunchKernelGGL((k_zinv_t<N, 9>), grid, dim3(TB), sh, st, p.kp, u, aux, y, zb); \
+        else hipLaunchKernelGGL((k_zinv_t<N, 6>), grid, dim3(TB), sh, st, p.kp, u, aux, y, zb);      \
         return;
         NPO_NZ_SIZES(NPO_CASE)
 #undef NPO_CASE
@@ -628,10 +674,10 @@ static void launch_zfwd(const npo_plan_s& p, int adj, const double2* tb, double2
     const size_t sh = zpass_lds(p, G);
     const dim3 grid(p.mp1, p.nr);
     switch (p.nz) {
-#define NPO_CASE(N)                                                                                         \
-    case N:                                                                                                 \
-        if (adj) hipLaunchKernelGGL((k_zfwd_t<N, 6>), grid, dim3(TB), sh, st, p.kp, G, tb, out0, out1, scale); \
-        else hipLaunchKernelGGL((k_zfwd_t<N, 3>), grid, dim3(TB), sh, st, p.kp, G, tb, out0, out1, scale);     \
+#define NPO_CASE(N)                                                                                      \
+    case N:                                                                                              \
+        if (adj) hipLaunchKernelGGL((k_zfwd_t<N, 6>), grid, dim3(TB), sh, st, p.kp, tb, out0, out1, scale); \
+        else hipLaunchKernelGGL((k_zfwd_t<N, 3>), grid, dim3(TB), sh, st, p.kp, tb, out0, out1, scale);     \
         return;
         NPO_NZ_SIZES(NPO_CASE)
 #undef NPO_CASE
@@ -640,25 +686,45 @@ static void launch_zfwd(const npo_plan_s& p, int adj, const double2* tb, double2
     }
 }
 
+// Tiles per azimuthal block: the largest of 4, 2 that divides the tiles of a
+// radial node and still leaves at least 2048 blocks (8 per CU), else 1.
+static int theta_tiles_per_block(const npo_plan_s& p, int ZB) {
+    const int tiles = p.nz / ZB;
+    for (int q : {4, 2})
+        if (tiles % q == 0 && (long long)(tiles / q) * p.nr >= 2048) return q;
+    return 1;
+}
+
+template <int NT, int ADJ>
+static void launch_theta_zb(const npo_plan_s& p, int ZB, dim3 grid, size_t sh, int nq, int Q, const double2* zb,
+                            double2* tb, const TimeArg& ta, hipStream_t st) {
+    if (ZB == 8) hipLaunchKernelGGL((k_theta_t<NT, ADJ, 8>), grid, dim3(TB), sh, st, p.kp, nq, Q, zb, tb, ta);
+    else if (ZB == 4) hipLaunchKernelGGL((k_theta_t<NT, ADJ, 4>), grid, dim3(TB), sh, st, p.kp, nq, Q, zb, tb, ta);
+    else hipLaunchKernelGGL((k_theta_t<NT, ADJ, 2>), grid, dim3(TB), sh, st, p.kp, nq, Q, zb, tb, ta);
+}
+
 static void launch_theta(const npo_plan_s& p, int adj, const double2* zb, double2* tb, const TimeArg& ta,
                          hipStream_t st) {
     const int ZB = adj ? p.zb_theta_adj : p.zb_theta_fwd;
     const size_t sh = theta_lds(p, ZB, adj);
-    int lzb = 0;
-    while ((1 << lzb) < ZB) ++lzb;
-    const int nzb = p.nz / ZB;
-    const int nblk = nzb * p.nr;
+    if (!fast_nt(p.nt)) {
+        hipLaunchKernelGGL(k_theta, dim3(p.nz / ZB, p.nr), dim3(256), sh, st, p.kp, adj, ZB, zb, tb, ta);
+        return;
+    }
+    const int Q = theta_tiles_per_block(p, ZB);
+    const int nq = p.nz / ZB / Q;
+    const int nblk = nq * p.nr;
     const dim3 grid((nblk + 7) / 8 * 8);
     switch (p.nt) {
-#define NPO_CASE(N)                                                                                          \
-    case N:                                                                                                  \
-        if (adj) hipLaunchKernelGGL((k_theta_t<N, 1>), grid, dim3(TB), sh, st, p.kp, lzb, nzb, zb, tb, ta); \
-        else hipLaunchKernelGGL((k_theta_t<N, 0>), grid, dim3(TB), sh, st, p.kp, lzb, nzb, zb, tb, ta);     \
+#define NPO_CASE(N)                                                                 \
+    case N:                                                                         \
+        if (adj) launch_theta_zb<N, 1>(p, ZB, grid, sh, nq, Q, zb, tb, ta, st);     \
+        else launch_theta_zb<N, 0>(p, ZB, grid, sh, nq, Q, zb, tb, ta, st);         \
         return;
         NPO_NT_SIZES(NPO_CASE)
 #undef NPO_CASE
     default:
-        hipLaunchKernelGGL(k_theta, dim3(nzb, p.nr), dim3(256), sh, st, p.kp, adj, ZB, zb, tb, ta);
+        return;
     }
 }
 

@@ -40,3 +40,48 @@ def test_host_checkpoint_schedule_matches_closed_form():
             assert rec + (n - 1) == closed_form(n, s)[0], (n, s)
     for n, s in ((4000, 8), (4000, 32), (4000, 128), (4000, 4000), (9817, 4000)):
         assert npo.npo_ckpt_count(n, s) + n - 1 == closed_form(n, s)[0]
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libnpo.so not built")
+@pytest.mark.parametrize("grid,code", [
+    ((7, 12, 24), -4),     # nr below the 7-point stencil
+    ((65, 12, 24), -4),    # nr above one workgroup's column
+    ((16, 7, 24), -4),     # ntheta not 2^a 3^b
+    ((16, 12, 25), -4),    # nz not 2^a 3^b
+    ((16, 12, 27), -4),    # nz odd (two axial columns share one azimuthal transform)
+    ((16, 12, 4096), -4),  # nz above the supported range
+])
+def test_plan_create_rejects_unsupported_grids_before_any_device_call(grid, code):
+    """Argument checks return their status synchronously, with a message, and
+    touch no device (this runs without a GPU)."""
+    from paper_2509_10103_amd import npo
+    with pytest.raises(npo.NpoError) as e:
+        npo.npo_plan_create(*grid, 10.0, 2000.0, 8.0, 1.0, 0.01, 0.0, 10)
+    assert f"npo error {code}" in str(e.value)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libnpo.so not built")
+@pytest.mark.parametrize("args", [
+    (16, 12, 24, -1.0, 2000.0, 8.0, 1.0, 0.01, 0.0, 10, 2),   # lz <= 0
+    (16, 12, 24, 10.0, 0.0, 8.0, 1.0, 0.01, 0.0, 10, 2),      # Re <= 0
+    (16, 12, 24, 10.0, 2000.0, 8.0, -1.0, 0.01, 0.0, 10, 2),  # A < 0
+    (16, 12, 24, 10.0, 2000.0, 8.0, 1.0, 0.0, 0.0, 10, 2),    # dt <= 0
+    (16, 12, 24, 10.0, 2000.0, 8.0, 1.0, 0.01, 0.0, 0, 2),    # nsteps < 1
+    (16, 12, 24, 10.0, 2000.0, 8.0, 1.0, 0.01, 0.0, 10, 0),   # no corrector pass
+    (16, 12, 24, 10.0, 2000.0, 8.0, 1.0, 0.01, 0.0, 10, 4),   # more passes than supported
+])
+def test_plan_create_rejects_bad_parameters(args):
+    from paper_2509_10103_amd import npo
+    with pytest.raises(npo.NpoError) as e:
+        npo.npo_plan_create(*args)
+    assert "npo error -1" in str(e.value)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libnpo.so not built")
+def test_null_arguments_are_rejected():
+    from paper_2509_10103_amd import npo
+    L = npo.lib()
+    assert L.npo_plan_create(None, None, None, 0, None) == -1
+    assert L.npo_forward_step(None, None, None, None, 0, None) == -1
+    assert L.npo_ckpt_count(0, 1, None) == -1
+    assert b"null" in L.npo_last_error() or b"bad" in L.npo_last_error()

@@ -1,0 +1,112 @@
+"""Edge cases of the HIP path against the oracle: the largest compiled
+transform lengths, the generic (run-time radix) kernels at the largest axial
+length, a steady base flow (A = 0), the one-step horizon with a single
+checkpoint slot and the longest recompute chain (one slot, many steps)."""
+import math
+
+import numpy as np
+import pytest
+
+from tests.gpu_common import make, to_dev, to_host, relerr, maxrel, seed_field
+from oracle.checkpoint import closed_form
+from paper_2509_10103_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+# largest compiled lengths (N_theta = 128, N_z = 1536), few radial nodes
+MAXFAST = dict(nr=12, nt=128, nz=1536, lz=100.0, re=2000.0, wo=8.0, amp=1.0, dt=0.02, t0=0.5)
+# N_theta = 54 and N_z = 2048 have no compiled kernels: the generic transforms run
+GENERIC = dict(nr=10, nt=54, nz=2048, lz=120.0, re=2500.0, wo=6.0, amp=0.7, dt=0.02, t0=3.0)
+STEADY = dict(nr=16, nt=12, nz=24, lz=2 * math.pi, re=1500.0, wo=8.0, amp=0.0, dt=0.02, t0=0.3)
+
+
+@pytest.fixture(scope="module", params=[MAXFAST, GENERIC], ids=["max-compiled", "generic-2048"])
+def big(request):
+    cfg = request.param
+    P, G = make(cfg)
+    P.cache_limit = 0
+    u = synth.solenoidal_modes(P.r, P.M, P.K, P.lz, 3) * 1e-2
+    y = synth.random_field(P.shape, 4)
+    rng = np.random.default_rng(9)
+    modes = [(0, 0), (P.M, P.K), (P.M, P.K + 1)] + \
+            [(int(rng.integers(0, P.M + 1)), int(rng.integers(0, P.nk))) for _ in range(12)]
+    return cfg, P, G, u, y, modes
+
+
+def test_nonlinear_term_at_extreme_lengths(big):
+    cfg, P, G, u, y, modes = big
+    from paper_2509_10103_amd import npo
+    out = G.field()
+    npo.npo_nonlinear(G.handle, G.ws, to_dev(u), cfg["t0"] + 0.7, out)
+    assert maxrel(to_host(out), P.N(u, cfg["t0"] + 0.7)) < 1e-12
+
+
+def test_nonlinear_adjoint_term_at_extreme_lengths(big):
+    """<N'(u)^+ y, v>_W = <y, N'(u) v>_W with the oracle's tangent, for a random v."""
+    cfg, P, G, u, y, modes = big
+    from paper_2509_10103_amd import npo
+    out = G.field()
+    t = cfg["t0"] + 0.7
+    npo.npo_nonlinear_adj(G.handle, G.ws, to_dev(u), t, to_dev(y), out)
+    v = synth.random_field(P.shape, 5)
+    lhs = P.wdot(to_host(out), v)
+    rhs = P.wdot(y, P.N_tan(u, t, v))
+    assert abs(lhs - rhs) < 1e-11 * math.sqrt(P.wdot(y, y) * P.wdot(P.N_tan(u, t, v), P.N_tan(u, t, v)))
+
+
+def test_solve_at_extreme_lengths_sampled(big):
+    cfg, P, G, u, y, modes = big
+    from paper_2509_10103_amd import npo
+    out = G.field()
+    npo.npo_solve(G.handle, G.ws, to_dev(y), out)
+    h = to_host(out)
+    for m, kk in modes:
+        ref = P.S_mode(m, P.alpha[kk], y[:, :, m, kk:kk + 1])[:, :, 0]
+        assert maxrel(h[:, :, m, kk], ref) < 1e-11, (m, kk)
+
+
+def test_steady_base_flow_step_and_adjoint():
+    """A = 0: the base flow is steady Poiseuille (no Womersley part)."""
+    P, G = make(STEADY)
+    from paper_2509_10103_amd import npo
+    u = seed_field(P, 7, 1e-3)
+    y = synth.random_field(P.shape, 8)
+    out = G.field()
+    npo.npo_forward_step(G.handle, G.ws, to_dev(u), out, 3)
+    assert relerr(P, to_host(out), P.step(u, 3)) < 1e-12
+    lam = G.field()
+    npo.npo_adjoint_step(G.handle, G.ws, to_dev(u), to_dev(y), lam, 3)
+    assert relerr(P, to_host(lam), P.step_adj(u, 3, y)) < 1e-11
+
+
+def test_one_step_horizon_with_one_slot():
+    """N = 1, N_G = 1: the sweep is one step, the adjoint sweep one adjoint step."""
+    cfg = dict(STEADY, amp=0.8, nsteps=1)
+    P, G = make(cfg)
+    from paper_2509_10103_amd import npo
+    u0 = seed_field(P, 11, 1e-4)
+    ck, uN, lam0 = G.arena(1), G.field(), G.field()
+    npo.npo_forward_run(G.handle, G.ws, ck, 1, to_dev(u0), uN)
+    u1 = P.step(u0, 0)
+    assert relerr(P, to_host(uN), u1) < 1e-12
+    nrec = npo.npo_adjoint_run(G.handle, G.ws, ck, 1, uN, lam0)
+    assert nrec == 0
+    assert relerr(P, to_host(lam0), P.step_adj(u0, 0, u1)) < 1e-11
+
+
+def test_single_slot_longest_recompute_equals_full_storage():
+    """N = 20 with one slot re-advances from u0 before every adjoint step
+    (N(N-1)/2 advances) and must give the stored-everything result bitwise."""
+    cfg = dict(STEADY, amp=0.8, nsteps=20)
+    P, G = make(cfg)
+    from paper_2509_10103_amd import npo
+    u0 = to_dev(seed_field(P, 12, 1e-4))
+    res = {}
+    for nck in (1, 20):
+        ck, uN, lam0 = G.arena(nck), G.field(), G.field()
+        npo.npo_forward_run(G.handle, G.ws, ck, nck, u0, uN)
+        nrec = npo.npo_adjoint_run(G.handle, G.ws, ck, nck, uN, lam0)
+        assert nrec + 19 == closed_form(20, nck)[0]
+        res[nck] = to_host(lam0)
+    assert nrec == 0
+    assert np.array_equal(res[1], res[20])
