@@ -262,14 +262,40 @@ __global__ void k_zfwd(KP p, int nfo, int G, const double2* __restrict__ tb, dou
 
 // ============================================ compile-time-sized transforms
 constexpr int TB = 256;   // threads per block of the transform kernels
+// Radix ceiling of the azimuthal transforms: the adjoint pass (4.5 sequences
+// per axial point) gains from fewer LDS passes, the forward pass (1.5-3) from
+// more butterflies per pass (both measured at 96 x 768).
+template <int ADJ>
+constexpr int theta_maxr() { return ADJ ? 16 : 8; }
 
 // Padded LDS index: one complex of padding per 16, so that the strided
 // accesses of the early Stockham passes spread over the LDS banks.
 __device__ __forceinline__ int lp(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int lp_size(int n) { return n + (n >> 4) + 1; }
 
+// Radix plans.  With a ceiling of 8 (few sequences per block: parallelism
+// per pass matters) the radices are taken greedily from {8, 4, 3, 2}; with a
+// ceiling of 16 (many sequences per block: fewer LDS passes matter) the plan
+// has the fewest passes over {16, 12, 8, 6, 4, 3, 2}, the largest first radix
+// among such plans.
+constexpr int kRadices[7] = {16, 12, 8, 6, 4, 3, 2};
+__host__ __device__ constexpr int min_passes(int n) {
+    if (n == 1) return 0;
+    int best = 1 << 20;
+    for (int i = 0; i < 7; ++i)
+        if (n % kRadices[i] == 0) {
+            const int c = 1 + min_passes(n / kRadices[i]);
+            if (c < best) best = c;
+        }
+    return best;
+}
+template <int MAXR>
 __host__ __device__ constexpr int pick_radix(int rem) {
-    return rem % 8 == 0 ? 8 : (rem % 4 == 0 ? 4 : (rem % 3 == 0 ? 3 : 2));
+    if (MAXR <= 8) return rem % 8 == 0 ? 8 : (rem % 4 == 0 ? 4 : (rem % 3 == 0 ? 3 : 2));
+    const int target = min_passes(rem);
+    for (int i = 0; i < 7; ++i)
+        if (rem % kRadices[i] == 0 && 1 + min_passes(rem / kRadices[i]) == target) return kRadices[i];
+    return 2;
 }
 
 // a * w (forward) or a * conj(w) (inverse)
@@ -323,12 +349,71 @@ __device__ __forceinline__ void dft8(double2* v) {
     v[2] = cadd(e2, r2); v[6] = csub(e2, r2);
     v[3] = cadd(e3, r3); v[7] = csub(e3, r3);
 }
+
+// exp(-2 pi i k / R) for the constant twiddles inside the composite radices
+template <int R>
+__device__ __forceinline__ double2 unit_root(int k);
+template <>
+__device__ __forceinline__ double2 unit_root<16>(int k) {
+    constexpr double c[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                              0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                              -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+                              0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+    return make_double2(c[k & 15], -c[(k + 12) & 15]);   // sin(x) = cos(x - pi/2)
+}
+template <>
+__device__ __forceinline__ double2 unit_root<12>(int k) {
+    constexpr double c[12] = {1.0, 0.86602540378443864676, 0.5, 0.0, -0.5, -0.86602540378443864676,
+                              -1.0, -0.86602540378443864676, -0.5, 0.0, 0.5, 0.86602540378443864676};
+    return make_double2(c[k % 12], -c[(k + 9) % 12]);
+}
+template <>
+__device__ __forceinline__ double2 unit_root<6>(int k) {
+    constexpr double c[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
+    constexpr double s[6] = {0.0, 0.86602540378443864676, 0.86602540378443864676, 0.0,
+                             -0.86602540378443864676, -0.86602540378443864676};
+    return make_double2(c[k % 6], -s[k % 6]);
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft(double2* v);
+
+// Composite length R = R1 * R2 (Cooley-Tukey in registers): length-R2 DFTs
+// over n2 of v[n1 + R1 n2], twiddles w_R^(n1 k2), length-R1 DFTs over n1;
+// output k = k2 + R2 k1 in natural order.
+template <int R1, int R2, bool INV>
+__device__ __forceinline__ void dft_split(double2* v) {
+    constexpr int R = R1 * R2;
+    double2 y[R1][R2];
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) {
+        double2 c[R2];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) c[n2] = v[n1 + R1 * n2];
+        dft<R2, INV>(c);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) y[n1][k2] = (n1 * k2) ? tw_mul<INV>(c[k2], unit_root<R>(n1 * k2)) : c[k2];
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) {
+        double2 c[R1];
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) c[n1] = y[n1][k2];
+        dft<R1, INV>(c);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) v[k2 + R2 * k1] = c[k1];
+    }
+}
+
 template <int R, bool INV>
 __device__ __forceinline__ void dft(double2* v) {
     if constexpr (R == 2) dft2<INV>(v[0], v[1]);
     else if constexpr (R == 3) dft3<INV>(v[0], v[1], v[2]);
     else if constexpr (R == 4) dft4<INV>(v[0], v[1], v[2], v[3]);
-    else dft8<INV>(v);
+    else if constexpr (R == 8) dft8<INV>(v);
+    else if constexpr (R == 6) dft_split<2, 3, INV>(v);
+    else if constexpr (R == 12) dft_split<4, 3, INV>(v);
+    else dft_split<4, 4, INV>(v);   // 16
 }
 
 // One Stockham autosort pass of radix R over B sequences of length N stored
@@ -361,15 +446,15 @@ __device__ __forceinline__ void stockham_pass(const double2* __restrict__ x, dou
 
 // B transforms of length N in LDS (a: data, b: scratch, both padded); the
 // passes end with a barrier.  Returns the buffer holding the result.
-template <int N, bool INV, int NS = 1>
+template <int N, bool INV, int MAXR, int NS = 1>
 __device__ __forceinline__ double2* fft_ct(double2* a, double2* b, int B, const double2* tw) {
     if constexpr (NS == N) {
         return a;
     } else {
-        constexpr int R = pick_radix(N / NS);
+        constexpr int R = pick_radix<MAXR>(N / NS);
         stockham_pass<N, R, NS, INV>(a, b, B, tw);
         __syncthreads();
-        return fft_ct<N, INV, NS * R>(b, a, B, tw);
+        return fft_ct<N, INV, MAXR, NS * R>(b, a, B, tw);
     }
 }
 
@@ -419,7 +504,7 @@ __global__ __launch_bounds__(TB) void k_zinv_t(KP p, const double2* __restrict__
         }
         __syncthreads();
         if (f + 1 < NF) fetch(f + 1);
-        const double2* res = fft_ct<NZ, true>(A, Bf, 1, tw);
+        const double2* res = fft_ct<NZ, true, 8>(A, Bf, 1, tw);
         double2* row = zb + ((size_t)(j * NF + f) * mp1 + m) * NZ;
         for (int z = threadIdx.x; z < NZ; z += TB) row[z] = res[lp(z)];
         __syncthreads();
@@ -457,7 +542,7 @@ __global__ __launch_bounds__(TB) void k_zfwd_t(KP p, const double2* __restrict__
         }
         __syncthreads();
         if (f + 1 < NFO) fetch(f + 1);
-        const double2* res = fft_ct<NZ, false>(A, Bf, 1, tw);
+        const double2* res = fft_ct<NZ, false, 8>(A, Bf, 1, tw);
         double2* out = f < 3 ? out0 : out1;
         const int c = f < 3 ? f : f - 3;
         for (int kk = threadIdx.x; kk < NK; kk += TB) {
@@ -556,7 +641,7 @@ __global__ __launch_bounds__(TB) void k_theta_t(KP p, int nq, int Q, const doubl
         place();
         __syncthreads();
         if (tile + 1 < Q) fetch(z0 + ZB);
-        double2* R1 = fft_ct<NT, true>(A, Bf, NIN, tw);
+        double2* R1 = fft_ct<NT, true, theta_maxr<ADJ>()>(A, Bf, NIN, tw);
         double2* O = (R1 == A) ? Bf : A;
         for (int t = threadIdx.x; t < ZB * NT; t += TB) {
             const int zi = t / NT, th = t - zi * NT;
@@ -591,7 +676,7 @@ __global__ __launch_bounds__(TB) void k_theta_t(KP p, int nq, int Q, const doubl
             }
         }
         __syncthreads();
-        const double2* R2 = fft_ct<NT, false>(O, R1, NOUT, tw);
+        const double2* R2 = fft_ct<NT, false, theta_maxr<ADJ>()>(O, R1, NOUT, tw);
         for (int t = threadIdx.x; t < NFO * MP1 * ZB; t += TB) {
             const int zi = t % ZB, q0 = t / ZB;
             const int f = q0 / MP1, m = q0 - f * MP1;
