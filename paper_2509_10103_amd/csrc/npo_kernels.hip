@@ -422,11 +422,6 @@ struct AdjOut {
     double2* Zout;
     double qy, qz;
 };
-__device__ __forceinline__ void adj_store(const AdjOut& o, size_t id, double2 mu) {
-    if (o.out0) o.out0[id] = mu;
-    if (o.Yout) o.Yout[id] = caxpy(o.Yin ? o.Yin[id] : czero(), o.qy, mu);
-    if (o.Zout) o.Zout[id] = caxpy(o.Zin ? o.Zin[id] : czero(), o.qz, mu);
-}
 template <bool useB>
 __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, double ca, const double2* Bin, double cb,
                                                   AdjOut ao) {
@@ -437,24 +432,48 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
     const int pe = m & 1, po = (m + 1) & 1;
     const size_t opsz = (size_t)N1 * LUW;
     const Slot sl = slot_of(p, g, m, q);
+    constexpr int NJ = NR_MAX / RJ;
     __shared__ double2 sy[3][NR_MAX][RQ];
     __shared__ double2 sphi[NR_MAX][RQ];
     __shared__ double2 sa[RQ];
-
-    // v = ca A + cb W^{-1} curl^H (W B); B staged in LDS for the stencils
-    if constexpr (useB) {
-        for (int j = jg; j < nr; j += RJ)
-            for (int c = 0; c < 3; ++c) sy[c][j][q] = sl.valid ? Bin[fidx(p, c, j, m, sl.kk)] : czero();
-        __syncthreads();
-    }
-    double2 V[NR_MAX / RJ][3];
+    __shared__ double2 sred[RJ][RQ];
+    // every global input is requested up front: A, B (staged in LDS for the
+    // curl stencils), the homogeneous solutions and the accumulators Y, Z
+    const double* hom = p.HOM + ((size_t)sl.ka * p.mp1 + m) * (3 * nr + 1);
+    double2 V[NJ][3], Yv[NJ][3], Zv[NJ][3];
+    double hv[NJ][3];
 #pragma unroll
-    for (int jj = 0; jj < NR_MAX / RJ; ++jj) {
+    for (int jj = 0; jj < NJ; ++jj) {
         const int j = jg + jj * RJ;
-        V[jj][0] = V[jj][1] = V[jj][2] = czero();
+#pragma unroll
+        for (int c = 0; c < 3; ++c) V[jj][c] = Yv[jj][c] = Zv[jj][c] = czero();
+        hv[jj][0] = hv[jj][1] = hv[jj][2] = 0.0;
         if (j < nr && sl.valid) {
-            for (int c = 0; c < 3; ++c) V[jj][c] = cscale(Ain[fidx(p, c, j, m, sl.kk)], ca);
-            if constexpr (useB) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const size_t id = fidx(p, c, j, m, sl.kk);
+                V[jj][c] = cscale(Ain[id], ca);
+                if (ao.Yout && ao.Yin) Yv[jj][c] = ao.Yin[id];
+                if (ao.Zout && ao.Zin) Zv[jj][c] = ao.Zin[id];
+                if constexpr (useB) sy[c][j][q] = Bin[id];
+            }
+            if (j < N1) {
+                hv[jj][0] = hom[j];
+                hv[jj][1] = hom[nr + j];
+                hv[jj][2] = hom[2 * nr + j];
+            }
+        } else if (useB && j < nr) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sy[c][j][q] = czero();
+        }
+    }
+    if constexpr (useB) {
+        // v = ca A + cb W^{-1} curl^H (W B)
+        __syncthreads();
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) {
+            const int j = jg + jj * RJ;
+            if (j < nr && sl.valid) {
                 double2 cr, ct, cz;
                 curlH_row(p, m, sl.al, j, &sy[0][0][q], &sy[1][0][q], &sy[2][0][q], RQ, cr, ct, cz);
                 const double iw = cb / p.w[j];
@@ -463,44 +482,40 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
                 V[jj][2] = caxpy(V[jj][2], iw, cz);
             }
         }
+        __syncthreads();
     }
-    if constexpr (useB) __syncthreads();
+    // y = W v on interior rows in the (+, -, z) basis (the solve's wall output
+    // is identically zero), and each thread's share of the transposed
+    // influence (for the mean mode, flux) sum over its rows
+    double2 pr = czero();
 #pragma unroll
-    for (int jj = 0; jj < NR_MAX / RJ; ++jj) {
+    for (int jj = 0; jj < NJ; ++jj) {
         const int j = jg + jj * RJ;
-        if (j < nr)
-            for (int c = 0; c < 3; ++c) sy[c][j][q] = V[jj][c];
-    }
-    __syncthreads();
-    // y = W lambda on interior rows (the solve's wall output is identically zero)
-    for (int j = jg; j < nr; j += RJ) {
+        if (j >= nr) continue;
         const double wj = (j < N1) ? p.w[j] : 0.0;
-        const double2 yr = cscale(sy[0][j][q], wj), yt = cscale(sy[1][j][q], wj);
-        const double2 yz = cscale(sy[2][j][q], wj);
+        const double2 yr = cscale(V[jj][0], wj), yt = cscale(V[jj][1], wj), yz = cscale(V[jj][2], wj);
+        double2 y0, y1;
         if (sl.mean) {
-            sy[0][j][q] = czero();
-            sy[1][j][q] = yt;
+            y0 = czero();
+            y1 = yt;
+            pr = caxpy(pr, hv[jj][0], yz);
         } else {
-            sy[0][j][q] = cscale(cadd(yr, cmuli(yt)), 0.5);
-            sy[1][j][q] = cscale(csub(yr, cmuli(yt)), 0.5);
+            y0 = cscale(cadd(yr, cmuli(yt)), 0.5);
+            y1 = cscale(csub(yr, cmuli(yt)), 0.5);
+            pr = caxpy(pr, hv[jj][0], y0);
+            pr = caxpy(pr, hv[jj][1], y1);
+            pr = cadd(pr, cscale(cmuli(yz), -sl.al * hv[jj][2]));   // conj(i a uhz) = -i a uhz
         }
+        sy[0][j][q] = y0;
+        sy[1][j][q] = y1;
         sy[2][j][q] = yz;
     }
+    sred[jg][q] = pr;
     __syncthreads();
-    const double* hom = p.HOM + ((size_t)sl.ka * p.mp1 + m) * (3 * nr + 1);
-    // transposed influence (or, for the mean mode, flux) correction
     if (t < RQ && sl.valid) {
-        double2 pr = czero();
-        if (sl.mean) {
-            for (int i = 0; i < N1; ++i) pr = caxpy(pr, hom[i], sy[2][i][q]);
-        } else {
-            for (int i = 0; i < N1; ++i) {
-                pr = caxpy(pr, hom[i], sy[0][i][q]);
-                pr = caxpy(pr, hom[nr + i], sy[1][i][q]);
-                pr = cadd(pr, cscale(cmuli(sy[2][i][q]), -sl.al * hom[2 * nr + i]));   // conj(i a uhz) = -i a uhz
-            }
-        }
-        sa[q] = cscale(pr, 1.0 / hom[3 * nr]);
+        double2 s = czero();
+        for (int i = 0; i < RJ; ++i) s = cadd(s, sred[i][q]);
+        sa[q] = cscale(s, 1.0 / hom[3 * nr]);
     }
     __syncthreads();
     if (sl.valid) {
@@ -551,7 +566,10 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
     }
     __syncthreads();
     if (!sl.valid) return;
-    for (int j = jg; j < nr; j += RJ) {
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+        const int j = jg + jj * RJ;
+        if (j >= nr) continue;
         const double rj = p.r[j];
         const double iw = 1.0 / p.w[j];
         double2 mv[3];
@@ -572,13 +590,20 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
             mv[1] = cscale(cmuli(csub(Rm, Rp)), iw);
             mv[2] = cscale(Rz, iw);
         }
-        for (int c = 0; c < 3; ++c) adj_store(ao, fidx(p, c, j, m, sl.kk), mv[c]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const size_t id = fidx(p, c, j, m, sl.kk);
+            if (ao.out0) ao.out0[id] = mv[c];
+            if (ao.Yout) ao.Yout[id] = caxpy(Yv[jj][c], ao.qy, mv[c]);
+            if (ao.Zout) ao.Zout[id] = caxpy(Zv[jj][c], ao.qz, mv[c]);
+        }
     }
 }
 
 // ----------------------------------------------- adjoint combine (E^dag etc.)
-// out = E^dag Z + A + curl^dag B  (Z, A, B optional).  Z, then B, is staged in
-// LDS and every transposed stencil reads it there through the 13-tap tables.
+// out = E^dag Z + A + curl^dag B  (Z, A, B optional).  All inputs are
+// requested up front; Z, then B, is staged in LDS and every transposed
+// stencil reads it there through the 13-tap tables.
 __global__ __launch_bounds__(RT) void k_final(KP p, const double2* __restrict__ Z, const double2* __restrict__ Ain,
                                               const double2* __restrict__ Bin, double2* __restrict__ out) {
     int g, m;
@@ -590,27 +615,41 @@ __global__ __launch_bounds__(RT) void k_final(KP p, const double2* __restrict__ 
     const double a2 = sl.al * sl.al;
     const double re2 = 0.5 / p.re, idt = 1.0 / p.dt;
     const int pe = m & 1, po = (m + 1) & 1;
+    constexpr int NJ = NR_MAX / RJ;
     __shared__ double2 s3[3][NR_MAX][RQ];
-    double2 E[NR_MAX / RJ][3];
+    double2 E[NJ][3], Av[NJ][3], Bv[NJ][3];
 #pragma unroll
-    for (int jj = 0; jj < NR_MAX / RJ; ++jj) E[jj][0] = E[jj][1] = E[jj][2] = czero();
-    if (Z) {
-        // E_n^T applied to W Z in the (+, -, z) basis
-        for (int j = jg; j < nr; j += RJ) {
-            double2 zp = czero(), zm = czero(), zz = czero();
-            if (sl.valid) {
+    for (int jj = 0; jj < NJ; ++jj) {
+        const int j = jg + jj * RJ;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) E[jj][c] = Av[jj][c] = Bv[jj][c] = czero();
+        if (j >= nr) continue;
+        double2 zp = czero(), zm = czero(), zz = czero();
+        if (sl.valid) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const size_t id = fidx(p, c, j, m, kk);
+                if (Ain) Av[jj][c] = Ain[id];
+                if (Bin) Bv[jj][c] = Bin[id];
+            }
+            if (Z) {
                 const double2 zr = Z[fidx(p, 0, j, m, kk)], zt = Z[fidx(p, 1, j, m, kk)];
                 zz = Z[fidx(p, 2, j, m, kk)];
                 zp = cadd(zr, cmuli(zt));
                 zm = csub(zr, cmuli(zt));
             }
+        }
+        if (Z) {
+            // E_n^T is applied to W Z in the (+, -, z) basis
             s3[0][j][q] = zp;
             s3[1][j][q] = zm;
             s3[2][j][q] = zz;
         }
+    }
+    if (Z) {
         __syncthreads();
 #pragma unroll
-        for (int jj = 0; jj < NR_MAX / RJ; ++jj) {
+        for (int jj = 0; jj < NJ; ++jj) {
             const int j = jg + jj * RJ;
             if (j < nr && sl.valid) {
                 const double rc = p.r[j], wj = p.w[j];
@@ -629,11 +668,16 @@ __global__ __launch_bounds__(RT) void k_final(KP p, const double2* __restrict__ 
         if (Bin) __syncthreads();
     }
     if (Bin) {
-        for (int j = jg; j < nr; j += RJ)
-            for (int c = 0; c < 3; ++c) s3[c][j][q] = sl.valid ? Bin[fidx(p, c, j, m, kk)] : czero();
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) {
+            const int j = jg + jj * RJ;
+            if (j < nr)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) s3[c][j][q] = Bv[jj][c];
+        }
         __syncthreads();
 #pragma unroll
-        for (int jj = 0; jj < NR_MAX / RJ; ++jj) {
+        for (int jj = 0; jj < NJ; ++jj) {
             const int j = jg + jj * RJ;
             if (j < nr && sl.valid) {
                 double2 cr, ct, cz;
@@ -646,15 +690,12 @@ __global__ __launch_bounds__(RT) void k_final(KP p, const double2* __restrict__ 
     }
     if (!sl.valid) return;
 #pragma unroll
-    for (int jj = 0; jj < NR_MAX / RJ; ++jj) {
+    for (int jj = 0; jj < NJ; ++jj) {
         const int j = jg + jj * RJ;
         if (j >= nr) continue;
         const double iw = 1.0 / p.w[j];
-        for (int c = 0; c < 3; ++c) {
-            const size_t id = fidx(p, c, j, m, kk);
-            const double2 av = Ain ? Ain[id] : czero();
-            out[id] = caxpy(av, iw, E[jj][c]);
-        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[fidx(p, c, j, m, kk)] = caxpy(Av[jj][c], iw, E[jj][c]);
     }
 }
 
