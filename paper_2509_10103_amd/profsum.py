@@ -46,15 +46,17 @@ def short_name(full):
     return n
 
 
-def family_kernels(nt, nz, names=()):
-    """Kernel name of each bench.py kernel family for transform lengths nt, nz;
-    the generic transform kernels stand in where `names` (the names seen in a
-    profile) holds no compile-time-sized one."""
+def family_kernels(nt, nz, names=(), shapes=(1, 4, 4)):
+    """Kernel name of each bench.py kernel family for transform lengths nt, nz
+    and launch shapes (zgroup, azimuthal z-block forward, adjoint); the generic
+    transform kernels stand in where `names` (the names seen in a profile)
+    holds no compile-time-sized one."""
+    zbf, zba = shapes[1], shapes[2]
     fz = f"k_zinv_t<{nz}, 6>" in names or not names
-    ft = f"k_theta_t<{nt}, 0>" in names or not names
+    ft = f"k_theta_t<{nt}, 0, {zbf}>" in names or not names
     zi = (lambda nf: f"k_zinv_t<{nz}, {nf}>") if fz else (lambda nf: "k_zinv")
     zf = (lambda nf: f"k_zfwd_t<{nz}, {nf}>") if fz else (lambda nf: "k_zfwd")
-    th = (lambda a: f"k_theta_t<{nt}, {a}>") if ft else (lambda a: "k_theta")
+    th = (lambda a: f"k_theta_t<{nt}, {a}, {zba if a else zbf}>") if ft else (lambda a: "k_theta")
     return {
         "curl": "k_curl_aux", "zinv_fwd": zi(6), "theta_fwd": th(0), "zfwd_fwd": zf(3),
         "zinv_adj": zi(9), "theta_adj": th(1), "zfwd_adj": zf(6),
@@ -76,7 +78,8 @@ def trace(stats_csv, bench_log, out_md, command):
     rows = list(csv.DictReader(open(stats_csv)))
     bench = json.loads([ln for ln in open(bench_log).read().splitlines() if ln.startswith('{"metric"')][-1])
     cfg = bench["config"]
-    fam = family_kernels(cfg["grid"][1], cfg["grid"][2], {short_name(r["Name"]) for r in rows})
+    fam = family_kernels(cfg["grid"][1], cfg["grid"][2], {short_name(r["Name"]) for r in rows},
+                         cfg.get("launch_shapes") or (1, 4, 4))
     inv = {v: k for k, v in fam.items()}
     lines = [f"# Kernel trace: {cfg['workload']}", "",
              f"Command (repository root, one MI355X): `{command}`", "",
@@ -107,7 +110,7 @@ def bytes_summary(fetch_csv, write_csv, cf_csv, cw_csv, out_md, commands, nt, nz
     cw = max(_counter(cw_csv, "WRITE_SIZE")["__amd_rocclr_copyBuffer"])
     ff = COPY_BYTES / (cf * 1024)
     fw = COPY_BYTES / (cw * 1024)
-    fam = family_kernels(nt, nz, set(fetch))
+    fam = family_kernels(nt, nz, set(fetch), shapes)
     per = {}
     lines = ["# HBM bytes per launch: workload grid " + f"{nt}x{nz} (theta x z)", "",
              "Commands (repository root, one MI355X, each counter in its own run):", ""]
