@@ -553,8 +553,8 @@ __global__ __launch_bounds__(TB) void k_zfwd_t(KP p, const double2* __restrict__
     }
 }
 
-// Azimuthal transforms and products.  A block owns Q consecutive tiles of ZB
-// axial points at node j and walks through them, loading the next tile's
+// Azimuthal transforms and products.  A block owns Q tiles of ZB axial points
+// at node j (nq tiles apart) and walks through them, loading the next tile's
 // inputs into registers while the current one is transformed.  Blocks are
 // placed so that consecutive tiles of one j run on the same XCD (hardware
 // round-robin over 8 XCDs by workgroup id), where they share L2 lines of the
@@ -629,9 +629,12 @@ __global__ __launch_bounds__(TB) void k_theta_t(KP p, int nq, int Q, const doubl
             }
         }
     };
-    int z0 = zq * Q * ZB;
+    // tiles zq, zq + nq, ...: neighbouring blocks (same XCD, same time) hold
+    // neighbouring tiles, so the halves of a 128-byte line are read and
+    // written together in L2
+    int z0 = zq * ZB;
     fetch(z0);
-    for (int tile = 0; tile < Q; ++tile, z0 += ZB) {
+    for (int tile = 0; tile < Q; ++tile, z0 += nq * ZB) {
         if constexpr (NGAP > 0) {
             for (int t = threadIdx.x; t < NIN * NGAP; t += TB) {
                 const int s = t / NGAP, q = t - s * NGAP;
@@ -640,7 +643,7 @@ __global__ __launch_bounds__(TB) void k_theta_t(KP p, int nq, int Q, const doubl
         }
         place();
         __syncthreads();
-        if (tile + 1 < Q) fetch(z0 + ZB);
+        if (tile + 1 < Q) fetch(z0 + nq * ZB);
         double2* R1 = fft_ct<NT, true, theta_maxr<ADJ>()>(A, Bf, NIN, tw);
         double2* O = (R1 == A) ? Bf : A;
         for (int t = threadIdx.x; t < ZB * NT; t += TB) {
