@@ -217,7 +217,21 @@ __global__ __launch_bounds__(RT) void k_solve(KP p, const double2* __restrict__ 
     __shared__ double2 sp[NR_MAX][RQ];
     __shared__ double2 sa[RQ];
 
-    // u (kind 0: R) in the (+, -, z) basis, staged in LDS
+    // u (kind 0: R) in the (+, -, z) basis, staged in LDS; the homogeneous
+    // solutions the combine step needs are requested at the same time
+    constexpr int NJ = NR_MAX / RJ;
+    const double* hom = p.HOM + ((size_t)sl.ka * p.mp1 + m) * (3 * nr + 1);
+    double hv[NJ][3];
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+        const int j = jg + jj * RJ;
+        hv[jj][0] = hv[jj][1] = hv[jj][2] = 0.0;
+        if (j < N1 && sl.valid) {
+            hv[jj][0] = hom[j];
+            hv[jj][1] = hom[nr + j];
+            hv[jj][2] = hom[2 * nr + j];
+        }
+    }
     for (int j = jg; j < nr; j += RJ) {
         double2 up = czero(), um = czero(), uz = czero();
         if (sl.valid) {
@@ -234,9 +248,9 @@ __global__ __launch_bounds__(RT) void k_solve(KP p, const double2* __restrict__ 
     if constexpr (kind != 0) {
         // R = E u^n + N: stencils read from LDS, results held in registers
         // until every lane has read its neighbours
-        double2 Rv[NR_MAX / RJ][3];
+        double2 Rv[NJ][3];
 #pragma unroll
-        for (int jj = 0; jj < NR_MAX / RJ; ++jj) {
+        for (int jj = 0; jj < NJ; ++jj) {
             const int j = jg + jj * RJ;
             Rv[jj][0] = Rv[jj][1] = Rv[jj][2] = czero();
             if (j < nr && sl.valid) {
@@ -334,7 +348,6 @@ __global__ __launch_bounds__(RT) void k_solve(KP p, const double2* __restrict__ 
         }
     }
     __syncthreads();
-    const double* hom = p.HOM + ((size_t)sl.ka * p.mp1 + m) * (3 * nr + 1);
     if (t < RQ && sl.valid) {
         if (sl.mean) {
             // zero flux: u_z += c g with c = -sum w u_z / sum w g
@@ -353,17 +366,20 @@ __global__ __launch_bounds__(RT) void k_solve(KP p, const double2* __restrict__ 
     }
     __syncthreads();
     // combine and store (each lane touches only its own (row, mode) here)
-    for (int j = jg; j < nr; j += RJ) {
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+        const int j = jg + jj * RJ;
+        if (j >= nr) continue;
         double2 ur = czero(), ut = czero(), uz = czero();
         if (j < N1 && sl.valid) {
             const double2 a = sa[q];
             if (sl.mean) {
                 ut = sR[1][j][q];
-                uz = cadd(sR[2][j][q], cscale(a, hom[j]));
+                uz = cadd(sR[2][j][q], cscale(a, hv[jj][0]));
             } else {
-                const double2 up = cadd(sR[0][j][q], cscale(a, hom[j]));
-                const double2 um = cadd(sR[1][j][q], cscale(a, hom[nr + j]));
-                uz = cadd(sR[2][j][q], cscale(cmuli(a), sl.al * hom[2 * nr + j]));
+                const double2 up = cadd(sR[0][j][q], cscale(a, hv[jj][0]));
+                const double2 um = cadd(sR[1][j][q], cscale(a, hv[jj][1]));
+                uz = cadd(sR[2][j][q], cscale(cmuli(a), sl.al * hv[jj][2]));
                 ur = cscale(cadd(up, um), 0.5);
                 ut = cscale(cmuli(csub(um, up)), 0.5);   // (up - um)/(2i)
             }
