@@ -49,6 +49,8 @@ __global__ void k_curl_aux(KP p, const double2* __restrict__ u, double2* __restr
 // real vector x[i*s] in LDS; entries needed from earlier rows ride in shift
 // registers so no load is on the dependence chain.
 constexpr int LUW = 9;
+// radial sizes with compile-time substitution chains (others use the loops)
+#define NPO_NR_SIZES(X) X(16) X(24) X(32) X(48) X(64)
 
 // (L U) x = b in place.
 __device__ void gsubst(const double* __restrict__ LU, int n1, double* x, int s) {
@@ -119,6 +121,138 @@ __device__ void gsubst_T(const double* __restrict__ LU, int n1, double* x, int s
         l32 = l31; l31 = r3;
         l41 = r4;
     }
+}
+
+// Fully unrolled substitutions for a compile-time size N1.  Factor rows reach
+// the chain through a ring of PF rows in registers: the row used at step i is
+// refilled with row i + PF, and a scheduling barrier after every step keeps
+// those loads where they are written, so PF rows' loads stay in flight and the
+// L2 latency is paid once per PF rows rather than once per few rows (without
+// unrolling, loads carried around a loop are drained at every iteration).
+template <int N1, int PF>
+__device__ __forceinline__ void gsubst_u(const double* __restrict__ LU, double* x, int s) {
+    double y1 = 0.0, y2 = 0.0, y3 = 0.0, y4 = 0.0, y5 = 0.0;   // y_{i-1} .. y_{i-5}
+    double Lr[PF][5];
+#pragma unroll
+    for (int r = 0; r < PF; ++r)
+        if (r < N1)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) Lr[r][c] = LU[r * LUW + c];
+#pragma unroll
+    for (int i = 0; i < N1; ++i) {
+        const int r = i % PF;
+        double y = x[i * s];
+        y = fma(-Lr[r][0], y5, y);
+        y = fma(-Lr[r][1], y4, y);
+        y = fma(-Lr[r][2], y3, y);
+        y = fma(-Lr[r][3], y2, y);
+        y = fma(-Lr[r][4], y1, y);
+        x[i * s] = y;
+        y5 = y4; y4 = y3; y3 = y2; y2 = y1; y1 = y;
+        if (i + PF < N1)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) Lr[r][c] = LU[(i + PF) * LUW + c];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    double x1 = 0.0, x2 = 0.0, x3 = 0.0;                       // x_{i+1} .. x_{i+3}
+    double Ur[PF][4];
+#pragma unroll
+    for (int r = 0; r < PF; ++r)
+        if (r < N1)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Ur[r][c] = LU[(N1 - 1 - r) * LUW + 5 + c];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+        const int i = N1 - 1 - k, r = k % PF;
+        double v = x[i * s];
+        v = fma(-Ur[r][3], x3, v);
+        v = fma(-Ur[r][2], x2, v);
+        v = fma(-Ur[r][1], x1, v);
+        v *= Ur[r][0];
+        x[i * s] = v;
+        x3 = x2; x2 = x1; x1 = v;
+        if (k + PF < N1)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Ur[r][c] = LU[(i - PF) * LUW + 5 + c];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <int N1, int PF>
+__device__ __forceinline__ void gsubst_T_u(const double* __restrict__ LU, double* x, int s) {
+    double z1 = 0.0, z2 = 0.0, z3 = 0.0;                       // z_{i-1} .. z_{i-3}
+    double u61 = 0.0, u71 = 0.0, u72 = 0.0, u81 = 0.0, u82 = 0.0, u83 = 0.0;
+    double Ur[PF][4];
+#pragma unroll
+    for (int r = 0; r < PF; ++r)
+        if (r < N1)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Ur[r][c] = LU[r * LUW + 5 + c];
+#pragma unroll
+    for (int i = 0; i < N1; ++i) {
+        const int r = i % PF;
+        const double inv = Ur[r][0], r6 = Ur[r][1], r7 = Ur[r][2], r8 = Ur[r][3];
+        double v = x[i * s];
+        v = fma(-u83, z3, v);
+        v = fma(-u72, z2, v);
+        v = fma(-u61, z1, v);
+        v *= inv;
+        x[i * s] = v;
+        z3 = z2; z2 = z1; z1 = v;
+        u83 = u82; u82 = u81; u81 = r8;
+        u72 = u71; u71 = r7;
+        u61 = r6;
+        if (i + PF < N1)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Ur[r][c] = LU[(i + PF) * LUW + 5 + c];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    double x1 = 0.0, x2 = 0.0, x3 = 0.0, x4 = 0.0, x5 = 0.0;   // x_{i+1} .. x_{i+5}
+    double l41 = 0.0, l31 = 0.0, l32 = 0.0, l21 = 0.0, l22 = 0.0, l23 = 0.0;
+    double l11 = 0.0, l12 = 0.0, l13 = 0.0, l14 = 0.0, l01 = 0.0, l02 = 0.0, l03 = 0.0, l04 = 0.0, l05 = 0.0;
+    double Lr[PF][5];
+#pragma unroll
+    for (int r = 0; r < PF; ++r)
+        if (r < N1)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) Lr[r][c] = LU[(N1 - 1 - r) * LUW + c];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+        const int i = N1 - 1 - k, r = k % PF;
+        double v = x[i * s];
+        v = fma(-l05, x5, v);
+        v = fma(-l14, x4, v);
+        v = fma(-l23, x3, v);
+        v = fma(-l32, x2, v);
+        v = fma(-l41, x1, v);
+        x[i * s] = v;
+        x5 = x4; x4 = x3; x3 = x2; x2 = x1; x1 = v;
+        l05 = l04; l04 = l03; l03 = l02; l02 = l01; l01 = Lr[r][0];
+        l14 = l13; l13 = l12; l12 = l11; l11 = Lr[r][1];
+        l23 = l22; l22 = l21; l21 = Lr[r][2];
+        l32 = l31; l31 = Lr[r][3];
+        l41 = Lr[r][4];
+        if (k + PF < N1)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) Lr[r][c] = LU[(i - PF) * LUW + c];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Substitutions for a compile-time interior size N1C (0: the size n1 given at
+// run time).  Ring depths: 8 rows in the forward solve, 6 in the adjoint one
+// (which keeps its accumulator inputs in registers across the chains and must
+// stay within 256 VGPRs for two waves per SIMD).
+constexpr int PF_FWD = 8, PF_ADJ = 6;
+template <int N1C>
+__device__ __forceinline__ void subst(const double* __restrict__ LU, int n1, double* x, int s) {
+    if constexpr (N1C > 0) gsubst_u<N1C, PF_FWD>(LU, x, s);
+    else gsubst(LU, n1, x, s);
+}
+template <int N1C>
+__device__ __forceinline__ void subst_T(const double* __restrict__ LU, int n1, double* x, int s) {
+    if constexpr (N1C > 0) gsubst_T_u<N1C, PF_ADJ>(LU, x, s);
+    else gsubst_T(LU, n1, x, s);
 }
 
 // -(Poisson wall column) at interior row j: right-hand side of the
@@ -200,7 +334,7 @@ __device__ __forceinline__ Slot slot_of(const KP& p, int g, int m, int q) {
 // ------------------------------------------------------------ forward solve
 // Lanes are (radial row, mode) in the pointwise phases and independent real
 // right-hand sides (operator, mode, re/im) in the substitution phases.
-template <int kind>
+template <int kind, int NRC>
 __global__ __launch_bounds__(RT) void k_solve(KP p, const double2* __restrict__ ain,
                                               const double2* __restrict__ bin, const double2* __restrict__ cin,
                                               double2* __restrict__ uout, double2* __restrict__ auxout) {
@@ -317,7 +451,8 @@ __global__ __launch_bounds__(RT) void k_solve(KP p, const double2* __restrict__ 
         const int qq = t % RQ, part = t / RQ;
         const Slot s2 = slot_of(p, g, m, qq);
         if (s2.valid && !s2.mean)
-            gsubst(p.PLU + ((size_t)s2.ka * p.mp1 + m) * opsz, N1, reinterpret_cast<double*>(&sp[0][qq]) + part, 2 * RQ);
+            subst<NRC ? NRC - 1 : 0>(p.PLU + ((size_t)s2.ka * p.mp1 + m) * opsz, N1,
+                                     reinterpret_cast<double*>(&sp[0][qq]) + part, 2 * RQ);
     }
     __syncthreads();
     // Helmholtz right-hand sides R - grad p; the mean mode keeps (R_theta, R_z)
@@ -343,7 +478,7 @@ __global__ __launch_bounds__(RT) void k_solve(KP p, const double2* __restrict__ 
         const Slot s2 = slot_of(p, g, m, qq);
         if (s2.valid && !(s2.mean && op == 0)) {
             const int n = op == 0 ? m + 1 : (op == 1 ? abs(m - 1) : m);
-            gsubst(p.HLU + ((size_t)s2.ka * (p.M + 2) + n) * opsz, N1,
+            subst<NRC ? NRC - 1 : 0>(p.HLU + ((size_t)s2.ka * (p.M + 2) + n) * opsz, N1,
                    reinterpret_cast<double*>(&sR[op][0][qq]) + part, 2 * RQ);
         }
     }
@@ -438,7 +573,7 @@ struct AdjOut {
     double2* Zout;
     double qy, qz;
 };
-template <bool useB>
+template <bool useB, int NRC>
 __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, double ca, const double2* Bin, double cb,
                                                   AdjOut ao) {
     int g, m;
@@ -555,7 +690,7 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
         const Slot s2 = slot_of(p, g, m, qq);
         if (s2.valid && !(s2.mean && op == 0)) {
             const int n = op == 0 ? m + 1 : (op == 1 ? abs(m - 1) : m);
-            gsubst_T(p.HLU + ((size_t)s2.ka * (p.M + 2) + n) * opsz, N1,
+            subst_T<NRC ? NRC - 1 : 0>(p.HLU + ((size_t)s2.ka * (p.M + 2) + n) * opsz, N1,
                      reinterpret_cast<double*>(&sy[op][0][qq]) + part, 2 * RQ);
         }
     }
@@ -577,7 +712,8 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
         const int qq = t % RQ, part = t / RQ;
         const Slot s2 = slot_of(p, g, m, qq);
         if (s2.valid && !s2.mean)
-            gsubst_T(p.PLU + ((size_t)s2.ka * p.mp1 + m) * opsz, N1, reinterpret_cast<double*>(&sphi[0][qq]) + part,
+            subst_T<NRC ? NRC - 1 : 0>(p.PLU + ((size_t)s2.ka * p.mp1 + m) * opsz, N1,
+                                       reinterpret_cast<double*>(&sphi[0][qq]) + part,
                      2 * RQ);
     }
     __syncthreads();
@@ -927,9 +1063,20 @@ hipError_t launch_solve(const npo_plan_s& p, int kind, const double2* a, const d
                         double2* u_out, double2* aux_out, hipStream_t st) {
     prof_begin(p, kind == 1 ? KID_SOLVE_P : (kind == 2 ? KID_SOLVE_C : KID_SOLVE_R), st);
     const dim3 grid((radial_groups(p.K) * p.mp1 + 7) / 8 * 8);
-    if (kind == 1) hipLaunchKernelGGL(k_solve<1>, grid, dim3(RT), 0, st, p.kp, a, b, c, u_out, aux_out);
-    else if (kind == 2) hipLaunchKernelGGL(k_solve<2>, grid, dim3(RT), 0, st, p.kp, a, b, c, u_out, aux_out);
-    else hipLaunchKernelGGL(k_solve<0>, grid, dim3(RT), 0, st, p.kp, a, b, c, u_out, aux_out);
+    switch (p.nr) {
+#define NPO_CASE(R)                                                                                                 \
+    case R:                                                                                                         \
+        if (kind == 1) hipLaunchKernelGGL((k_solve<1, R>), grid, dim3(RT), 0, st, p.kp, a, b, c, u_out, aux_out);      \
+        else if (kind == 2) hipLaunchKernelGGL((k_solve<2, R>), grid, dim3(RT), 0, st, p.kp, a, b, c, u_out, aux_out); \
+        else hipLaunchKernelGGL((k_solve<0, R>), grid, dim3(RT), 0, st, p.kp, a, b, c, u_out, aux_out);                \
+        break;
+        NPO_NR_SIZES(NPO_CASE)
+#undef NPO_CASE
+    default:
+        if (kind == 1) hipLaunchKernelGGL((k_solve<1, 0>), grid, dim3(RT), 0, st, p.kp, a, b, c, u_out, aux_out);
+        else if (kind == 2) hipLaunchKernelGGL((k_solve<2, 0>), grid, dim3(RT), 0, st, p.kp, a, b, c, u_out, aux_out);
+        else hipLaunchKernelGGL((k_solve<0, 0>), grid, dim3(RT), 0, st, p.kp, a, b, c, u_out, aux_out);
+    }
     prof_end(p, kind == 1 ? KID_SOLVE_P : (kind == 2 ? KID_SOLVE_C : KID_SOLVE_R), st);
     return hipGetLastError();
 }
@@ -940,8 +1087,18 @@ hipError_t launch_solve_adj(const npo_plan_s& p, const double2* A, double ca, co
     AdjOut ao{out0, Yin, Yout, Zin, Zout, qy, qz};
     prof_begin(p, B ? KID_SOLVE_ADJ2 : KID_SOLVE_ADJ, st);
     const dim3 grid((radial_groups(p.K) * p.mp1 + 7) / 8 * 8);
-    if (B) hipLaunchKernelGGL(k_solve_adj<true>, grid, dim3(RT), 0, st, p.kp, A, ca, B, cb, ao);
-    else hipLaunchKernelGGL(k_solve_adj<false>, grid, dim3(RT), 0, st, p.kp, A, ca, B, cb, ao);
+    switch (p.nr) {
+#define NPO_CASE(R)                                                                                        \
+    case R:                                                                                                \
+        if (B) hipLaunchKernelGGL((k_solve_adj<true, R>), grid, dim3(RT), 0, st, p.kp, A, ca, B, cb, ao);    \
+        else hipLaunchKernelGGL((k_solve_adj<false, R>), grid, dim3(RT), 0, st, p.kp, A, ca, B, cb, ao);     \
+        break;
+        NPO_NR_SIZES(NPO_CASE)
+#undef NPO_CASE
+    default:
+        if (B) hipLaunchKernelGGL((k_solve_adj<true, 0>), grid, dim3(RT), 0, st, p.kp, A, ca, B, cb, ao);
+        else hipLaunchKernelGGL((k_solve_adj<false, 0>), grid, dim3(RT), 0, st, p.kp, A, ca, B, cb, ao);
+    }
     prof_end(p, B ? KID_SOLVE_ADJ2 : KID_SOLVE_ADJ, st);
     return hipGetLastError();
 }
