@@ -46,12 +46,13 @@ def short_name(full):
     return n
 
 
-def family_kernels(nt, nz, names=(), shapes=(1, 4, 4)):
-    """Kernel name of each bench.py kernel family for transform lengths nt, nz
-    and launch shapes (zgroup, azimuthal z-block forward, adjoint); the generic
-    transform kernels stand in where `names` (the names seen in a profile)
-    holds no compile-time-sized one."""
+def family_kernels(nt, nz, names=(), shapes=(1, 4, 4), nr=64):
+    """Kernel name of each bench.py kernel family for transform lengths nt, nz,
+    radial size nr and launch shapes (zgroup, azimuthal z-block forward,
+    adjoint); the generic kernels stand in where `names` (the names seen in a
+    profile) holds no compile-time-sized one."""
     zbf, zba = shapes[1], shapes[2]
+    nrc = nr if (f"k_solve<1, {nr}>" in names or f"k_solve<2, {nr}>" in names or not names) else 0
     fz = f"k_zinv_t<{nz}, 6>" in names or not names
     ft = f"k_theta_t<{nt}, 0, {zbf}>" in names or not names
     zi = (lambda nf: f"k_zinv_t<{nz}, {nf}>") if fz else (lambda nf: "k_zinv")
@@ -60,8 +61,8 @@ def family_kernels(nt, nz, names=(), shapes=(1, 4, 4)):
     return {
         "curl": "k_curl_aux", "zinv_fwd": zi(6), "theta_fwd": th(0), "zfwd_fwd": zf(3),
         "zinv_adj": zi(9), "theta_adj": th(1), "zfwd_adj": zf(6),
-        "solve_pred": "k_solve<1>", "solve_corr": "k_solve<2>", "solve_raw": "k_solve<0>",
-        "solve_adj": "k_solve_adj<false>", "solve_adj2": "k_solve_adj<true>", "adj_combine": "k_final",
+        "solve_pred": f"k_solve<1, {nrc}>", "solve_corr": f"k_solve<2, {nrc}>", "solve_raw": f"k_solve<0, {nrc}>",
+        "solve_adj": f"k_solve_adj<false, {nrc}>", "solve_adj2": f"k_solve_adj<true, {nrc}>", "adj_combine": "k_final",
         "wdot": "k_wdot_partial", "project": "k_project", "axpby": "k_axpby",
     }
 
@@ -79,7 +80,7 @@ def trace(stats_csv, bench_log, out_md, command):
     bench = json.loads([ln for ln in open(bench_log).read().splitlines() if ln.startswith('{"metric"')][-1])
     cfg = bench["config"]
     fam = family_kernels(cfg["grid"][1], cfg["grid"][2], {short_name(r["Name"]) for r in rows},
-                         cfg.get("launch_shapes") or (1, 4, 4))
+                         cfg.get("launch_shapes") or (1, 4, 4), cfg["grid"][0])
     inv = {v: k for k, v in fam.items()}
     lines = [f"# Kernel trace: {cfg['workload']}", "",
              f"Command (repository root, one MI355X): `{command}`", "",
@@ -104,13 +105,13 @@ def trace(stats_csv, bench_log, out_md, command):
     open(out_md, "w").write("\n".join(lines))
 
 
-def bytes_summary(fetch_csv, write_csv, cf_csv, cw_csv, out_md, commands, nt, nz, shapes):
+def bytes_summary(fetch_csv, write_csv, cf_csv, cw_csv, out_md, commands, nt, nz, shapes, nr=64):
     fetch, write = _counter(fetch_csv, "FETCH_SIZE"), _counter(write_csv, "WRITE_SIZE")
     cf = max(_counter(cf_csv, "FETCH_SIZE")["__amd_rocclr_copyBuffer"])
     cw = max(_counter(cw_csv, "WRITE_SIZE")["__amd_rocclr_copyBuffer"])
     ff = COPY_BYTES / (cf * 1024)
     fw = COPY_BYTES / (cw * 1024)
-    fam = family_kernels(nt, nz, set(fetch), shapes)
+    fam = family_kernels(nt, nz, set(fetch), shapes, nr)
     per = {}
     lines = ["# HBM bytes per launch: workload grid " + f"{nt}x{nz} (theta x z)", "",
              "Commands (repository root, one MI355X, each counter in its own run):", ""]
