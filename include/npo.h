@@ -197,8 +197,10 @@ npo_status npo_normalize(npo_plan plan, void* ws, void* u, double e0, void* stre
  * Families: 0 curl, 1-3 forward axial-inverse / azimuthal / axial-forward
  * transforms, 4-6 the same for the adjoint, 7 predictor solve, 8 corrector
  * solve, 9 plain solve, 10 adjoint solve, 11 adjoint combine, 12 reduction,
- * 13 projection, 14 axpby, 15 adjoint solve of the composed input. */
-#define NPO_KERNEL_FAMILIES 16
+ * 13 projection, 14 axpby, 15 adjoint solve of the composed input, 16 adjoint
+ * axial-inverse transform of the adjoint field alone (when the forward
+ * transforms of the same state are reused). */
+#define NPO_KERNEL_FAMILIES 17
 npo_status npo_profile_begin(npo_plan plan, int32_t stride);
 npo_status npo_profile_read(npo_plan plan, int64_t* launches, int64_t* sampled, double* avg_ms);
 

@@ -326,11 +326,17 @@ hipError_t adj_step(const npo_plan_s& p, void* ws, const double2* un, const doub
     hipError_t e;
     const npo::TimeArg t0 = at_step(dstep, n, 0), t1 = at_step(dstep, n, 1);
     const int C = p.ncorr;
+    // stage recompute; the forward evaluations leave the axial transforms of
+    // u^n (zst[0]) and of w_{c-1} (zst[c]) for the adjoint evaluations
+    char* wb = static_cast<char*>(ws);
+    auto zst = [&](int c) { return reinterpret_cast<double2*>(wb + p.ws.zst[c]); };
     if ((e = npo::launch_curl_aux(p, un, w.aux0, st)) != hipSuccess) return e;
-    if ((e = npo::launch_nl(p, 0, un, w.aux0, nullptr, t0, w.nn, nullptr, ws, st)) != hipSuccess) return e;
+    if ((e = npo::launch_nl(p, 0, un, w.aux0, nullptr, t0, w.nn, nullptr, ws, st, nullptr, zst(0))) != hipSuccess)
+        return e;
     if ((e = npo::launch_solve(p, 1, un, w.nn, nullptr, w.st[0], w.auxs[0], st)) != hipSuccess) return e;
     for (int c = 1; c < C; ++c) {
-        if ((e = npo::launch_nl(p, 0, w.st[c - 1], w.auxs[c - 1], nullptr, t1, w.ns, nullptr, ws, st)) != hipSuccess)
+        if ((e = npo::launch_nl(p, 0, w.st[c - 1], w.auxs[c - 1], nullptr, t1, w.ns, nullptr, ws, st, nullptr,
+                                zst(c))) != hipSuccess)
             return e;
         if ((e = npo::launch_solve(p, 2, un, w.nn, w.ns, w.st[c], w.auxs[c], st)) != hipSuccess) return e;
     }
@@ -340,14 +346,17 @@ hipError_t adj_step(const npo_plan_s& p, void* ws, const double2* un, const doub
                                    st)) != hipSuccess)
         return e;
     for (int c = C; c >= 1; --c) {
-        if ((e = npo::launch_nl(p, 1, w.st[c - 1], w.auxs[c - 1], mu[c & 1], t1, w.fa, w.fb, ws, st)) != hipSuccess)
+        // w_{c-1} was evaluated forward above for c < C
+        const double2* pre = c < C ? zst(c) : nullptr;
+        if ((e = npo::launch_nl(p, 1, w.st[c - 1], w.auxs[c - 1], mu[c & 1], t1, w.fa, w.fb, ws, st, pre)) !=
+            hipSuccess)
             return e;
         double2* next = (c > 1) ? mu[(c - 1) & 1] : nullptr;
         if ((e = npo::launch_solve_adj(p, w.fa, 0.5, w.fb, 0.5, next, w.yb, c == 1 ? 1.0 : 0.5, w.yb, w.zb2, 1.0,
                                        w.zb2, st)) != hipSuccess)
             return e;
     }
-    if ((e = npo::launch_nl(p, 1, un, w.aux0, w.yb, t0, w.fa2, w.fb2, ws, st)) != hipSuccess) return e;
+    if ((e = npo::launch_nl(p, 1, un, w.aux0, w.yb, t0, w.fa2, w.fb2, ws, st, zst(0))) != hipSuccess) return e;
     return npo::launch_final(p, w.zb2, w.fa2, w.fb2, lamout, st);
 }
 
@@ -703,6 +712,7 @@ npo_status npo_plan_create(const npo_grid* grid, const npo_flow* flow, const npo
     L.cur = take(fb); L.lam = take(fb); L.tmp = take(fb); L.g = take(fb);
     L.trial = take(fb); L.trialN = take(fb);
     L.zbuf = take(9 * gb); L.tbuf = take(6 * gb);
+    for (int c = 0; c < npo::NCORR_MAX; ++c) L.zst[c] = c < p->ncorr ? take(6 * gb) : 0;
     L.red = take((npo::NR_MAX * 4 + 512) * 8);
     L.step = take(256);
     L.total = off;

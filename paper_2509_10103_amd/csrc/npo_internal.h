@@ -12,7 +12,7 @@ namespace npo {
 enum KernelId {
     KID_CURL = 0, KID_ZINV_F, KID_THETA_F, KID_ZFWD_F, KID_ZINV_A, KID_THETA_A, KID_ZFWD_A,
     KID_SOLVE_P, KID_SOLVE_C, KID_SOLVE_R, KID_SOLVE_ADJ, KID_FINAL, KID_WDOT, KID_PROJECT, KID_AXPBY,
-    KID_SOLVE_ADJ2, KID_COUNT
+    KID_SOLVE_ADJ2, KID_ZINV_Y, KID_COUNT
 };
 constexpr int PROF_SLOTS = 256;   // sampled launches kept per kernel family
 
@@ -80,6 +80,7 @@ struct WsLayout {
     size_t cur, lam, tmp;       // checkpoint-run state buffers
     size_t g, trial, trialN;    // iterate buffers
     size_t zbuf, tbuf;          // z-transformed and theta-pass intermediates
+    size_t zst[NCORR_MAX];      // z-transformed u, w of the stage states kept for the adjoint
     size_t red;                 // reduction partials + scalars
     size_t step;                // device step index read by captured step graphs
     size_t total;
@@ -126,8 +127,13 @@ void prof_end(const npo_plan_s& p, int kid, hipStream_t st);
 size_t zpass_lds(const npo_plan_s& p, int G);
 size_t theta_lds(const npo_plan_s& p, int ZB, int adj);
 hipError_t launch_curl_aux(const npo_plan_s& p, const double2* u, double2* aux, hipStream_t st);
+// uw_pre (adjoint only): the axial transforms of the six u, w fields of this
+// state, left by an earlier forward evaluation (then only y is transformed);
+// uw_save (forward only): where the forward evaluation leaves them (default:
+// the workspace's shared buffer).
 hipError_t launch_nl(const npo_plan_s& p, int adjoint, const double2* u, const double2* aux,
-                     const double2* y, const TimeArg& ta, double2* out0, double2* out1, void* ws, hipStream_t st);
+                     const double2* y, const TimeArg& ta, double2* out0, double2* out1, void* ws, hipStream_t st,
+                     const double2* uw_pre = nullptr, double2* uw_save = nullptr);
 // *d = v (set) or *d += v (add), one thread.
 hipError_t launch_step_index(long long* d, long long v, int add, hipStream_t st);
 // solve kinds: 0 = out = S(R) with R = a (raw); 1 = predictor S(E a + b);

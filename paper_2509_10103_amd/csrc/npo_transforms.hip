@@ -89,7 +89,7 @@ __device__ double2* fft_lds(double2* a, double2* b, int B, int n, const int* fac
 
 // ------------------------------------------------------ axial inverse FFT
 // Block (m, j).  Fields: 0..2 u, 3 w_r (built from u), 4..5 aux, 6..8 y.
-__global__ void k_zinv(KP p, int nf, int G, const double2* __restrict__ u, const double2* __restrict__ aux,
+__global__ void k_zinv(KP p, int fbase, int nf, int G, const double2* __restrict__ u, const double2* __restrict__ aux,
                        const double2* __restrict__ y, double2* __restrict__ zb) {
     extern __shared__ double2 sh[];
     const int m = blockIdx.x, j = blockIdx.y;
@@ -102,7 +102,7 @@ __global__ void k_zinv(KP p, int nf, int G, const double2* __restrict__ u, const
         for (int t = threadIdx.x; t < g * nz; t += blockDim.x) A[t] = czero();
         __syncthreads();
         for (int t = threadIdx.x; t < g * nk; t += blockDim.x) {
-            const int fi = t / nk, kk = t - fi * nk, f = f0 + fi;
+            const int fi = t / nk, kk = t - fi * nk, f = fbase + f0 + fi;
             double2 v;
             if (f < 3) {
                 v = u[fidx(p, f, j, m, kk)];
@@ -145,12 +145,12 @@ __device__ __forceinline__ void phase_of(const KP& p, const TimeArg& ta, double&
     sincos(p.omega * t, &sw, &cw);
 }
 
-__global__ void k_theta(KP p, int adj, int ZB, const double2* __restrict__ zb, double2* __restrict__ tb,
-                        TimeArg ta) {
+__global__ void k_theta(KP p, int adj, int ZB, const double2* __restrict__ zu, int nfu, const double2* __restrict__ zy,
+                        int nfy, double2* __restrict__ tb, TimeArg ta) {
     extern __shared__ double2 sh[];
     const int j = blockIdx.y, z0 = blockIdx.x * ZB;
     const int nt = p.nt, mp1 = p.mp1, nz = p.nz;
-    const int nf = adj ? 9 : 6, nfo = adj ? 6 : 3;
+    const int nfo = adj ? 6 : 3;
     const int H = ZB / 2;
     const int nin = adj ? 4 * ZB + H : 3 * ZB;
     const int nout = adj ? 3 * ZB : ZB + H;
@@ -162,15 +162,19 @@ __global__ void k_theta(KP p, int adj, int ZB, const double2* __restrict__ zb, d
     const int npair = adj ? 4 : 3;
     for (int t = threadIdx.x; t < npair * ZB * mp1; t += blockDim.x) {
         const int zi = t % ZB, m = (t / ZB) % mp1, pi = t / (ZB * mp1);
-        const double2 xa = zb[((size_t)(j * nf + 2 * pi) * mp1 + m) * nz + z0 + zi];
-        const double2 xb = zb[((size_t)(j * nf + 2 * pi + 1) * mp1 + m) * nz + z0 + zi];
+        // u, w pairs from zu (nfu fields per node), y pairs from zy (nfy per node)
+        const double2* src = pi < 3 ? zu + (size_t)j * nfu * mp1 * nz : zy + (size_t)j * nfy * mp1 * nz;
+        const int fl = pi < 3 ? 2 * pi : 2 * pi - 6;
+        const double2 xa = src[((size_t)fl * mp1 + m) * nz + z0 + zi];
+        const double2 xb = src[((size_t)(fl + 1) * mp1 + m) * nz + z0 + zi];
         place_pair(A + (pi * ZB + zi) * nt, nt, m, xa, xb);
     }
     if (adj) {
         for (int t = threadIdx.x; t < H * mp1; t += blockDim.x) {
             const int zi = t % H, m = t / H;
-            const double2 xa = zb[((size_t)(j * nf + 8) * mp1 + m) * nz + z0 + zi];
-            const double2 xb = zb[((size_t)(j * nf + 8) * mp1 + m) * nz + z0 + zi + H];
+            const double2* src = zy + ((size_t)j * nfy + 2) * mp1 * nz;
+            const double2 xa = src[(size_t)m * nz + z0 + zi];
+            const double2 xb = src[(size_t)m * nz + z0 + zi + H];
             place_pair(A + (4 * ZB + zi) * nt, nt, m, xa, xb);
         }
     }
@@ -458,11 +462,12 @@ __device__ __forceinline__ double2* fft_ct(double2* a, double2* b, int B, const 
     }
 }
 
-// Inverse axial transforms.  Fields: 0..2 u, 3 w_r (built from u), 4..5 aux,
-// 6..8 y; NF = 6 (forward term) or 9 (adjoint term).  One field per round;
+// Inverse axial transforms of fields F0 .. F0+NF-1 of the list 0..2 u, 3 w_r
+// (built from u), 4..5 aux, 6..8 y (forward term 0..5, adjoint term 0..8, or
+// the adjoint field alone 6..8), written as NF fields per node.  One field per round;
 // the next field's inputs are loaded into registers while the current one is
 // transformed, so the global-load latency overlaps the LDS passes.
-template <int NZ, int NF>
+template <int NZ, int F0, int NF>
 __global__ __launch_bounds__(TB) void k_zinv_t(KP p, const double2* __restrict__ u, const double2* __restrict__ aux,
                                               const double2* __restrict__ y, double2* __restrict__ zb) {
     constexpr int K = (NZ - 1) / 3, NK = 2 * K + 1;
@@ -495,7 +500,7 @@ __global__ __launch_bounds__(TB) void k_zinv_t(KP p, const double2* __restrict__
             }
         }
     };
-    fetch(0);
+    fetch(F0);
     for (int f = 0; f < NF; ++f) {
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
@@ -503,7 +508,7 @@ __global__ __launch_bounds__(TB) void k_zinv_t(KP p, const double2* __restrict__
             if (z < NZ) A[lp(z)] = v[i];
         }
         __syncthreads();
-        if (f + 1 < NF) fetch(f + 1);
+        if (f + 1 < NF) fetch(F0 + f + 1);
         const double2* res = fft_ct<NZ, true, 8>(A, Bf, 1, tw);
         double2* row = zb + ((size_t)(j * NF + f) * mp1 + m) * NZ;
         for (int z = threadIdx.x; z < NZ; z += TB) row[z] = res[lp(z)];
@@ -560,10 +565,11 @@ __global__ __launch_bounds__(TB) void k_zfwd_t(KP p, const double2* __restrict__
 // round-robin over 8 XCDs by workgroup id), where they share L2 lines of the
 // [j][f][m][z] intermediates.
 template <int NT, int ADJ, int ZB>
-__global__ __launch_bounds__(TB) void k_theta_t(KP p, int nq, int Q, const double2* __restrict__ zb,
-                                               double2* __restrict__ tb, TimeArg ta) {
+__global__ __launch_bounds__(TB) void k_theta_t(KP p, int nq, int Q, const double2* __restrict__ zu, int nfu,
+                                               const double2* __restrict__ zy, int nfy, double2* __restrict__ tb,
+                                               TimeArg ta) {
     constexpr int M = (NT - 1) / 3, MP1 = M + 1;
-    constexpr int NF = ADJ ? 9 : 6, NFO = ADJ ? 6 : 3;
+    constexpr int NFO = ADJ ? 6 : 3;
     constexpr int H = ZB / 2;
     constexpr int NIN = ADJ ? 4 * ZB + H : 3 * ZB;
     constexpr int NOUT = ADJ ? 3 * ZB : ZB + H;
@@ -586,7 +592,9 @@ __global__ __launch_bounds__(TB) void k_theta_t(KP p, int nq, int Q, const doubl
     double U, Om, cw, sw;
     phase_of(p, ta, cw, sw);
     base_at(p, j, cw, sw, U, Om);
-    const double2* base = zb + (size_t)j * NF * MP1 * nz;
+    // u, w pairs from zu (nfu fields per node), y pairs from zy (nfy per node)
+    const double2* bu = zu + (size_t)j * nfu * MP1 * nz;
+    const double2* by = ADJ ? zy + (size_t)j * nfy * MP1 * nz : nullptr;
     double2 xa[PER], xb[PER];
     auto fetch = [&](int z0) {
 #pragma unroll
@@ -595,12 +603,14 @@ __global__ __launch_bounds__(TB) void k_theta_t(KP p, int nq, int Q, const doubl
             if (e < NP) {
                 const int zi = e % ZB, q = e / ZB;
                 const int pi = q / MP1, m = q - pi * MP1;
-                xa[i] = base[(size_t)(2 * pi * MP1 + m) * nz + z0 + zi];
-                xb[i] = base[(size_t)((2 * pi + 1) * MP1 + m) * nz + z0 + zi];
+                const double2* src = pi < 3 ? bu : by;
+                const int fl = pi < 3 ? 2 * pi : 2 * pi - 6;
+                xa[i] = src[(size_t)(fl * MP1 + m) * nz + z0 + zi];
+                xb[i] = src[(size_t)((fl + 1) * MP1 + m) * nz + z0 + zi];
             } else if (ADJ && e < NL) {
                 const int e2 = e - NP, m = e2 / H, zi = e2 - m * H;
-                xa[i] = base[(size_t)(8 * MP1 + m) * nz + z0 + zi];
-                xb[i] = base[(size_t)(8 * MP1 + m) * nz + z0 + zi + H];
+                xa[i] = by[(size_t)(2 * MP1 + m) * nz + z0 + zi];
+                xb[i] = by[(size_t)(2 * MP1 + m) * nz + z0 + zi + H];
             }
         }
     };
@@ -738,21 +748,23 @@ size_t theta_lds(const npo_plan_s& p, int ZB, int adj) {
     return (size_t)2 * nseq * p.nt * sizeof(double2);
 }
 
-static void launch_zinv(const npo_plan_s& p, int adj, const double2* u, const double2* aux, const double2* y,
+// Inverse axial transforms of fields f0 .. f0+nf-1 (written nf per node).
+static void launch_zinv(const npo_plan_s& p, int f0, int nf, const double2* u, const double2* aux, const double2* y,
                         double2* zb, hipStream_t st) {
     const int G = p.zgroup;
     const size_t sh = zpass_lds(p, G);
     const dim3 grid(p.mp1, p.nr);
     switch (p.nz) {
-#define NPO_CASE(N)                                                                                \
-    case N:                                                                                        \
-        if (adj) hipLaunchKernelGGL((k_zinv_t<N, 9>), grid, dim3(TB), sh, st, p.kp, u, aux, y, zb); \
-        else hipLaunchKernelGGL((k_zinv_t<N, 6>), grid, dim3(TB), sh, st, p.kp, u, aux, y, zb);      \
+#define NPO_CASE(N)                                                                                         \
+    case N:                                                                                                 \
+        if (nf == 9) hipLaunchKernelGGL((k_zinv_t<N, 0, 9>), grid, dim3(TB), sh, st, p.kp, u, aux, y, zb);    \
+        else if (nf == 3) hipLaunchKernelGGL((k_zinv_t<N, 6, 3>), grid, dim3(TB), sh, st, p.kp, u, aux, y, zb); \
+        else hipLaunchKernelGGL((k_zinv_t<N, 0, 6>), grid, dim3(TB), sh, st, p.kp, u, aux, y, zb);            \
         return;
         NPO_NZ_SIZES(NPO_CASE)
 #undef NPO_CASE
     default:
-        hipLaunchKernelGGL(k_zinv, grid, dim3(256), sh, st, p.kp, adj ? 9 : 6, G, u, aux, y, zb);
+        hipLaunchKernelGGL(k_zinv, grid, dim3(256), sh, st, p.kp, f0, nf, G, u, aux, y, zb);
     }
 }
 
@@ -784,19 +796,22 @@ static int theta_tiles_per_block(const npo_plan_s& p, int ZB) {
 }
 
 template <int NT, int ADJ>
-static void launch_theta_zb(const npo_plan_s& p, int ZB, dim3 grid, size_t sh, int nq, int Q, const double2* zb,
-                            double2* tb, const TimeArg& ta, hipStream_t st) {
-    if (ZB == 8) hipLaunchKernelGGL((k_theta_t<NT, ADJ, 8>), grid, dim3(TB), sh, st, p.kp, nq, Q, zb, tb, ta);
-    else if (ZB == 4) hipLaunchKernelGGL((k_theta_t<NT, ADJ, 4>), grid, dim3(TB), sh, st, p.kp, nq, Q, zb, tb, ta);
-    else hipLaunchKernelGGL((k_theta_t<NT, ADJ, 2>), grid, dim3(TB), sh, st, p.kp, nq, Q, zb, tb, ta);
+static void launch_theta_zb(const npo_plan_s& p, int ZB, dim3 grid, size_t sh, int nq, int Q, const double2* zu,
+                            int nfu, const double2* zy, int nfy, double2* tb, const TimeArg& ta, hipStream_t st) {
+    if (ZB == 8)
+        hipLaunchKernelGGL((k_theta_t<NT, ADJ, 8>), grid, dim3(TB), sh, st, p.kp, nq, Q, zu, nfu, zy, nfy, tb, ta);
+    else if (ZB == 4)
+        hipLaunchKernelGGL((k_theta_t<NT, ADJ, 4>), grid, dim3(TB), sh, st, p.kp, nq, Q, zu, nfu, zy, nfy, tb, ta);
+    else
+        hipLaunchKernelGGL((k_theta_t<NT, ADJ, 2>), grid, dim3(TB), sh, st, p.kp, nq, Q, zu, nfu, zy, nfy, tb, ta);
 }
 
-static void launch_theta(const npo_plan_s& p, int adj, const double2* zb, double2* tb, const TimeArg& ta,
-                         hipStream_t st) {
+static void launch_theta(const npo_plan_s& p, int adj, const double2* zu, int nfu, const double2* zy, int nfy,
+                         double2* tb, const TimeArg& ta, hipStream_t st) {
     const int ZB = adj ? p.zb_theta_adj : p.zb_theta_fwd;
     const size_t sh = theta_lds(p, ZB, adj);
     if (!fast_nt(p.nt)) {
-        hipLaunchKernelGGL(k_theta, dim3(p.nz / ZB, p.nr), dim3(256), sh, st, p.kp, adj, ZB, zb, tb, ta);
+        hipLaunchKernelGGL(k_theta, dim3(p.nz / ZB, p.nr), dim3(256), sh, st, p.kp, adj, ZB, zu, nfu, zy, nfy, tb, ta);
         return;
     }
     const int Q = theta_tiles_per_block(p, ZB);
@@ -804,10 +819,10 @@ static void launch_theta(const npo_plan_s& p, int adj, const double2* zb, double
     const int nblk = nq * p.nr;
     const dim3 grid((nblk + 7) / 8 * 8);
     switch (p.nt) {
-#define NPO_CASE(N)                                                                 \
-    case N:                                                                         \
-        if (adj) launch_theta_zb<N, 1>(p, ZB, grid, sh, nq, Q, zb, tb, ta, st);     \
-        else launch_theta_zb<N, 0>(p, ZB, grid, sh, nq, Q, zb, tb, ta, st);         \
+#define NPO_CASE(N)                                                                                   \
+    case N:                                                                                           \
+        if (adj) launch_theta_zb<N, 1>(p, ZB, grid, sh, nq, Q, zu, nfu, zy, nfy, tb, ta, st);         \
+        else launch_theta_zb<N, 0>(p, ZB, grid, sh, nq, Q, zu, nfu, zy, nfy, tb, ta, st);             \
         return;
         NPO_NT_SIZES(NPO_CASE)
 #undef NPO_CASE
@@ -818,16 +833,36 @@ static void launch_theta(const npo_plan_s& p, int adj, const double2* zb, double
 
 // ---------------------------------------------------------------- launcher
 hipError_t launch_nl(const npo_plan_s& p, int adj, const double2* u, const double2* aux, const double2* y,
-                     const TimeArg& ta, double2* out0, double2* out1, void* ws, hipStream_t st) {
+                     const TimeArg& ta, double2* out0, double2* out1, void* ws, hipStream_t st, const double2* uw_pre,
+                     double2* uw_save) {
     char* base = static_cast<char*>(ws);
     double2* zb = reinterpret_cast<double2*>(base + p.ws.zbuf);
     double2* tb = reinterpret_cast<double2*>(base + p.ws.tbuf);
-    prof_begin(p, adj ? KID_ZINV_A : KID_ZINV_F, st);
-    launch_zinv(p, adj, u, aux, y, zb, st);
-    prof_end(p, adj ? KID_ZINV_A : KID_ZINV_F, st);
-    prof_begin(p, adj ? KID_THETA_A : KID_THETA_F, st);
-    launch_theta(p, adj, zb, tb, ta, st);
-    prof_end(p, adj ? KID_THETA_A : KID_THETA_F, st);
+    const size_t g1 = (size_t)p.mp1 * p.nz;     // one field of one radial node
+    if (!adj) {
+        double2* zo = uw_save ? uw_save : zb;
+        prof_begin(p, KID_ZINV_F, st);
+        launch_zinv(p, 0, 6, u, aux, y, zo, st);
+        prof_end(p, KID_ZINV_F, st);
+        prof_begin(p, KID_THETA_F, st);
+        launch_theta(p, 0, zo, 6, nullptr, 0, tb, ta, st);
+        prof_end(p, KID_THETA_F, st);
+    } else if (uw_pre) {
+        // u, w of this state were transformed by an earlier forward evaluation
+        prof_begin(p, KID_ZINV_Y, st);
+        launch_zinv(p, 6, 3, u, aux, y, zb, st);
+        prof_end(p, KID_ZINV_Y, st);
+        prof_begin(p, KID_THETA_A, st);
+        launch_theta(p, 1, uw_pre, 6, zb, 3, tb, ta, st);
+        prof_end(p, KID_THETA_A, st);
+    } else {
+        prof_begin(p, KID_ZINV_A, st);
+        launch_zinv(p, 0, 9, u, aux, y, zb, st);
+        prof_end(p, KID_ZINV_A, st);
+        prof_begin(p, KID_THETA_A, st);
+        launch_theta(p, 1, zb, 9, zb + 6 * g1, 9, tb, ta, st);
+        prof_end(p, KID_THETA_A, st);
+    }
     const double scale = 1.0 / ((double)p.nt * p.nz);
     prof_begin(p, adj ? KID_ZFWD_A : KID_ZFWD_F, st);
     launch_zfwd(p, adj, tb, out0, out1, scale, st);

@@ -77,7 +77,7 @@ SIGNATURES = {
 
 KERNEL_FAMILIES = ("curl", "zinv_fwd", "theta_fwd", "zfwd_fwd", "zinv_adj", "theta_adj", "zfwd_adj",
                    "solve_pred", "solve_corr", "solve_raw", "solve_adj", "adj_combine", "wdot", "project", "axpby",
-                   "solve_adj2")
+                   "solve_adj2", "zinv_adjy")
 
 
 def lib():

@@ -53,14 +53,14 @@ def family_kernels(nt, nz, names=(), shapes=(1, 4, 4), nr=64):
     profile) holds no compile-time-sized one."""
     zbf, zba = shapes[1], shapes[2]
     nrc = nr if (f"k_solve<1, {nr}>" in names or f"k_solve<2, {nr}>" in names or not names) else 0
-    fz = f"k_zinv_t<{nz}, 6>" in names or not names
+    fz = f"k_zinv_t<{nz}, 0, 6>" in names or not names
     ft = f"k_theta_t<{nt}, 0, {zbf}>" in names or not names
-    zi = (lambda nf: f"k_zinv_t<{nz}, {nf}>") if fz else (lambda nf: "k_zinv")
+    zi = (lambda nf: f"k_zinv_t<{nz}, {6 if nf == 3 else 0}, {nf}>") if fz else (lambda nf: "k_zinv")
     zf = (lambda nf: f"k_zfwd_t<{nz}, {nf}>") if fz else (lambda nf: "k_zfwd")
     th = (lambda a: f"k_theta_t<{nt}, {a}, {zba if a else zbf}>") if ft else (lambda a: "k_theta")
     return {
         "curl": "k_curl_aux", "zinv_fwd": zi(6), "theta_fwd": th(0), "zfwd_fwd": zf(3),
-        "zinv_adj": zi(9), "theta_adj": th(1), "zfwd_adj": zf(6),
+        "zinv_adj": zi(9), "theta_adj": th(1), "zfwd_adj": zf(6), "zinv_adjy": zi(3),
         "solve_pred": f"k_solve<1, {nrc}>", "solve_corr": f"k_solve<2, {nrc}>", "solve_raw": f"k_solve<0, {nrc}>",
         "solve_adj": f"k_solve_adj<false, {nrc}>", "solve_adj2": f"k_solve_adj<true, {nrc}>", "adj_combine": "k_final",
         "wdot": "k_wdot_partial", "project": "k_project", "axpby": "k_axpby",
