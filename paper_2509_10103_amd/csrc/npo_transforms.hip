@@ -277,8 +277,9 @@ constexpr int theta_maxr() { return ADJ ? 16 : 8; }
 __device__ __forceinline__ int lp(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int lp_size(int n) { return n + (n >> 4) + 1; }
 
-// Radix plans.  With a ceiling of 8 (few sequences per block: parallelism
-// per pass matters) the radices are taken greedily from {8, 4, 3, 2}; with a
+// Radix plans.  With a ceiling of 4 or 8 (few sequences per block:
+// parallelism per pass matters) the radices are taken greedily from {8, 4, 3,
+// 2} or {4, 3, 2}; with a
 // ceiling of 16 (many sequences per block: fewer LDS passes matter) the plan
 // has the fewest passes over {16, 12, 8, 6, 4, 3, 2}, the largest first radix
 // among such plans.
@@ -295,6 +296,7 @@ __host__ __device__ constexpr int min_passes(int n) {
 }
 template <int MAXR>
 __host__ __device__ constexpr int pick_radix(int rem) {
+    if (MAXR <= 4) return rem % 4 == 0 ? 4 : (rem % 3 == 0 ? 3 : 2);
     if (MAXR <= 8) return rem % 8 == 0 ? 8 : (rem % 4 == 0 ? 4 : (rem % 3 == 0 ? 3 : 2));
     const int target = min_passes(rem);
     for (int i = 0; i < 7; ++i)
@@ -509,7 +511,9 @@ __global__ __launch_bounds__(TB) void k_zinv_t(KP p, const double2* __restrict__
         }
         __syncthreads();
         if (f + 1 < NF) fetch(F0 + f + 1);
-        const double2* res = fft_ct<NZ, true, 8>(A, Bf, 1, tw);
+        // radix <= 4 for the six- and nine-field passes (more butterflies per
+        // pass beat fewer passes there; measured at N_z = 768)
+        const double2* res = fft_ct<NZ, true, (NF >= 6 ? 4 : 8)>(A, Bf, 1, tw);
         double2* row = zb + ((size_t)(j * NF + f) * mp1 + m) * NZ;
         for (int z = threadIdx.x; z < NZ; z += TB) row[z] = res[lp(z)];
         __syncthreads();
