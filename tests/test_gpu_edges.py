@@ -110,3 +110,23 @@ def test_single_slot_longest_recompute_equals_full_storage():
         res[nck] = to_host(lam0)
     assert nrec == 0
     assert np.array_equal(res[1], res[20])
+
+
+@pytest.mark.parametrize("ncorr", [1, 3])
+def test_corrector_pass_counts(ncorr):
+    """One and three corrector passes: the step and its adjoint against the
+    oracle (the adjoint reuses the forward axial transforms of every stage
+    but the last, whose number depends on the pass count)."""
+    from oracle.pipe import Pipe
+    from paper_2509_10103_amd import npo
+    c = dict(STEADY, amp=0.9)
+    P = Pipe(c["nr"], c["nt"], c["nz"], c["lz"], c["re"], c["wo"], c["amp"], c["dt"], c["t0"], ncorr=ncorr)
+    G = npo.Plan(c["nr"], c["nt"], c["nz"], c["lz"], c["re"], c["wo"], c["amp"], c["dt"], c["t0"], 4, ncorr)
+    u = seed_field(P, 13, 1e-3)
+    y = synth.random_field(P.shape, 14)
+    out = G.field()
+    npo.npo_forward_step(G.handle, G.ws, to_dev(u), out, 2)
+    assert relerr(P, to_host(out), P.step(u, 2)) < 1e-12
+    lam = G.field()
+    npo.npo_adjoint_step(G.handle, G.ws, to_dev(u), to_dev(y), lam, 2)
+    assert relerr(P, to_host(lam), P.step_adj(u, 2, y)) < 1e-11
