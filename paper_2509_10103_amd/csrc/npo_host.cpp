@@ -835,32 +835,41 @@ npo_status npo_forward_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const 
     const size_t fa = first_adj(acts);
     const bool gr = p->use_graphs && !p->prof.on;
     if (gr && p->graph_ws != ws) HIPCHK(build_graphs(*p, ws));
+    // Slot 0 holds u0.  The state lives at `where` (a slot or cur): a step
+    // whose result the schedule stores next writes it straight into the slot,
+    // and the step after reads it from there, so states are not copied between
+    // buffers.
     HIPCHK(hipMemcpyAsync(slot(0), u0, fb, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(w.cur, u0, fb, hipMemcpyDeviceToDevice, st));
+    const double2* where = slot(0);
     long long pos = 0;
     bool aux = false, synced = false;   // synced: the device step index equals pos
     for (size_t i = 0; i < fa; ++i) {
         const Act& a = acts[i];
         if (a.kind == A_ADV) {
             for (long long k = 0; k < a.a; ++k) {
-                if (gr && aux) {
+                double2* out = w.cur;
+                if (k + 1 == a.a && i + 1 < fa && acts[i + 1].kind == A_STORE) out = slot(acts[i + 1].a);
+                if (gr && aux && where == w.cur && out == w.cur) {
                     if (!synced) HIPCHK(npo::launch_step_index(w.step, pos, 0, st));
                     HIPCHK(hipGraphLaunch(p->g_fwd, st));
                     synced = true;
                 } else {
-                    HIPCHK(fwd_step(*p, ws, w.cur, w.cur, pos, aux, st));
+                    HIPCHK(fwd_step(*p, ws, where, out, pos, aux, st));
                     synced = false;
                 }
+                where = out;
                 aux = true;
                 ++pos;
             }
         } else if (a.kind == A_STORE) {
             if (a.b != pos) return fail(NPO_ESTATE, "schedule store position mismatch");
-            HIPCHK(hipMemcpyAsync(slot(a.a), w.cur, fb, hipMemcpyDeviceToDevice, st));
+            if (where != slot(a.a)) HIPCHK(hipMemcpyAsync(slot(a.a), where, fb, hipMemcpyDeviceToDevice, st));
+            where = slot(a.a);
         }
     }
     if (pos != p->nsteps - 1) return fail(NPO_ESTATE, "schedule descent did not reach the last step");
-    // u^{N-1} stays in cur for the first adjoint step; the last step goes to uN
+    // u^{N-1} is left in cur for the first adjoint step; the last step goes to uN
+    if (where != w.cur) HIPCHK(hipMemcpyAsync(w.cur, where, fb, hipMemcpyDeviceToDevice, st));
     HIPCHK(fwd_step(*p, ws, w.cur, F(uN), pos, aux, st));
     return NPO_OK;
 }
@@ -877,40 +886,48 @@ npo_status npo_adjoint_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const 
     const bool gr = p->use_graphs && !p->prof.on;
     if (gr && p->graph_ws != ws) HIPCHK(build_graphs(*p, ws));
     HIPCHK(hipMemcpyAsync(w.lam, lamN, fb, hipMemcpyDeviceToDevice, st));
+    // the state lives at `where` (cur or a slot), as in the forward sweep: a
+    // restore only points at its slot
+    const double2* where = w.cur;
     long long pos = p->nsteps - 1, adv = 0;
     bool aux = false, synced = false;   // synced: the device step index equals pos
     for (size_t i = first_adj(acts); i < acts.size(); ++i) {
         const Act& a = acts[i];
         if (a.kind == A_RESTORE) {
-            HIPCHK(hipMemcpyAsync(w.cur, slot(a.a), fb, hipMemcpyDeviceToDevice, st));
+            where = slot(a.a);
             pos = a.b;
             aux = false;
             synced = false;
         } else if (a.kind == A_ADV) {
             for (long long k = 0; k < a.a; ++k) {
-                if (gr && aux) {
+                double2* out = w.cur;
+                if (k + 1 == a.a && i + 1 < acts.size() && acts[i + 1].kind == A_STORE) out = slot(acts[i + 1].a);
+                if (gr && aux && where == w.cur && out == w.cur) {
                     if (!synced) HIPCHK(npo::launch_step_index(w.step, pos, 0, st));
                     HIPCHK(hipGraphLaunch(p->g_fwd, st));
                     synced = true;
                 } else {
-                    HIPCHK(fwd_step(*p, ws, w.cur, w.cur, pos, aux, st));
+                    HIPCHK(fwd_step(*p, ws, where, out, pos, aux, st));
                     synced = false;
                 }
+                where = out;
                 aux = true;
                 ++pos;
             }
             adv += a.a;
         } else if (a.kind == A_STORE) {
             if (a.b != pos) return fail(NPO_ESTATE, "schedule store position mismatch");
-            HIPCHK(hipMemcpyAsync(slot(a.a), w.cur, fb, hipMemcpyDeviceToDevice, st));
+            if (where != slot(a.a)) HIPCHK(hipMemcpyAsync(slot(a.a), where, fb, hipMemcpyDeviceToDevice, st));
+            where = slot(a.a);
         } else {
             if (a.a != pos) return fail(NPO_ESTATE, "schedule adjoint position mismatch");
-            if (gr) {
+            if (gr && where == w.cur) {
                 if (!synced) HIPCHK(npo::launch_step_index(w.step, pos, 0, st));
                 HIPCHK(hipGraphLaunch(p->g_adj, st));
                 synced = true;
             } else {
-                HIPCHK(adj_step(*p, ws, w.cur, w.lam, w.lam, pos, st));
+                HIPCHK(adj_step(*p, ws, where, w.lam, w.lam, pos, st));
+                synced = false;
             }
             aux = false;   // the adjoint step reuses aux0 for its own work
         }

@@ -1,6 +1,6 @@
 """Edge cases of the HIP path against the oracle: the largest compiled
 transform lengths, the generic (run-time radix) kernels at the largest axial
-length, a steady base flow (A = 0), the one-step horizon with a single
+length, an axial length that is not a multiple of 4, a steady base flow (A = 0), the one-step horizon with a single
 checkpoint slot and the longest recompute chain (one slot, many steps)."""
 import math
 
@@ -18,9 +18,12 @@ MAXFAST = dict(nr=12, nt=128, nz=1536, lz=100.0, re=2000.0, wo=8.0, amp=1.0, dt=
 # N_theta = 54 and N_z = 2048 have no compiled kernels: the generic transforms run
 GENERIC = dict(nr=10, nt=54, nz=2048, lz=120.0, re=2500.0, wo=6.0, amp=0.7, dt=0.02, t0=3.0)
 STEADY = dict(nr=16, nt=12, nz=24, lz=2 * math.pi, re=1500.0, wo=8.0, amp=0.0, dt=0.02, t0=0.3)
+# N_z = 54 is not a multiple of 4: the azimuthal inputs are stored in runs of
+# two z-points (generic axial kernels, compiled azimuthal kernel at N_theta = 24)
+ODDRUN = dict(nr=10, nt=24, nz=54, lz=12.0, re=1800.0, wo=5.0, amp=0.9, dt=0.02, t0=1.0)
 
 
-@pytest.fixture(scope="module", params=[MAXFAST, GENERIC], ids=["max-compiled", "generic-2048"])
+@pytest.fixture(scope="module", params=[MAXFAST, GENERIC, ODDRUN], ids=["max-compiled", "generic-2048", "runs-of-2"])
 def big(request):
     cfg = request.param
     P, G = make(cfg)
