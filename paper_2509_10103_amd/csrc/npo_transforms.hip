@@ -715,6 +715,198 @@ __global__ __launch_bounds__(TB) void k_theta_t(KP p, int nq, int Q, const doubl
     }
 }
 
+// Stockham passes of length N (radices pick_radix<8>) from stride NS up to
+// stride STOP, each ending with a barrier; returns the buffer with the result.
+template <int N, bool INV, int NS, int STOP>
+__device__ __forceinline__ double2* fft_span(double2* a, double2* b, int B, const double2* tw) {
+    if constexpr (NS == STOP) {
+        return a;
+    } else {
+        constexpr int R = pick_radix<8>(STOP / NS);
+        stockham_pass<N, R, NS, INV>(a, b, B, tw);
+        __syncthreads();
+        return fft_span<N, INV, NS * R, STOP>(b, a, B, tw);
+    }
+}
+
+// Forward azimuthal pass for N_theta = 3P (then M = P - 1), with the first
+// and last passes of both transforms pruned and fused.  Plan: inverse radices
+// 3, then pick_radix<8> over P / 4, then 4; forward radices in reverse order.
+//  * First inverse pass (radix 3, stride P): butterfly jj reads positions jj
+//    (mode jj), P + jj (inside the zero band) and 2P + jj (conjugate of mode
+//    P - jj, zero for jj = 0), and butterfly P - jj needs the same two modes,
+//    so one thread loads modes jj and P - jj from global memory and runs both;
+//    nothing is placed in LDS beforehand.
+//  * Last inverse pass and first forward pass (radix 4): the last inverse
+//    butterfly jj leaves theta = jj + q N / 4, exactly the inputs of forward
+//    butterfly jj, so one thread runs both with the products in between.
+//  * Last forward pass (radix 3, stride P): X[m] for m <= M is output 0 of
+//    butterfly m, and X[N - m] output 2 of butterfly P - m; a thread running
+//    both butterflies unpacks the two real fields and stores them.
+// N_z is transformed as its own (real) sequence.  Five barriers per tile
+// instead of eight, and about 40% fewer LDS accesses than the generic plan;
+// for the adjoint products (five input sequences per column) the register
+// demand of the fused middle outweighs that, and the adjoint keeps k_theta_t.
+template <int NT, int ZB>
+__global__ __launch_bounds__(TB) void k_theta_p(KP p, int nq, int Q, const double2* __restrict__ zu, int nfu,
+                                               double2* __restrict__ tb, TimeArg ta) {
+    static_assert(NT % 12 == 0, "N_theta = 3P with P a multiple of 4");
+    constexpr int P = NT / 3, MP1 = P;
+    constexpr int NIN = 3 * ZB, NOUT = 2 * ZB;
+    constexpr int PH = P / 2 + 1;                      // first-pass items per sequence: butterflies jj, P - jj
+    constexpr int NST = 3 * PH * ZB;
+    constexpr int PST = (NST + TB - 1) / TB;
+    constexpr int NBL = NT / 4;
+    constexpr int NMID = ZB * NBL;
+    constexpr int NEND = NOUT * PH;
+    const int nblk = nq * p.nr;
+    const int per = (nblk + 7) >> 3;
+    const int Lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (Lb >= nblk) return;
+    const int j = Lb / nq, zq = Lb - j * nq, nz = p.nz;
+    extern __shared__ double2 sh[];
+    double2* tw = sh;
+    double2* A = sh + NT;
+    double2* Bf = A + lp_size(NIN * NT);
+    for (int t = threadIdx.x; t < NT; t += TB) tw[t] = p.twt[t];
+    double U, Om, cw, sw;
+    phase_of(p, ta, cw, sw);
+    base_at(p, j, cw, sw, U, Om);
+    const double2* bu = zu + (size_t)j * nfu * MP1 * nz;
+    // item e: column zi = e % ZB, butterfly pair jj, field pair pi (u_r u_t,
+    // u_z w_r, w_t w_z); modes jj and P - jj of both fields
+    double2 a1[PST], b1[PST], a2[PST], b2[PST];
+    auto fetch = [&](int z0) {
+#pragma unroll
+        for (int i = 0; i < PST; ++i) {
+            const int e = threadIdx.x + i * TB;
+            a1[i] = b1[i] = a2[i] = b2[i] = czero();
+            if (e < NST) {
+                const int zi = e % ZB, q = e / ZB;
+                const int pi = q / PH, jj = q - pi * PH;
+                const size_t ra = (size_t)2 * pi * MP1 * nz + z0 + zi, rb = ra + (size_t)MP1 * nz;
+                a1[i] = bu[ra + (size_t)jj * nz];
+                b1[i] = bu[rb + (size_t)jj * nz];
+                if (jj) {
+                    a2[i] = bu[ra + (size_t)(P - jj) * nz];
+                    b2[i] = bu[rb + (size_t)(P - jj) * nz];
+                }
+            }
+        }
+    };
+    // first inverse pass: position jj holds xa + i xb of mode jj, position
+    // 2P + jj the conjugate pair of mode P - jj (and symmetrically for P - jj)
+    auto first_pass = [&]() {
+#pragma unroll
+        for (int i = 0; i < PST; ++i) {
+            const int e = threadIdx.x + i * TB;
+            if (e >= NST) continue;
+            const int zi = e % ZB, q = e / ZB;
+            const int pi = q / PH, jj = q - pi * PH;
+            const int sb = (pi * ZB + zi) * NT;
+            if (jj == 0) {
+                double2 v0 = make_double2(a1[i].x, b1[i].x), v1 = czero(), v2 = czero();
+                dft3<true>(v0, v1, v2);
+                A[lp(sb)] = v0;
+                A[lp(sb + 1)] = v1;
+                A[lp(sb + 2)] = v2;
+            } else {
+                const double2 m1 = make_double2(a1[i].x - b1[i].y, a1[i].y + b1[i].x);    // mode jj
+                const double2 c1 = make_double2(a1[i].x + b1[i].y, -a1[i].y + b1[i].x);   // its conjugate pair
+                const double2 m2 = make_double2(a2[i].x - b2[i].y, a2[i].y + b2[i].x);    // mode P - jj
+                const double2 c2 = make_double2(a2[i].x + b2[i].y, -a2[i].y + b2[i].x);
+                double2 v0 = m1, v1 = czero(), v2 = c2;
+                dft3<true>(v0, v1, v2);
+                A[lp(sb + 3 * jj)] = v0;
+                A[lp(sb + 3 * jj + 1)] = v1;
+                A[lp(sb + 3 * jj + 2)] = v2;
+                if (2 * jj != P) {
+                    double2 u0 = m2, u1 = czero(), u2 = c1;
+                    dft3<true>(u0, u1, u2);
+                    A[lp(sb + 3 * (P - jj))] = u0;
+                    A[lp(sb + 3 * (P - jj) + 1)] = u1;
+                    A[lp(sb + 3 * (P - jj) + 2)] = u2;
+                }
+            }
+        }
+    };
+    auto inv_tail = [&](const double2* X, int s, int jj, const double2* w, double2* v) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = X[lp(s * NT + jj + q * NBL)];
+#pragma unroll
+        for (int q = 1; q < 4; ++q) v[q] = tw_mul<true>(v[q], w[q]);
+        dft4<true>(v[0], v[1], v[2], v[3]);
+    };
+    auto fwd_head = [&](double2* Y, int s, int jj, double2* v) {
+        dft4<false>(v[0], v[1], v[2], v[3]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Y[lp(s * NT + 4 * jj + q)] = v[q];
+    };
+    int z0 = zq * ZB;
+    fetch(z0);
+    for (int tile = 0; tile < Q; ++tile, z0 += nq * ZB) {
+        first_pass();
+        __syncthreads();
+        if (tile + 1 < Q) fetch(z0 + nq * ZB);
+        double2* R1 = fft_span<NT, true, 3, NBL>(A, Bf, NIN, tw);
+        double2* O = (R1 == A) ? Bf : A;
+        for (int t = threadIdx.x; t < NMID; t += TB) {
+            const int jj = t % NBL, zi = t / NBL;
+            double2 w[4];
+#pragma unroll
+            for (int q = 1; q < 4; ++q) w[q] = tw[q * jj];
+            double2 s0[4], s1[4], s2[4];
+            inv_tail(R1, 0 * ZB + zi, jj, w, s0);
+            inv_tail(R1, 1 * ZB + zi, jj, w, s1);
+            inv_tail(R1, 2 * ZB + zi, jj, w, s2);
+            double2 o0[4], o1[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double ur = s0[q].x, ut = s0[q].y, uz = s1[q].x, wr = s1[q].y, wt = s2[q].x, wz = s2[q].y;
+                const double uzU = uz + U;
+                o0[q] = make_double2(ut * wz - uzU * wt - uz * Om, uzU * wr - ur * wz);
+                o1[q] = make_double2(ur * (wt + Om) - ut * wr, 0.0);
+            }
+            fwd_head(O, zi, jj, o0);
+            fwd_head(O, ZB + zi, jj, o1);
+        }
+        __syncthreads();
+        const double2* R2 = fft_span<NT, false, 4, P>(O, R1, NOUT, tw);
+        for (int t = threadIdx.x; t < NEND; t += TB) {
+            const int jA = t % PH, s = t / PH;
+            const int jB = jA == 0 ? 0 : P - jA;
+            // outputs 0 and 2 of the last forward butterflies jA and jB
+            auto bfly = [&](int jx, double2& y0, double2& y2) {
+                double2 v0 = R2[lp(s * NT + jx)], v1 = R2[lp(s * NT + jx + P)], v2 = R2[lp(s * NT + jx + 2 * P)];
+                v1 = tw_mul<false>(v1, tw[jx]);
+                v2 = tw_mul<false>(v2, tw[2 * jx]);
+                dft3<false>(v0, v1, v2);
+                y0 = v0;
+                y2 = v2;
+            };
+            double2 yA0, yA2, yB0, yB2;
+            bfly(jA, yA0, yA2);
+            if (jB != jA) bfly(jB, yB0, yB2);
+            else { yB0 = yA0; yB2 = yA2; }
+            // sequence s < ZB: N_r + i N_t of column s; else N_z of column s - ZB
+            const int zc = s < ZB ? s : s - ZB;
+            auto emit = [&](int m, double2 a, double2 bm) {
+                const double2 b = cconj(bm);      // conj X[N - m]
+                const size_t col = (size_t)m * nz + z0 + zc;
+                if (s < ZB) {
+                    tb[(size_t)(j * 3 + 0) * MP1 * nz + col] = cscale(cadd(a, b), 0.5);
+                    tb[(size_t)(j * 3 + 1) * MP1 * nz + col] = cscale(cmuli(csub(b, a)), 0.5);
+                } else {
+                    tb[(size_t)(j * 3 + 2) * MP1 * nz + col] = cscale(cadd(a, b), 0.5);
+                }
+            };
+            emit(jA, yA0, jA == 0 ? yA0 : yB2);
+            if (jB != jA) emit(jB, yB0, yA2);
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- dispatch
 #define NPO_NZ_SIZES(X) X(24) X(48) X(96) X(144) X(192) X(288) X(384) X(576) X(768) X(1024) X(1536)
 #define NPO_NT_SIZES(X) X(12) X(24) X(48) X(64) X(96) X(128)
@@ -799,15 +991,21 @@ static int theta_tiles_per_block(const npo_plan_s& p, int ZB) {
     return 1;
 }
 
+template <int NT, int ADJ, int ZB>
+static void launch_theta_k(dim3 grid, size_t sh, const npo_plan_s& p, int nq, int Q, const double2* zu, int nfu,
+                           const double2* zy, int nfy, double2* tb, const TimeArg& ta, hipStream_t st) {
+    if constexpr (NT % 12 == 0 && !ADJ)
+        hipLaunchKernelGGL((k_theta_p<NT, ZB>), grid, dim3(TB), sh, st, p.kp, nq, Q, zu, nfu, tb, ta);
+    else
+        hipLaunchKernelGGL((k_theta_t<NT, ADJ, ZB>), grid, dim3(TB), sh, st, p.kp, nq, Q, zu, nfu, zy, nfy, tb, ta);
+}
+
 template <int NT, int ADJ>
 static void launch_theta_zb(const npo_plan_s& p, int ZB, dim3 grid, size_t sh, int nq, int Q, const double2* zu,
                             int nfu, const double2* zy, int nfy, double2* tb, const TimeArg& ta, hipStream_t st) {
-    if (ZB == 8)
-        hipLaunchKernelGGL((k_theta_t<NT, ADJ, 8>), grid, dim3(TB), sh, st, p.kp, nq, Q, zu, nfu, zy, nfy, tb, ta);
-    else if (ZB == 4)
-        hipLaunchKernelGGL((k_theta_t<NT, ADJ, 4>), grid, dim3(TB), sh, st, p.kp, nq, Q, zu, nfu, zy, nfy, tb, ta);
-    else
-        hipLaunchKernelGGL((k_theta_t<NT, ADJ, 2>), grid, dim3(TB), sh, st, p.kp, nq, Q, zu, nfu, zy, nfy, tb, ta);
+    if (ZB == 8) launch_theta_k<NT, ADJ, 8>(grid, sh, p, nq, Q, zu, nfu, zy, nfy, tb, ta, st);
+    else if (ZB == 4) launch_theta_k<NT, ADJ, 4>(grid, sh, p, nq, Q, zu, nfu, zy, nfy, tb, ta, st);
+    else launch_theta_k<NT, ADJ, 2>(grid, sh, p, nq, Q, zu, nfu, zy, nfy, tb, ta, st);
 }
 
 static void launch_theta(const npo_plan_s& p, int adj, const double2* zu, int nfu, const double2* zy, int nfy,

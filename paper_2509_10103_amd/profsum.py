@@ -54,10 +54,15 @@ def family_kernels(nt, nz, names=(), shapes=(1, 4, 4), nr=64):
     zbf, zba = shapes[1], shapes[2]
     nrc = nr if (f"k_solve<1, {nr}>" in names or f"k_solve<2, {nr}>" in names or not names) else 0
     fz = f"k_zinv_t<{nz}, 0, 6>" in names or not names
-    ft = f"k_theta_t<{nt}, 0, {zbf}>" in names or not names
+    ft = f"k_theta_t<{nt}, 0, {zbf}>" in names or f"k_theta_p<{nt}, {zbf}>" in names or not names
     zi = (lambda nf: f"k_zinv_t<{nz}, {6 if nf == 3 else 0}, {nf}>") if fz else (lambda nf: "k_zinv")
     zf = (lambda nf: f"k_zfwd_t<{nz}, {nf}>") if fz else (lambda nf: "k_zfwd")
-    th = (lambda a: f"k_theta_t<{nt}, {a}, {zba if a else zbf}>") if ft else (lambda a: "k_theta")
+    def th(a):
+        if not ft:
+            return "k_theta"
+        if a == 0 and nt % 12 == 0:
+            return f"k_theta_p<{nt}, {zbf}>"
+        return f"k_theta_t<{nt}, {a}, {zba if a else zbf}>"
     return {
         "curl": "k_curl_aux", "zinv_fwd": zi(6), "theta_fwd": th(0), "zfwd_fwd": zf(3),
         "zinv_adj": zi(9), "theta_adj": th(1), "zfwd_adj": zf(6), "zinv_adjy": zi(3),

@@ -21,9 +21,12 @@ STEADY = dict(nr=16, nt=12, nz=24, lz=2 * math.pi, re=1500.0, wo=8.0, amp=0.0, d
 # N_z = 54 is not a multiple of 4: the azimuthal inputs are stored in runs of
 # two z-points (generic axial kernels, compiled azimuthal kernel at N_theta = 24)
 ODDRUN = dict(nr=10, nt=24, nz=54, lz=12.0, re=1800.0, wo=5.0, amp=0.9, dt=0.02, t0=1.0)
+# N_theta = 48: the pruned forward azimuthal plan with one middle pass of radix 4
+THETA48 = dict(nr=8, nt=48, nz=48, lz=8.0, re=2200.0, wo=7.0, amp=1.1, dt=0.02, t0=0.2)
 
 
-@pytest.fixture(scope="module", params=[MAXFAST, GENERIC, ODDRUN], ids=["max-compiled", "generic-2048", "runs-of-2"])
+@pytest.fixture(scope="module", params=[MAXFAST, GENERIC, ODDRUN, THETA48],
+                ids=["max-compiled", "generic-2048", "runs-of-2", "theta-48"])
 def big(request):
     cfg = request.param
     P, G = make(cfg)
