@@ -464,6 +464,20 @@ __device__ __forceinline__ double2* fft_ct(double2* a, double2* b, int B, const 
     }
 }
 
+// Stockham passes of length N (radices pick_radix<MAXR>) from stride NS up to
+// stride STOP, each ending with a barrier; returns the buffer with the result.
+template <int N, bool INV, int MAXR, int NS, int STOP>
+__device__ __forceinline__ double2* fft_span(double2* a, double2* b, int B, const double2* tw) {
+    if constexpr (NS == STOP) {
+        return a;
+    } else {
+        constexpr int R = pick_radix<MAXR>(STOP / NS);
+        stockham_pass<N, R, NS, INV>(a, b, B, tw);
+        __syncthreads();
+        return fft_span<N, INV, MAXR, NS * R, STOP>(b, a, B, tw);
+    }
+}
+
 // Inverse axial transforms of fields F0 .. F0+NF-1 of the list 0..2 u, 3 w_r
 // (built from u), 4..5 aux, 6..8 y (forward term 0..5, adjoint term 0..8, or
 // the adjoint field alone 6..8), written as NF fields per node.  One field per round;
@@ -516,6 +530,79 @@ __global__ __launch_bounds__(TB) void k_zinv_t(KP p, const double2* __restrict__
         const double2* res = fft_ct<NZ, true, (NF >= 6 ? 4 : 8)>(A, Bf, 1, tw);
         double2* row = zb + ((size_t)(j * NF + f) * mp1 + m) * NZ;
         for (int z = threadIdx.x; z < NZ; z += TB) row[z] = res[lp(z)];
+        __syncthreads();
+    }
+}
+
+// Inverse axial transforms for N_z = 3P (then K = P - 1), same fields and
+// output as k_zinv_t.  Plan: radix 3 (stride P), pick_radix<MAXR> passes, radix
+// 4 (stride N_z / 4).  The first pass runs on the modes in registers: its
+// butterfly jj reads z = jj (mode jj), z = P + jj (in the zero band) and
+// z = 2P + jj (mode jj - P, zero for jj = 0), so nothing is placed in LDS
+// beforehand; the last pass stores its outputs straight to the row.  Two LDS
+// round trips and two barriers fewer per field than k_zinv_t.
+template <int NZ, int F0, int NF>
+__global__ __launch_bounds__(TB) void k_zinv_p(KP p, const double2* __restrict__ u, const double2* __restrict__ aux,
+                                              const double2* __restrict__ y, double2* __restrict__ zb) {
+    static_assert(NZ % 12 == 0, "N_z = 3P with P a multiple of 4");
+    constexpr int P = NZ / 3, NK = 2 * P - 1;
+    constexpr int PB = (P + TB - 1) / TB;             // first-pass butterflies per thread
+    constexpr int NB4 = NZ / 4;                       // last-pass butterflies
+    constexpr int MAXR = NF >= 6 ? 4 : 8;
+    extern __shared__ double2 sh[];
+    double2* tw = sh;
+    double2* A = sh + NZ;
+    double2* Bf = A + lp_size(NZ);
+    const int m = blockIdx.x, j = blockIdx.y, mp1 = p.mp1;
+    const double mr = m / p.r[j];
+    for (int t = threadIdx.x; t < NZ; t += TB) tw[t] = p.twz[t];
+    auto load = [&](int f, int kk) -> double2 {
+        if (f < 3) return u[fidx(p, f, j, m, kk)];
+        if (f == 3)
+            return csub(cscale(cmuli(u[fidx(p, 2, j, m, kk)]), mr), cscale(cmuli(u[fidx(p, 1, j, m, kk)]), alpha_of(p, kk)));
+        if (f < 6) return aux[fidx(p, f - 4, j, m, kk)];
+        return y[fidx(p, f - 6, j, m, kk)];
+    };
+    // modes jj (z = jj) and jj - P (z = 2P + jj, stored at kk = jj + NK - P)
+    double2 v0[PB], v2[PB];
+    auto fetch = [&](int f) {
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+            const int jj = threadIdx.x + b * TB;
+            v0[b] = v2[b] = czero();
+            if (jj < P) {
+                v0[b] = load(f, jj);
+                if (jj) v2[b] = load(f, jj + NK - P);
+            }
+        }
+    };
+    fetch(F0);
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+            const int jj = threadIdx.x + b * TB;
+            if (jj < P) {
+                double2 a = v0[b], c = czero(), d = v2[b];
+                dft3<true>(a, c, d);
+                A[lp(3 * jj)] = a;
+                A[lp(3 * jj + 1)] = c;
+                A[lp(3 * jj + 2)] = d;
+            }
+        }
+        __syncthreads();
+        if (f + 1 < NF) fetch(F0 + f + 1);
+        const double2* X = fft_span<NZ, true, MAXR, 3, NB4>(A, Bf, 1, tw);
+        double2* row = zb + ((size_t)(j * NF + f) * mp1 + m) * NZ;
+        for (int jj = threadIdx.x; jj < NB4; jj += TB) {
+            double2 v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = X[lp(jj + q * NB4)];
+#pragma unroll
+            for (int q = 1; q < 4; ++q) v[q] = tw_mul<true>(v[q], tw[q * jj]);
+            dft4<true>(v[0], v[1], v[2], v[3]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) row[jj + q * NB4] = v[q];
+        }
         __syncthreads();
     }
 }
@@ -715,20 +802,6 @@ __global__ __launch_bounds__(TB) void k_theta_t(KP p, int nq, int Q, const doubl
     }
 }
 
-// Stockham passes of length N (radices pick_radix<8>) from stride NS up to
-// stride STOP, each ending with a barrier; returns the buffer with the result.
-template <int N, bool INV, int NS, int STOP>
-__device__ __forceinline__ double2* fft_span(double2* a, double2* b, int B, const double2* tw) {
-    if constexpr (NS == STOP) {
-        return a;
-    } else {
-        constexpr int R = pick_radix<8>(STOP / NS);
-        stockham_pass<N, R, NS, INV>(a, b, B, tw);
-        __syncthreads();
-        return fft_span<N, INV, NS * R, STOP>(b, a, B, tw);
-    }
-}
-
 // Forward azimuthal pass for N_theta = 3P (then M = P - 1), with the first
 // and last passes of both transforms pruned and fused.  Plan: inverse radices
 // 3, then pick_radix<8> over P / 4, then 4; forward radices in reverse order.
@@ -848,7 +921,7 @@ __global__ __launch_bounds__(TB) void k_theta_p(KP p, int nq, int Q, const doubl
         first_pass();
         __syncthreads();
         if (tile + 1 < Q) fetch(z0 + nq * ZB);
-        double2* R1 = fft_span<NT, true, 3, NBL>(A, Bf, NIN, tw);
+        double2* R1 = fft_span<NT, true, 8, 3, NBL>(A, Bf, NIN, tw);
         double2* O = (R1 == A) ? Bf : A;
         for (int t = threadIdx.x; t < NMID; t += TB) {
             const int jj = t % NBL, zi = t / NBL;
@@ -871,7 +944,7 @@ __global__ __launch_bounds__(TB) void k_theta_p(KP p, int nq, int Q, const doubl
             fwd_head(O, ZB + zi, jj, o1);
         }
         __syncthreads();
-        const double2* R2 = fft_span<NT, false, 4, P>(O, R1, NOUT, tw);
+        const double2* R2 = fft_span<NT, false, 8, 4, P>(O, R1, NOUT, tw);
         for (int t = threadIdx.x; t < NEND; t += TB) {
             const int jA = t % PH, s = t / PH;
             const int jB = jA == 0 ? 0 : P - jA;
@@ -944,6 +1017,23 @@ size_t theta_lds(const npo_plan_s& p, int ZB, int adj) {
     return (size_t)2 * nseq * p.nt * sizeof(double2);
 }
 
+template <int NZ, int F0, int NF>
+static void launch_zinv_k(dim3 grid, size_t sh, const npo_plan_s& p, const double2* u, const double2* aux,
+                          const double2* y, double2* zb, hipStream_t st) {
+    if constexpr (NZ % 12 == 0)
+        hipLaunchKernelGGL((k_zinv_p<NZ, F0, NF>), grid, dim3(TB), sh, st, p.kp, u, aux, y, zb);
+    else
+        hipLaunchKernelGGL((k_zinv_t<NZ, F0, NF>), grid, dim3(TB), sh, st, p.kp, u, aux, y, zb);
+}
+
+template <int NZ>
+static void launch_zinv_n(dim3 grid, size_t sh, const npo_plan_s& p, int nf, const double2* u, const double2* aux,
+                          const double2* y, double2* zb, hipStream_t st) {
+    if (nf == 9) launch_zinv_k<NZ, 0, 9>(grid, sh, p, u, aux, y, zb, st);
+    else if (nf == 3) launch_zinv_k<NZ, 6, 3>(grid, sh, p, u, aux, y, zb, st);
+    else launch_zinv_k<NZ, 0, 6>(grid, sh, p, u, aux, y, zb, st);
+}
+
 // Inverse axial transforms of fields f0 .. f0+nf-1 (written nf per node).
 static void launch_zinv(const npo_plan_s& p, int f0, int nf, const double2* u, const double2* aux, const double2* y,
                         double2* zb, hipStream_t st) {
@@ -953,9 +1043,7 @@ static void launch_zinv(const npo_plan_s& p, int f0, int nf, const double2* u, c
     switch (p.nz) {
 #define NPO_CASE(N)                                                                                         \
     case N:                                                                                                 \
-        if (nf == 9) hipLaunchKernelGGL((k_zinv_t<N, 0, 9>), grid, dim3(TB), sh, st, p.kp, u, aux, y, zb);    \
-        else if (nf == 3) hipLaunchKernelGGL((k_zinv_t<N, 6, 3>), grid, dim3(TB), sh, st, p.kp, u, aux, y, zb); \
-        else hipLaunchKernelGGL((k_zinv_t<N, 0, 6>), grid, dim3(TB), sh, st, p.kp, u, aux, y, zb);            \
+        launch_zinv_n<N>(grid, sh, p, nf, u, aux, y, zb, st);                                               \
         return;
         NPO_NZ_SIZES(NPO_CASE)
 #undef NPO_CASE
