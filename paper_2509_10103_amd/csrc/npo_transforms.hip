@@ -649,6 +649,63 @@ __global__ __launch_bounds__(TB) void k_zfwd_t(KP p, const double2* __restrict__
     }
 }
 
+// Forward axial transforms for N_z = 3P (then K = P - 1), same inputs and
+// outputs as k_zfwd_t.  Plan: radix 4 (stride N_z / 4), pick_radix<8> passes,
+// radix 3 (stride P).  The first pass runs on the row in registers, and the
+// last pass computes only the outputs that survive the truncation (z = jj and
+// z = 2P + jj of butterfly jj; z = P + jj lies outside the band) and stores
+// them to the spectral field.
+template <int NZ, int NFO>
+__global__ __launch_bounds__(TB) void k_zfwd_p(KP p, const double2* __restrict__ tb, double2* __restrict__ out0,
+                                              double2* __restrict__ out1, double scale) {
+    static_assert(NZ % 12 == 0, "N_z = 3P with P a multiple of 4");
+    constexpr int P = NZ / 3, NK = 2 * P - 1;
+    constexpr int NB4 = NZ / 4;
+    constexpr int PB = (NB4 + TB - 1) / TB;           // first-pass butterflies per thread
+    extern __shared__ double2 sh[];
+    double2* tw = sh;
+    double2* A = sh + NZ;
+    double2* Bf = A + lp_size(NZ);
+    const int m = blockIdx.x, j = blockIdx.y, mp1 = p.mp1;
+    for (int t = threadIdx.x; t < NZ; t += TB) tw[t] = p.twz[t];
+    double2 v[PB][4];
+    auto fetch = [&](int f) {
+        const double2* row = tb + ((size_t)(j * NFO + f) * mp1 + m) * NZ;
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+            const int jj = threadIdx.x + b * TB;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[b][q] = jj < NB4 ? row[jj + q * NB4] : czero();
+        }
+    };
+    fetch(0);
+    for (int f = 0; f < NFO; ++f) {
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+            const int jj = threadIdx.x + b * TB;
+            if (jj < NB4) {
+                dft4<false>(v[b][0], v[b][1], v[b][2], v[b][3]);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) A[lp(4 * jj + q)] = v[b][q];
+            }
+        }
+        __syncthreads();
+        if (f + 1 < NFO) fetch(f + 1);
+        const double2* X = fft_span<NZ, false, 8, 4, P>(A, Bf, 1, tw);
+        double2* out = f < 3 ? out0 : out1;
+        const int c = f < 3 ? f : f - 3;
+        for (int jj = threadIdx.x; jj < P; jj += TB) {
+            double2 a = X[lp(jj)], b = X[lp(jj + P)], d = X[lp(jj + 2 * P)];
+            b = tw_mul<false>(b, tw[jj]);
+            d = tw_mul<false>(d, tw[2 * jj]);
+            dft3<false>(a, b, d);
+            out[fidx(p, c, j, m, jj)] = cscale(a, scale);
+            if (jj) out[fidx(p, c, j, m, jj + NK - P)] = cscale(d, scale);
+        }
+        __syncthreads();
+    }
+}
+
 // Azimuthal transforms and products.  A block owns Q tiles of ZB axial points
 // at node j (nq tiles apart) and walks through them, loading the next tile's
 // inputs into registers while the current one is transformed.  Blocks are
@@ -1052,6 +1109,15 @@ static void launch_zinv(const npo_plan_s& p, int f0, int nf, const double2* u, c
     }
 }
 
+template <int NZ, int NFO>
+static void launch_zfwd_k(dim3 grid, size_t sh, const npo_plan_s& p, const double2* tb, double2* out0, double2* out1,
+                          double scale, hipStream_t st) {
+    if constexpr (NZ % 12 == 0)
+        hipLaunchKernelGGL((k_zfwd_p<NZ, NFO>), grid, dim3(TB), sh, st, p.kp, tb, out0, out1, scale);
+    else
+        hipLaunchKernelGGL((k_zfwd_t<NZ, NFO>), grid, dim3(TB), sh, st, p.kp, tb, out0, out1, scale);
+}
+
 static void launch_zfwd(const npo_plan_s& p, int adj, const double2* tb, double2* out0, double2* out1,
                         double scale, hipStream_t st) {
     const int G = p.zgroup;
@@ -1060,8 +1126,8 @@ static void launch_zfwd(const npo_plan_s& p, int adj, const double2* tb, double2
     switch (p.nz) {
 #define NPO_CASE(N)                                                                                      \
     case N:                                                                                              \
-        if (adj) hipLaunchKernelGGL((k_zfwd_t<N, 6>), grid, dim3(TB), sh, st, p.kp, tb, out0, out1, scale); \
-        else hipLaunchKernelGGL((k_zfwd_t<N, 3>), grid, dim3(TB), sh, st, p.kp, tb, out0, out1, scale);     \
+        if (adj) launch_zfwd_k<N, 6>(grid, sh, p, tb, out0, out1, scale, st);                                \
+        else launch_zfwd_k<N, 3>(grid, sh, p, tb, out0, out1, scale, st);                                    \
         return;
         NPO_NZ_SIZES(NPO_CASE)
 #undef NPO_CASE
