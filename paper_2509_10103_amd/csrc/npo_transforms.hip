@@ -1003,7 +1003,7 @@ __global__ __launch_bounds__(TB) void k_theta_p(KP p, int nq, int Q, const doubl
         __syncthreads();
         const double2* R2 = fft_span<NT, false, 8, 4, P>(O, R1, NOUT, tw);
         for (int t = threadIdx.x; t < NEND; t += TB) {
-            const int jA = t % PH, s = t / PH;
+            const int s = t % NOUT, jA = t / NOUT;   // columns fastest: contiguous z stores
             const int jB = jA == 0 ? 0 : P - jA;
             // outputs 0 and 2 of the last forward butterflies jA and jB
             auto bfly = [&](int jx, double2& y0, double2& y2) {
