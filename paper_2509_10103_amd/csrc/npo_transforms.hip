@@ -874,9 +874,7 @@ __global__ __launch_bounds__(TB) void k_theta_t(KP p, int nq, int Q, const doubl
 //    butterfly m, and X[N - m] output 2 of butterfly P - m; a thread running
 //    both butterflies unpacks the two real fields and stores them.
 // N_z is transformed as its own (real) sequence.  Five barriers per tile
-// instead of eight, and about 40% fewer LDS accesses than the generic plan;
-// for the adjoint products (five input sequences per column) the register
-// demand of the fused middle outweighs that, and the adjoint keeps k_theta_t.
+// instead of eight, and about 40% fewer LDS accesses than the generic plan.
 template <int NT, int ZB>
 __global__ __launch_bounds__(TB) void k_theta_p(KP p, int nq, int Q, const double2* __restrict__ zu, int nfu,
                                                double2* __restrict__ tb, TimeArg ta) {
@@ -1037,6 +1035,193 @@ __global__ __launch_bounds__(TB) void k_theta_p(KP p, int nq, int Q, const doubl
     }
 }
 
+// Adjoint azimuthal pass for N_theta = 3P with the pruned, fused plan of
+// k_theta_p: inputs u (u_r u_t, u_z w_r, w_t w_z from zu), y (y_r y_t from zy)
+// and y_z of columns zi and zi + H paired; outputs A = (Om + w) x Y and
+// B = Y x (U + u) as the three sequences (A_r, A_t), (A_z, B_r), (B_t, B_z)
+// of each column.
+template <int NT, int ZB>
+__global__ __launch_bounds__(TB) void k_theta_pa(KP p, int nq, int Q, const double2* __restrict__ zu, int nfu,
+                                                const double2* __restrict__ zy, int nfy, double2* __restrict__ tb,
+                                                TimeArg ta) {
+    static_assert(NT % 12 == 0, "N_theta = 3P with P a multiple of 4");
+    constexpr int P = NT / 3, MP1 = P;
+    constexpr int H = ZB / 2;
+    constexpr int NIN = 4 * ZB + H, NOUT = 3 * ZB;
+    constexpr int PH = P / 2 + 1;
+    constexpr int NPS = 4 * PH * ZB;                   // first-pass items of the field pairs
+    constexpr int NST = NPS + PH * H;                  // + of the paired y_z columns
+    constexpr int PST = (NST + TB - 1) / TB;
+    constexpr int NBL = NT / 4;
+    constexpr int NMID = ZB * NBL;
+    constexpr int NEND = NOUT * PH;
+    const int nblk = nq * p.nr;
+    const int per = (nblk + 7) >> 3;
+    const int Lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (Lb >= nblk) return;
+    const int j = Lb / nq, zq = Lb - j * nq, nz = p.nz;
+    extern __shared__ double2 sh[];
+    double2* tw = sh;
+    double2* A = sh + NT;
+    double2* Bf = A + lp_size(NIN * NT);
+    for (int t = threadIdx.x; t < NT; t += TB) tw[t] = p.twt[t];
+    double U, Om, cw, sw;
+    phase_of(p, ta, cw, sw);
+    base_at(p, j, cw, sw, U, Om);
+    const double2* bu = zu + (size_t)j * nfu * MP1 * nz;
+    const double2* by = zy + (size_t)j * nfy * MP1 * nz;
+    double2 a1[PST], b1[PST], a2[PST], b2[PST];
+    auto fetch = [&](int z0) {
+#pragma unroll
+        for (int i = 0; i < PST; ++i) {
+            const int e = threadIdx.x + i * TB;
+            a1[i] = b1[i] = a2[i] = b2[i] = czero();
+            size_t ra = 0, rb = 0;
+            const double2* src = nullptr;
+            int jj = 0;
+            if (e < NPS) {
+                const int zi = e % ZB, q = e / ZB;
+                const int pi = q / PH;
+                jj = q - pi * PH;
+                src = pi < 3 ? bu : by;
+                ra = (size_t)(pi < 3 ? 2 * pi : 0) * MP1 * nz + z0 + zi;
+                rb = ra + (size_t)MP1 * nz;
+            } else if (e < NST) {
+                const int e2 = e - NPS, zi = e2 % H;
+                jj = e2 / H;
+                src = by;
+                ra = (size_t)2 * MP1 * nz + z0 + zi;
+                rb = ra + H;
+            }
+            if (src) {
+                a1[i] = src[ra + (size_t)jj * nz];
+                b1[i] = src[rb + (size_t)jj * nz];
+                if (jj) {
+                    a2[i] = src[ra + (size_t)(P - jj) * nz];
+                    b2[i] = src[rb + (size_t)(P - jj) * nz];
+                }
+            }
+        }
+    };
+    auto first_pass = [&]() {
+#pragma unroll
+        for (int i = 0; i < PST; ++i) {
+            const int e = threadIdx.x + i * TB;
+            if (e >= NST) continue;
+            int s, jj;
+            if (e < NPS) {
+                const int zi = e % ZB, q = e / ZB;
+                const int pi = q / PH;
+                jj = q - pi * PH;
+                s = pi * ZB + zi;
+            } else {
+                const int e2 = e - NPS;
+                jj = e2 / H;
+                s = 4 * ZB + e2 % H;
+            }
+            const int sb = s * NT;
+            if (jj == 0) {
+                double2 v0 = make_double2(a1[i].x, b1[i].x), v1 = czero(), v2 = czero();
+                dft3<true>(v0, v1, v2);
+                A[lp(sb)] = v0;
+                A[lp(sb + 1)] = v1;
+                A[lp(sb + 2)] = v2;
+            } else {
+                const double2 m1 = make_double2(a1[i].x - b1[i].y, a1[i].y + b1[i].x);
+                const double2 c1 = make_double2(a1[i].x + b1[i].y, -a1[i].y + b1[i].x);
+                const double2 m2 = make_double2(a2[i].x - b2[i].y, a2[i].y + b2[i].x);
+                const double2 c2 = make_double2(a2[i].x + b2[i].y, -a2[i].y + b2[i].x);
+                double2 v0 = m1, v1 = czero(), v2 = c2;
+                dft3<true>(v0, v1, v2);
+                A[lp(sb + 3 * jj)] = v0;
+                A[lp(sb + 3 * jj + 1)] = v1;
+                A[lp(sb + 3 * jj + 2)] = v2;
+                if (2 * jj != P) {
+                    double2 u0 = m2, u1 = czero(), u2 = c1;
+                    dft3<true>(u0, u1, u2);
+                    A[lp(sb + 3 * (P - jj))] = u0;
+                    A[lp(sb + 3 * (P - jj) + 1)] = u1;
+                    A[lp(sb + 3 * (P - jj) + 2)] = u2;
+                }
+            }
+        }
+    };
+    auto inv_tail = [&](const double2* X, int s, int jj, const double2* w, double2* v) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = X[lp(s * NT + jj + q * NBL)];
+#pragma unroll
+        for (int q = 1; q < 4; ++q) v[q] = tw_mul<true>(v[q], w[q]);
+        dft4<true>(v[0], v[1], v[2], v[3]);
+    };
+    auto fwd_head = [&](double2* Y, int s, int jj, double2* v) {
+        dft4<false>(v[0], v[1], v[2], v[3]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Y[lp(s * NT + 4 * jj + q)] = v[q];
+    };
+    int z0 = zq * ZB;
+    fetch(z0);
+    for (int tile = 0; tile < Q; ++tile, z0 += nq * ZB) {
+        first_pass();
+        __syncthreads();
+        if (tile + 1 < Q) fetch(z0 + nq * ZB);
+        double2* R1 = fft_span<NT, true, 8, 3, NBL>(A, Bf, NIN, tw);
+        double2* O = (R1 == A) ? Bf : A;
+        for (int t = threadIdx.x; t < NMID; t += TB) {
+            const int jj = t % NBL, zi = t / NBL;
+            double2 w[4];
+#pragma unroll
+            for (int q = 1; q < 4; ++q) w[q] = tw[q * jj];
+            double2 s0[4], s1[4], s2[4], s3[4], s4[4];
+            inv_tail(R1, 0 * ZB + zi, jj, w, s0);
+            inv_tail(R1, 1 * ZB + zi, jj, w, s1);
+            inv_tail(R1, 2 * ZB + zi, jj, w, s2);
+            inv_tail(R1, 3 * ZB + zi, jj, w, s3);
+            inv_tail(R1, 4 * ZB + (zi < H ? zi : zi - H), jj, w, s4);
+            double2 o0[4], o1[4], o2[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double ur = s0[q].x, ut = s0[q].y, uz = s1[q].x, wr = s1[q].y, wt = s2[q].x, wz = s2[q].y;
+                const double yr = s3[q].x, yt = s3[q].y, yz = (zi < H) ? s4[q].x : s4[q].y;
+                const double wtO = wt + Om, uzU = uz + U;
+                o0[q] = make_double2(wtO * yz - wz * yt, wz * yr - wr * yz);
+                o1[q] = make_double2(wr * yt - wtO * yr, yt * uzU - yz * ut);
+                o2[q] = make_double2(yz * ur - yr * uzU, yr * ut - yt * ur);
+            }
+            fwd_head(O, zi, jj, o0);
+            fwd_head(O, ZB + zi, jj, o1);
+            fwd_head(O, 2 * ZB + zi, jj, o2);
+        }
+        __syncthreads();
+        const double2* R2 = fft_span<NT, false, 8, 4, P>(O, R1, NOUT, tw);
+        for (int t = threadIdx.x; t < NEND; t += TB) {
+            const int s = t % NOUT, jA = t / NOUT;
+            const int jB = jA == 0 ? 0 : P - jA;
+            auto bfly = [&](int jx, double2& y0, double2& y2) {
+                double2 v0 = R2[lp(s * NT + jx)], v1 = R2[lp(s * NT + jx + P)], v2 = R2[lp(s * NT + jx + 2 * P)];
+                v1 = tw_mul<false>(v1, tw[jx]);
+                v2 = tw_mul<false>(v2, tw[2 * jx]);
+                dft3<false>(v0, v1, v2);
+                y0 = v0;
+                y2 = v2;
+            };
+            double2 yA0, yA2, yB0, yB2;
+            bfly(jA, yA0, yA2);
+            if (jB != jA) bfly(jB, yB0, yB2);
+            else { yB0 = yA0; yB2 = yA2; }
+            const int f0 = 2 * (s / ZB), zc = s % ZB;
+            auto emit = [&](int m, double2 a, double2 bm) {
+                const double2 b = cconj(bm);
+                const size_t col = (size_t)m * nz + z0 + zc;
+                tb[(size_t)(j * 6 + f0) * MP1 * nz + col] = cscale(cadd(a, b), 0.5);
+                tb[(size_t)(j * 6 + f0 + 1) * MP1 * nz + col] = cscale(cmuli(csub(b, a)), 0.5);
+            };
+            emit(jA, yA0, jA == 0 ? yA0 : yB2);
+            if (jB != jA) emit(jB, yB0, yA2);
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- dispatch
 #define NPO_NZ_SIZES(X) X(24) X(48) X(96) X(144) X(192) X(288) X(384) X(576) X(768) X(1024) X(1536)
 #define NPO_NT_SIZES(X) X(12) X(24) X(48) X(64) X(96) X(128)
@@ -1150,6 +1335,8 @@ static void launch_theta_k(dim3 grid, size_t sh, const npo_plan_s& p, int nq, in
                            const double2* zy, int nfy, double2* tb, const TimeArg& ta, hipStream_t st) {
     if constexpr (NT % 12 == 0 && !ADJ)
         hipLaunchKernelGGL((k_theta_p<NT, ZB>), grid, dim3(TB), sh, st, p.kp, nq, Q, zu, nfu, tb, ta);
+    else if constexpr (NT % 12 == 0)
+        hipLaunchKernelGGL((k_theta_pa<NT, ZB>), grid, dim3(TB), sh, st, p.kp, nq, Q, zu, nfu, zy, nfy, tb, ta);
     else
         hipLaunchKernelGGL((k_theta_t<NT, ADJ, ZB>), grid, dim3(TB), sh, st, p.kp, nq, Q, zu, nfu, zy, nfy, tb, ta);
 }

@@ -61,8 +61,8 @@ def family_kernels(nt, nz, names=(), shapes=(1, 4, 4), nr=64):
     def th(a):
         if not ft:
             return "k_theta"
-        if a == 0 and nt % 12 == 0:
-            return f"k_theta_p<{nt}, {zbf}>"
+        if nt % 12 == 0:
+            return f"k_theta_pa<{nt}, {zba}>" if a else f"k_theta_p<{nt}, {zbf}>"
         return f"k_theta_t<{nt}, {a}, {zba if a else zbf}>"
     return {
         "curl": "k_curl_aux", "zinv_fwd": zi(6), "theta_fwd": th(0), "zfwd_fwd": zf(3),
