@@ -535,8 +535,8 @@ __global__ __launch_bounds__(TB) void k_zinv_t(KP p, const double2* __restrict__
 }
 
 // Inverse axial transforms for N_z = 3P (then K = P - 1), same fields and
-// output as k_zinv_t.  Plan: radix 3 (stride P), pick_radix<MAXR> passes, radix
-// 4 (stride N_z / 4).  The first pass runs on the modes in registers: its
+// output as k_zinv_t.  Plan: radix 3 (stride P), pick_radix<8> passes, radix 4
+// (stride N_z / 4).  The first pass runs on the modes in registers: its
 // butterfly jj reads z = jj (mode jj), z = P + jj (in the zero band) and
 // z = 2P + jj (mode jj - P, zero for jj = 0), so nothing is placed in LDS
 // beforehand; the last pass stores its outputs straight to the row.  Two LDS
@@ -548,7 +548,6 @@ __global__ __launch_bounds__(TB) void k_zinv_p(KP p, const double2* __restrict__
     constexpr int P = NZ / 3, NK = 2 * P - 1;
     constexpr int PB = (P + TB - 1) / TB;             // first-pass butterflies per thread
     constexpr int NB4 = NZ / 4;                       // last-pass butterflies
-    constexpr int MAXR = NF >= 6 ? 4 : 8;
     extern __shared__ double2 sh[];
     double2* tw = sh;
     double2* A = sh + NZ;
@@ -591,7 +590,7 @@ __global__ __launch_bounds__(TB) void k_zinv_p(KP p, const double2* __restrict__
         }
         __syncthreads();
         if (f + 1 < NF) fetch(F0 + f + 1);
-        const double2* X = fft_span<NZ, true, MAXR, 3, NB4>(A, Bf, 1, tw);
+        const double2* X = fft_span<NZ, true, 8, 3, NB4>(A, Bf, 1, tw);
         double2* row = zb + ((size_t)(j * NF + f) * mp1 + m) * NZ;
         for (int jj = threadIdx.x; jj < NB4; jj += TB) {
             double2 v[4];
