@@ -21,12 +21,14 @@ STEADY = dict(nr=16, nt=12, nz=24, lz=2 * math.pi, re=1500.0, wo=8.0, amp=0.0, d
 # N_z = 54 is not a multiple of 4: the azimuthal inputs are stored in runs of
 # two z-points (generic axial kernels, compiled azimuthal kernel at N_theta = 24)
 ODDRUN = dict(nr=10, nt=24, nz=54, lz=12.0, re=1800.0, wo=5.0, amp=0.9, dt=0.02, t0=1.0)
-# N_theta = 48: the pruned forward azimuthal plan with one middle pass of radix 4
+# N_theta = 48: the pruned azimuthal plans with one middle pass of radix 4
 THETA48 = dict(nr=8, nt=48, nz=48, lz=8.0, re=2200.0, wo=7.0, amp=1.1, dt=0.02, t0=0.2)
+# N_theta = 64 and N_z = 1024 are compiled but not multiples of 3: the unpruned kernels
+POW2 = dict(nr=8, nt=64, nz=1024, lz=60.0, re=1700.0, wo=9.0, amp=0.8, dt=0.02, t0=2.0)
 
 
-@pytest.fixture(scope="module", params=[MAXFAST, GENERIC, ODDRUN, THETA48],
-                ids=["max-compiled", "generic-2048", "runs-of-2", "theta-48"])
+@pytest.fixture(scope="module", params=[MAXFAST, GENERIC, ODDRUN, THETA48, POW2],
+                ids=["max-compiled", "generic-2048", "runs-of-2", "theta-48", "pow2-64x1024"])
 def big(request):
     cfg = request.param
     P, G = make(cfg)
