@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 from paper_2509_10103_amd import configs, synth  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0
+HBM_RESERVE = 6 << 30
 
 
 def alg_bytes(cfg):
@@ -123,10 +124,19 @@ def main():
     cfg = dict(configs.WORKLOADS[args.workload])
     if args.nsteps:
         cfg["nsteps"] = args.nsteps
-    nck = args.ckpt or min(cfg["n_ckpt"], cfg["nsteps"])
     torch.cuda.set_device(0)
     G = npo.Plan(cfg["nr"], cfg["nt"], cfg["nz"], cfg["lz"], cfg["re"], cfg["wo"], cfg["amp"], cfg["dt"],
                  cfg["t0"], cfg["nsteps"])
+    if args.ckpt:
+        nck = args.ckpt
+    elif cfg["n_ckpt"]:
+        nck = min(cfg["n_ckpt"], cfg["nsteps"])
+    else:
+        # checkpoint arena sized to the free HBM after the plan and workspace,
+        # keeping HBM_RESERVE for fields, tuning and the runtime
+        fb = 3 * cfg["nr"] * G.shape[2] * G.shape[3] * 16
+        free = torch.cuda.mem_get_info()[0]
+        nck = int(max(1, min(cfg["nsteps"], (free - HBM_RESERVE) // fb)))
     from paper_2509_10103_amd import tune
     shapes, _ = tune.tune(G, cfg["nr"], cfg["nt"], cfg["nz"], use_cache=False, save=False)
     shapes = list(shapes)

@@ -24,10 +24,11 @@ C1 = _mk("plain-32x24x48", 32, 24, 48, 4 * math.pi, 2000.0, 8.0, 0.5, 0.04, 0.0,
 
 # Plain method at paper-like scale: L = 25 D, 64 x 96 x 768, Re 2000, Wo 8,
 # A 1, one pulsation period at dt_D = 0.005 from tau0 = T/2 (deceleration),
-# localised oblique seed with E0 = 1e-5, 4000 checkpoints, seed 2.
+# localised oblique seed with E0 = 1e-5, seed 2.  Checkpoints: as many as the
+# HBM holds (n_ckpt None; about 5300 slots of 50 MB on a 288 GB device).
 _T2 = period(2000.0, 8.0)
 C2 = _mk("paper-64x96x768", 64, 96, 768, 50.0, 2000.0, 8.0, 1.0, 0.02, 0.5 * _T2, int(round(_T2 / 0.02)),
-         1e-5, 2, 4000, 10, "oblique")
+         1e-5, 2, None, 10, "oblique")
 
 # Differentiation workload: L = 12 D, 48 x 64 x 384, Re 1500, Wo 10, A 1,
 # 20 D/U units at dt_D = 0.005 from tau0 = T/2, E0 = 1e-5, seed 3.
