@@ -321,7 +321,7 @@ hipError_t fwd_step(const npo_plan_s& p, void* ws, const double2* un, double2* u
 //   mu_C = S^+ lam; mu_{c-1} = S^+ (N'(w_{c-1})^+ mu_c / 2), c = C..1;
 //   lam_n = E^+ (sum mu_c) + N'(u_n)^+ (mu_0 + sum_{c>=1} mu_c / 2).
 hipError_t adj_step(const npo_plan_s& p, void* ws, const double2* un, const double2* lamin, double2* lamout,
-                    long long n, hipStream_t st, const long long* dstep = nullptr) {
+                    long long n, hipStream_t st, const long long* dstep = nullptr, bool have_aux = false) {
     WsPtrs w = wsptrs(p, ws);
     hipError_t e;
     const npo::TimeArg t0 = at_step(dstep, n, 0), t1 = at_step(dstep, n, 1);
@@ -330,7 +330,7 @@ hipError_t adj_step(const npo_plan_s& p, void* ws, const double2* un, const doub
     // u^n (zst[0]) and of w_{c-1} (zst[c]) for the adjoint evaluations
     char* wb = static_cast<char*>(ws);
     auto zst = [&](int c) { return reinterpret_cast<double2*>(wb + p.ws.zst[c]); };
-    if ((e = npo::launch_curl_aux(p, un, w.aux0, st)) != hipSuccess) return e;
+    if (!have_aux && (e = npo::launch_curl_aux(p, un, w.aux0, st)) != hipSuccess) return e;
     if ((e = npo::launch_nl(p, 0, un, w.aux0, nullptr, t0, w.nn, nullptr, ws, st, nullptr, zst(0))) != hipSuccess)
         return e;
     if ((e = npo::launch_solve(p, 1, un, w.nn, nullptr, w.st[0], w.auxs[0], st)) != hipSuccess) return e;
@@ -362,8 +362,9 @@ hipError_t adj_step(const npo_plan_s& p, void* ws, const double2* un, const doub
 
 // ------------------------------------------------------- captured step graphs
 // The forward advance (cur -> cur, vorticity parts of cur present, then
-// step += 1) and the adjoint step (lam -> lam at u = cur) read their step
-// index from the workspace, so one capture per workspace serves every step.
+// step += 1) and the adjoint step (lam -> lam at u = cur, vorticity parts of
+// cur present) read their step index from the workspace, so one capture per
+// workspace serves every step.
 void drop_graphs(npo_plan_s& p) {
     if (p.g_fwd) (void)hipGraphExecDestroy(p.g_fwd);
     if (p.g_adj) (void)hipGraphExecDestroy(p.g_adj);
@@ -376,7 +377,7 @@ hipError_t capture(npo_plan_s& p, void* ws, bool adjoint, hipGraphExec_t* exec) 
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(p.graph_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    hipError_t e1 = adjoint ? adj_step(p, ws, w.cur, w.lam, w.lam, 0, p.graph_stream, w.step)
+    hipError_t e1 = adjoint ? adj_step(p, ws, w.cur, w.lam, w.lam, 0, p.graph_stream, w.step, true)
                             : fwd_step(p, ws, w.cur, w.cur, 0, true, p.graph_stream, w.step);
     if (e1 == hipSuccess && !adjoint) e1 = npo::launch_step_index(w.step, 1, 1, p.graph_stream);
     e = hipStreamEndCapture(p.graph_stream, &g);
@@ -921,12 +922,14 @@ npo_status npo_adjoint_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const 
             where = slot(a.a);
         } else {
             if (a.a != pos) return fail(NPO_ESTATE, "schedule adjoint position mismatch");
+            // after an advance aux0 already holds the vorticity parts of u^pos
             if (gr && where == w.cur) {
+                if (!aux) HIPCHK(npo::launch_curl_aux(*p, w.cur, w.aux0, st));
                 if (!synced) HIPCHK(npo::launch_step_index(w.step, pos, 0, st));
                 HIPCHK(hipGraphLaunch(p->g_adj, st));
                 synced = true;
             } else {
-                HIPCHK(adj_step(*p, ws, where, w.lam, w.lam, pos, st));
+                HIPCHK(adj_step(*p, ws, where, w.lam, w.lam, pos, st, nullptr, aux));
                 synced = false;
             }
             aux = false;   // the adjoint step reuses aux0 for its own work
