@@ -341,9 +341,10 @@ hipError_t adj_step(const npo_plan_s& p, void* ws, const double2* un, const doub
         if ((e = npo::launch_solve(p, 2, un, w.nn, w.ns, w.st[c], w.auxs[c], st)) != hipSuccess) return e;
     }
     double2* mu[2] = {w.muC, w.muP};
-    // mu_C = S^+ lam;  Y = mu_C / 2;  Z = mu_C
-    if ((e = npo::launch_solve_adj(p, lamin, 1.0, nullptr, 0.0, mu[C & 1], nullptr, 0.5, w.yb, nullptr, 1.0, w.zb2,
-                                   st)) != hipSuccess)
+    // mu_C = S^+ lam; the accumulators start as Y = mu_C / 2 and Z = mu_C, which
+    // the solve of stage C reads straight from mu_C (input scales 1/2 and 1)
+    if ((e = npo::launch_solve_adj(p, lamin, 1.0, nullptr, 0.0, mu[C & 1], nullptr, 0.0, nullptr, nullptr, 0.0,
+                                   nullptr, st)) != hipSuccess)
         return e;
     for (int c = C; c >= 1; --c) {
         // w_{c-1} was evaluated forward above for c < C
@@ -352,8 +353,11 @@ hipError_t adj_step(const npo_plan_s& p, void* ws, const double2* un, const doub
             hipSuccess)
             return e;
         double2* next = (c > 1) ? mu[(c - 1) & 1] : nullptr;
-        if ((e = npo::launch_solve_adj(p, w.fa, 0.5, w.fb, 0.5, next, w.yb, c == 1 ? 1.0 : 0.5, w.yb, w.zb2, 1.0,
-                                       w.zb2, st)) != hipSuccess)
+        const bool first = c == C;
+        const double2* Yin = first ? mu[C & 1] : w.yb;
+        const double2* Zin = first ? mu[C & 1] : w.zb2;
+        if ((e = npo::launch_solve_adj(p, w.fa, 0.5, w.fb, 0.5, next, Yin, c == 1 ? 1.0 : 0.5, w.yb, Zin, 1.0, w.zb2,
+                                       st, first ? 0.5 : 1.0, 1.0)) != hipSuccess)
             return e;
     }
     if ((e = npo::launch_nl(p, 1, un, w.aux0, w.yb, t0, w.fa2, w.fb2, ws, st, zst(0))) != hipSuccess) return e;

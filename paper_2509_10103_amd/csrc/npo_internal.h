@@ -140,11 +140,11 @@ hipError_t launch_step_index(long long* d, long long v, int add, hipStream_t st)
 // 2 = corrector S(E a + (b + c)/2).  aux_out may be null.
 hipError_t launch_solve(const npo_plan_s& p, int kind, const double2* a, const double2* b,
                         const double2* c, double2* u_out, double2* aux_out, hipStream_t st);
-// mu = S^dag(ca*A + cb*curl^dag(B)); out0 = mu; Yout = Yin + qy*mu; Zout = Zin + qz*mu
+// mu = S^dag(ca*A + cb*curl^dag(B)); out0 = mu; Yout = sy*Yin + qy*mu; Zout = sz*Zin + qz*mu
 // (B, out0, Yin, Yout, Zin, Zout optional; Yin may alias Yout and Zin Zout).
 hipError_t launch_solve_adj(const npo_plan_s& p, const double2* A, double ca, const double2* B, double cb,
                             double2* out0, const double2* Yin, double qy, double2* Yout, const double2* Zin,
-                            double qz, double2* Zout, hipStream_t st);
+                            double qz, double2* Zout, hipStream_t st, double sy = 1.0, double sz = 1.0);
 // out = E^dag Z + A + curl^dag B
 hipError_t launch_final(const npo_plan_s& p, const double2* Z, const double2* A, const double2* B,
                         double2* out, hipStream_t st);

@@ -562,16 +562,16 @@ __device__ __forceinline__ void curlH_row(const KP& p, int m, double al, int j, 
 }
 
 // ------------------------------------------------------------ adjoint solve
-// mu = S^dag(ca*A + cb*curl^dag B); out0 = mu; Yout = Yin + qy*mu; Zout = Zin + qz*mu.
-// S^dag = W^{-1} S^H W is applied as the reversed chain of conjugate-
-// transposed steps of the forward solve.
+// mu = S^dag(ca*A + cb*curl^dag B); out0 = mu; Yout = sy*Yin + qy*mu;
+// Zout = sz*Zin + qz*mu.  S^dag = W^{-1} S^H W is applied as the reversed chain
+// of conjugate-transposed steps of the forward solve.
 struct AdjOut {
     double2* out0;
     const double2* Yin;
     double2* Yout;
     const double2* Zin;
     double2* Zout;
-    double qy, qz;
+    double qy, qz, sy, sz;
 };
 template <bool useB, int NRC>
 __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, double ca, const double2* Bin, double cb,
@@ -604,8 +604,8 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
             for (int c = 0; c < 3; ++c) {
                 const size_t id = fidx(p, c, j, m, sl.kk);
                 V[jj][c] = cscale(Ain[id], ca);
-                if (ao.Yout && ao.Yin) Yv[jj][c] = ao.Yin[id];
-                if (ao.Zout && ao.Zin) Zv[jj][c] = ao.Zin[id];
+                if (ao.Yout && ao.Yin) Yv[jj][c] = cscale(ao.Yin[id], ao.sy);
+                if (ao.Zout && ao.Zin) Zv[jj][c] = cscale(ao.Zin[id], ao.sz);
                 if constexpr (useB) sy[c][j][q] = Bin[id];
             }
             if (j < N1) {
@@ -1083,8 +1083,8 @@ hipError_t launch_solve(const npo_plan_s& p, int kind, const double2* a, const d
 
 hipError_t launch_solve_adj(const npo_plan_s& p, const double2* A, double ca, const double2* B, double cb,
                             double2* out0, const double2* Yin, double qy, double2* Yout, const double2* Zin,
-                            double qz, double2* Zout, hipStream_t st) {
-    AdjOut ao{out0, Yin, Yout, Zin, Zout, qy, qz};
+                            double qz, double2* Zout, hipStream_t st, double sy, double sz) {
+    AdjOut ao{out0, Yin, Yout, Zin, Zout, qy, qz, sy, sz};
     prof_begin(p, B ? KID_SOLVE_ADJ2 : KID_SOLVE_ADJ, st);
     const dim3 grid((radial_groups(p.K) * p.mp1 + 7) / 8 * 8);
     switch (p.nr) {
