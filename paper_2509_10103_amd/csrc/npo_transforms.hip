@@ -858,6 +858,79 @@ __global__ __launch_bounds__(TB) void k_theta_t(KP p, int nq, int Q, const doubl
     }
 }
 
+// Pieces shared by the pruned azimuthal kernels (N_theta = 3P, sequences of
+// length NT back to back in padded LDS; see k_theta_p for the plan).
+
+// First inverse pass of one packed sequence (base sb), butterflies jj and
+// P - jj: xa + i xb of mode jj sits at position jj and its conjugate pair at
+// 2P + jj (and symmetrically for mode P - jj); position P + jj is in the
+// zero band.  (a1, b1) are modes jj of the two real fields, (a2, b2) modes
+// P - jj (unused for jj = 0).
+template <int NT>
+__device__ __forceinline__ void theta_first_pair(double2* A, int sb, int jj, double2 a1, double2 b1, double2 a2,
+                                                 double2 b2) {
+    constexpr int P = NT / 3;
+    if (jj == 0) {
+        double2 v0 = make_double2(a1.x, b1.x), v1 = czero(), v2 = czero();
+        dft3<true>(v0, v1, v2);
+        A[lp(sb)] = v0;
+        A[lp(sb + 1)] = v1;
+        A[lp(sb + 2)] = v2;
+        return;
+    }
+    const double2 m1 = make_double2(a1.x - b1.y, a1.y + b1.x);    // mode jj
+    const double2 c1 = make_double2(a1.x + b1.y, -a1.y + b1.x);   // its conjugate pair
+    const double2 m2 = make_double2(a2.x - b2.y, a2.y + b2.x);    // mode P - jj
+    const double2 c2 = make_double2(a2.x + b2.y, -a2.y + b2.x);
+    double2 v0 = m1, v1 = czero(), v2 = c2;
+    dft3<true>(v0, v1, v2);
+    A[lp(sb + 3 * jj)] = v0;
+    A[lp(sb + 3 * jj + 1)] = v1;
+    A[lp(sb + 3 * jj + 2)] = v2;
+    if (2 * jj != P) {
+        double2 u0 = m2, u1 = czero(), u2 = c1;
+        dft3<true>(u0, u1, u2);
+        A[lp(sb + 3 * (P - jj))] = u0;
+        A[lp(sb + 3 * (P - jj) + 1)] = u1;
+        A[lp(sb + 3 * (P - jj) + 2)] = u2;
+    }
+}
+
+// Last inverse pass (radix 4, stride NT / 4) of sequence s, butterfly jj,
+// twiddled by w[1..3] = tw[q jj]: v[q] = values at theta = jj + q NT / 4.
+template <int NT>
+__device__ __forceinline__ void theta_inv_tail(const double2* X, int s, int jj, const double2* w, double2* v) {
+    constexpr int NBL = NT / 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = X[lp(s * NT + jj + q * NBL)];
+#pragma unroll
+    for (int q = 1; q < 4; ++q) v[q] = tw_mul<true>(v[q], w[q]);
+    dft4<true>(v[0], v[1], v[2], v[3]);
+}
+
+// First forward pass (radix 4, stride 1, no twiddles) of output sequence s,
+// butterfly jj, on the values at theta = jj + q NT / 4.
+template <int NT>
+__device__ __forceinline__ void theta_fwd_head(double2* Y, int s, int jj, double2* v) {
+    dft4<false>(v[0], v[1], v[2], v[3]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Y[lp(s * NT + 4 * jj + q)] = v[q];
+}
+
+// Outputs 0 and 2 of the last forward butterfly jx (radix 3, stride P) of
+// sequence s: X[jx] and X[2P + jx].
+template <int NT>
+__device__ __forceinline__ void theta_last_pair(const double2* R, const double2* tw, int s, int jx, double2& y0,
+                                                double2& y2) {
+    constexpr int P = NT / 3;
+    double2 v0 = R[lp(s * NT + jx)], v1 = R[lp(s * NT + jx + P)], v2 = R[lp(s * NT + jx + 2 * P)];
+    v1 = tw_mul<false>(v1, tw[jx]);
+    v2 = tw_mul<false>(v2, tw[2 * jx]);
+    dft3<false>(v0, v1, v2);
+    y0 = v0;
+    y2 = v2;
+}
+
 // Forward azimuthal pass for N_theta = 3P (then M = P - 1), with the first
 // and last passes of both transforms pruned and fused.  Plan: inverse radices
 // 3, then pick_radix<8> over P / 4, then 4; forward radices in reverse order.
@@ -921,8 +994,6 @@ __global__ __launch_bounds__(TB) void k_theta_p(KP p, int nq, int Q, const doubl
             }
         }
     };
-    // first inverse pass: position jj holds xa + i xb of mode jj, position
-    // 2P + jj the conjugate pair of mode P - jj (and symmetrically for P - jj)
     auto first_pass = [&]() {
 #pragma unroll
         for (int i = 0; i < PST; ++i) {
@@ -930,44 +1001,8 @@ __global__ __launch_bounds__(TB) void k_theta_p(KP p, int nq, int Q, const doubl
             if (e >= NST) continue;
             const int zi = e % ZB, q = e / ZB;
             const int pi = q / PH, jj = q - pi * PH;
-            const int sb = (pi * ZB + zi) * NT;
-            if (jj == 0) {
-                double2 v0 = make_double2(a1[i].x, b1[i].x), v1 = czero(), v2 = czero();
-                dft3<true>(v0, v1, v2);
-                A[lp(sb)] = v0;
-                A[lp(sb + 1)] = v1;
-                A[lp(sb + 2)] = v2;
-            } else {
-                const double2 m1 = make_double2(a1[i].x - b1[i].y, a1[i].y + b1[i].x);    // mode jj
-                const double2 c1 = make_double2(a1[i].x + b1[i].y, -a1[i].y + b1[i].x);   // its conjugate pair
-                const double2 m2 = make_double2(a2[i].x - b2[i].y, a2[i].y + b2[i].x);    // mode P - jj
-                const double2 c2 = make_double2(a2[i].x + b2[i].y, -a2[i].y + b2[i].x);
-                double2 v0 = m1, v1 = czero(), v2 = c2;
-                dft3<true>(v0, v1, v2);
-                A[lp(sb + 3 * jj)] = v0;
-                A[lp(sb + 3 * jj + 1)] = v1;
-                A[lp(sb + 3 * jj + 2)] = v2;
-                if (2 * jj != P) {
-                    double2 u0 = m2, u1 = czero(), u2 = c1;
-                    dft3<true>(u0, u1, u2);
-                    A[lp(sb + 3 * (P - jj))] = u0;
-                    A[lp(sb + 3 * (P - jj) + 1)] = u1;
-                    A[lp(sb + 3 * (P - jj) + 2)] = u2;
-                }
-            }
+            theta_first_pair<NT>(A, (pi * ZB + zi) * NT, jj, a1[i], b1[i], a2[i], b2[i]);
         }
-    };
-    auto inv_tail = [&](const double2* X, int s, int jj, const double2* w, double2* v) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = X[lp(s * NT + jj + q * NBL)];
-#pragma unroll
-        for (int q = 1; q < 4; ++q) v[q] = tw_mul<true>(v[q], w[q]);
-        dft4<true>(v[0], v[1], v[2], v[3]);
-    };
-    auto fwd_head = [&](double2* Y, int s, int jj, double2* v) {
-        dft4<false>(v[0], v[1], v[2], v[3]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Y[lp(s * NT + 4 * jj + q)] = v[q];
     };
     int z0 = zq * ZB;
     fetch(z0);
@@ -983,9 +1018,9 @@ __global__ __launch_bounds__(TB) void k_theta_p(KP p, int nq, int Q, const doubl
 #pragma unroll
             for (int q = 1; q < 4; ++q) w[q] = tw[q * jj];
             double2 s0[4], s1[4], s2[4];
-            inv_tail(R1, 0 * ZB + zi, jj, w, s0);
-            inv_tail(R1, 1 * ZB + zi, jj, w, s1);
-            inv_tail(R1, 2 * ZB + zi, jj, w, s2);
+            theta_inv_tail<NT>(R1, 0 * ZB + zi, jj, w, s0);
+            theta_inv_tail<NT>(R1, 1 * ZB + zi, jj, w, s1);
+            theta_inv_tail<NT>(R1, 2 * ZB + zi, jj, w, s2);
             double2 o0[4], o1[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -994,26 +1029,17 @@ __global__ __launch_bounds__(TB) void k_theta_p(KP p, int nq, int Q, const doubl
                 o0[q] = make_double2(ut * wz - uzU * wt - uz * Om, uzU * wr - ur * wz);
                 o1[q] = make_double2(ur * (wt + Om) - ut * wr, 0.0);
             }
-            fwd_head(O, zi, jj, o0);
-            fwd_head(O, ZB + zi, jj, o1);
+            theta_fwd_head<NT>(O, zi, jj, o0);
+            theta_fwd_head<NT>(O, ZB + zi, jj, o1);
         }
         __syncthreads();
         const double2* R2 = fft_span<NT, false, 8, 4, P>(O, R1, NOUT, tw);
         for (int t = threadIdx.x; t < NEND; t += TB) {
             const int s = t % NOUT, jA = t / NOUT;   // columns fastest: contiguous z stores
             const int jB = jA == 0 ? 0 : P - jA;
-            // outputs 0 and 2 of the last forward butterflies jA and jB
-            auto bfly = [&](int jx, double2& y0, double2& y2) {
-                double2 v0 = R2[lp(s * NT + jx)], v1 = R2[lp(s * NT + jx + P)], v2 = R2[lp(s * NT + jx + 2 * P)];
-                v1 = tw_mul<false>(v1, tw[jx]);
-                v2 = tw_mul<false>(v2, tw[2 * jx]);
-                dft3<false>(v0, v1, v2);
-                y0 = v0;
-                y2 = v2;
-            };
             double2 yA0, yA2, yB0, yB2;
-            bfly(jA, yA0, yA2);
-            if (jB != jA) bfly(jB, yB0, yB2);
+            theta_last_pair<NT>(R2, tw, s, jA, yA0, yA2);
+            if (jB != jA) theta_last_pair<NT>(R2, tw, s, jB, yB0, yB2);
             else { yB0 = yA0; yB2 = yA2; }
             // sequence s < ZB: N_r + i N_t of column s; else N_z of column s - ZB
             const int zc = s < ZB ? s : s - ZB;
@@ -1118,44 +1144,8 @@ __global__ __launch_bounds__(TB) void k_theta_pa(KP p, int nq, int Q, const doub
                 jj = e2 / H;
                 s = 4 * ZB + e2 % H;
             }
-            const int sb = s * NT;
-            if (jj == 0) {
-                double2 v0 = make_double2(a1[i].x, b1[i].x), v1 = czero(), v2 = czero();
-                dft3<true>(v0, v1, v2);
-                A[lp(sb)] = v0;
-                A[lp(sb + 1)] = v1;
-                A[lp(sb + 2)] = v2;
-            } else {
-                const double2 m1 = make_double2(a1[i].x - b1[i].y, a1[i].y + b1[i].x);
-                const double2 c1 = make_double2(a1[i].x + b1[i].y, -a1[i].y + b1[i].x);
-                const double2 m2 = make_double2(a2[i].x - b2[i].y, a2[i].y + b2[i].x);
-                const double2 c2 = make_double2(a2[i].x + b2[i].y, -a2[i].y + b2[i].x);
-                double2 v0 = m1, v1 = czero(), v2 = c2;
-                dft3<true>(v0, v1, v2);
-                A[lp(sb + 3 * jj)] = v0;
-                A[lp(sb + 3 * jj + 1)] = v1;
-                A[lp(sb + 3 * jj + 2)] = v2;
-                if (2 * jj != P) {
-                    double2 u0 = m2, u1 = czero(), u2 = c1;
-                    dft3<true>(u0, u1, u2);
-                    A[lp(sb + 3 * (P - jj))] = u0;
-                    A[lp(sb + 3 * (P - jj) + 1)] = u1;
-                    A[lp(sb + 3 * (P - jj) + 2)] = u2;
-                }
-            }
+            theta_first_pair<NT>(A, s * NT, jj, a1[i], b1[i], a2[i], b2[i]);
         }
-    };
-    auto inv_tail = [&](const double2* X, int s, int jj, const double2* w, double2* v) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = X[lp(s * NT + jj + q * NBL)];
-#pragma unroll
-        for (int q = 1; q < 4; ++q) v[q] = tw_mul<true>(v[q], w[q]);
-        dft4<true>(v[0], v[1], v[2], v[3]);
-    };
-    auto fwd_head = [&](double2* Y, int s, int jj, double2* v) {
-        dft4<false>(v[0], v[1], v[2], v[3]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Y[lp(s * NT + 4 * jj + q)] = v[q];
     };
     int z0 = zq * ZB;
     fetch(z0);
@@ -1171,11 +1161,11 @@ __global__ __launch_bounds__(TB) void k_theta_pa(KP p, int nq, int Q, const doub
 #pragma unroll
             for (int q = 1; q < 4; ++q) w[q] = tw[q * jj];
             double2 s0[4], s1[4], s2[4], s3[4], s4[4];
-            inv_tail(R1, 0 * ZB + zi, jj, w, s0);
-            inv_tail(R1, 1 * ZB + zi, jj, w, s1);
-            inv_tail(R1, 2 * ZB + zi, jj, w, s2);
-            inv_tail(R1, 3 * ZB + zi, jj, w, s3);
-            inv_tail(R1, 4 * ZB + (zi < H ? zi : zi - H), jj, w, s4);
+            theta_inv_tail<NT>(R1, 0 * ZB + zi, jj, w, s0);
+            theta_inv_tail<NT>(R1, 1 * ZB + zi, jj, w, s1);
+            theta_inv_tail<NT>(R1, 2 * ZB + zi, jj, w, s2);
+            theta_inv_tail<NT>(R1, 3 * ZB + zi, jj, w, s3);
+            theta_inv_tail<NT>(R1, 4 * ZB + (zi < H ? zi : zi - H), jj, w, s4);
             double2 o0[4], o1[4], o2[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -1186,26 +1176,18 @@ __global__ __launch_bounds__(TB) void k_theta_pa(KP p, int nq, int Q, const doub
                 o1[q] = make_double2(wr * yt - wtO * yr, yt * uzU - yz * ut);
                 o2[q] = make_double2(yz * ur - yr * uzU, yr * ut - yt * ur);
             }
-            fwd_head(O, zi, jj, o0);
-            fwd_head(O, ZB + zi, jj, o1);
-            fwd_head(O, 2 * ZB + zi, jj, o2);
+            theta_fwd_head<NT>(O, zi, jj, o0);
+            theta_fwd_head<NT>(O, ZB + zi, jj, o1);
+            theta_fwd_head<NT>(O, 2 * ZB + zi, jj, o2);
         }
         __syncthreads();
         const double2* R2 = fft_span<NT, false, 8, 4, P>(O, R1, NOUT, tw);
         for (int t = threadIdx.x; t < NEND; t += TB) {
             const int s = t % NOUT, jA = t / NOUT;
             const int jB = jA == 0 ? 0 : P - jA;
-            auto bfly = [&](int jx, double2& y0, double2& y2) {
-                double2 v0 = R2[lp(s * NT + jx)], v1 = R2[lp(s * NT + jx + P)], v2 = R2[lp(s * NT + jx + 2 * P)];
-                v1 = tw_mul<false>(v1, tw[jx]);
-                v2 = tw_mul<false>(v2, tw[2 * jx]);
-                dft3<false>(v0, v1, v2);
-                y0 = v0;
-                y2 = v2;
-            };
             double2 yA0, yA2, yB0, yB2;
-            bfly(jA, yA0, yA2);
-            if (jB != jA) bfly(jB, yB0, yB2);
+            theta_last_pair<NT>(R2, tw, s, jA, yA0, yA2);
+            if (jB != jA) theta_last_pair<NT>(R2, tw, s, jB, yB0, yB2);
             else { yB0 = yA0; yB2 = yA2; }
             const int f0 = 2 * (s / ZB), zc = s % ZB;
             auto emit = [&](int m, double2 a, double2 bm) {
