@@ -541,7 +541,7 @@ __global__ __launch_bounds__(TB) void k_zinv_t(KP p, const double2* __restrict__
 // z = 2P + jj (mode jj - P, zero for jj = 0), so nothing is placed in LDS
 // beforehand; the last pass stores its outputs straight to the row.  Two LDS
 // round trips and two barriers fewer per field than k_zinv_t.
-template <int NZ, int F0, int NF>
+template <int NZ, int F0, int NF, int MB>
 __global__ __launch_bounds__(TB) void k_zinv_p(KP p, const double2* __restrict__ u, const double2* __restrict__ aux,
                                               const double2* __restrict__ y, double2* __restrict__ zb) {
     static_assert(NZ % 12 == 0, "N_z = 3P with P a multiple of 4");
@@ -552,31 +552,38 @@ __global__ __launch_bounds__(TB) void k_zinv_p(KP p, const double2* __restrict__
     double2* tw = sh;
     double2* A = sh + NZ;
     double2* Bf = A + lp_size(NZ);
-    const int m = blockIdx.x, j = blockIdx.y, mp1 = p.mp1;
-    const double mr = m / p.r[j];
+    // MB consecutive m per block, NF fields each: rounds rd = (m - m0) NF + f
+    const int m0 = blockIdx.x * MB, j = blockIdx.y, mp1 = p.mp1;
+    const int nround = MB == 1 ? NF : (mp1 - m0 < MB ? mp1 - m0 : MB) * NF;
+    const double rj = p.r[j];
     for (int t = threadIdx.x; t < NZ; t += TB) tw[t] = p.twz[t];
-    auto load = [&](int f, int kk) -> double2 {
+    auto load = [&](int m, int f, int kk) -> double2 {
         if (f < 3) return u[fidx(p, f, j, m, kk)];
         if (f == 3)
-            return csub(cscale(cmuli(u[fidx(p, 2, j, m, kk)]), mr), cscale(cmuli(u[fidx(p, 1, j, m, kk)]), alpha_of(p, kk)));
+            return csub(cscale(cmuli(u[fidx(p, 2, j, m, kk)]), m / rj), cscale(cmuli(u[fidx(p, 1, j, m, kk)]), alpha_of(p, kk)));
         if (f < 6) return aux[fidx(p, f - 4, j, m, kk)];
         return y[fidx(p, f - 6, j, m, kk)];
     };
     // modes jj (z = jj) and jj - P (z = 2P + jj, stored at kk = jj + NK - P)
     double2 v0[PB], v2[PB];
-    auto fetch = [&](int f) {
+    auto fetch = [&](int rd) {
+        const int m = m0 + rd / NF, f = F0 + rd % NF;
 #pragma unroll
         for (int b = 0; b < PB; ++b) {
             const int jj = threadIdx.x + b * TB;
             v0[b] = v2[b] = czero();
             if (jj < P) {
-                v0[b] = load(f, jj);
-                if (jj) v2[b] = load(f, jj + NK - P);
+                v0[b] = load(m, f, jj);
+                if (jj) v2[b] = load(m, f, jj + NK - P);
             }
         }
     };
-    fetch(F0);
-    for (int f = 0; f < NF; ++f) {
+    fetch(0);
+    // unrolled: the field of each round is known at compile time
+#pragma unroll
+    for (int rd = 0; rd < MB * NF; ++rd) {
+        if (rd >= nround) break;
+        const int m = m0 + rd / NF, f = rd % NF;
 #pragma unroll
         for (int b = 0; b < PB; ++b) {
             const int jj = threadIdx.x + b * TB;
@@ -589,7 +596,7 @@ __global__ __launch_bounds__(TB) void k_zinv_p(KP p, const double2* __restrict__
             }
         }
         __syncthreads();
-        if (f + 1 < NF) fetch(F0 + f + 1);
+        if (rd + 1 < nround) fetch(rd + 1);
         const double2* X = fft_span<NZ, true, 8, 3, NB4>(A, Bf, 1, tw);
         double2* row = zb + ((size_t)(j * NF + f) * mp1 + m) * NZ;
         for (int jj = threadIdx.x; jj < NB4; jj += TB) {
@@ -654,7 +661,7 @@ __global__ __launch_bounds__(TB) void k_zfwd_t(KP p, const double2* __restrict__
 // last pass computes only the outputs that survive the truncation (z = jj and
 // z = 2P + jj of butterfly jj; z = P + jj lies outside the band) and stores
 // them to the spectral field.
-template <int NZ, int NFO>
+template <int NZ, int NFO, int MB>
 __global__ __launch_bounds__(TB) void k_zfwd_p(KP p, const double2* __restrict__ tb, double2* __restrict__ out0,
                                               double2* __restrict__ out1, double scale) {
     static_assert(NZ % 12 == 0, "N_z = 3P with P a multiple of 4");
@@ -665,10 +672,13 @@ __global__ __launch_bounds__(TB) void k_zfwd_p(KP p, const double2* __restrict__
     double2* tw = sh;
     double2* A = sh + NZ;
     double2* Bf = A + lp_size(NZ);
-    const int m = blockIdx.x, j = blockIdx.y, mp1 = p.mp1;
+    // MB consecutive m per block, NFO fields each: rounds rd = (m - m0) NFO + f
+    const int m0 = blockIdx.x * MB, j = blockIdx.y, mp1 = p.mp1;
+    const int nround = MB == 1 ? NFO : (mp1 - m0 < MB ? mp1 - m0 : MB) * NFO;
     for (int t = threadIdx.x; t < NZ; t += TB) tw[t] = p.twz[t];
     double2 v[PB][4];
-    auto fetch = [&](int f) {
+    auto fetch = [&](int rd) {
+        const int m = m0 + rd / NFO, f = rd % NFO;
         const double2* row = tb + ((size_t)(j * NFO + f) * mp1 + m) * NZ;
 #pragma unroll
         for (int b = 0; b < PB; ++b) {
@@ -678,7 +688,11 @@ __global__ __launch_bounds__(TB) void k_zfwd_p(KP p, const double2* __restrict__
         }
     };
     fetch(0);
-    for (int f = 0; f < NFO; ++f) {
+    // unrolled: the field of each round is known at compile time
+#pragma unroll
+    for (int rd = 0; rd < MB * NFO; ++rd) {
+        if (rd >= nround) break;
+        const int m = m0 + rd / NFO, f = rd % NFO;
 #pragma unroll
         for (int b = 0; b < PB; ++b) {
             const int jj = threadIdx.x + b * TB;
@@ -689,7 +703,7 @@ __global__ __launch_bounds__(TB) void k_zfwd_p(KP p, const double2* __restrict__
             }
         }
         __syncthreads();
-        if (f + 1 < NFO) fetch(f + 1);
+        if (rd + 1 < nround) fetch(rd + 1);
         const double2* X = fft_span<NZ, false, 8, 4, P>(A, Bf, 1, tw);
         double2* out = f < 3 ? out0 : out1;
         const int c = f < 3 ? f : f - 3;
@@ -1240,13 +1254,22 @@ size_t theta_lds(const npo_plan_s& p, int ZB, int adj) {
     return (size_t)2 * nseq * p.nt * sizeof(double2);
 }
 
+// m per block of the pruned axial kernels: two when a block would carry only
+// three fields (the block start-up, twiddle staging and first load, is then
+// paid once per six transforms as in the six-field passes)
+template <int NF>
+constexpr int zpass_mb() { return NF <= 3 ? 2 : 1; }
+
 template <int NZ, int F0, int NF>
 static void launch_zinv_k(dim3 grid, size_t sh, const npo_plan_s& p, const double2* u, const double2* aux,
                           const double2* y, double2* zb, hipStream_t st) {
-    if constexpr (NZ % 12 == 0)
-        hipLaunchKernelGGL((k_zinv_p<NZ, F0, NF>), grid, dim3(TB), sh, st, p.kp, u, aux, y, zb);
-    else
+    if constexpr (NZ % 12 == 0) {
+        constexpr int MB = zpass_mb<NF>();
+        const dim3 g((p.mp1 + MB - 1) / MB, grid.y);
+        hipLaunchKernelGGL((k_zinv_p<NZ, F0, NF, MB>), g, dim3(TB), sh, st, p.kp, u, aux, y, zb);
+    } else {
         hipLaunchKernelGGL((k_zinv_t<NZ, F0, NF>), grid, dim3(TB), sh, st, p.kp, u, aux, y, zb);
+    }
 }
 
 template <int NZ>
@@ -1278,10 +1301,13 @@ static void launch_zinv(const npo_plan_s& p, int f0, int nf, const double2* u, c
 template <int NZ, int NFO>
 static void launch_zfwd_k(dim3 grid, size_t sh, const npo_plan_s& p, const double2* tb, double2* out0, double2* out1,
                           double scale, hipStream_t st) {
-    if constexpr (NZ % 12 == 0)
-        hipLaunchKernelGGL((k_zfwd_p<NZ, NFO>), grid, dim3(TB), sh, st, p.kp, tb, out0, out1, scale);
-    else
+    if constexpr (NZ % 12 == 0) {
+        constexpr int MB = zpass_mb<NFO>();
+        const dim3 g((p.mp1 + MB - 1) / MB, grid.y);
+        hipLaunchKernelGGL((k_zfwd_p<NZ, NFO, MB>), g, dim3(TB), sh, st, p.kp, tb, out0, out1, scale);
+    } else {
         hipLaunchKernelGGL((k_zfwd_t<NZ, NFO>), grid, dim3(TB), sh, st, p.kp, tb, out0, out1, scale);
+    }
 }
 
 static void launch_zfwd(const npo_plan_s& p, int adj, const double2* tb, double2* out0, double2* out1,

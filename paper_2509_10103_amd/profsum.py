@@ -53,11 +53,14 @@ def family_kernels(nt, nz, names=(), shapes=(1, 4, 4), nr=64):
     profile) holds no compile-time-sized one."""
     zbf, zba = shapes[1], shapes[2]
     nrc = nr if (f"k_solve<1, {nr}>" in names or f"k_solve<2, {nr}>" in names or not names) else 0
-    zk = "p" if nz % 12 == 0 else "t"       # pruned axial kernels for N_z = 3P
-    fz = f"k_zinv_{zk}<{nz}, 0, 6>" in names or not names
+    pz = nz % 12 == 0                       # pruned axial kernels for N_z = 3P,
+    # with two m per block for the three-field passes
+    zk = "p" if pz else "t"
+    mb = (lambda nf: f", {2 if nf <= 3 else 1}") if pz else (lambda nf: "")
+    fz = f"k_zinv_{zk}<{nz}, 0, 6{mb(6)}>" in names or not names
     ft = f"k_theta_t<{nt}, 0, {zbf}>" in names or f"k_theta_p<{nt}, {zbf}>" in names or not names
-    zi = (lambda nf: f"k_zinv_{zk}<{nz}, {6 if nf == 3 else 0}, {nf}>") if fz else (lambda nf: "k_zinv")
-    zf = (lambda nf: f"k_zfwd_{zk}<{nz}, {nf}>") if fz else (lambda nf: "k_zfwd")
+    zi = (lambda nf: f"k_zinv_{zk}<{nz}, {6 if nf == 3 else 0}, {nf}{mb(nf)}>") if fz else (lambda nf: "k_zinv")
+    zf = (lambda nf: f"k_zfwd_{zk}<{nz}, {nf}{mb(nf)}>") if fz else (lambda nf: "k_zfwd")
     def th(a):
         if not ft:
             return "k_theta"
