@@ -1,6 +1,7 @@
 """Edge cases of the HIP path against the oracle: the largest compiled
 transform lengths, the generic (run-time radix) kernels at the largest axial
-length, an axial length that is not a multiple of 4, a steady base flow (A = 0), the one-step horizon with a single
+length, an axial length that is not a multiple of 4, an odd number of azimuthal
+modes, a steady base flow (A = 0), the one-step horizon with a single
 checkpoint slot and the longest recompute chain (one slot, many steps)."""
 import math
 
@@ -138,3 +139,21 @@ def test_corrector_pass_counts(ncorr):
     lam = G.field()
     npo.npo_adjoint_step(G.handle, G.ws, to_dev(u), to_dev(y), lam, 2)
     assert relerr(P, to_host(lam), P.step_adj(u, 2, y)) < 1e-11
+
+
+def test_step_and_adjoint_with_odd_mode_count():
+    """N_theta = 128 gives M + 1 = 43 azimuthal modes: the three-field axial
+    passes (two m per block) end on a block holding one m.  The adjoint step
+    runs the adjoint-field-only inverse pass for every stage but the last."""
+    cfg = dict(nr=8, nt=128, nz=24, lz=6.0, re=1900.0, wo=6.0, amp=0.9, dt=0.02, t0=0.4)
+    P, G = make(cfg)
+    assert (P.M + 1) % 2 == 1
+    from paper_2509_10103_amd import npo
+    u = seed_field(P, 15, 1e-3)
+    y = synth.random_field(P.shape, 16)
+    out = G.field()
+    npo.npo_forward_step(G.handle, G.ws, to_dev(u), out, 4)
+    assert relerr(P, to_host(out), P.step(u, 4)) < 1e-12
+    lam = G.field()
+    npo.npo_adjoint_step(G.handle, G.ws, to_dev(u), to_dev(y), lam, 4)
+    assert relerr(P, to_host(lam), P.step_adj(u, 4, y)) < 1e-11
