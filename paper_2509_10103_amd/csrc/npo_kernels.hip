@@ -295,23 +295,32 @@ __device__ __forceinline__ double2 taps13(const KP& p, const double* T, int pi, 
 // Radial kernels: a block owns one azimuthal index m and RG consecutive |k|
 // (RQ = 2*RG modes: +k and -k).  Lanes run over modes, so global loads and
 // stores of a radial row touch contiguous runs of kk; the block count is
-// padded to a multiple of 8 and consecutive logical blocks (same |k| group,
-// neighbouring m: they share Helmholtz operators) are placed on one XCD.
+// padded to a multiple of 8 and consecutive logical blocks are placed on one
+// XCD.  Logical blocks run over bands of GB consecutive |k| groups, m outer,
+// group inner, so the blocks resident on an XCD at once cover a few groups
+// times a few m: neighbouring groups share the 128-byte lines their runs
+// straddle (a row is 8176 bytes at K = 255, so most runs are not line
+// aligned), and neighbouring m share Helmholtz operators (n = m +- 1).
 constexpr int RG = 8;
 constexpr int RQ = 2 * RG;
 constexpr int RT = 256;    // threads per radial block
 constexpr int RJ = RT / RQ; // radial rows handled concurrently
+constexpr int GB = 8;      // |k| groups per band of logical blocks
 
 __host__ __device__ __forceinline__ int radial_groups(int K) { return (K + 1 + RG - 1) / RG; }
 
 __device__ __forceinline__ bool block_group(const KP& p, int& g, int& m) {
-    const int nb = radial_groups(p.K) * p.mp1;
+    const int ng = radial_groups(p.K);
+    const int nb = ng * p.mp1;
     const int per = (nb + 7) / 8;
     const int b = blockIdx.x;
     const int L = (b % 8) * per + b / 8;
     if (L >= nb) return false;
-    m = L % p.mp1;
-    g = L / p.mp1;
+    // band gb holds groups gb*GB .. gb*GB + gw - 1 (the last band may be narrower)
+    const int gb = L / (GB * p.mp1), rem = L - gb * GB * p.mp1;
+    const int gw = ng - gb * GB < GB ? ng - gb * GB : GB;
+    m = rem / gw;
+    g = gb * GB + rem % gw;
     return true;
 }
 
