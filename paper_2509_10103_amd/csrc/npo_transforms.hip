@@ -566,8 +566,20 @@ __global__ __launch_bounds__(TB) void k_zinv_p(KP p, const double2* __restrict__
     };
     // modes jj (z = jj) and jj - P (z = 2P + jj, stored at kk = jj + NK - P)
     double2 v0[PB], v2[PB];
+    // u_theta of the current m, kept from its round for omega_r (field 3), which
+    // is formed from it and from u_z (still in v0, v2 from the round before)
+    double2 s0[PB], s2[PB];
     auto fetch = [&](int rd) {
         const int m = m0 + rd / NF, f = F0 + rd % NF;
+        if (f == 3 && rd % NF == 3) {
+#pragma unroll
+            for (int b = 0; b < PB; ++b) {
+                const int jj = threadIdx.x + b * TB;
+                v0[b] = csub(cscale(cmuli(v0[b]), m / rj), cscale(cmuli(s0[b]), alpha_of(p, jj)));
+                v2[b] = csub(cscale(cmuli(v2[b]), m / rj), cscale(cmuli(s2[b]), alpha_of(p, jj + NK - P)));
+            }
+            return;
+        }
 #pragma unroll
         for (int b = 0; b < PB; ++b) {
             const int jj = threadIdx.x + b * TB;
@@ -575,6 +587,10 @@ __global__ __launch_bounds__(TB) void k_zinv_p(KP p, const double2* __restrict__
             if (jj < P) {
                 v0[b] = load(m, f, jj);
                 if (jj) v2[b] = load(m, f, jj + NK - P);
+            }
+            if (f == 1) {
+                s0[b] = v0[b];
+                s2[b] = v2[b];
             }
         }
     };
