@@ -271,7 +271,7 @@ size_t first_adj(const std::vector<Act>& acts) {
 
 // -------------------------------------------------------------- step drivers
 struct WsPtrs {
-    double2 *aux0, *nn, *ns, *muC, *muP, *yb, *zb2, *fa, *fb, *fa2, *fb2, *cur, *lam, *tmp, *g, *trial, *trialN;
+    double2 *aux0, *nn, *ns, *muC, *muP, *yb, *zb2, *fa, *fb, *fa2, *fb2, *cur, *lam, *tmp, *g, *trial, *trialN, *r0;
     double2* st[npo::NCORR_MAX];
     double2* auxs[npo::NCORR_MAX];
     double* red;
@@ -283,7 +283,7 @@ WsPtrs wsptrs(const npo_plan_s& p, void* ws) {
     WsPtrs w;
     w.aux0 = F(p.ws.aux0); w.nn = F(p.ws.nn); w.ns = F(p.ws.ns);
     for (int c = 0; c < npo::NCORR_MAX; ++c) { w.st[c] = F(p.ws.st[c]); w.auxs[c] = F(p.ws.auxs[c]); }
-    w.muC = F(p.ws.muC); w.muP = F(p.ws.muP); w.yb = F(p.ws.yb); w.zb2 = F(p.ws.zb2);
+    w.muC = F(p.ws.muC); w.muP = F(p.ws.muP); w.yb = F(p.ws.yb); w.zb2 = F(p.ws.zb2); w.r0 = F(p.ws.r0);
     w.step = reinterpret_cast<long long*>(b + p.ws.step);
     w.fa = F(p.ws.fa); w.fb = F(p.ws.fb); w.fa2 = F(p.ws.fa2); w.fb2 = F(p.ws.fb2);
     w.cur = F(p.ws.cur); w.lam = F(p.ws.lam); w.tmp = F(p.ws.tmp); w.g = F(p.ws.g);
@@ -297,7 +297,8 @@ WsPtrs wsptrs(const npo_plan_s& p, void* ws) {
 npo::TimeArg at_step(const long long* dstep, long long n, int off) { return npo::TimeArg{dstep, n, off, 0, 0.0}; }
 
 // u_out = Phi(u_n).  If have_aux, w.aux0 already holds the vorticity parts of u_n.
-// Stages: w_0 = S(E u + N(u)), w_c = S(E u + (N(u) + N(w_{c-1}))/2), u_out = w_ncorr.
+// Stages: w_0 = S(E u + N(u)), w_c = S(E u + (N(u) + N(w_{c-1}))/2), u_out = w_ncorr;
+// the predictor leaves R0 = E u + N(u)/2, and each corrector solves S(R0 + N(w_{c-1})/2).
 hipError_t fwd_step(const npo_plan_s& p, void* ws, const double2* un, double2* uout, long long n, bool have_aux,
                     hipStream_t st, const long long* dstep = nullptr) {
     WsPtrs w = wsptrs(p, ws);
@@ -305,12 +306,12 @@ hipError_t fwd_step(const npo_plan_s& p, void* ws, const double2* un, double2* u
     const npo::TimeArg t0 = at_step(dstep, n, 0), t1 = at_step(dstep, n, 1);
     if (!have_aux && (e = npo::launch_curl_aux(p, un, w.aux0, st)) != hipSuccess) return e;
     if ((e = npo::launch_nl(p, 0, un, w.aux0, nullptr, t0, w.nn, nullptr, ws, st)) != hipSuccess) return e;
-    if ((e = npo::launch_solve(p, 1, un, w.nn, nullptr, w.st[0], w.auxs[0], st)) != hipSuccess) return e;
+    if ((e = npo::launch_solve(p, 1, un, w.nn, w.st[0], w.auxs[0], st, w.r0)) != hipSuccess) return e;
     for (int c = 1; c <= p.ncorr; ++c) {
         if ((e = npo::launch_nl(p, 0, w.st[c - 1], w.auxs[c - 1], nullptr, t1, w.ns, nullptr, ws, st)) != hipSuccess)
             return e;
         const bool last = c == p.ncorr;
-        if ((e = npo::launch_solve(p, 2, un, w.nn, w.ns, last ? uout : w.st[c], last ? w.aux0 : w.auxs[c], st)) !=
+        if ((e = npo::launch_solve(p, 2, w.r0, w.ns, last ? uout : w.st[c], last ? w.aux0 : w.auxs[c], st)) !=
             hipSuccess)
             return e;
     }
@@ -333,12 +334,14 @@ hipError_t adj_step(const npo_plan_s& p, void* ws, const double2* un, const doub
     if (!have_aux && (e = npo::launch_curl_aux(p, un, w.aux0, st)) != hipSuccess) return e;
     if ((e = npo::launch_nl(p, 0, un, w.aux0, nullptr, t0, w.nn, nullptr, ws, st, nullptr, zst(0))) != hipSuccess)
         return e;
-    if ((e = npo::launch_solve(p, 1, un, w.nn, nullptr, w.st[0], w.auxs[0], st)) != hipSuccess) return e;
+    if ((e = npo::launch_solve(p, 1, un, w.nn, w.st[0], w.auxs[0], st, C > 1 ? w.r0 : nullptr)) !=
+        hipSuccess)
+        return e;
     for (int c = 1; c < C; ++c) {
         if ((e = npo::launch_nl(p, 0, w.st[c - 1], w.auxs[c - 1], nullptr, t1, w.ns, nullptr, ws, st, nullptr,
                                 zst(c))) != hipSuccess)
             return e;
-        if ((e = npo::launch_solve(p, 2, un, w.nn, w.ns, w.st[c], w.auxs[c], st)) != hipSuccess) return e;
+        if ((e = npo::launch_solve(p, 2, w.r0, w.ns, w.st[c], w.auxs[c], st)) != hipSuccess) return e;
     }
     double2* mu[2] = {w.muC, w.muP};
     // mu_C = S^+ lam; the accumulators start as Y = mu_C / 2 and Z = mu_C, which
@@ -712,7 +715,7 @@ npo_status npo_plan_create(const npo_grid* grid, const npo_flow* flow, const npo
     L.aux0 = take(f2);
     for (int c = 0; c < npo::NCORR_MAX; ++c) { L.auxs[c] = take(f2); L.st[c] = take(fb); }
     L.nn = take(fb); L.ns = take(fb);
-    L.muC = take(fb); L.muP = take(fb); L.yb = take(fb); L.zb2 = take(fb);
+    L.muC = take(fb); L.muP = take(fb); L.yb = take(fb); L.zb2 = take(fb); L.r0 = take(fb);
     L.fa = take(fb); L.fb = take(fb); L.fa2 = take(fb); L.fb2 = take(fb);
     L.cur = take(fb); L.lam = take(fb); L.tmp = take(fb); L.g = take(fb);
     L.trial = take(fb); L.trialN = take(fb);
@@ -794,7 +797,7 @@ npo_status npo_nonlinear_adj(npo_plan p, void* ws, const void* u, double t, cons
 npo_status npo_solve(npo_plan p, void* ws, const void* R, void* out, void* stream) {
     if (check_plan(p) || !R || !out) return fail(NPO_EINVAL, "null argument");
     (void)ws;
-    HIPCHK(npo::launch_solve(*p, 0, CF(R), nullptr, nullptr, F(out), nullptr, ST(stream)));
+    HIPCHK(npo::launch_solve(*p, 0, CF(R), nullptr, F(out), nullptr, ST(stream)));
     return NPO_OK;
 }
 

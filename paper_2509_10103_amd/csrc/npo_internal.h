@@ -75,6 +75,7 @@ struct WsLayout {
     size_t st[NCORR_MAX];       // stage iterates w_0 .. w_{ncorr-1}
     size_t nn, ns;              // N(u^n), N(w_c)
     size_t muC, muP, yb, zb2;   // adjoint temporaries
+    size_t r0;                  // E u^n + N(u^n)/2 of the current step, read by the corrector passes
     size_t fa, fb;              // adjoint convective outputs (A, B)
     size_t fa2, fb2;
     size_t cur, lam, tmp;       // checkpoint-run state buffers
@@ -136,10 +137,11 @@ hipError_t launch_nl(const npo_plan_s& p, int adjoint, const double2* u, const d
                      const double2* uw_pre = nullptr, double2* uw_save = nullptr);
 // *d = v (set) or *d += v (add), one thread.
 hipError_t launch_step_index(long long* d, long long v, int add, hipStream_t st);
-// solve kinds: 0 = out = S(R) with R = a (raw); 1 = predictor S(E a + b);
-// 2 = corrector S(E a + (b + c)/2).  aux_out may be null.
-hipError_t launch_solve(const npo_plan_s& p, int kind, const double2* a, const double2* b,
-                        const double2* c, double2* u_out, double2* aux_out, hipStream_t st);
+// solve kinds: 0 = out = S(R) with R = a (raw); 1 = predictor S(E a + b),
+// which also stores R0 = E a + b/2 in the (+, -, z) basis when r0_out is given;
+// 2 = corrector S(R0 + b/2) with a = R0.  aux_out may be null.
+hipError_t launch_solve(const npo_plan_s& p, int kind, const double2* a, const double2* b, double2* u_out,
+                        double2* aux_out, hipStream_t st, double2* r0_out = nullptr);
 // mu = S^dag(ca*A + cb*curl^dag(B)); out0 = mu; Yout = sy*Yin + qy*mu; Zout = sz*Zin + qz*mu
 // (B, out0, Yin, Yout, Zin, Zout optional; Yin may alias Yout and Zin Zout).
 hipError_t launch_solve_adj(const npo_plan_s& p, const double2* A, double ca, const double2* B, double cb,

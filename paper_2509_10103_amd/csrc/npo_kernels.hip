@@ -345,8 +345,8 @@ __device__ __forceinline__ Slot slot_of(const KP& p, int g, int m, int q) {
 // right-hand sides (operator, mode, re/im) in the substitution phases.
 template <int kind, int NRC>
 __global__ __launch_bounds__(RT) void k_solve(KP p, const double2* __restrict__ ain,
-                                              const double2* __restrict__ bin, const double2* __restrict__ cin,
-                                              double2* __restrict__ uout, double2* __restrict__ auxout) {
+                                              const double2* __restrict__ bin, double2* __restrict__ uout,
+                                              double2* __restrict__ auxout, double2* __restrict__ r0out) {
     int g, m;
     if (!block_group(p, g, m)) return;
     const int t = threadIdx.x, q = t % RQ, jg = t / RQ;
@@ -360,7 +360,7 @@ __global__ __launch_bounds__(RT) void k_solve(KP p, const double2* __restrict__ 
     __shared__ double2 sp[NR_MAX][RQ];
     __shared__ double2 sa[RQ];
 
-    // u (kind 0: R) in the (+, -, z) basis, staged in LDS; the homogeneous
+    // u (kind 0: R; kind 2: R0 + N/2) in the (+, -, z) basis, staged in LDS; the homogeneous
     // solutions the combine step needs are requested at the same time
     constexpr int NJ = NR_MAX / RJ;
     const double* hom = p.HOM + ((size_t)sl.ka * p.mp1 + m) * (3 * nr + 1);
@@ -378,17 +378,25 @@ __global__ __launch_bounds__(RT) void k_solve(KP p, const double2* __restrict__ 
     for (int j = jg; j < nr; j += RJ) {
         double2 up = czero(), um = czero(), uz = czero();
         if (sl.valid) {
-            const double2 ur = ain[fidx(p, 0, j, m, sl.kk)], ut = ain[fidx(p, 1, j, m, sl.kk)];
-            uz = ain[fidx(p, 2, j, m, sl.kk)];
-            up = cadd(ur, cmuli(ut));
-            um = csub(ur, cmuli(ut));
+            if constexpr (kind == 2) {
+                // R = R0 + N/2 with R0 = E u^n + N(u^n)/2 stored in the (+, -, z) basis
+                const double2 nr_ = bin[fidx(p, 0, j, m, sl.kk)], nt_ = bin[fidx(p, 1, j, m, sl.kk)];
+                up = caxpy(ain[fidx(p, 0, j, m, sl.kk)], 0.5, cadd(nr_, cmuli(nt_)));
+                um = caxpy(ain[fidx(p, 1, j, m, sl.kk)], 0.5, csub(nr_, cmuli(nt_)));
+                uz = caxpy(ain[fidx(p, 2, j, m, sl.kk)], 0.5, bin[fidx(p, 2, j, m, sl.kk)]);
+            } else {
+                const double2 ur = ain[fidx(p, 0, j, m, sl.kk)], ut = ain[fidx(p, 1, j, m, sl.kk)];
+                uz = ain[fidx(p, 2, j, m, sl.kk)];
+                up = cadd(ur, cmuli(ut));
+                um = csub(ur, cmuli(ut));
+            }
         }
         sR[0][j][q] = up;
         sR[1][j][q] = um;
         sR[2][j][q] = uz;
     }
     __syncthreads();
-    if constexpr (kind != 0) {
+    if constexpr (kind == 1) {
         // R = E u^n + N: stencils read from LDS, results held in registers
         // until every lane has read its neighbours
         double2 Rv[NJ][3];
@@ -417,14 +425,17 @@ __global__ __launch_bounds__(RT) void k_solve(KP p, const double2* __restrict__ 
                 double2 Nr = bin[fidx(p, 0, j, m, kk)];
                 double2 Nt = bin[fidx(p, 1, j, m, kk)];
                 double2 Nz = bin[fidx(p, 2, j, m, kk)];
-                if constexpr (kind == 2) {
-                    Nr = cscale(cadd(Nr, cin[fidx(p, 0, j, m, kk)]), 0.5);
-                    Nt = cscale(cadd(Nt, cin[fidx(p, 1, j, m, kk)]), 0.5);
-                    Nz = cscale(cadd(Nz, cin[fidx(p, 2, j, m, kk)]), 0.5);
+                const double2 Ep = caxpy(cscale(up, idt), re2, lp), Em = caxpy(cscale(um, idt), re2, lm),
+                              Ez = caxpy(cscale(uz, idt), re2, lz);
+                Rv[jj][0] = cadd(Ep, cadd(Nr, cmuli(Nt)));
+                Rv[jj][1] = cadd(Em, csub(Nr, cmuli(Nt)));
+                Rv[jj][2] = cadd(Ez, Nz);
+                // R0 = E u^n + N(u^n)/2 for the corrector passes of this step
+                if (r0out) {
+                    r0out[fidx(p, 0, j, m, kk)] = caxpy(Ep, 0.5, cadd(Nr, cmuli(Nt)));
+                    r0out[fidx(p, 1, j, m, kk)] = caxpy(Em, 0.5, csub(Nr, cmuli(Nt)));
+                    r0out[fidx(p, 2, j, m, kk)] = caxpy(Ez, 0.5, Nz);
                 }
-                Rv[jj][0] = cadd(caxpy(cscale(up, idt), re2, lp), cadd(Nr, cmuli(Nt)));
-                Rv[jj][1] = cadd(caxpy(cscale(um, idt), re2, lm), csub(Nr, cmuli(Nt)));
-                Rv[jj][2] = cadd(caxpy(cscale(uz, idt), re2, lz), Nz);
             }
         }
         __syncthreads();
@@ -1068,25 +1079,30 @@ hipError_t launch_curl_aux(const npo_plan_s& p, const double2* u, double2* aux, 
     return hipGetLastError();
 }
 
-hipError_t launch_solve(const npo_plan_s& p, int kind, const double2* a, const double2* b, const double2* c,
-                        double2* u_out, double2* aux_out, hipStream_t st) {
-    prof_begin(p, kind == 1 ? KID_SOLVE_P : (kind == 2 ? KID_SOLVE_C : KID_SOLVE_R), st);
+template <int R>
+static void launch_solve_r(const npo_plan_s& p, int kind, dim3 grid, const double2* a, const double2* b,
+                           double2* u_out, double2* aux_out, double2* r0_out, hipStream_t st) {
+    if (kind == 1) hipLaunchKernelGGL((k_solve<1, R>), grid, dim3(RT), 0, st, p.kp, a, b, u_out, aux_out, r0_out);
+    else if (kind == 2) hipLaunchKernelGGL((k_solve<2, R>), grid, dim3(RT), 0, st, p.kp, a, b, u_out, aux_out, r0_out);
+    else hipLaunchKernelGGL((k_solve<0, R>), grid, dim3(RT), 0, st, p.kp, a, b, u_out, aux_out, r0_out);
+}
+
+hipError_t launch_solve(const npo_plan_s& p, int kind, const double2* a, const double2* b, double2* u_out,
+                        double2* aux_out, hipStream_t st, double2* r0_out) {
+    const int kid = kind == 1 ? KID_SOLVE_P : (kind == 2 ? KID_SOLVE_C : KID_SOLVE_R);
+    prof_begin(p, kid, st);
     const dim3 grid((radial_groups(p.K) * p.mp1 + 7) / 8 * 8);
     switch (p.nr) {
-#define NPO_CASE(R)                                                                                                 \
-    case R:                                                                                                         \
-        if (kind == 1) hipLaunchKernelGGL((k_solve<1, R>), grid, dim3(RT), 0, st, p.kp, a, b, c, u_out, aux_out);      \
-        else if (kind == 2) hipLaunchKernelGGL((k_solve<2, R>), grid, dim3(RT), 0, st, p.kp, a, b, c, u_out, aux_out); \
-        else hipLaunchKernelGGL((k_solve<0, R>), grid, dim3(RT), 0, st, p.kp, a, b, c, u_out, aux_out);                \
+#define NPO_CASE(R)                                                          \
+    case R:                                                                  \
+        launch_solve_r<R>(p, kind, grid, a, b, u_out, aux_out, r0_out, st);    \
         break;
         NPO_NR_SIZES(NPO_CASE)
 #undef NPO_CASE
     default:
-        if (kind == 1) hipLaunchKernelGGL((k_solve<1, 0>), grid, dim3(RT), 0, st, p.kp, a, b, c, u_out, aux_out);
-        else if (kind == 2) hipLaunchKernelGGL((k_solve<2, 0>), grid, dim3(RT), 0, st, p.kp, a, b, c, u_out, aux_out);
-        else hipLaunchKernelGGL((k_solve<0, 0>), grid, dim3(RT), 0, st, p.kp, a, b, c, u_out, aux_out);
+        launch_solve_r<0>(p, kind, grid, a, b, u_out, aux_out, r0_out, st);
     }
-    prof_end(p, kind == 1 ? KID_SOLVE_P : (kind == 2 ? KID_SOLVE_C : KID_SOLVE_R), st);
+    prof_end(p, kid, st);
     return hipGetLastError();
 }
 
