@@ -37,7 +37,7 @@ def alg_bytes(cfg):
         "curl": 5 * f1, "zinv_fwd": 5 * f1 + 6 * g1, "theta_fwd": 9 * g1, "zfwd_fwd": 3 * g1 + 3 * f1,
         "zinv_adj": 8 * f1 + 9 * g1, "theta_adj": 15 * g1, "zfwd_adj": 6 * g1 + 6 * f1,
         "solve_pred": 14 * f1, "solve_corr": 11 * f1, "solve_raw": 6 * f1, "solve_adj": 6 * f1,
-        "solve_adj2": 18 * f1, "adj_combine": 12 * f1, "wdot": 6 * f1, "project": 6 * f1, "axpby": 9 * f1,
+        "solve_adj2": 15 * f1, "adj_combine": 12 * f1, "wdot": 6 * f1, "project": 6 * f1, "axpby": 9 * f1,
         "zinv_adjy": 3 * f1 + 3 * g1,
     }
 

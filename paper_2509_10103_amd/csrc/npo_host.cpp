@@ -344,8 +344,8 @@ hipError_t adj_step(const npo_plan_s& p, void* ws, const double2* un, const doub
         if ((e = npo::launch_solve(p, 2, w.r0, w.ns, w.st[c], w.auxs[c], st)) != hipSuccess) return e;
     }
     double2* mu[2] = {w.muC, w.muP};
-    // mu_C = S^+ lam; the accumulators start as Y = mu_C / 2 and Z = mu_C, which
-    // the solve of stage C reads straight from mu_C (input scales 1/2 and 1)
+    // mu_C = S^+ lam; the accumulator Z starts as mu_C, which the solve of
+    // stage C reads straight from mu_C
     if ((e = npo::launch_solve_adj(p, lamin, 1.0, nullptr, 0.0, mu[C & 1], nullptr, 0.0, nullptr, nullptr, 0.0,
                                    nullptr, st)) != hipSuccess)
         return e;
@@ -355,13 +355,15 @@ hipError_t adj_step(const npo_plan_s& p, void* ws, const double2* un, const doub
         if ((e = npo::launch_nl(p, 1, w.st[c - 1], w.auxs[c - 1], mu[c & 1], t1, w.fa, w.fb, ws, st, pre)) !=
             hipSuccess)
             return e;
-        double2* next = (c > 1) ? mu[(c - 1) & 1] : nullptr;
-        const bool first = c == C;
-        const double2* Yin = first ? mu[C & 1] : w.yb;
-        const double2* Zin = first ? mu[C & 1] : w.zb2;
-        if ((e = npo::launch_solve_adj(p, w.fa, 0.5, w.fb, 0.5, next, Yin, c == 1 ? 1.0 : 0.5, w.yb, Zin, 1.0, w.zb2,
-                                       st, first ? 0.5 : 1.0, 1.0)) != hipSuccess)
-            return e;
+        // Z accumulates mu_c (c = C..0); Y = mu_0 + sum_{c>=1} mu_c / 2 equals
+        // (Z + mu_0) / 2, so only the last pass forms it, as Z_in / 2 + mu_0
+        const double2* Zin = c == C ? mu[C & 1] : w.zb2;
+        if (c > 1)
+            e = npo::launch_solve_adj(p, w.fa, 0.5, w.fb, 0.5, mu[(c - 1) & 1], nullptr, 0.0, nullptr, Zin, 1.0, w.zb2,
+                                      st);
+        else
+            e = npo::launch_solve_adj(p, w.fa, 0.5, w.fb, 0.5, nullptr, Zin, 1.0, w.yb, Zin, 1.0, w.zb2, st, 0.5, 1.0);
+        if (e != hipSuccess) return e;
     }
     if ((e = npo::launch_nl(p, 1, un, w.aux0, w.yb, t0, w.fa2, w.fb2, ws, st, zst(0))) != hipSuccess) return e;
     return npo::launch_final(p, w.zb2, w.fa2, w.fb2, lamout, st);
