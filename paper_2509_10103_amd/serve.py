@@ -22,16 +22,26 @@ import time
 import numpy as np
 
 
+def estimate_workspace(cfg):
+    """Upper bound of a plan's workspace bytes: about 23 state fields (stage
+    iterates and their vorticity parts, nonlinear terms, adjoint temporaries,
+    run state) plus 15 axially transformed scalar fields and 6 more per
+    corrector pass, each rounded up to 256 bytes."""
+    nr, nt, nz = cfg["nr"], cfg["nt"], cfg["nz"]
+    M, K = (nt - 1) // 3, (nz - 1) // 3
+    f = 3 * nr * (M + 1) * (2 * K + 1) * 16
+    g = nr * (M + 1) * nz * 16
+    return 24 * f + (15 + 6 * cfg.get("ncorr", 2)) * g + 64 * 256 + 64 * 1024
+
+
 def estimate_footprint(cfg):
     """Device bytes of one job: arena + workspace + operator caches + 2 fields."""
     nr, nt, nz = cfg["nr"], cfg["nt"], cfg["nz"]
     M, K = (nt - 1) // 3, (nz - 1) // 3
     f = 3 * nr * (M + 1) * (2 * K + 1) * 16
-    g = nr * (M + 1) * nz * 16
-    ws = 25 * f + 15 * g
     cache = (K + 1) * ((M + 2) + (M + 1)) * (nr - 1) * 9 * 8 + (K + 1) * (M + 1) * (3 * nr + 1) * 8
     n_ckpt = max(1, min(cfg.get("n_ckpt") or cfg["nsteps"], cfg["nsteps"]))
-    return n_ckpt * f + ws + cache + 2 * f
+    return n_ckpt * f + estimate_workspace(cfg) + cache + 2 * f
 
 
 class Job:

@@ -62,3 +62,17 @@ def test_served_jobs_equal_alone_under_staggered_arrivals():
         u0, uN = j.result
         assert np.array_equal(u0.cpu().numpy(), a0)
         assert np.array_equal(uN.cpu().numpy(), aN)
+
+
+@pytest.mark.parametrize("ncorr", [1, 2, 3])
+def test_footprint_estimate_bounds_the_workspace(ncorr):
+    """The serving loop admits jobs by estimate_workspace: it must bound what
+    a plan of that configuration asks for."""
+    from paper_2509_10103_amd import npo, serve
+    big = [dict(small_cfgs(1)[0], nr=64, nt=96, nz=768)] if ncorr == 2 else []
+    for c in small_cfgs(4) + big:
+        c = dict(c, ncorr=ncorr)
+        G = npo.Plan(c["nr"], c["nt"], c["nz"], c["lz"], c["re"], c["wo"], c["amp"], c["dt"], c["t0"],
+                     c["nsteps"], ncorr)
+        assert serve.estimate_workspace(c) >= G.info["workspace_bytes"], (c["nr"], c["nt"], c["nz"], ncorr)
+        del G
