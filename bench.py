@@ -8,6 +8,12 @@ the next iterate's checkpoints in place.  The initial forward sweep is done
 before the timed region.  Metric: forward + adjoint grid-point-steps per
 second, counting one forward and one adjoint sweep of N_r*N_theta*N_z points
 per step per iteration; recomputation and extra trial sweeps are not counted.
+
+The run keeps to a wall-clock budget (``--budget``, measured from process
+start, covering imports, plan set-up, the initial sweep, warm-up and timing):
+at most one warm-up iteration is run, and timed iterations stop at
+``--steps`` or when the next one would not fit the budget; ``steps`` in the
+JSON line is the number actually timed.
 """
 import argparse
 import json
@@ -16,7 +22,9 @@ import os
 import sys
 import time
 
-import numpy as np
+T_START = time.perf_counter()
+
+import numpy as np  # noqa: E402
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -25,6 +33,8 @@ from paper_2509_10103_amd import configs, synth  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0
 HBM_RESERVE = 6 << 30
+BUDGET_S = 420.0          # the whole run, from process start
+TAIL_S = 20.0             # kept free for the profiler read, the CPU leg and the JSON line
 
 
 def alg_bytes(cfg):
@@ -42,27 +52,79 @@ def alg_bytes(cfg):
     }
 
 
+def path_field_bytes(cfg):
+    """f: bytes of one complex128 spectral scalar field."""
+    M, K = (cfg["nt"] - 1) // 3, (cfg["nz"] - 1) // 3
+    return cfg["nr"] * (M + 1) * (2 * K + 1) * 16
+
+
+def path_step_bytes(cfg, ncorr):
+    """Compulsory HBM bytes of one forward and one adjoint step of the
+    two-exchange design with `ncorr` corrector passes, in units of f.
+
+    One corrector pass: a forward step moves 33f (nonlinear term: u in, N out,
+    6f per evaluation; predictor solve: u^n, N^n in, state out, 9f; corrector
+    solve: u^n, N^n, N* in, state out, 12f, plus its evaluation 6f), an adjoint
+    step about 60f including the recompute of its stage.  Each further corrector
+    pass adds one evaluation and one corrector solve to the forward step (18f),
+    and to the adjoint step the recompute of that stage (18f), the adjoint of its
+    nonlinear term (state and adjoint field in, result out: 9f), its transposed
+    solve (6f) and the accumulator update (6f): 39f."""
+    return 15 + 18 * ncorr, 60 + 39 * (ncorr - 1)
+
+
+def host_cores():
+    """Host cores this process may use (the GPU machine grants 16 per GPU whatever
+    the machine has)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cfg, seed):
-    """Time the CPU oracle on a bounded sample of the same workload: one
-    forward step (predictor and corrector passes) at full size, one BLAS
-    thread.  The oracle's adjoint step costs about five forward steps, so the
-    sample is forward-only; one forward step counts as one grid-point-step
-    per point in the metric's unit, which overstates the oracle's forward +
-    adjoint rate (conservative for the GPU comparison)."""
+    """Time the CPU oracle on a bounded sample of the same workload at full
+    size: one forward step (it also fills the oracle's operator-factor cache)
+    and then one adjoint step, which recomputes the step's stages and applies
+    their transposes, i.e. the work of one forward and one adjoint step of the
+    sweep pair the metric counts (2 grid-point-steps per point).  BLAS may use
+    every host core but two (those are left to the GPU leg running beside it);
+    the reported `cores` is the CPU time over the wall time of the sample."""
     from threadpoolctl import threadpool_limits
     from oracle.pipe import Pipe
-    with threadpool_limits(limits=1):
+    threads = max(1, host_cores() - 2)
+    with threadpool_limits(limits=threads):
         P = Pipe(cfg["nr"], cfg["nt"], cfg["nz"], cfg["lz"], cfg["re"], cfg["wo"], cfg["amp"], cfg["dt"], cfg["t0"])
         P.cache_limit = 0
         u = make_raw(cfg, P.r, P.M, P.K, seed)
         u *= math.sqrt(cfg["e0"] / P.energy(u))            # the cost does not depend on the values
         t = time.perf_counter()
-        P.step(u, 0)
+        un = P.step(u, 0)
         tf = time.perf_counter() - t
+        c0, t = os.times(), time.perf_counter()
+        P.step_adj(u, 0, un)
+        ta = time.perf_counter() - t
+        c1 = os.times()
+    used = (c1.user + c1.system - c0.user - c0.system) / ta
     pts = cfg["nr"] * cfg["nt"] * cfg["nz"]
-    return {"value": pts / tf, "unit": "grid-point-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 forward step of the same workload at full size ({tf:.1f} s, NumPy/SciPy oracle, "
-                      f"1 BLAS thread); the oracle's adjoint step (about 5x the forward step) is not in the sample"}
+    return {"value": 2 * pts / ta, "unit": "grid-point-steps/s", "cores": round(used, 2), "kind": "oracle",
+            "threads_allowed": threads, "host_cores": host_cores(), "cpu_model": cpu_model(),
+            "sample": f"one adjoint step of the same workload at full size ({ta:.1f} s; it recomputes the "
+                      f"step's stages, so it is the work of one forward and one adjoint step = 2 grid-point-"
+                      f"steps per point), after one forward step ({tf:.1f} s, fills the operator-factor cache); "
+                      f"NumPy/SciPy oracle, BLAS limited to {threads} threads, {used:.2f} cores busy on average"}
 
 
 def start_cpu_leg(workload):
@@ -86,26 +148,48 @@ def make_raw(cfg, r, M, K, seed):
     return synth.solenoidal_modes(r, M, K, cfg["lz"], seed)
 
 
+def elapsed():
+    return time.perf_counter() - T_START
+
+
+def copy_calibration():
+    """Counter calibration workload: one plain device-to-device copy of 1 GiB
+    (FETCH_SIZE / WRITE_SIZE of this dispatch give the scale factors of the
+    hardware byte counters)."""
+    import torch
+    a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"[bench] copied {b.numel()} bytes", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1, help="timed optimisation iterations")
-    ap.add_argument("--warmup", type=int, default=0, help="untimed optimisation iterations")
+    ap.add_argument("--steps", type=int, default=4, help="timed optimisation iterations (at most; see --budget)")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed optimisation iterations (at most one is run)")
+    ap.add_argument("--budget", type=float, default=BUDGET_S,
+                    help="wall-clock seconds for the whole run, from process start")
     ap.add_argument("--workload", default="c2", choices=sorted(configs.WORKLOADS))
     ap.add_argument("--nsteps", type=int, default=0, help="shorter horizon (development only)")
     ap.add_argument("--ckpt", type=int, default=0, help="checkpoint slots (default: the workload's)")
+    ap.add_argument("--shapes", default="", help="launch shapes zgroup,zb_fwd,zb_adj (default: tuned)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--stride", type=int, default=8, help="profiler sampling stride")
-    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve"],
-                    help="plain: one instance (the metric); batch / serve: the systems layers")
+    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "copy"],
+                    help="plain: one instance (the metric); batch / serve: the systems layers; "
+                         "copy: the 1 GiB copy that calibrates the byte counters")
     ap.add_argument("--batch-n", type=int, default=16, help="instances of the batched workload")
     ap.add_argument("--serve-n", type=int, default=24, help="requests of the served workload")
     ap.add_argument("--serve-iters", type=int, default=2, help="iterations per served request")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sharded design is described "
-              f"in DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this build measures one GPU's "
+              f"share; how the path would shard over several GPUs is a design note, not a run", file=sys.stderr)
         sys.exit(2)
     if args.cpu_leg:
         print(json.dumps(cpu_baseline(configs.WORKLOADS[args.workload], configs.WORKLOADS[args.workload]["seed"])))
@@ -117,6 +201,8 @@ def main():
     import torch
     from paper_2509_10103_amd import npo
 
+    if args.mode == "copy":
+        return copy_calibration()
     if args.mode == "batch":
         return bench_batch(args)
     if args.mode == "serve":
@@ -127,6 +213,7 @@ def main():
     torch.cuda.set_device(0)
     G = npo.Plan(cfg["nr"], cfg["nt"], cfg["nz"], cfg["lz"], cfg["re"], cfg["wo"], cfg["amp"], cfg["dt"],
                  cfg["t0"], cfg["nsteps"])
+    ncorr = 2
     if args.ckpt:
         nck = args.ckpt
     elif cfg["n_ckpt"]:
@@ -138,8 +225,11 @@ def main():
         free = torch.cuda.mem_get_info()[0]
         nck = int(max(1, min(cfg["nsteps"], (free - HBM_RESERVE) // fb)))
     from paper_2509_10103_amd import tune
-    shapes, _ = tune.tune(G, cfg["nr"], cfg["nt"], cfg["nz"], use_cache=False, save=False)
-    shapes = list(shapes)
+    if args.shapes:
+        shapes = [int(x) for x in args.shapes.split(",")]
+        npo.npo_plan_set_tuning(G.handle, *shapes)
+    else:
+        shapes = list(tune.tune(G, cfg["nr"], cfg["nt"], cfg["nz"], save=False)[0])
     r = npo.npo_plan_tables(G.handle, cfg["nr"])[0]
     raw = make_raw(cfg, r, G.M, G.K, cfg["seed"])
     u0 = torch.from_numpy(raw).to("cuda")
@@ -147,52 +237,83 @@ def main():
     npo.npo_normalize(G.handle, G.ws, u0, cfg["e0"])
     arena = G.arena(nck)
     uN = G.field()
+    n_rec = npo.npo_ckpt_count(cfg["nsteps"], nck)
     print(f"[bench] {cfg['name']} nsteps={cfg['nsteps']} n_ckpt={nck} arena={arena.numel() * 16 / 2**30:.1f} GiB "
-          f"launch shapes {shapes}",
-          file=sys.stderr, flush=True)
+          f"recompute/sweep={n_rec} launch shapes {shapes} (t={elapsed():.1f} s)", file=sys.stderr, flush=True)
     t = time.perf_counter()
     npo.npo_forward_run(G.handle, G.ws, arena, nck, u0, uN)
     torch.cuda.synchronize()
-    print(f"[bench] initial forward sweep {time.perf_counter() - t:.2f} s", file=sys.stderr, flush=True)
+    t_sweep = time.perf_counter() - t
+    print(f"[bench] initial forward sweep {t_sweep:.2f} s (t={elapsed():.1f} s)", file=sys.stderr, flush=True)
 
     def one_iter():
         st = npo.npo_iterate(G.handle, G.ws, arena, nck, u0, uN, cfg["e0"])
         if not st["accepted"]:
             npo.npo_forward_run(G.handle, G.ws, arena, nck, u0, uN)
+            st["forward_sweeps"] += 1
         return st
 
-    for _ in range(args.warmup):
+    # an iteration is one adjoint sweep (about 1.8 forward sweeps of work plus
+    # the recompute) and at least one trial sweep: estimate it before warm-up
+    t_est = t_sweep * (3.0 + n_rec / max(cfg["nsteps"], 1))
+    warm = 0
+    for _ in range(min(args.warmup, 1)):
+        if elapsed() + 2 * t_est + TAIL_S > args.budget:
+            break
+        t = time.perf_counter()
         one_iter()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        t_est = time.perf_counter() - t
+        warm += 1
+        print(f"[bench] warm-up iteration {t_est:.2f} s (t={elapsed():.1f} s)", file=sys.stderr, flush=True)
     npo.npo_profile_begin(G.handle, args.stride)
     lat = []
     hist = []
     t0 = time.perf_counter()
     for i in range(args.steps):
+        # the next iteration must fit the budget (the first timed one always runs)
+        if i > 0 and elapsed() + 1.15 * max(t_est, max(lat)) + TAIL_S > args.budget:
+            break
         ti = time.perf_counter()
         st = one_iter()
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - ti)
         hist.append(st)
         print(f"[bench] iteration {i}: G {st['G_old']:.6g} -> {st['G_new']:.6g} accepted={int(st['accepted'])} "
-              f"sweeps={int(st['forward_sweeps'])} {lat[-1]:.2f} s", file=sys.stderr, flush=True)
+              f"sweeps={int(st['forward_sweeps'])} {lat[-1]:.2f} s (t={elapsed():.1f} s)", file=sys.stderr,
+              flush=True)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    wall = time.perf_counter() - t0
+    timed = len(lat)
     prof = npo.npo_profile_read(G.handle)
     pts = cfg["nr"] * cfg["nt"] * cfg["nz"]
-    counted = args.steps * 2 * cfg["nsteps"] * pts
-    value = counted / elapsed
+    counted = timed * 2 * cfg["nsteps"] * pts
+    value = counted / wall
     ab = alg_bytes(cfg)
     tot = {k: v["launches"] * v["avg_ms"] for k, v in prof.items()}
     dom = max(tot, key=tot.get)
     avg_s = prof[dom]["avg_ms"] * 1e-3
     achieved = ab[dom] / avg_s / 1e9 if avg_s > 0 else 0.0
-    # HBM traffic of the dominant kernel from the committed counter summary
-    # (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-calibrated), only while it was
-    # taken on these kernel sources
+    # HBM traffic per launch from the committed counter summary (rocprofv3
+    # FETCH_SIZE / WRITE_SIZE, copy-calibrated), only while it was taken on
+    # these kernel sources
     from paper_2509_10103_amd import profsum
     tr = profsum.load_traffic(os.path.join(ROOT, "profiles", f"{cfg['name']}_hbm_bytes.md"), cfg["nt"], cfg["nz"])
     traffic = tr[dom]["fetch"] + tr[dom]["write"] if tr and dom in tr else None
+    # the whole path against the compulsory bytes of the two-exchange design:
+    # every forward advance (trial sweeps and recompute) and adjoint step run
+    f1 = path_field_bytes(cfg)
+    bf, ba = path_step_bytes(cfg, ncorr)
+    n_fwd = sum(h["forward_sweeps"] for h in hist) * cfg["nsteps"] + timed * n_rec
+    n_adj = timed * cfg["nsteps"]
+    b_alg = (n_fwd * bf + n_adj * ba) * f1
+    measured = None
+    if tr:
+        measured = sum(v["launches"] * (tr[k]["fetch"] + tr[k]["write"]) for k, v in prof.items() if k in tr)
+    path = {"alg_bytes": b_alg, "achieved": b_alg / wall / 1e9, "frac": b_alg / wall / 1e9 / PEAK_HBM_GBS,
+            "unit": "GB/s", "forward_advances": n_fwd, "adjoint_steps": n_adj,
+            "bytes_per_forward_step_f": bf, "bytes_per_adjoint_step_f": ba, "f_bytes": f1,
+            "measured_bytes": measured, "alg_over_measured": (b_alg / measured) if measured else None}
     kern = {k: {"launches": v["launches"], "avg_us": round(v["avg_ms"] * 1e3, 2),
                 "share": round(tot[k] / max(sum(tot.values()), 1e-30), 4),
                 "GBps_alg": round(ab[k] / (v["avg_ms"] * 1e-3) / 1e9, 1) if v["avg_ms"] > 0 else None}
@@ -202,9 +323,9 @@ def main():
         "value": value,
         "unit": "grid-point-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "steps": timed,
+        "warmup": warm,
+        "ms_per_step": wall / timed * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -212,15 +333,19 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["name"], "grid": [cfg["nr"], cfg["nt"], cfg["nz"]], "lz_radii": cfg["lz"],
                    "re": cfg["re"], "wo": cfg["wo"], "amp": cfg["amp"], "dt": cfg["dt"], "t0": cfg["t0"],
-                   "nsteps": cfg["nsteps"], "n_ckpt": nck, "launch_shapes": shapes, "e0": cfg["e0"], "seed": cfg["seed"],
+                   "nsteps": cfg["nsteps"], "ncorr": ncorr, "n_ckpt": nck, "recompute_per_sweep": n_rec,
+                   "launch_shapes": shapes, "e0": cfg["e0"], "seed": cfg["seed"],
+                   "steps_requested": args.steps, "warmup_requested": args.warmup, "budget_s": args.budget,
+                   "run_s": round(elapsed(), 1),
                    "iteration_latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
                    "gains": [[h["G_old"], h["G_new"], int(h["accepted"]), int(h["forward_sweeps"])] for h in hist]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "alg_bytes_per_launch": ab[dom], "avg_launch_us": avg_s * 1e6},
+                     "alg_bytes_per_launch": ab[dom], "avg_launch_us": avg_s * 1e6, "path": path},
         "kernels": kern,
     }
     out["cpu_baseline"] = finish_cpu_leg(cpu_proc) if cpu_proc is not None else None
+    out["config"]["run_s"] = round(elapsed(), 1)
     print(json.dumps(out), flush=True)
 
 
