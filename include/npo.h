@@ -93,9 +93,12 @@ npo_status npo_plan_info(npo_plan plan, npo_info* out);
  * nodes col0[j] .. col0[j]+6.  Any pointer may be NULL. */
 npo_status npo_plan_tables(npo_plan plan, double* r, double* w, double* D1, double* D2, int32_t* col0);
 
-/* Laminar Sexl-Womersley flow at time t (Sec. 2): U(r_j,t) and
- * Omega_theta(r_j,t) = -dU/dr, written to host arrays of length nr. */
-npo_status npo_base_flow(npo_plan plan, double t, double* U, double* Om);
+/* Laminar Sexl-Womersley flow at time t (Sec. 2, base flow driven at bulk
+ * velocity u_b(t)): U_dev[j] = U(r_j, t) and dUdr_dev[j] = dU/dr(r_j, t)
+ * (= -Omega_theta), j = 0..nr-1, written by a kernel on `stream` into caller
+ * device arrays of nr doubles.  t is in the solver's time units (absolute,
+ * not relative to t0).  NPO_EINVAL for a null pointer or non-finite t. */
+npo_status npo_base_flow(npo_plan plan, double t, double* U_dev, double* dUdr_dev, void* stream);
 
 /* Pieces of the step, exposed for testing each kernel (all device pointers,
  * workspace ws of workspace_bytes):
@@ -145,11 +148,21 @@ npo_status npo_inner(npo_plan plan, void* ws, const void* a, const void* b, doub
  * for the mean mode); the normal equations are solved twice (one refinement).
  * out may alias u. */
 npo_status npo_project(npo_plan plan, void* ws, const void* u, void* out, void* stream);
-/* Gradient step of Sec. 2.2: u_new = (1 + lambda_+ alpha) u0 - alpha udag with
- * lambda_+ the '+' root of the energy constraint (E0dag = <udag,udag>/2,
- * C0 = <u0,udag> given), then rescaled to energy e0 on the device. */
-npo_status npo_update(npo_plan plan, void* ws, const void* u0, const void* udag, double e0,
-                      double alpha, double e0dag, double c0, void* u_new, void* stream);
+/* Gradient step of Sec. 2.2 with every scalar computed and kept on the device:
+ * g is the projected W-gradient of the gain (udag = -g, the paper's sign
+ * convention u_dag(T) = -u(T)).  On `stream` the call forms
+ *   E0dag = <g,g>_W / 2,  C0 = <u0, udag>_W,
+ *   alpha_max = (E0dag/e0 - C0^2/(4 e0^2))^(-1/2)   (infinite if g || u0),
+ *   lambda_+  = '+' root of the energy constraint at step al (discriminant
+ *               clamped at 0, where it sits at al = alpha_max),
+ *   u_new     = (1 + lambda_+ al) u0 - al udag, rescaled to energy e0,
+ * with al = alpha if alpha > 0, else al = alpha_max (an empty step when that is
+ * infinite).  info_dev (device, 5 doubles) receives E0dag, C0, alpha_max,
+ * lambda_+ and E_new, the energy of u_new before the final rescale (equal to
+ * e0 up to rounding when lambda_+ is exact).  u_new must not alias u0 or g.
+ * ws: workspace of workspace_bytes (reduction partials). */
+npo_status npo_update(npo_plan plan, void* ws, const void* u0, const void* g, double e0,
+                      double alpha, void* u_new, double* info_dev, void* stream);
 
 /* One adjoint-looping iteration (Sec. 2.1-2.2) on the host: requires that the
  * arena holds the forward sweep of u0 (npo_forward_run, or the accepted trial

@@ -762,20 +762,17 @@ npo_status npo_plan_tables(npo_plan p, double* r, double* w, double* D1, double*
     return NPO_OK;
 }
 
-npo_status npo_base_flow(npo_plan p, double t, double* U, double* Om) {
-    if (check_plan(p) || !U || !Om) return fail(NPO_EINVAL, "null argument");
-    const double cw = cos(p->omega * t), sw = sin(p->omega * t);
-    for (int j = 0; j < p->nr; ++j) {
-        const double r = p->r[j];
-        U[j] = 1.0 - r * r + (p->ut_re[j] * cw - p->ut_im[j] * sw);
-        Om[j] = 2.0 * r - (p->dut_re[j] * cw - p->dut_im[j] * sw);
-    }
-    return NPO_OK;
-}
 
 #define ST(s) reinterpret_cast<hipStream_t>(s)
 #define CF(x) reinterpret_cast<const double2*>(x)
 #define F(x) reinterpret_cast<double2*>(x)
+
+npo_status npo_base_flow(npo_plan p, double t, double* U_dev, double* dUdr_dev, void* stream) {
+    if (check_plan(p) || !U_dev || !dUdr_dev) return fail(NPO_EINVAL, "null argument");
+    if (!std::isfinite(t)) return fail(NPO_EINVAL, "t must be finite");
+    HIPCHK(npo::launch_base_flow(*p, t, U_dev, dUdr_dev, ST(stream)));
+    return NPO_OK;
+}
 
 npo_status npo_nonlinear(npo_plan p, void* ws, const void* u, double t, void* out, void* stream) {
     if (check_plan(p) || !ws || !u || !out) return fail(NPO_EINVAL, "null argument");
@@ -970,8 +967,10 @@ static double lambda_plus(double al, double E0, double E0d, double C0) {
     return a + std::sqrt(disc > 0.0 ? disc : 0.0);
 }
 
-npo_status npo_update(npo_plan p, void* ws, const void* u0, const void* udag, double e0, double alpha, double e0dag,
-                      double c0, void* u_new, void* stream) {
+// The gradient step with host scalars (the line search of npo_iterate, which
+// needs E0dag and C0 on the host anyway for alpha_max).
+static npo_status update_host(npo_plan p, void* ws, const void* u0, const void* udag, double e0, double alpha,
+                              double e0dag, double c0, void* u_new, void* stream) {
     if (check_plan(p) || !ws || !u0 || !udag || !u_new) return fail(NPO_EINVAL, "null argument");
     if (!(e0 > 0) || !(alpha > 0)) return fail(NPO_EINVAL, "e0 and alpha must be positive");
     WsPtrs w = wsptrs(*p, ws);
@@ -980,6 +979,26 @@ npo_status npo_update(npo_plan p, void* ws, const void* u0, const void* udag, do
     HIPCHK(npo::launch_axpby(*p, 1.0 + lam * alpha, CF(u0), -alpha, CF(udag), F(u_new), st));
     double* en = w.red + npo::NR_MAX * 4 + 256;
     HIPCHK(npo::launch_wdot(*p, CF(u_new), CF(u_new), w.red, en, st));
+    // energy = <u,u>/2
+    HIPCHK(npo::launch_rescale(*p, F(u_new), en, 2.0 * e0, st));
+    return NPO_OK;
+}
+
+npo_status npo_update(npo_plan p, void* ws, const void* u0, const void* g, double e0, double alpha, void* u_new,
+                      double* info_dev, void* stream) {
+    if (check_plan(p) || !ws || !u0 || !g || !u_new || !info_dev) return fail(NPO_EINVAL, "null argument");
+    if (!(e0 > 0)) return fail(NPO_EINVAL, "e0 must be positive");
+    if (!std::isfinite(alpha)) return fail(NPO_EINVAL, "alpha must be finite (<= 0 selects alpha_max)");
+    if (u_new == u0 || u_new == g) return fail(NPO_EINVAL, "u_new must not alias u0 or g");
+    WsPtrs w = wsptrs(*p, ws);
+    const hipStream_t st = ST(stream);
+    double* sc = w.red + npo::NR_MAX * 4 + 256 + 16;     // sc[0..1] inner products, sc[2..3] coefficients
+    HIPCHK(npo::launch_wdot(*p, CF(g), CF(g), w.red, sc, st));
+    HIPCHK(npo::launch_wdot(*p, CF(u0), CF(g), w.red, sc + 1, st));
+    HIPCHK(npo::launch_update_dev(*p, sc, e0, alpha, info_dev, sc + 2, CF(u0), CF(g), F(u_new), st));
+    double* en = sc + 4;
+    HIPCHK(npo::launch_wdot(*p, CF(u_new), CF(u_new), w.red, en, st));
+    HIPCHK(npo::launch_half(en, info_dev, st));
     // energy = <u,u>/2
     HIPCHK(npo::launch_rescale(*p, F(u_new), en, 2.0 * e0, st));
     return NPO_OK;
@@ -1020,7 +1039,7 @@ npo_status npo_iterate(npo_plan p, void* ws, void* ckpt, int32_t nck, void* u0, 
     HIPCHK(npo::launch_axpby(*p, -1.0, w.g, 0.0, nullptr, w.tmp, st));
     double al = amax;
     for (int hv = 0; hv <= max_halvings; ++hv) {
-        s = npo_update(p, ws, u0, w.tmp, e0, al, E0d, C0, w.trial, stream);
+        s = update_host(p, ws, u0, w.tmp, e0, al, E0d, C0, w.trial, stream);
         if (s) return s;
         s = npo_forward_run(p, ws, ckpt, nck, w.trial, w.trialN, stream);
         if (s) return s;

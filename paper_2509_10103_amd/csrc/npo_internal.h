@@ -158,6 +158,15 @@ hipError_t launch_axpby(const npo_plan_s& p, double ca, const double2* a, double
                         double2* out, hipStream_t st);
 // out = s * 2 pi L_z c_m w_j * x
 hipError_t launch_wscale(const npo_plan_s& p, const double2* x, double2* out, double s, hipStream_t st);
+// Device-scalar gradient step: from sc[0] = <g,g>_W, sc[1] = <u0,g>_W write
+// info[0..3] = E0dag, C0, alpha_max, lambda_+ and out = (1 + lambda_+ al) u0 + al g
+// (al = alpha, or alpha_max when alpha <= 0); coef holds 2 doubles of scratch.
+hipError_t launch_update_dev(const npo_plan_s& p, const double* sc, double e0, double alpha, double* info,
+                             double* coef, const double2* u0, const double2* g, double2* out, hipStream_t st);
+// U[j] = U(r_j, t), dUdr[j] = dU/dr(r_j, t) of the laminar base flow (device arrays of nr)
+hipError_t launch_base_flow(const npo_plan_s& p, double t, double* U, double* dUdr, hipStream_t st);
+// info[4] = en[0] / 2
+hipError_t launch_half(const double* en, double* info, hipStream_t st);
 // x *= sqrt(e0 / energy_dev[0])
 hipError_t launch_rescale(const npo_plan_s& p, double2* x, const double* energy_dev, double e0,
                           hipStream_t st);

@@ -1058,6 +1058,59 @@ __global__ void k_rescale(size_t n, double2* __restrict__ x, const double* __res
     x[i] = cscale(x[i], s);
 }
 
+// Scalars of the gradient step (Sec. 2.2) from sc[0] = <g,g>_W and
+// sc[1] = <u0,g>_W, with udag = -g: E0dag = <g,g>/2, C0 = <u0,udag> = -<u0,g>,
+// alpha_max from the reality condition of the multiplier, lambda_+ the '+' root
+// of the energy constraint at step al (alpha, or alpha_max when alpha <= 0; the
+// discriminant is clamped at 0, where it sits at alpha_max).  Writes
+// info[0..3] = E0dag, C0, alpha_max, lambda_+ and coef[0..1] such that
+// u_new = coef[0] u0 + coef[1] g.  With alpha_max infinite (g parallel to u0)
+// and alpha <= 0 the step is empty: coef = (1, 0), lambda_+ = 0.
+__global__ void k_update_coef(const double* __restrict__ sc, double e0, double alpha, double* __restrict__ info,
+                              double* __restrict__ coef) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double E0d = 0.5 * sc[0], C0 = -sc[1];
+    const double q = E0d / e0 - C0 * C0 / (4.0 * e0 * e0);
+    const double amax = q > 0.0 ? 1.0 / sqrt(q) : __builtin_inf();
+    const double al = alpha > 0.0 ? alpha : amax;
+    double lam = 0.0, c0 = 1.0, c1 = 0.0;
+    if (al < __builtin_inf()) {
+        const double a = (al * C0 - 2.0 * e0) / (2.0 * al * e0);
+        const double disc = a * a - (al * E0d - C0) / (al * e0);
+        lam = a + sqrt(disc > 0.0 ? disc : 0.0);
+        c0 = 1.0 + lam * al;
+        c1 = al;
+    }
+    info[0] = E0d; info[1] = C0; info[2] = amax; info[3] = lam;
+    coef[0] = c0; coef[1] = c1;
+}
+
+// out = coef[0] a + coef[1] b with the coefficients read from device memory.
+__global__ void k_axpby_dev(size_t n, const double* __restrict__ coef, const double2* __restrict__ a,
+                            const double2* __restrict__ b, double2* __restrict__ out) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = caxpy(cscale(a[i], coef[0]), coef[1], b[i]);
+}
+
+// Laminar base flow at time t (Sec. 2, Sexl-Womersley profile): U(r_j, t) and
+// dU/dr = -Omega_theta at every radial node, from the same device helper the
+// transform kernels use.
+__global__ void k_base_flow(KP p, double t, double* __restrict__ U, double* __restrict__ dUdr) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= p.nr) return;
+    double sw, cw, u, om;
+    sincos(p.omega * t, &sw, &cw);
+    base_at(p, j, cw, sw, u, om);
+    U[j] = u;
+    dUdr[j] = -om;
+}
+
+// info[4] = <u,u>_W / 2 (the energy of the updated iterate before rescaling).
+__global__ void k_half(const double* __restrict__ en, double* __restrict__ info) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) info[4] = 0.5 * en[0];
+}
+
 // Device step index of captured step graphs: *d = v or *d += v.
 __global__ void k_step_index(long long* d, long long v, int add) {
     if (threadIdx.x == 0) *d = add ? *d + v : v;
@@ -1164,6 +1217,26 @@ hipError_t launch_axpby(const npo_plan_s& p, double ca, const double2* a, double
 hipError_t launch_wscale(const npo_plan_s& p, const double2* x, double2* out, double s, hipStream_t st) {
     const size_t n = field_elems(p);
     hipLaunchKernelGGL(k_wscale, dim3((n + 255) / 256), dim3(256), 0, st, p.kp, x, out, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_dev(const npo_plan_s& p, const double* sc, double e0, double alpha, double* info,
+                             double* coef, const double2* u0, const double2* g, double2* out, hipStream_t st) {
+    const size_t n = field_elems(p);
+    hipLaunchKernelGGL(k_update_coef, dim3(1), dim3(64), 0, st, sc, e0, alpha, info, coef);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_axpby_dev, dim3((n + 255) / 256), dim3(256), 0, st, n, coef, u0, g, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_base_flow(const npo_plan_s& p, double t, double* U, double* dUdr, hipStream_t st) {
+    hipLaunchKernelGGL(k_base_flow, dim3(1), dim3(64), 0, st, p.kp, t, U, dUdr);
+    return hipGetLastError();
+}
+
+hipError_t launch_half(const double* en, double* info, hipStream_t st) {
+    hipLaunchKernelGGL(k_half, dim3(1), dim3(64), 0, st, en, info);
     return hipGetLastError();
 }
 

@@ -52,7 +52,7 @@ SIGNATURES = {
     "npo_plan_destroy": (_I32, [_P]),
     "npo_plan_info": (_I32, [_P, ctypes.POINTER(Info)]),
     "npo_plan_tables": (_I32, [_P, _DP, _DP, _DP, _DP, ctypes.POINTER(_I32)]),
-    "npo_base_flow": (_I32, [_P, _D, _DP, _DP]),
+    "npo_base_flow": (_I32, [_P, _D, _P, _P, _P]),
     "npo_nonlinear": (_I32, [_P, _P, _P, _D, _P, _P]),
     "npo_nonlinear_adj": (_I32, [_P, _P, _P, _D, _P, _P, _P]),
     "npo_solve": (_I32, [_P, _P, _P, _P, _P]),
@@ -64,7 +64,7 @@ SIGNATURES = {
     "npo_ckpt_count": (_I32, [_I64, _I32, ctypes.POINTER(_I64)]),
     "npo_inner": (_I32, [_P, _P, _P, _P, _P, _P]),
     "npo_project": (_I32, [_P, _P, _P, _P, _P]),
-    "npo_update": (_I32, [_P, _P, _P, _P, _D, _D, _D, _D, _P, _P]),
+    "npo_update": (_I32, [_P, _P, _P, _P, _D, _D, _P, _P, _P]),
     "npo_iterate": (_I32, [_P, _P, _P, _I32, _P, _P, _D, _D, _I32, _DP, _P]),
     "npo_normalize": (_I32, [_P, _P, _P, _D, _P]),
     "npo_euclid_grad": (_I32, [_P, _P, _D, _P, _P]),
@@ -104,6 +104,60 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+# Argument checks before a call: a wrong dtype, a strided view or an undersized
+# buffer would make the kernels read or write past an allocation, so they are
+# refused here with NpoError instead.
+_INFO = {}
+
+
+def _plan_info(plan):
+    key = plan.value if isinstance(plan, ctypes.c_void_p) else int(plan)
+    inf = _INFO.get(key)
+    if inf is None:
+        inf = npo_plan_info(plan)
+        _INFO[key] = inf
+    return inf
+
+
+def _dev(t, what):
+    if t is None:
+        raise NpoError(f"{what}: missing tensor")
+    if not getattr(t, "is_cuda", False):
+        raise NpoError(f"{what}: must be a device tensor")
+    if not t.is_contiguous():
+        raise NpoError(f"{what}: must be contiguous")
+    return _ptr(t)
+
+
+def _fld(plan, t, what, count=1):
+    """A field (or `count` consecutive fields): complex128, contiguous, on the device."""
+    import torch
+    p = _dev(t, what)
+    if t.dtype != torch.complex128:
+        raise NpoError(f"{what}: dtype {t.dtype}, expected complex128")
+    need = _plan_info(plan)["field_elems"] * count
+    bad = t.numel() < need if count > 1 else t.numel() != need
+    if bad:
+        raise NpoError(f"{what}: {t.numel()} complex elements, expected {'at least ' if count > 1 else ''}{need}")
+    return p
+
+
+def _wsp(plan, ws):
+    p = _dev(ws, "workspace")
+    need = _plan_info(plan)["workspace_bytes"]
+    if ws.numel() * ws.element_size() < need:
+        raise NpoError(f"workspace: {ws.numel() * ws.element_size()} bytes, plan needs {need}")
+    return p
+
+
+def _scal(t, what, n=1):
+    import torch
+    p = _dev(t, what)
+    if t.dtype != torch.float64 or t.numel() < n:
+        raise NpoError(f"{what}: expected at least {n} float64 elements on the device")
+    return p
+
+
 def _stream(stream=None):
     if stream is not None:
         return ctypes.c_void_p(stream)
@@ -122,6 +176,7 @@ def npo_plan_create(nr, ntheta, nz, lz, re, wo, amp, dt, t0, nsteps, ncorr=2):
 
 
 def npo_plan_destroy(plan):
+    _INFO.pop(plan.value if isinstance(plan, ctypes.c_void_p) else int(plan), None)
     _check(lib().npo_plan_destroy(plan))
 
 
@@ -140,44 +195,49 @@ def npo_plan_tables(plan, nr):
     return r, w, D1, D2, col0
 
 
-def npo_base_flow(plan, t, nr):
-    U, Om = np.zeros(nr), np.zeros(nr)
-    _check(lib().npo_base_flow(plan, t, U.ctypes.data_as(_DP), Om.ctypes.data_as(_DP)))
-    return U, Om
+def npo_base_flow(plan, t, U_dev, dUdr_dev, stream=None):
+    nr = _plan_info(plan)["nr"]
+    _check(lib().npo_base_flow(plan, t, _scal(U_dev, "U_dev", nr), _scal(dUdr_dev, "dUdr_dev", nr),
+                               _stream(stream)))
 
 
 # --------------------------------------------------------- device calls
 def npo_nonlinear(plan, ws, u, t, out, stream=None):
-    _check(lib().npo_nonlinear(plan, _ptr(ws), _ptr(u), t, _ptr(out), _stream(stream)))
+    _check(lib().npo_nonlinear(plan, _wsp(plan, ws), _fld(plan, u, "u"), t, _fld(plan, out, "out"), _stream(stream)))
 
 
 def npo_nonlinear_adj(plan, ws, u, t, y, out, stream=None):
-    _check(lib().npo_nonlinear_adj(plan, _ptr(ws), _ptr(u), t, _ptr(y), _ptr(out), _stream(stream)))
+    _check(lib().npo_nonlinear_adj(plan, _wsp(plan, ws), _fld(plan, u, "u"), t, _fld(plan, y, "y"),
+                                   _fld(plan, out, "out"), _stream(stream)))
 
 
 def npo_solve(plan, ws, R, out, stream=None):
-    _check(lib().npo_solve(plan, _ptr(ws), _ptr(R), _ptr(out), _stream(stream)))
+    _check(lib().npo_solve(plan, _ptr(ws), _fld(plan, R, "R"), _fld(plan, out, "out"), _stream(stream)))
 
 
 def npo_solve_adj(plan, ws, y, out, stream=None):
-    _check(lib().npo_solve_adj(plan, _ptr(ws), _ptr(y), _ptr(out), _stream(stream)))
+    _check(lib().npo_solve_adj(plan, _ptr(ws), _fld(plan, y, "y"), _fld(plan, out, "out"), _stream(stream)))
 
 
 def npo_forward_step(plan, ws, u_n, u_np1, n, stream=None):
-    _check(lib().npo_forward_step(plan, _ptr(ws), _ptr(u_n), _ptr(u_np1), n, _stream(stream)))
+    _check(lib().npo_forward_step(plan, _wsp(plan, ws), _fld(plan, u_n, "u_n"), _fld(plan, u_np1, "u_np1"), n,
+                                  _stream(stream)))
 
 
 def npo_adjoint_step(plan, ws, u_n, lam_np1, lam_n, n, stream=None):
-    _check(lib().npo_adjoint_step(plan, _ptr(ws), _ptr(u_n), _ptr(lam_np1), _ptr(lam_n), n, _stream(stream)))
+    _check(lib().npo_adjoint_step(plan, _wsp(plan, ws), _fld(plan, u_n, "u_n"), _fld(plan, lam_np1, "lam_np1"),
+                                  _fld(plan, lam_n, "lam_n"), n, _stream(stream)))
 
 
 def npo_forward_run(plan, ws, ckpt, n_ckpt, u0, uN, stream=None):
-    _check(lib().npo_forward_run(plan, _ptr(ws), _ptr(ckpt), n_ckpt, _ptr(u0), _ptr(uN), _stream(stream)))
+    _check(lib().npo_forward_run(plan, _wsp(plan, ws), _fld(plan, ckpt, "checkpoint arena", max(int(n_ckpt), 1)),
+                                 n_ckpt, _fld(plan, u0, "u0"), _fld(plan, uN, "uN"), _stream(stream)))
 
 
 def npo_adjoint_run(plan, ws, ckpt, n_ckpt, lamN, lam0, stream=None):
     c = _I64()
-    _check(lib().npo_adjoint_run(plan, _ptr(ws), _ptr(ckpt), n_ckpt, _ptr(lamN), _ptr(lam0), ctypes.byref(c),
+    _check(lib().npo_adjoint_run(plan, _wsp(plan, ws), _fld(plan, ckpt, "checkpoint arena", max(int(n_ckpt), 1)),
+                                 n_ckpt, _fld(plan, lamN, "lamN"), _fld(plan, lam0, "lam0"), ctypes.byref(c),
                                  _stream(stream)))
     return c.value
 
@@ -189,28 +249,30 @@ def npo_ckpt_count(nsteps, n_ckpt):
 
 
 def npo_inner(plan, ws, a, b, out_dev, stream=None):
-    _check(lib().npo_inner(plan, _ptr(ws), _ptr(a), _ptr(b), _ptr(out_dev), _stream(stream)))
+    _check(lib().npo_inner(plan, _wsp(plan, ws), _fld(plan, a, "a"), _fld(plan, b, "b"), _scal(out_dev, "out_dev"),
+                           _stream(stream)))
 
 
 def npo_project(plan, ws, u, out, stream=None):
-    _check(lib().npo_project(plan, _ptr(ws), _ptr(u), _ptr(out), _stream(stream)))
+    _check(lib().npo_project(plan, _wsp(plan, ws), _fld(plan, u, "u"), _fld(plan, out, "out"), _stream(stream)))
 
 
-def npo_update(plan, ws, u0, udag, e0, alpha, e0dag, c0, u_new, stream=None):
-    _check(lib().npo_update(plan, _ptr(ws), _ptr(u0), _ptr(udag), e0, alpha, e0dag, c0, _ptr(u_new),
-                            _stream(stream)))
+def npo_update(plan, ws, u0, g, e0, alpha, u_new, info_dev, stream=None):
+    _check(lib().npo_update(plan, _wsp(plan, ws), _fld(plan, u0, "u0"), _fld(plan, g, "g"), e0, alpha,
+                            _fld(plan, u_new, "u_new"), _scal(info_dev, "info_dev", 5), _stream(stream)))
 
 
 def npo_iterate(plan, ws, ckpt, n_ckpt, u0, uN, e0, tol=1e-8, max_halvings=30, stream=None):
     st = np.zeros(8)
-    _check(lib().npo_iterate(plan, _ptr(ws), _ptr(ckpt), n_ckpt, _ptr(u0), _ptr(uN), e0, tol, max_halvings,
+    _check(lib().npo_iterate(plan, _wsp(plan, ws), _fld(plan, ckpt, "checkpoint arena", max(int(n_ckpt), 1)),
+                             n_ckpt, _fld(plan, u0, "u0"), _fld(plan, uN, "uN"), e0, tol, max_halvings,
                              st.ctypes.data_as(_DP), _stream(stream)))
     keys = ("G_old", "G_new", "alpha", "alpha_max", "E0dag", "C0", "accepted", "forward_sweeps")
     return dict(zip(keys, st.tolist()))
 
 
 def npo_normalize(plan, ws, u, e0, stream=None):
-    _check(lib().npo_normalize(plan, _ptr(ws), _ptr(u), e0, _stream(stream)))
+    _check(lib().npo_normalize(plan, _wsp(plan, ws), _fld(plan, u, "u"), e0, _stream(stream)))
 
 
 def npo_plan_set_tuning(plan, zgroup, zb_fwd, zb_adj):
@@ -228,7 +290,7 @@ def npo_plan_get_tuning(plan):
 
 
 def npo_euclid_grad(plan, lam, scale, out, stream=None):
-    _check(lib().npo_euclid_grad(plan, _ptr(lam), scale, _ptr(out), _stream(stream)))
+    _check(lib().npo_euclid_grad(plan, _fld(plan, lam, "lam"), scale, _fld(plan, out, "out"), _stream(stream)))
 
 
 def npo_profile_begin(plan, stride=1):

@@ -43,13 +43,79 @@ def test_tables_match_oracle(prob):
 
 
 def test_base_flow_matches_oracle(prob):
+    """npo_base_flow writes U and dU/dr into device arrays on the stream."""
+    import torch
     P, G, u, y, f = prob
     from paper_2509_10103_amd import npo
-    for t in (0.0, 3.7, 50.0):
-        U, Om = npo.npo_base_flow(G.handle, t, P.nr)
+    U = torch.full((P.nr,), np.nan, dtype=torch.float64, device="cuda")
+    dU = torch.full((P.nr,), np.nan, dtype=torch.float64, device="cuda")
+    for t in (0.0, 3.7, 50.0, 98.17):
+        npo.npo_base_flow(G.handle, t, U, dU)
         Uo, Oo = P.base(t)
-        assert np.max(np.abs(U - Uo)) < 1e-13
-        assert np.max(np.abs(Om - Oo)) < 1e-12
+        assert np.max(np.abs(to_host(U) - Uo)) < 1e-13
+        assert np.max(np.abs(to_host(dU) + Oo)) < 1e-12
+
+
+def test_base_flow_rejects_bad_arguments(prob):
+    import torch
+    P, G, u, y, f = prob
+    from paper_2509_10103_amd import npo
+    short = torch.zeros(P.nr - 1, dtype=torch.float64, device="cuda")
+    ok = torch.zeros(P.nr, dtype=torch.float64, device="cuda")
+    with pytest.raises(npo.NpoError):
+        npo.npo_base_flow(G.handle, 1.0, short, ok)
+    with pytest.raises(npo.NpoError):
+        npo.npo_base_flow(G.handle, float("nan"), ok, ok)
+
+
+@pytest.mark.parametrize("frac", [1.0, 0.25, 0.0])
+def test_update_scalars_and_iterate_match_oracle(prob, frac):
+    """npo_update: E0dag, C0, alpha_max, lambda_+ and E_new on the device, and the
+    rescaled iterate, against the oracle's update at the same step (frac = 0
+    asks the library for alpha_max itself)."""
+    import torch
+    P, G, u, y, f = prob
+    from paper_2509_10103_amd import npo
+    from oracle import optimize as opt
+    e0 = 1e-2
+    g = opt.project(P, y) * 1e-1
+    udag = -g
+    E0d = 0.5 * P.wdot(udag, udag)
+    C0 = P.wdot(u, udag)
+    amax = opt.alpha_max(e0, E0d, C0)
+    alpha = amax * (frac if frac > 0 else 1.0)
+    ref, inf = opt.update(P, u, udag, e0, alpha)
+    info = torch.full((5,), np.nan, dtype=torch.float64, device="cuda")
+    out = G.field()
+    npo.npo_update(G.handle, G.ws, to_dev(u), to_dev(g), e0, alpha if frac > 0 else 0.0, out, info)
+    d = to_host(info)
+    assert abs(d[0] - E0d) < 1e-13 * E0d
+    assert abs(d[1] - C0) < 1e-12 * np.sqrt(2 * E0d * 2 * e0)
+    assert abs(d[2] - amax) < 1e-11 * amax
+    lam = opt.lambda_plus(alpha, e0, E0d, C0)
+    if frac < 1.0 and frac > 0.0:
+        assert abs(d[3] - lam) < 1e-10 * max(abs(lam), 1.0 / alpha)
+        assert relerr(P, to_host(out), ref) < 1e-12
+    else:
+        # at alpha_max the discriminant is zero up to rounding, and its square
+        # root turns a rounding difference of 1e-16 into ~1e-8 of lambda_+
+        assert abs(d[3] - lam) < 1e-6 / alpha
+    # the iterate is the oracle's update formula fed the library's lambda_+
+    un = (1.0 + d[3] * alpha) * u - alpha * udag
+    assert abs(d[4] - P.energy(un)) < 1e-12 * P.energy(un)
+    assert abs(d[4] - e0) < 1e-6 * e0                     # lambda_+ keeps the energy
+    assert relerr(P, to_host(out), opt.normalise(P, un, e0)) < 1e-12
+    assert abs(P.energy(to_host(out)) - e0) < 1e-13 * e0
+
+
+def test_update_rejects_aliasing(prob):
+    import torch
+    P, G, u, y, f = prob
+    from paper_2509_10103_amd import npo
+    info = torch.zeros(5, dtype=torch.float64, device="cuda")
+    a = to_dev(u)
+    with pytest.raises(npo.NpoError):
+        npo.npo_update(G.handle, G.ws, a, to_dev(y), 1e-2, 0.0, a, info)
 
 
 def test_inner_product(prob):
