@@ -119,6 +119,19 @@ npo_status npo_solve_adj(npo_plan plan, void* ws, const void* y, void* out, void
  * u_n and u_np1 may alias. */
 npo_status npo_forward_step(npo_plan plan, void* ws, const void* u_n, void* u_np1, int64_t n,
                             void* stream);
+/* The same step for callers that cannot allocate device memory (code under
+ * HIP stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * instead of a caller workspace it uses a fixed device array of
+ * NPO_SCRATCH_BYTES that the library holds on every device it runs on until
+ * the process ends.  Results are bitwise those of npo_forward_step.  The call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ * Grids whose workspace_bytes exceed NPO_SCRATCH_BYTES are rejected with
+ * NPO_EINVAL before anything is enqueued; the current device must be the
+ * plan's.  Every call on one device shares that device's array: calls that
+ * overlap on one device (several streams or threads) race and must be
+ * serialised by the caller.  u_n and u_np1 may alias. */
+#define NPO_SCRATCH_BYTES (64ll << 20)
+npo_status npo_forward_step_noalloc(npo_plan plan, const void* u_n, void* u_np1, int64_t n, void* stream);
 /* Exact discrete adjoint of that step (W inner product): lam_n = Phi'(u_n)^dag lam_np1
  * (Sec. 2 adjoint equations, integrated backward). lam_n may alias lam_np1. */
 npo_status npo_adjoint_step(npo_plan plan, void* ws, const void* u_n, const void* lam_np1,

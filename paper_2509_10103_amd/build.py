@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libnpo.so")
-SOURCES = ["npo_host.cpp", "npo_kernels.hip", "npo_transforms.hip"]
+SOURCES = ["npo_host.cpp", "npo_kernels.hip", "npo_transforms.hip", "npo_noalloc.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions anywhere in the device code

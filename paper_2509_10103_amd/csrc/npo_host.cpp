@@ -468,6 +468,9 @@ npo_status npo_plan_create(const npo_grid* grid, const npo_flow* flow, const npo
     p->dt = time->dt; p->t0 = time->t0; p->nsteps = time->nsteps; p->ncorr = time->ncorr;
     p->omega = flow->wo * flow->wo / flow->re;
     (void)hipGetDevice(&p->device);
+    // once per device: the address of the fixed workspace of the no-allocation
+    // forward step (a failure is reported by that entry point, not here)
+    (void)npo::scratch_setup(p->device);
 
     // radial tables
     std::vector<ld> r = radial_nodes(nr);
@@ -810,6 +813,22 @@ npo_status npo_solve_adj(npo_plan p, void* ws, const void* y, void* out, void* s
 
 npo_status npo_forward_step(npo_plan p, void* ws, const void* un, void* unp1, int64_t n, void* stream) {
     if (check_plan(p) || !ws || !un || !unp1) return fail(NPO_EINVAL, "null argument");
+    HIPCHK(fwd_step(*p, ws, CF(un), F(unp1), n, false, ST(stream)));
+    return NPO_OK;
+}
+
+npo_status npo_forward_step_noalloc(npo_plan p, const void* un, void* unp1, int64_t n, void* stream) {
+    if (check_plan(p) || !un || !unp1) return fail(NPO_EINVAL, "null argument");
+    if (p->ws.total > (size_t)NPO_SCRATCH_BYTES)
+        return fail(NPO_EINVAL, "npo_forward_step_noalloc: this grid needs " + std::to_string(p->ws.total) +
+                                    " workspace bytes, the fixed scratch holds " +
+                                    std::to_string((long long)NPO_SCRATCH_BYTES) + "; use npo_forward_step");
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != p->device) return fail(NPO_EINVAL, "npo_forward_step_noalloc: current device is not the plan's");
+    hipError_t se = hipSuccess;
+    void* ws = npo::scratch_ptr(dev, &se);
+    if (!ws) return hipfail(se, "npo_forward_step_noalloc: device address of the fixed scratch");
     HIPCHK(fwd_step(*p, ws, CF(un), F(unp1), n, false, ST(stream)));
     return NPO_OK;
 }

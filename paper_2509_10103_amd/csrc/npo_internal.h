@@ -156,6 +156,12 @@ hipError_t launch_project(const npo_plan_s& p, const double2* u, double2* out, h
 // out = ca*a + cb*b
 hipError_t launch_axpby(const npo_plan_s& p, double ca, const double2* a, double cb, const double2* b,
                         double2* out, hipStream_t st);
+// Fixed workspace of npo_forward_step_noalloc (npo_noalloc.hip): resolve the
+// device address of the static array on `device` (the current device) once;
+// scratch_ptr returns it (null with *err set if it was never resolved or failed).
+hipError_t scratch_setup(int device);
+void* scratch_ptr(int device, hipError_t* err);
+
 // out = s * 2 pi L_z c_m w_j * x
 hipError_t launch_wscale(const npo_plan_s& p, const double2* x, double2* out, double s, hipStream_t st);
 // Device-scalar gradient step: from sc[0] = <g,g>_W, sc[1] = <u0,g>_W write

@@ -39,6 +39,8 @@ class Info(ctypes.Structure):
                 ("dt", ctypes.c_double), ("t0", ctypes.c_double), ("nsteps", ctypes.c_int64)]
 
 
+SCRATCH_BYTES = 64 << 20     # NPO_SCRATCH_BYTES of include/npo.h
+
 _P = ctypes.c_void_p
 _D = ctypes.c_double
 _I32 = ctypes.c_int32
@@ -58,6 +60,7 @@ SIGNATURES = {
     "npo_solve": (_I32, [_P, _P, _P, _P, _P]),
     "npo_solve_adj": (_I32, [_P, _P, _P, _P, _P]),
     "npo_forward_step": (_I32, [_P, _P, _P, _P, _I64, _P]),
+    "npo_forward_step_noalloc": (_I32, [_P, _P, _P, _I64, _P]),
     "npo_adjoint_step": (_I32, [_P, _P, _P, _P, _P, _I64, _P]),
     "npo_forward_run": (_I32, [_P, _P, _P, _I32, _P, _P, _P]),
     "npo_adjoint_run": (_I32, [_P, _P, _P, _I32, _P, _P, ctypes.POINTER(_I64), _P]),
@@ -222,6 +225,11 @@ def npo_solve_adj(plan, ws, y, out, stream=None):
 def npo_forward_step(plan, ws, u_n, u_np1, n, stream=None):
     _check(lib().npo_forward_step(plan, _wsp(plan, ws), _fld(plan, u_n, "u_n"), _fld(plan, u_np1, "u_np1"), n,
                                   _stream(stream)))
+
+
+def npo_forward_step_noalloc(plan, u_n, u_np1, n, stream=None):
+    _check(lib().npo_forward_step_noalloc(plan, _fld(plan, u_n, "u_n"), _fld(plan, u_np1, "u_np1"), n,
+                                          _stream(stream)))
 
 
 def npo_adjoint_step(plan, ws, u_n, lam_np1, lam_n, n, stream=None):
