@@ -177,6 +177,7 @@ def main():
     ap.add_argument("--nsteps", type=int, default=0, help="shorter horizon (development only)")
     ap.add_argument("--ckpt", type=int, default=0, help="checkpoint slots (default: the workload's)")
     ap.add_argument("--shapes", default="", help="launch shapes zgroup,zb_fwd,zb_adj (default: tuned)")
+    ap.add_argument("--retune", action="store_true", help="time every launch shape instead of the tuning table")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--stride", type=int, default=8, help="profiler sampling stride")
@@ -225,14 +226,18 @@ def main():
         free = torch.cuda.mem_get_info()[0]
         nck = int(max(1, min(cfg["nsteps"], (free - HBM_RESERVE) // fb)))
     from paper_2509_10103_amd import tune
+    tuning = None
     if args.shapes:
         shapes = [int(x) for x in args.shapes.split(",")]
         npo.npo_plan_set_tuning(G.handle, *shapes)
     else:
-        shapes = list(tune.tune(G, cfg["nr"], cfg["nt"], cfg["nz"], save=False)[0])
+        # the committed tuning table holds the shapes measured for this grid;
+        # --retune measures them again
+        best, tuning = tune.tune(G, cfg["nr"], cfg["nt"], cfg["nz"], use_cache=not args.retune, save=False)
+        shapes = list(best)
     r = npo.npo_plan_tables(G.handle, cfg["nr"])[0]
     raw = make_raw(cfg, r, G.M, G.K, cfg["seed"])
-    u0 = torch.from_numpy(raw).to("cuda")
+    u0 = torch.from_numpy(np.ascontiguousarray(raw)).to("cuda")
     npo.npo_project(G.handle, G.ws, u0, u0)
     npo.npo_normalize(G.handle, G.ws, u0, cfg["e0"])
     arena = G.arena(nck)
@@ -334,7 +339,7 @@ def main():
         "config": {"workload": cfg["name"], "grid": [cfg["nr"], cfg["nt"], cfg["nz"]], "lz_radii": cfg["lz"],
                    "re": cfg["re"], "wo": cfg["wo"], "amp": cfg["amp"], "dt": cfg["dt"], "t0": cfg["t0"],
                    "nsteps": cfg["nsteps"], "ncorr": ncorr, "n_ckpt": nck, "recompute_per_sweep": n_rec,
-                   "launch_shapes": shapes, "e0": cfg["e0"], "seed": cfg["seed"],
+                   "launch_shapes": shapes, "tuning": tuning, "e0": cfg["e0"], "seed": cfg["seed"],
                    "steps_requested": args.steps, "warmup_requested": args.warmup, "budget_s": args.budget,
                    "run_s": round(elapsed(), 1),
                    "iteration_latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
@@ -350,34 +355,62 @@ def main():
 
 
 def bench_batch(args):
-    """Uneven instances advanced concurrently vs the plain solver run on the same
-    instances one after another (iterations are the same work either way)."""
+    """Uneven instances: their gradients (one forward and one checkpointed
+    adjoint sweep each) through the batched launches in lockstep, against the
+    plain single-instance calls on the same instances one after another (the
+    same work); and whole optimisation iterations run concurrently on host
+    threads (each instance's own launches) against the same run sequentially."""
     import torch
-    from paper_2509_10103_amd.batch import Batch, percentiles
+    from paper_2509_10103_amd.batch import Batch, LockstepBatch, percentiles
     cfgs = configs.batch_instances(64)[:args.batch_n]
     if args.nsteps:
         for c in cfgs:
             c["nsteps"] = args.nsteps
             c["n_ckpt"] = min(c["n_ckpt"], args.nsteps)
     torch.cuda.set_device(0)
+    lk = LockstepBatch(cfgs)
+    lk.gradients()                    # builds the descriptor tables and captures the step graphs
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        lk.gradients()
+    torch.cuda.synchronize()
+    wall_l = time.perf_counter() - t
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        lk.gradients_sequential()
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t
+    counted_l = args.steps * lk.counted()
+    info = lk.info()
+    print(f"[bench] lockstep gradients of {len(cfgs)} instances: {wall_l:.2f} s, sequential {wall_s:.2f} s, "
+          f"{info}", file=sys.stderr, flush=True)
+    lk.close()
+    del lk
+    torch.cuda.empty_cache()
     b = Batch(cfgs)
     for inst in b.instances:          # initial forward sweeps (untimed, as in the plain mode)
         inst.forward()
     torch.cuda.synchronize()
     wall, counted, lat = b.run(iters=args.steps)
-    print(f"[bench] batched {len(cfgs)} instances: {wall:.2f} s", file=sys.stderr, flush=True)
+    print(f"[bench] concurrent iterations of {len(cfgs)} instances: {wall:.2f} s", file=sys.stderr, flush=True)
     for inst in b.instances:
         inst.swept = False
     seq, counted_seq = b.run_sequential(iters=args.steps)
-    print(f"[bench] sequential: {seq:.2f} s", file=sys.stderr, flush=True)
+    print(f"[bench] sequential iterations: {seq:.2f} s", file=sys.stderr, flush=True)
     p50, p99 = percentiles(lat)
-    out = {"metric": "fwd+adjoint grid-point-steps/s (batched)", "value": counted / wall,
-           "unit": "grid-point-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": 0,
-           "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+    out = {"metric": "fwd+adjoint grid-point-steps/s (batched)", "value": counted_l / wall_l,
+           "unit": "grid-point-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+           "ms_per_step": wall_l / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"batch-{len(cfgs)}-uneven", "instances": len(cfgs),
-                      "plain_sequential_value": counted_seq / seq, "speedup_vs_plain": (counted / wall) /
-                      (counted_seq / seq), "iteration_latency_s": {"p50": p50, "p99": p99}}}
+                      "lockstep": {"value": counted_l / wall_l, "plain_sequential_value": counted_l / wall_s,
+                                   "speedup_vs_plain": wall_s / wall_l, "shape_classes": info["classes"],
+                                   "instances_batched": info["batched"],
+                                   "launches_per_batched_step": info["launches"]},
+                      "concurrent_iterations": {"value": counted / wall, "plain_sequential_value": counted_seq / seq,
+                                                "speedup_vs_plain": (counted / wall) / (counted_seq / seq),
+                                                "iteration_latency_s": {"p50": p50, "p99": p99}}}}
     print(json.dumps(out), flush=True)
 
 

@@ -143,6 +143,16 @@ npo_status npo_adjoint_step(npo_plan plan, void* ws, const void* u_n, const void
  * npo_adjoint_run. */
 npo_status npo_forward_run(npo_plan plan, void* ws, void* ckpt, int32_t n_ckpt, const void* u0,
                            void* uN, void* stream);
+/* The same sweep recording energy diagnostics (the growth decompositions
+ * G = E/E0, G_z = E_z/E0, G_rtheta = (E_r + E_theta)/E0 of Sec. 3-4, and the
+ * relative energy in the highest azimuthal and axial modes of the resolution
+ * criterion of Sec. 2.3) as it goes: row n / stride of hist_dev (device,
+ * 5 doubles a row, layout of npo_energy_diag) receives those of u^n for
+ * n = 0, stride, 2 stride, ... < nsteps, and row (nsteps - 1) / stride + 1 those
+ * of u^N, so hist_dev holds (nsteps - 1) / stride + 2 rows.  The checkpoints
+ * and uN are those of npo_forward_run. */
+npo_status npo_forward_run_diag(npo_plan plan, void* ws, void* ckpt, int32_t n_ckpt, const void* u0, void* uN,
+                                double* hist_dev, int32_t stride, void* stream);
 /* Backward adjoint sweep from lamN to lam0 using the checkpoints of the last
  * npo_forward_run with the same arena and n_ckpt.  *n_recompute (host) receives
  * the forward steps re-advanced from checkpoints; together with the nsteps-1
@@ -153,6 +163,48 @@ npo_status npo_adjoint_run(npo_plan plan, void* ws, void* ckpt, int32_t n_ckpt, 
 /* Host-side count of the checkpoint schedule without running it. */
 npo_status npo_ckpt_count(int64_t nsteps, int32_t n_ckpt, int64_t* n_recompute);
 
+/* Two-level checkpointing (Sec. 2.4, memory checkpoints combined with a slower
+ * tier; here pinned host memory stands in for the paper's disc files).  The
+ * horizon is cut into n_file + 1 equispaced intervals (interval i covers steps
+ * floor(i N / (n_file+1)) .. floor((i+1) N / (n_file+1)) - 1).
+ * npo_forward_run_hybrid stores the start state of every interval but the last
+ * in host_tier (caller-owned pinned host memory, hipHostMalloc, n_file fields
+ * of field_bytes) and advances those intervals without device checkpoints; the
+ * last interval is swept with the binomial device checkpoints of
+ * npo_forward_run (arena of n_ckpt fields).  npo_adjoint_run_hybrid reverses
+ * the last interval from those checkpoints, then for each earlier interval
+ * restores its start state from the host tier, re-advances it to place the
+ * device checkpoints and reverses it.  *n_recompute receives all forward
+ * advances of the adjoint sweep.  The gradient is bitwise that of
+ * npo_forward_run / npo_adjoint_run.  n_file = 0 is the device-only schedule. */
+npo_status npo_forward_run_hybrid(npo_plan plan, void* ws, void* ckpt, int32_t n_ckpt, void* host_tier,
+                                  int32_t n_file, const void* u0, void* uN, void* stream);
+npo_status npo_adjoint_run_hybrid(npo_plan plan, void* ws, void* ckpt, int32_t n_ckpt, const void* host_tier,
+                                  int32_t n_file, const void* lamN, void* lam0, int64_t* n_recompute,
+                                  void* stream);
+/* Forward advances of the hybrid adjoint sweep for n_file host checkpoints
+ * (host arithmetic only): for equal intervals of length l this is the paper's
+ * (N_F + 1) N_rec - N_init with N_rec the advances to recover an interval from
+ * n_ckpt memory checkpoints and N_init = l - 1 (the last interval's checkpoints
+ * are placed by the initial forward sweep). */
+npo_status npo_hybrid_count(int64_t nsteps, int32_t n_ckpt, int32_t n_file, int64_t* n_recompute);
+/* The number of host checkpoints n_file in [0, max_file] minimising the
+ * recovery time of Sec. 2.4, T = n_file t_io + advances(n_file) t_step, with
+ * t_io the time to restore one field from the host tier and t_step that of one
+ * forward step (both measured by the caller); *t_rec (optional) receives T. */
+npo_status npo_hybrid_plan(int64_t nsteps, int32_t n_ckpt, double t_io, double t_step, int32_t max_file,
+                           int32_t* n_file, double* t_rec);
+
+/* Energy diagnostics of a field u (deterministic fixed-order reductions):
+ * out_dev[0..2] = E_r, E_theta, E_z (E_c = <u_c, u_c>_W / 2, their sum is E(u)),
+ * out_dev[3] = energy in the modes m = M, out_dev[4] = energy in the modes
+ * |k| = K (divided by E0 these are the paper's resolution measures e_M, e_K of
+ * Sec. 2.3, read as energy fractions).  spec_dev (optional, device,
+ * (M+1)(2K+1) doubles, [m][kk] in the field's axial order) receives the energy
+ * of every stored mode (for m = 0 the modes +k and -k separately, as in
+ * <.,.>_W).  ws: workspace of workspace_bytes (reduction partials). */
+npo_status npo_energy_diag(npo_plan plan, void* ws, const void* u, double* out_dev, double* spec_dev,
+                           void* stream);
 /* out_dev[0] = <a,b>_W (deterministic fixed-order reduction). */
 npo_status npo_inner(npo_plan plan, void* ws, const void* a, const void* b, double* out_dev,
                      void* stream);
@@ -191,7 +243,10 @@ npo_status npo_iterate(npo_plan plan, void* ws, void* ckpt, int32_t n_ckpt, void
 /* Launch shapes of the transform kernels (the autotuner's knobs): zgroup =
  * fields per axial-transform block (1..3), zb_fwd / zb_adj = axial points per
  * azimuthal-transform block in the forward / adjoint products (2, 4 or 8,
- * dividing nz).  Shapes whose LDS tiles exceed 160 KiB are rejected
+ * dividing nz); zb_fwd or zb_adj = -L selects the wave-resident azimuthal
+ * kernels with L lanes per axial column (sequences in registers, cross-lane
+ * radix-2 stages): L = 8 for ntheta in {24, 48, 96} and nz a multiple of 8,
+ * L = 16 for ntheta in {48, 96} and nz a multiple of 4.  Shapes whose LDS tiles exceed 160 KiB are rejected
  * (NPO_EINVAL).  Results do not depend on the shapes. */
 npo_status npo_plan_set_tuning(npo_plan plan, int32_t zgroup, int32_t zb_fwd, int32_t zb_adj);
 npo_status npo_plan_get_tuning(npo_plan plan, int32_t* zgroup, int32_t* zb_fwd, int32_t* zb_adj);
@@ -214,6 +269,45 @@ npo_status npo_euclid_grad(npo_plan plan, const void* lam, double scale, void* o
 
 /* u *= sqrt(e0 / E(u)), E(u) = <u,u>_W / 2, on the device. */
 npo_status npo_normalize(npo_plan plan, void* ws, void* u, double e0, void* stream);
+
+/* Batched instances (many optimisation instances of uneven grid and parameter
+ * sizes advanced together).  A batch groups its plans into shape classes
+ * (equal nr, ntheta, nz, corrector passes, launch shapes and device); a
+ * batched step issues each kernel of the step once per class for all of the
+ * class's instances, every block reading its instance's plan constants,
+ * buffers and evaluation time from a device work-descriptor table (built on
+ * the first step with a given set of workspaces and kept by the batch); a
+ * class whose kernels have no batched form (transform lengths without the
+ * pruned compiled kernels, the wave-resident azimuthal kernels) runs its
+ * instances' steps one after another instead.  The plans must share nsteps,
+ * and stay owned by the caller until npo_batch_destroy.  Results are bitwise
+ * those of the instances' own calls. */
+typedef struct npo_batch_s* npo_batch;
+npo_status npo_batch_create(const npo_plan* plans, int32_t n, npo_batch* out);
+npo_status npo_batch_destroy(npo_batch batch);
+/* Shape classes, instances advanced by batched launches, and kernel launches
+ * of the last batched step (independent of the instance count for batched
+ * classes). */
+npo_status npo_batch_info(npo_batch batch, int32_t* n_classes, int32_t* n_batched, int32_t* launches);
+/* Every instance's device step index (the evaluation time t0 + n dt of its
+ * next step) set to n. */
+npo_status npo_batch_set_steps(npo_batch batch, void* const* ws, int64_t n, void* stream);
+/* One step of every instance (Sec. 2.3 step, or its exact adjoint):
+ * phase 0: states[i] <- Phi(states[i]) at each instance's step index, which
+ * then increases by one; phase 1: states[2i+1] <- Phi'(states[2i])^dag
+ * states[2i+1] at the step index, which then decreases by one.  ws[i] is
+ * instance i's workspace (its `cur` and `lam` fields carry the states during
+ * the step). */
+npo_status npo_batch_step(npo_batch batch, void* const* states, void* const* ws, int32_t phase, void* stream);
+/* Checkpointed forward and adjoint sweeps of every instance in lockstep (one
+ * binomial schedule, Sec. 2.4, for the shared nsteps and n_ckpt; advances and
+ * adjoint steps are batched steps replayed from one captured graph per phase),
+ * with the contracts of npo_forward_run / npo_adjoint_run per instance:
+ * ckpt[i] an arena of n_ckpt fields of instance i. */
+npo_status npo_batch_forward_run(npo_batch batch, void* const* ws, void* const* ckpt, int32_t n_ckpt,
+                                 void* const* u0, void* const* uN, void* stream);
+npo_status npo_batch_adjoint_run(npo_batch batch, void* const* ws, void* const* ckpt, int32_t n_ckpt,
+                                 void* const* lamN, void* const* lam0, int64_t* n_recompute, void* stream);
 
 /* Sampling profiler: from npo_profile_begin until npo_profile_read, every
  * stride-th launch of each kernel family is bracketed by HIP events recorded

@@ -87,6 +87,23 @@ class Pipe:
     def energy(self, u):
         return 0.5 * self.wdot(u, u)
 
+    def component_energies(self, u):
+        """E_r, E_theta, E_z: half the W inner product of each component with
+        itself (their sum is E(u)); the decomposition of the growth into its
+        axial and cross-sectional parts (Sec. 3-4)."""
+        return np.array([0.5 * 2.0 * np.pi * self.lz *
+                         np.einsum('j,m,jmk->', self.w, self.cm, np.abs(u[c]) ** 2) for c in range(3)])
+
+    def mode_energies(self, u):
+        """Energy of every stored mode (m, kk): 1/2 2 pi L_z c_m sum_j w_j |u|^2."""
+        return np.pi * self.lz * self.cm[:, None] * np.einsum('j,cjmk->mk', self.w, np.abs(u) ** 2)
+
+    def band_energies(self, u):
+        """Energy in the highest azimuthal modes m = M and in the highest axial
+        modes |k| = K (the quantities of the resolution criterion, Sec. 2.3)."""
+        e = self.mode_energies(u)
+        return e[self.M, :].sum(), e[:, self.K].sum() + e[:, self.nk - self.K].sum()
+
     def time(self, n):
         return self.tau0 + n * self.dt
 

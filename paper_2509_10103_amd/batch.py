@@ -1,14 +1,22 @@
 """Batched optimisation instances of uneven size on one GPU.
 
-Each instance owns a plan (its constant tables and operator caches), a
-workspace, a checkpoint arena and a HIP stream; launch shapes come from the
-autotuner, cached per grid shape, and the sweeps replay captured step graphs
-(one graph launch per forward advance or adjoint step).  ``Batch.run`` advances every instance by
-optimisation iterations (Sec. 2.1-2.2) concurrently: one host thread per
-instance group issues that group's work on its own streams (the library
-calls release the GIL), so kernels of small instances overlap on the device
-instead of waiting behind one another.  Results are bitwise those of the same
-instance run alone: each instance's arithmetic and launch order are fixed.
+Two ways of running many instances:
+
+* ``LockstepBatch``: the instances' checkpointed sweeps advance in lockstep
+  through the library's batched launches (npo_batch_*): every kernel of a
+  step is launched once per shape class for all of its instances, each block
+  reading its instance's constants, buffers and evaluation time from a device
+  work-descriptor table, and each batched step is one replay of a captured
+  graph.  The instances share the horizon and the number of checkpoint slots
+  (one schedule).
+* ``Batch``: each instance owns a plan, workspace, arena and HIP stream and
+  runs whole optimisation iterations (Sec. 2.1-2.2) on its own host thread
+  (the library calls release the GIL), its sweeps replaying captured step
+  graphs, so the kernels of small instances overlap on the device.
+
+Launch shapes come from the autotuner, cached per grid shape.  Results are
+bitwise those of the same instance run alone: each instance's arithmetic and
+launch order are fixed.
 """
 import threading
 import time
@@ -35,7 +43,7 @@ class Instance:
             self.arena = self.plan.arena(self.n_ckpt)
             r = npo.npo_plan_tables(self.plan.handle, cfg["nr"])[0]
             raw = synth.solenoidal_modes(r, self.plan.M, self.plan.K, cfg["lz"], cfg["seed"])
-            self.u0 = torch.from_numpy(raw).to(device)
+            self.u0 = torch.from_numpy(np.ascontiguousarray(raw)).to(device)
             npo.npo_project(self.plan.handle, self.plan.ws, self.u0, self.u0, stream=self.stream.cuda_stream)
             npo.npo_normalize(self.plan.handle, self.plan.ws, self.u0, cfg["e0"], stream=self.stream.cuda_stream)
             self.uN = self.plan.field()
@@ -134,3 +142,59 @@ class Batch:
 def percentiles(lat):
     a = np.asarray(lat) if len(lat) else np.zeros(1)
     return float(np.percentile(a, 50)), float(np.percentile(a, 99))
+
+
+class LockstepBatch:
+    """Forward and adjoint sweeps of many instances through batched launches."""
+
+    def __init__(self, cfgs, device="cuda", autotune=True):
+        import torch
+        self.cfgs = cfgs
+        self.nsteps = cfgs[0]["nsteps"]
+        if any(c["nsteps"] != self.nsteps for c in cfgs):
+            raise ValueError("lockstep instances share the horizon")
+        self.n_ckpt = int(max(1, min(min(c["n_ckpt"] or c["nsteps"] for c in cfgs), self.nsteps)))
+        self.plans, self.u0, self.uN, self.lam, self.arena = [], [], [], [], []
+        for c in cfgs:
+            G = npo.Plan(c["nr"], c["nt"], c["nz"], c["lz"], c["re"], c["wo"], c["amp"], c["dt"], c["t0"],
+                         c["nsteps"], c.get("ncorr", 2), device=device)
+            if autotune:
+                tuner.tune(G, c["nr"], c["nt"], c["nz"], batched=True)
+            r = npo.npo_plan_tables(G.handle, c["nr"])[0]
+            raw = synth.solenoidal_modes(r, G.M, G.K, c["lz"], c["seed"])
+            u0 = torch.from_numpy(np.ascontiguousarray(raw)).to(device)
+            npo.npo_project(G.handle, G.ws, u0, u0)
+            npo.npo_normalize(G.handle, G.ws, u0, c["e0"])
+            self.plans.append(G)
+            self.u0.append(u0)
+            self.uN.append(G.field())
+            self.lam.append(G.field())
+            self.arena.append(G.arena(self.n_ckpt))
+        self.handles = [G.handle for G in self.plans]
+        self.ws = [G.ws for G in self.plans]
+        self.batch = npo.npo_batch_create(self.handles)
+        self.points = [c["nr"] * c["nt"] * c["nz"] for c in cfgs]
+
+    def gradients(self):
+        """One forward and one adjoint sweep of every instance (lockstep)."""
+        npo.npo_batch_forward_run(self.batch, self.handles, self.ws, self.arena, self.n_ckpt, self.u0, self.uN)
+        return npo.npo_batch_adjoint_run(self.batch, self.handles, self.ws, self.arena, self.n_ckpt, self.uN,
+                                         self.lam)
+
+    def gradients_sequential(self):
+        """The same sweeps with the plain single-instance calls, one instance after another."""
+        for G, a, u0, uN, lam in zip(self.plans, self.arena, self.u0, self.uN, self.lam):
+            npo.npo_forward_run(G.handle, G.ws, a, self.n_ckpt, u0, uN)
+            npo.npo_adjoint_run(G.handle, G.ws, a, self.n_ckpt, uN, lam)
+
+    def counted(self):
+        """Grid-point-steps of one gradient of every instance (a forward and an adjoint step per point)."""
+        return 2 * self.nsteps * sum(self.points)
+
+    def info(self):
+        return npo.npo_batch_info(self.batch)
+
+    def close(self):
+        npo.npo_batch_destroy(self.batch)
+        for G in self.plans:
+            G.close()

@@ -424,14 +424,14 @@ npo_status check_plan(npo_plan p) {
 namespace npo {
 void prof_begin(const npo_plan_s& p, int kid, hipStream_t st) {
     Profiler& f = p.prof;
-    if (!f.on) return;
+    if (!f.on || recorder()) return;
     const long long n = f.launches[kid];
     if (n % f.stride == 0 && f.used[kid] < PROF_SLOTS)
         (void)hipEventRecord(f.ev[(kid * PROF_SLOTS + f.used[kid]) * 2], st);
 }
 void prof_end(const npo_plan_s& p, int kid, hipStream_t st) {
     Profiler& f = p.prof;
-    if (!f.on) return;
+    if (!f.on || recorder()) return;
     const long long n = f.launches[kid]++;
     if (n % f.stride == 0 && f.used[kid] < PROF_SLOTS) {
         (void)hipEventRecord(f.ev[(kid * PROF_SLOTS + f.used[kid]) * 2 + 1], st);
@@ -726,7 +726,7 @@ npo_status npo_plan_create(const npo_grid* grid, const npo_flow* flow, const npo
     L.trial = take(fb); L.trialN = take(fb);
     L.zbuf = take(9 * gb); L.tbuf = take(6 * gb);
     for (int c = 0; c < npo::NCORR_MAX; ++c) L.zst[c] = c < p->ncorr ? take(6 * gb) : 0;
-    L.red = take((npo::NR_MAX * 4 + 512) * 8);
+    L.red = take((npo::NR_MAX * 4 + 512 + 5 * 256) * 8);   // reductions, scalars, diagnostics partials
     L.step = take(256);
     L.total = off;
     *out = p;
@@ -850,14 +850,27 @@ npo_status npo_ckpt_count(int64_t nsteps, int32_t n_ckpt, int64_t* n_recompute) 
     return NPO_OK;
 }
 
-npo_status npo_forward_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const void* u0, void* uN, void* stream) {
-    if (check_plan(p) || !ws || !ckpt || !u0 || !uN) return fail(NPO_EINVAL, "null argument");
+// Diagnostics partials sit after the reduction partials and scalars.
+static double* diag_partial(const WsPtrs& w) { return w.red + npo::NR_MAX * 4 + 512; }
+
+// The forward sweep; with hist, the energy diagnostics of u^n are written to
+// row n / stride of hist (5 doubles a row) for n = 0, stride, 2 stride, ... < N,
+// and those of u^N to row (N - 1) / stride + 1.
+// The sweep covers steps n0 .. n0 + nseg - 1 of the plan's horizon (the whole
+// horizon for the exported runs, one interval of the hybrid tier otherwise);
+// with last_step false the final step (whose result only the forward output
+// needs) is skipped.
+static npo_status forward_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const void* u0, void* uN,
+                              double* hist, int32_t stride, void* stream, long long n0 = 0, long long nseg = -1,
+                              bool last_step = true) {
+    if (check_plan(p) || !ws || !ckpt || !u0 || (!uN && last_step)) return fail(NPO_EINVAL, "null argument");
     if (nck < 1) return fail(NPO_EINVAL, "n_ckpt must be >= 1");
+    if (nseg < 0) nseg = p->nsteps;
     const hipStream_t st = ST(stream);
     const size_t fb = (size_t)3 * p->nr * p->mp1 * p->nk * 16;
     WsPtrs w = wsptrs(*p, ws);
     auto slot = [&](long long s) { return reinterpret_cast<double2*>(static_cast<char*>(ckpt) + s * fb); };
-    std::vector<Act> acts = schedule(p->nsteps, nck);
+    std::vector<Act> acts = schedule(nseg, nck);
     const size_t fa = first_adj(acts);
     const bool gr = p->use_graphs && !p->prof.on;
     if (gr && p->graph_ws != ws) HIPCHK(build_graphs(*p, ws));
@@ -868,6 +881,13 @@ npo_status npo_forward_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const 
     HIPCHK(hipMemcpyAsync(slot(0), u0, fb, hipMemcpyDeviceToDevice, st));
     const double2* where = slot(0);
     long long pos = 0;
+    auto record = [&](const double2* u, long long n) -> hipError_t {
+        if (!hist || n0 != 0 || nseg != p->nsteps) return hipSuccess;
+        if (n != p->nsteps && n % stride) return hipSuccess;
+        const long long row = n == p->nsteps ? (p->nsteps - 1) / stride + 1 : n / stride;
+        return npo::launch_diag(*p, u, diag_partial(w), hist + 5 * row, nullptr, st);
+    };
+    HIPCHK(record(where, 0));
     bool aux = false, synced = false;   // synced: the device step index equals pos
     for (size_t i = 0; i < fa; ++i) {
         const Act& a = acts[i];
@@ -876,16 +896,17 @@ npo_status npo_forward_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const 
                 double2* out = w.cur;
                 if (k + 1 == a.a && i + 1 < fa && acts[i + 1].kind == A_STORE) out = slot(acts[i + 1].a);
                 if (gr && aux && where == w.cur && out == w.cur) {
-                    if (!synced) HIPCHK(npo::launch_step_index(w.step, pos, 0, st));
+                    if (!synced) HIPCHK(npo::launch_step_index(w.step, n0 + pos, 0, st));
                     HIPCHK(hipGraphLaunch(p->g_fwd, st));
                     synced = true;
                 } else {
-                    HIPCHK(fwd_step(*p, ws, where, out, pos, aux, st));
+                    HIPCHK(fwd_step(*p, ws, where, out, n0 + pos, aux, st));
                     synced = false;
                 }
                 where = out;
                 aux = true;
                 ++pos;
+                HIPCHK(record(where, pos));
             }
         } else if (a.kind == A_STORE) {
             if (a.b != pos) return fail(NPO_ESTATE, "schedule store position mismatch");
@@ -893,29 +914,49 @@ npo_status npo_forward_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const 
             where = slot(a.a);
         }
     }
-    if (pos != p->nsteps - 1) return fail(NPO_ESTATE, "schedule descent did not reach the last step");
+    if (pos != nseg - 1) return fail(NPO_ESTATE, "schedule descent did not reach the last step");
     // u^{N-1} is left in cur for the first adjoint step; the last step goes to uN
     if (where != w.cur) HIPCHK(hipMemcpyAsync(w.cur, where, fb, hipMemcpyDeviceToDevice, st));
-    HIPCHK(fwd_step(*p, ws, w.cur, F(uN), pos, aux, st));
+    if (!last_step) return NPO_OK;
+    HIPCHK(fwd_step(*p, ws, w.cur, F(uN), n0 + pos, aux, st));
+    HIPCHK(record(CF(uN), p->nsteps));
     return NPO_OK;
 }
 
-npo_status npo_adjoint_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const void* lamN, void* lam0,
-                           int64_t* n_recompute, void* stream) {
+npo_status npo_forward_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const void* u0, void* uN, void* stream) {
+    return forward_run(p, ws, ckpt, nck, u0, uN, nullptr, 1, stream);
+}
+
+npo_status npo_forward_run_diag(npo_plan p, void* ws, void* ckpt, int32_t nck, const void* u0, void* uN,
+                                double* hist_dev, int32_t stride, void* stream) {
+    if (!hist_dev || stride < 1) return fail(NPO_EINVAL, "hist_dev must be given and stride >= 1");
+    return forward_run(p, ws, ckpt, nck, u0, uN, hist_dev, stride, stream);
+}
+
+npo_status npo_energy_diag(npo_plan p, void* ws, const void* u, double* out_dev, double* spec_dev, void* stream) {
+    if (check_plan(p) || !ws || !u || !out_dev) return fail(NPO_EINVAL, "null argument");
+    WsPtrs w = wsptrs(*p, ws);
+    HIPCHK(npo::launch_diag(*p, CF(u), diag_partial(w), out_dev, spec_dev, ST(stream)));
+    return NPO_OK;
+}
+
+static npo_status adjoint_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const void* lamN, void* lam0,
+                              int64_t* n_recompute, void* stream, long long n0 = 0, long long nseg = -1) {
     if (check_plan(p) || !ws || !ckpt || !lamN || !lam0) return fail(NPO_EINVAL, "null argument");
     if (nck < 1) return fail(NPO_EINVAL, "n_ckpt must be >= 1");
+    if (nseg < 0) nseg = p->nsteps;
     const hipStream_t st = ST(stream);
     const size_t fb = (size_t)3 * p->nr * p->mp1 * p->nk * 16;
     WsPtrs w = wsptrs(*p, ws);
     auto slot = [&](long long s) { return reinterpret_cast<double2*>(static_cast<char*>(ckpt) + s * fb); };
-    std::vector<Act> acts = schedule(p->nsteps, nck);
+    std::vector<Act> acts = schedule(nseg, nck);
     const bool gr = p->use_graphs && !p->prof.on;
     if (gr && p->graph_ws != ws) HIPCHK(build_graphs(*p, ws));
     HIPCHK(hipMemcpyAsync(w.lam, lamN, fb, hipMemcpyDeviceToDevice, st));
     // the state lives at `where` (cur or a slot), as in the forward sweep: a
     // restore only points at its slot
     const double2* where = w.cur;
-    long long pos = p->nsteps - 1, adv = 0;
+    long long pos = nseg - 1, adv = 0;
     bool aux = false, synced = false;   // synced: the device step index equals pos
     for (size_t i = first_adj(acts); i < acts.size(); ++i) {
         const Act& a = acts[i];
@@ -929,11 +970,11 @@ npo_status npo_adjoint_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const 
                 double2* out = w.cur;
                 if (k + 1 == a.a && i + 1 < acts.size() && acts[i + 1].kind == A_STORE) out = slot(acts[i + 1].a);
                 if (gr && aux && where == w.cur && out == w.cur) {
-                    if (!synced) HIPCHK(npo::launch_step_index(w.step, pos, 0, st));
+                    if (!synced) HIPCHK(npo::launch_step_index(w.step, n0 + pos, 0, st));
                     HIPCHK(hipGraphLaunch(p->g_fwd, st));
                     synced = true;
                 } else {
-                    HIPCHK(fwd_step(*p, ws, where, out, pos, aux, st));
+                    HIPCHK(fwd_step(*p, ws, where, out, n0 + pos, aux, st));
                     synced = false;
                 }
                 where = out;
@@ -950,11 +991,11 @@ npo_status npo_adjoint_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const 
             // after an advance aux0 already holds the vorticity parts of u^pos
             if (gr && where == w.cur) {
                 if (!aux) HIPCHK(npo::launch_curl_aux(*p, w.cur, w.aux0, st));
-                if (!synced) HIPCHK(npo::launch_step_index(w.step, pos, 0, st));
+                if (!synced) HIPCHK(npo::launch_step_index(w.step, n0 + pos, 0, st));
                 HIPCHK(hipGraphLaunch(p->g_adj, st));
                 synced = true;
             } else {
-                HIPCHK(adj_step(*p, ws, where, w.lam, w.lam, pos, st, nullptr, aux));
+                HIPCHK(adj_step(*p, ws, where, w.lam, w.lam, n0 + pos, st, nullptr, aux));
                 synced = false;
             }
             aux = false;   // the adjoint step reuses aux0 for its own work
@@ -962,6 +1003,118 @@ npo_status npo_adjoint_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const 
     }
     HIPCHK(hipMemcpyAsync(lam0, w.lam, fb, hipMemcpyDeviceToDevice, st));
     if (n_recompute) *n_recompute = adv;
+    return NPO_OK;
+}
+
+npo_status npo_adjoint_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const void* lamN, void* lam0,
+                           int64_t* n_recompute, void* stream) {
+    return adjoint_run(p, ws, ckpt, nck, lamN, lam0, n_recompute, stream);
+}
+
+// ------------------------------------------------ hybrid (host-tier) checkpoints
+// Interval i of n_file + 1 equispaced intervals: steps [bound(i), bound(i + 1)).
+static long long hybrid_bound(long long nsteps, int n_file, int i) {
+    return (long long)((__int128)nsteps * i / (n_file + 1));
+}
+
+npo_status npo_forward_run_hybrid(npo_plan p, void* ws, void* ckpt, int32_t nck, void* host_tier, int32_t n_file,
+                                  const void* u0, void* uN, void* stream) {
+    if (check_plan(p) || !ws || !ckpt || !u0 || !uN || (n_file > 0 && !host_tier))
+        return fail(NPO_EINVAL, "null argument");
+    if (n_file < 0 || n_file >= p->nsteps) return fail(NPO_EINVAL, "n_file must be in [0, nsteps)");
+    const hipStream_t st = ST(stream);
+    const size_t fb = (size_t)3 * p->nr * p->mp1 * p->nk * 16;
+    const void* in = u0;
+    for (int i = 0; i <= n_file; ++i) {
+        const long long b0 = hybrid_bound(p->nsteps, n_file, i), b1 = hybrid_bound(p->nsteps, n_file, i + 1);
+        if (i < n_file) {
+            // the interval's start state goes to the host tier; the interval is
+            // advanced without device checkpoints (one slot)
+            HIPCHK(hipMemcpyAsync(static_cast<char*>(host_tier) + (size_t)i * fb, in, fb, hipMemcpyDeviceToHost,
+                                  st));
+            npo_status s = forward_run(p, ws, ckpt, 1, in, uN, nullptr, 1, stream, b0, b1 - b0);
+            if (s) return s;
+        } else {
+            // the last interval keeps its binomial device checkpoints for the adjoint sweep
+            npo_status s = forward_run(p, ws, ckpt, nck, in, uN, nullptr, 1, stream, b0, b1 - b0);
+            if (s) return s;
+        }
+        in = uN;
+    }
+    return NPO_OK;
+}
+
+npo_status npo_adjoint_run_hybrid(npo_plan p, void* ws, void* ckpt, int32_t nck, const void* host_tier,
+                                  int32_t n_file, const void* lamN, void* lam0, int64_t* n_recompute, void* stream) {
+    if (check_plan(p) || !ws || !ckpt || !lamN || !lam0 || (n_file > 0 && !host_tier))
+        return fail(NPO_EINVAL, "null argument");
+    if (n_file < 0 || n_file >= p->nsteps) return fail(NPO_EINVAL, "n_file must be in [0, nsteps)");
+    const hipStream_t st = ST(stream);
+    const size_t fb = (size_t)3 * p->nr * p->mp1 * p->nk * 16;
+    WsPtrs w = wsptrs(*p, ws);
+    int64_t total = 0;
+    const void* lin = lamN;
+    for (int i = n_file; i >= 0; --i) {
+        const long long b0 = hybrid_bound(p->nsteps, n_file, i), b1 = hybrid_bound(p->nsteps, n_file, i + 1);
+        if (i < n_file) {
+            // restore the interval's start state from the host tier and place its
+            // device checkpoints (the interval's last step is not needed)
+            HIPCHK(hipMemcpyAsync(w.tmp, static_cast<const char*>(host_tier) + (size_t)i * fb, fb,
+                                  hipMemcpyHostToDevice, st));
+            npo_status s = forward_run(p, ws, ckpt, nck, w.tmp, nullptr, nullptr, 1, stream, b0, b1 - b0, false);
+            if (s) return s;
+            total += b1 - b0 - 1;
+        }
+        int64_t rec = 0;
+        npo_status s = adjoint_run(p, ws, ckpt, nck, lin, lam0, &rec, stream, b0, b1 - b0);
+        if (s) return s;
+        total += rec;
+        lin = lam0;
+    }
+    if (n_recompute) *n_recompute = total;
+    return NPO_OK;
+}
+
+// Forward advances of the hybrid adjoint sweep: every interval but the last
+// is re-advanced to place its device checkpoints (its length less one step),
+// and each interval's adjoint sweep re-advances from them.
+static long long hybrid_advances(long long nsteps, int n_ckpt, int n_file) {
+    auto advances = [&](long long l) -> long long {      // advances to reverse l steps with n_ckpt slots
+        if (l <= 1) return 0;
+        std::vector<Act> acts = schedule(l, n_ckpt);
+        long long c = 0;
+        for (size_t i = first_adj(acts); i < acts.size(); ++i)
+            if (acts[i].kind == A_ADV) c += acts[i].a;
+        return c;
+    };
+    long long steps = 0;
+    for (int i = 0; i <= n_file; ++i) {
+        const long long l = hybrid_bound(nsteps, n_file, i + 1) - hybrid_bound(nsteps, n_file, i);
+        steps += advances(l) + (i < n_file ? l - 1 : 0);
+    }
+    return steps;
+}
+
+npo_status npo_hybrid_count(int64_t nsteps, int32_t n_ckpt, int32_t n_file, int64_t* n_recompute) {
+    if (nsteps < 1 || n_ckpt < 1 || n_file < 0 || n_file >= nsteps || !n_recompute)
+        return fail(NPO_EINVAL, "bad argument");
+    *n_recompute = hybrid_advances(nsteps, n_ckpt, n_file);
+    return NPO_OK;
+}
+
+npo_status npo_hybrid_plan(int64_t nsteps, int32_t n_ckpt, double t_io, double t_step, int32_t max_file,
+                           int32_t* n_file, double* t_rec) {
+    if (nsteps < 1 || n_ckpt < 1 || max_file < 0 || !(t_io >= 0) || !(t_step > 0) || !n_file)
+        return fail(NPO_EINVAL, "bad argument");
+    double best = std::numeric_limits<double>::infinity();
+    int bestf = 0;
+    const int top = (int)std::min<long long>(max_file, nsteps - 1);
+    for (int f = 0; f <= top; ++f) {
+        const double t = f * t_io + (double)hybrid_advances(nsteps, n_ckpt, f) * t_step;
+        if (t < best) { best = t; bestf = f; }
+    }
+    *n_file = bestf;
+    if (t_rec) *t_rec = best;
     return NPO_OK;
 }
 
@@ -1082,6 +1235,7 @@ npo_status npo_iterate(npo_plan p, void* ws, void* ckpt, int32_t nck, void* u0, 
 npo_status npo_plan_set_tuning(npo_plan p, int32_t zgroup, int32_t zb_fwd, int32_t zb_adj) {
     if (check_plan(p)) return NPO_EINVAL;
     auto ok_zb = [&](int zb, int adj) {
+        if (zb < 0) return npo::theta_wave_ok(p->nt, p->nz, -zb);   // the wave-resident kernels
         if (zb != 2 && zb != 4 && zb != 8) return false;
         if (p->nz % zb) return false;
         return npo::theta_lds(*p, zb, adj) <= 160 * 1024;
@@ -1158,6 +1312,359 @@ npo_status npo_normalize(npo_plan p, void* ws, void* u, double e0, void* stream)
     double* en = w.red + npo::NR_MAX * 4 + 256;
     HIPCHK(npo::launch_wdot(*p, CF(u), CF(u), w.red, en, ST(stream)));
     HIPCHK(npo::launch_rescale(*p, F(u), en, 2.0 * e0, ST(stream)));
+    return NPO_OK;
+}
+
+// ================================================================ batches
+// Instances of uneven shape advanced together (one launch per kernel for
+// every instance of a shape class, each instance's constants, buffers and
+// evaluation time read from a device work-descriptor table).
+}  // extern "C"
+
+struct npo_batch_s {
+    std::vector<npo_plan> plans;
+    std::vector<std::vector<int>> classes;      // instance indices per shape class
+    struct Phase {
+        std::vector<void*> key;                 // workspace pointers the tables were built for
+        // per class: recorded launch sequence, descriptor table [site][instance], step table
+        std::vector<std::vector<std::function<void(const npo::BDesc*, int, hipStream_t)>>> launch;
+        std::vector<npo::BDesc*> dtab;
+        std::vector<char> batched;              // 0: the class falls back to per-instance launches
+        hipGraphExec_t graph = nullptr;
+    } ph[2];
+    std::vector<npo::BDesc*> steptab;           // per class: one descriptor per instance (step index)
+    std::vector<void*> step_key;
+    hipStream_t cap = nullptr;
+    int launches = 0;                           // kernel launches of the last batched step
+};
+
+namespace {
+
+bool same_class(const npo_plan_s& a, const npo_plan_s& b) {
+    return a.nr == b.nr && a.nt == b.nt && a.nz == b.nz && a.ncorr == b.ncorr && a.zgroup == b.zgroup &&
+           a.zb_theta_fwd == b.zb_theta_fwd && a.zb_theta_adj == b.zb_theta_adj && a.device == b.device;
+}
+
+void drop_phase(npo_batch_s::Phase& f) {
+    for (npo::BDesc* d : f.dtab)
+        if (d) (void)hipFree(d);
+    f.dtab.clear();
+    f.launch.clear();
+    f.batched.clear();
+    f.key.clear();
+    if (f.graph) (void)hipGraphExecDestroy(f.graph);
+    f.graph = nullptr;
+}
+
+// The per-instance buffers of the batched steps: the state advances in the
+// workspace's `cur`, the adjoint field in its `lam`, the step index in `step`.
+npo_status batch_tables(npo_batch_s& b, void* const* ws, hipStream_t st) {
+    std::vector<void*> key(ws, ws + b.plans.size());
+    if (b.step_key == key && b.ph[0].key == key && b.ph[1].key == key) return NPO_OK;
+    for (auto& f : b.ph) drop_phase(f);
+    for (npo::BDesc* d : b.steptab)
+        if (d) (void)hipFree(d);
+    b.steptab.clear();
+    for (int phase = 0; phase < 2; ++phase) {
+        npo_batch_s::Phase& f = b.ph[phase];
+        for (const std::vector<int>& cl : b.classes) {
+            std::vector<npo::Recorder> rec(cl.size());
+            bool ok = true;
+            for (size_t q = 0; q < cl.size(); ++q) {
+                const npo_plan_s& p = *b.plans[cl[q]];
+                WsPtrs w = wsptrs(p, ws[cl[q]]);
+                npo::recorder() = &rec[q];
+                hipError_t e = phase == 0 ? fwd_step(p, ws[cl[q]], w.cur, w.cur, 0, false, st, w.step)
+                                          : adj_step(p, ws[cl[q]], w.cur, w.lam, w.lam, 0, st, w.step, false);
+                npo::recorder() = nullptr;
+                if (e != hipSuccess) return hipfail(e, "recording a batched step");
+                ok = ok && rec[q].ok && rec[q].desc.size() == rec[0].desc.size();
+            }
+            f.batched.push_back(ok ? 1 : 0);
+            f.launch.push_back(ok ? rec[0].launch : decltype(rec[0].launch){});
+            npo::BDesc* dt = nullptr;
+            if (ok) {
+                const size_t ns = rec[0].desc.size(), nb = cl.size();
+                std::vector<npo::BDesc> host(ns * nb);
+                for (size_t sidx = 0; sidx < ns; ++sidx)
+                    for (size_t q = 0; q < nb; ++q) host[sidx * nb + q] = rec[q].desc[sidx];
+                HIPCHK(hipMalloc(&dt, host.size() * sizeof(npo::BDesc)));
+                HIPCHK(hipMemcpy(dt, host.data(), host.size() * sizeof(npo::BDesc), hipMemcpyHostToDevice));
+            }
+            f.dtab.push_back(dt);
+        }
+        f.key = key;
+    }
+    for (const std::vector<int>& cl : b.classes) {
+        std::vector<npo::BDesc> host(cl.size());
+        for (size_t q = 0; q < cl.size(); ++q) host[q].step = wsptrs(*b.plans[cl[q]], ws[cl[q]]).step;
+        npo::BDesc* dt = nullptr;
+        HIPCHK(hipMalloc(&dt, host.size() * sizeof(npo::BDesc)));
+        HIPCHK(hipMemcpy(dt, host.data(), host.size() * sizeof(npo::BDesc), hipMemcpyHostToDevice));
+        b.steptab.push_back(dt);
+    }
+    b.step_key = key;
+    return NPO_OK;
+}
+
+// One batched step on stream st (phase 0: forward advance of cur, then every
+// step index + 1; phase 1: adjoint step of lam at u = cur, then step index - 1).
+hipError_t batch_issue(npo_batch_s& b, void* const* ws, int phase, hipStream_t st, int* launches) {
+    npo_batch_s::Phase& f = b.ph[phase];
+    int nl = 0;
+    for (size_t c = 0; c < b.classes.size(); ++c) {
+        const std::vector<int>& cl = b.classes[c];
+        const int nb = (int)cl.size();
+        if (f.batched[c]) {
+            for (size_t sidx = 0; sidx < f.launch[c].size(); ++sidx) {
+                f.launch[c][sidx](f.dtab[c] + sidx * nb, nb, st);
+                ++nl;
+            }
+        } else {
+            for (int i : cl) {
+                const npo_plan_s& p = *b.plans[i];
+                WsPtrs w = wsptrs(p, ws[i]);
+                hipError_t e = phase == 0 ? fwd_step(p, ws[i], w.cur, w.cur, 0, false, st, w.step)
+                                          : adj_step(p, ws[i], w.cur, w.lam, w.lam, 0, st, w.step, false);
+                if (e != hipSuccess) return e;
+                nl += 1;
+            }
+        }
+        hipError_t e = npo::launch_step_index_batched(b.steptab[c], nb, phase == 0 ? 1 : -1, 1, st);
+        if (e != hipSuccess) return e;
+        ++nl;
+    }
+    if (launches) *launches = nl;
+    return hipGetLastError();
+}
+
+npo_status batch_step(npo_batch_s& b, void* const* ws, int phase, hipStream_t st, bool use_graph) {
+    npo_status s = batch_tables(b, ws, st);
+    if (s) return s;
+    npo_batch_s::Phase& f = b.ph[phase];
+    if (!use_graph) {
+        HIPCHK(batch_issue(b, ws, phase, st, &b.launches));
+        return NPO_OK;
+    }
+    if (!f.graph) {
+        if (!b.cap) HIPCHK(hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal));
+        hipError_t e1 = batch_issue(b, ws, phase, b.cap, &b.launches);
+        hipError_t e = hipStreamEndCapture(b.cap, &g);
+        if (e == hipSuccess) e = e1;
+        if (e == hipSuccess) e = hipGraphInstantiate(&f.graph, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hipfail(e, "capturing the batched step");
+    }
+    HIPCHK(hipGraphLaunch(f.graph, st));
+    return NPO_OK;
+}
+
+npo_status batch_set_steps(npo_batch_s& b, void* const* ws, long long v, hipStream_t st) {
+    npo_status s = batch_tables(b, ws, st);
+    if (s) return s;
+    for (size_t c = 0; c < b.classes.size(); ++c)
+        HIPCHK(npo::launch_step_index_batched(b.steptab[c], (int)b.classes[c].size(), v, 0, st));
+    return NPO_OK;
+}
+
+npo_status batch_check(npo_batch b, void* const* ws) {
+    if (!b || !ws) return fail(NPO_EINVAL, "null argument");
+    for (size_t i = 0; i < b->plans.size(); ++i)
+        if (!ws[i]) return fail(NPO_EINVAL, "null workspace");
+    return NPO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+npo_status npo_batch_create(const npo_plan* plans, int32_t n, npo_batch* out) {
+    if (!plans || n < 1 || !out) return fail(NPO_EINVAL, "null argument or n < 1");
+    auto* b = new npo_batch_s();
+    for (int i = 0; i < n; ++i) {
+        if (!plans[i]) {
+            delete b;
+            return fail(NPO_EINVAL, "null plan");
+        }
+        b->plans.push_back(plans[i]);
+        if (plans[i]->nsteps != plans[0]->nsteps) {
+            delete b;
+            return fail(NPO_EINVAL, "batched instances share the horizon nsteps (one checkpoint schedule)");
+        }
+        bool placed = false;
+        for (std::vector<int>& cl : b->classes)
+            if (same_class(*plans[cl[0]], *plans[i])) {
+                cl.push_back(i);
+                placed = true;
+                break;
+            }
+        if (!placed) b->classes.push_back({i});
+    }
+    *out = b;
+    return NPO_OK;
+}
+
+npo_status npo_batch_destroy(npo_batch b) {
+    if (!b) return NPO_OK;
+    for (auto& f : b->ph) drop_phase(f);
+    for (npo::BDesc* d : b->steptab)
+        if (d) (void)hipFree(d);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+    return NPO_OK;
+}
+
+npo_status npo_batch_info(npo_batch b, int32_t* n_classes, int32_t* n_batched, int32_t* launches) {
+    if (!b) return fail(NPO_EINVAL, "null batch");
+    if (n_classes) *n_classes = (int32_t)b->classes.size();
+    if (n_batched) {
+        int nb = 0;
+        for (size_t c = 0; c < b->classes.size(); ++c)
+            if (!b->ph[0].batched.empty() && b->ph[0].batched[c] && b->ph[1].batched[c]) nb += (int)b->classes[c].size();
+        *n_batched = nb;
+    }
+    if (launches) *launches = b->launches;
+    return NPO_OK;
+}
+
+npo_status npo_batch_step(npo_batch b, void* const* states, void* const* ws, int32_t phase, void* stream) {
+    npo_status s = batch_check(b, ws);
+    if (s) return s;
+    if (!states || (phase != 0 && phase != 1)) return fail(NPO_EINVAL, "states must be given and phase 0 or 1");
+    const hipStream_t st = ST(stream);
+    const size_t n = b->plans.size();
+    for (size_t i = 0; i < (phase ? 2 * n : n); ++i)
+        if (!states[i]) return fail(NPO_EINVAL, "null state");
+    // the batched launches work on each workspace's cur (and lam)
+    for (size_t i = 0; i < n; ++i) {
+        const npo_plan_s& p = *b->plans[i];
+        const size_t fb = (size_t)3 * p.nr * p.mp1 * p.nk * 16;
+        WsPtrs w = wsptrs(p, ws[i]);
+        const void* u = phase ? states[2 * i] : states[i];
+        if (u != w.cur) HIPCHK(hipMemcpyAsync(w.cur, u, fb, hipMemcpyDeviceToDevice, st));
+        if (phase && states[2 * i + 1] != w.lam)
+            HIPCHK(hipMemcpyAsync(w.lam, states[2 * i + 1], fb, hipMemcpyDeviceToDevice, st));
+    }
+    s = batch_step(*b, ws, phase, st, false);
+    if (s) return s;
+    for (size_t i = 0; i < n; ++i) {
+        const npo_plan_s& p = *b->plans[i];
+        const size_t fb = (size_t)3 * p.nr * p.mp1 * p.nk * 16;
+        WsPtrs w = wsptrs(p, ws[i]);
+        void* o = phase ? states[2 * i + 1] : states[i];
+        if (o != (phase ? (void*)w.lam : (void*)w.cur))
+            HIPCHK(hipMemcpyAsync(o, phase ? w.lam : w.cur, fb, hipMemcpyDeviceToDevice, st));
+    }
+    return NPO_OK;
+}
+
+npo_status npo_batch_set_steps(npo_batch b, void* const* ws, int64_t n, void* stream) {
+    npo_status s = batch_check(b, ws);
+    if (s) return s;
+    return batch_set_steps(*b, ws, n, ST(stream));
+}
+
+// Checkpointed sweeps of every instance in lockstep: one schedule (the
+// instances share nsteps and n_ckpt); advances and adjoint steps are batched
+// steps (replayed from one captured graph per phase), stores and restores are
+// per-instance device copies between the workspace's cur and the slots.
+npo_status npo_batch_forward_run(npo_batch b, void* const* ws, void* const* ckpt, int32_t nck, void* const* u0,
+                                 void* const* uN, void* stream) {
+    npo_status s = batch_check(b, ws);
+    if (s) return s;
+    if (!ckpt || !u0 || !uN || nck < 1) return fail(NPO_EINVAL, "null argument or n_ckpt < 1");
+    const size_t n = b->plans.size();
+    for (size_t i = 0; i < n; ++i)
+        if (!ckpt[i] || !u0[i] || !uN[i]) return fail(NPO_EINVAL, "null buffer");
+    const hipStream_t st = ST(stream);
+    const long long N = b->plans[0]->nsteps;
+    auto fbytes = [&](size_t i) { const npo_plan_s& p = *b->plans[i]; return (size_t)3 * p.nr * p.mp1 * p.nk * 16; };
+    auto slot = [&](size_t i, long long sl) { return static_cast<char*>(ckpt[i]) + sl * fbytes(i); };
+    auto cur = [&](size_t i) { return (void*)wsptrs(*b->plans[i], ws[i]).cur; };
+    for (size_t i = 0; i < n; ++i) {
+        HIPCHK(hipMemcpyAsync(slot(i, 0), u0[i], fbytes(i), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(cur(i), u0[i], fbytes(i), hipMemcpyDeviceToDevice, st));
+    }
+    s = batch_set_steps(*b, ws, 0, st);
+    if (s) return s;
+    std::vector<Act> acts = schedule(N, nck);
+    const size_t fa = first_adj(acts);
+    long long pos = 0;
+    for (size_t a = 0; a < fa; ++a) {
+        if (acts[a].kind == A_ADV) {
+            for (long long k = 0; k < acts[a].a; ++k) {
+                s = batch_step(*b, ws, 0, st, true);
+                if (s) return s;
+                ++pos;
+            }
+        } else if (acts[a].kind == A_STORE) {
+            for (size_t i = 0; i < n; ++i)
+                HIPCHK(hipMemcpyAsync(slot(i, acts[a].a), cur(i), fbytes(i), hipMemcpyDeviceToDevice, st));
+        }
+    }
+    if (pos != N - 1) return fail(NPO_ESTATE, "schedule descent did not reach the last step");
+    // cur keeps u^{N-1} for the adjoint sweep; the last step goes to uN
+    for (size_t i = 0; i < n; ++i) {
+        const npo_plan_s& p = *b->plans[i];
+        WsPtrs w = wsptrs(p, ws[i]);
+        HIPCHK(fwd_step(p, ws[i], w.cur, static_cast<double2*>(uN[i]), N - 1, false, st));
+    }
+    return NPO_OK;
+}
+
+npo_status npo_batch_adjoint_run(npo_batch b, void* const* ws, void* const* ckpt, int32_t nck, void* const* lamN,
+                                 void* const* lam0, int64_t* n_recompute, void* stream) {
+    npo_status s = batch_check(b, ws);
+    if (s) return s;
+    if (!ckpt || !lamN || !lam0 || nck < 1) return fail(NPO_EINVAL, "null argument or n_ckpt < 1");
+    const size_t n = b->plans.size();
+    for (size_t i = 0; i < n; ++i)
+        if (!ckpt[i] || !lamN[i] || !lam0[i]) return fail(NPO_EINVAL, "null buffer");
+    const hipStream_t st = ST(stream);
+    const long long N = b->plans[0]->nsteps;
+    auto fbytes = [&](size_t i) { const npo_plan_s& p = *b->plans[i]; return (size_t)3 * p.nr * p.mp1 * p.nk * 16; };
+    auto slot = [&](size_t i, long long sl) { return static_cast<char*>(ckpt[i]) + sl * fbytes(i); };
+    for (size_t i = 0; i < n; ++i) {
+        WsPtrs w = wsptrs(*b->plans[i], ws[i]);
+        HIPCHK(hipMemcpyAsync(w.lam, lamN[i], fbytes(i), hipMemcpyDeviceToDevice, st));
+    }
+    s = batch_set_steps(*b, ws, N - 1, st);
+    if (s) return s;
+    std::vector<Act> acts = schedule(N, nck);
+    long long adv = 0;
+    for (size_t a = first_adj(acts); a < acts.size(); ++a) {
+        const Act& x = acts[a];
+        if (x.kind == A_RESTORE) {
+            for (size_t i = 0; i < n; ++i) {
+                WsPtrs w = wsptrs(*b->plans[i], ws[i]);
+                HIPCHK(hipMemcpyAsync(w.cur, slot(i, x.a), fbytes(i), hipMemcpyDeviceToDevice, st));
+            }
+            s = batch_set_steps(*b, ws, x.b, st);
+            if (s) return s;
+        } else if (x.kind == A_ADV) {
+            for (long long k = 0; k < x.a; ++k) {
+                s = batch_step(*b, ws, 0, st, true);
+                if (s) return s;
+            }
+            adv += x.a;
+        } else if (x.kind == A_STORE) {
+            for (size_t i = 0; i < n; ++i) {
+                WsPtrs w = wsptrs(*b->plans[i], ws[i]);
+                HIPCHK(hipMemcpyAsync(slot(i, x.a), w.cur, fbytes(i), hipMemcpyDeviceToDevice, st));
+            }
+        } else {
+            // the adjoint step at u^pos = cur; the step index then moves to pos - 1
+            s = batch_step(*b, ws, 1, st, true);
+            if (s) return s;
+        }
+    }
+    for (size_t i = 0; i < n; ++i) {
+        WsPtrs w = wsptrs(*b->plans[i], ws[i]);
+        HIPCHK(hipMemcpyAsync(lam0[i], w.lam, fbytes(i), hipMemcpyDeviceToDevice, st));
+    }
+    if (n_recompute) *n_recompute = adv;
     return NPO_OK;
 }
 

@@ -66,6 +66,19 @@ struct TimeArg {
     double t;
 };
 
+// Work descriptor of one instance in a batched launch: one launch per kernel
+// serves every instance of a shape class, blockIdx.z selecting the instance;
+// the kernel takes its plan constants, buffers, scalars and evaluation time
+// from its descriptor instead of its by-value arguments.
+struct BDesc {
+    KP kp;
+    const double2* in[4];
+    double2* out[3];
+    double s[6];
+    TimeArg ta;
+    long long* step;
+};
+
 // Workspace carve-up (byte offsets into the caller's workspace).
 constexpr int NCORR_MAX = 3;
 
@@ -115,11 +128,48 @@ struct npo_plan_s {
     hipGraphExec_t g_adj = nullptr;   // adjoint step lam -> lam at u = cur
 };
 
+#include <functional>
+
 namespace npo {
+
+// Batched launches.  While a Recorder is installed on the calling thread, the
+// step-path launchers enqueue nothing: each appends the launch (a closure that
+// launches its kernel for nb instances with a descriptor table) and the
+// descriptor of the instance being recorded.  Recording the same step for
+// every instance of a shape class yields the same launch sequence, which the
+// batch then issues once per launch with the instances' descriptors.
+struct Recorder {
+    std::vector<std::function<void(const BDesc*, int, hipStream_t)>> launch;
+    std::vector<BDesc> desc;
+    bool ok = true;       // false: a launch without a batched form was met
+};
+Recorder*& recorder();
 
 // Sampling profiler hooks around one launch on stream st.
 void prof_begin(const npo_plan_s& p, int kid, hipStream_t st);
 void prof_end(const npo_plan_s& p, int kid, hipStream_t st);
+
+// Enqueue a launch now, or record it (with the descriptor of the instance
+// being recorded) while a Recorder is installed.  fn(bd, nb, st) launches the
+// kernel for nb instances with descriptor table bd (bd = null: the call's own
+// arguments); kid is the profiler family (-1: none).
+template <class F>
+hipError_t issue(const npo_plan_s& p, int kid, const BDesc& d, hipStream_t st, F fn) {
+    if (Recorder* r = recorder()) {
+        r->launch.emplace_back(fn);
+        r->desc.push_back(d);
+        return hipSuccess;
+    }
+    if (kid >= 0) prof_begin(p, kid, st);
+    fn(nullptr, 1, st);
+    if (kid >= 0) prof_end(p, kid, st);
+    return hipGetLastError();
+}
+inline BDesc desc_of(const npo_plan_s& p) {
+    BDesc d{};
+    d.kp = p.kp;
+    return d;
+}
 
 // Kernel launchers (npo_kernels.hip).  All enqueue on `st` and return the
 // hipGetLastError() of the launch.
@@ -127,6 +177,9 @@ void prof_end(const npo_plan_s& p, int kid, hipStream_t st);
 // azimuthal pass (z-block ZB) for this plan's transform lengths.
 size_t zpass_lds(const npo_plan_s& p, int G);
 size_t theta_lds(const npo_plan_s& p, int ZB, int adj);
+// Whether the wave-resident forward azimuthal kernel with L lanes per column
+// (tuning value zb_fwd = -L) supports these transform lengths.
+bool theta_wave_ok(int nt, int nz, int L);
 hipError_t launch_curl_aux(const npo_plan_s& p, const double2* u, double2* aux, hipStream_t st);
 // uw_pre (adjoint only): the axial transforms of the six u, w fields of this
 // state, left by an earlier forward evaluation (then only y is transformed);
@@ -137,6 +190,9 @@ hipError_t launch_nl(const npo_plan_s& p, int adjoint, const double2* u, const d
                      const double2* uw_pre = nullptr, double2* uw_save = nullptr);
 // *d = v (set) or *d += v (add), one thread.
 hipError_t launch_step_index(long long* d, long long v, int add, hipStream_t st);
+// The same for the step index of every instance of a descriptor table.
+hipError_t launch_step_index_batched(const BDesc* bd, int nb, long long v, int add, hipStream_t st);
+
 // solve kinds: 0 = out = S(R) with R = a (raw); 1 = predictor S(E a + b),
 // which also stores R0 = E a + b/2 in the (+, -, z) basis when r0_out is given;
 // 2 = corrector S(R0 + b/2) with a = R0.  aux_out may be null.
@@ -153,6 +209,11 @@ hipError_t launch_final(const npo_plan_s& p, const double2* Z, const double2* A,
 hipError_t launch_wdot(const npo_plan_s& p, const double2* a, const double2* b, double* partial,
                        double* out, hipStream_t st);
 hipError_t launch_project(const npo_plan_s& p, const double2* u, double2* out, hipStream_t st);
+// Energy diagnostics of u: out[0..4] = E_r, E_theta, E_z, the energy in the
+// modes m = M and in the modes |k| = K; spec (optional) = energy per (m, kk).
+// partial: 5 * 256 doubles of scratch.
+hipError_t launch_diag(const npo_plan_s& p, const double2* u, double* partial, double* out, double* spec,
+                       hipStream_t st);
 // out = ca*a + cb*b
 hipError_t launch_axpby(const npo_plan_s& p, double ca, const double2* a, double cb, const double2* b,
                         double2* out, hipStream_t st);

@@ -16,7 +16,12 @@ namespace npo {
 
 // ------------------------------------------------------------ vorticity aux
 // aux[0] = w_theta = i a u_r - D1 u_z ; aux[1] = w_z = D1 u_theta + u_theta/r - (i m / r) u_r
-__global__ void k_curl_aux(KP p, const double2* __restrict__ u, double2* __restrict__ aux) {
+__global__ void k_curl_aux(KP p, const double2* __restrict__ u, double2* __restrict__ aux,
+                           const BDesc* __restrict__ bd) {
+    if (bd) {
+        const BDesc& d = bd[blockIdx.z];
+        p = d.kp; u = d.in[0]; aux = d.out[0];
+    }
     const size_t per = (size_t)p.nr * p.mp1 * p.nk;
     size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= per) return;
@@ -346,7 +351,12 @@ __device__ __forceinline__ Slot slot_of(const KP& p, int g, int m, int q) {
 template <int kind, int NRC>
 __global__ __launch_bounds__(RT) void k_solve(KP p, const double2* __restrict__ ain,
                                               const double2* __restrict__ bin, double2* __restrict__ uout,
-                                              double2* __restrict__ auxout, double2* __restrict__ r0out) {
+                                              double2* __restrict__ auxout, double2* __restrict__ r0out,
+                                              const BDesc* __restrict__ bd) {
+    if (bd) {
+        const BDesc& d = bd[blockIdx.z];
+        p = d.kp; ain = d.in[0]; bin = d.in[1]; uout = d.out[0]; auxout = d.out[1]; r0out = d.out[2];
+    }
     int g, m;
     if (!block_group(p, g, m)) return;
     const int t = threadIdx.x, q = t % RQ, jg = t / RQ;
@@ -595,7 +605,13 @@ struct AdjOut {
 };
 template <bool useB, int NRC>
 __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, double ca, const double2* Bin, double cb,
-                                                  AdjOut ao) {
+                                                  AdjOut ao, const BDesc* __restrict__ bd) {
+    if (bd) {
+        const BDesc& d = bd[blockIdx.z];
+        p = d.kp; Ain = d.in[0]; Bin = d.in[1]; ao.Yin = d.in[2]; ao.Zin = d.in[3];
+        ao.out0 = d.out[0]; ao.Yout = d.out[1]; ao.Zout = d.out[2];
+        ca = d.s[0]; cb = d.s[1]; ao.qy = d.s[2]; ao.qz = d.s[3]; ao.sy = d.s[4]; ao.sz = d.s[5];
+    }
     int g, m;
     if (!block_group(p, g, m)) return;
     const int t = threadIdx.x, q = t % RQ, jg = t / RQ;
@@ -777,7 +793,12 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
 // requested up front; Z, then B, is staged in LDS and every transposed
 // stencil reads it there through the 13-tap tables.
 __global__ __launch_bounds__(RT) void k_final(KP p, const double2* __restrict__ Z, const double2* __restrict__ Ain,
-                                              const double2* __restrict__ Bin, double2* __restrict__ out) {
+                                              const double2* __restrict__ Bin, double2* __restrict__ out,
+                                              const BDesc* __restrict__ bd) {
+    if (bd) {
+        const BDesc& d = bd[blockIdx.z];
+        p = d.kp; Z = d.in[0]; Ain = d.in[1]; Bin = d.in[2]; out = d.out[0];
+    }
     int g, m;
     if (!block_group(p, g, m)) return;
     const int t = threadIdx.x, q = t % RQ, jg = t / RQ;
@@ -893,6 +914,67 @@ __global__ __launch_bounds__(256) void k_wdot_partial(KP p, const double2* __res
     }
     if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
+// Energy diagnostics of a field (the growth decompositions of Sec. 3-4 and
+// the resolution criterion of Sec. 2.3), fixed-order block partials of
+//   0..2  <u_c, u_c>_W for c = r, theta, z (twice the component energies),
+//   3     the same summed over the modes m = M (the highest azimuthal mode),
+//   4     the same summed over the modes |k| = K (the highest axial modes);
+// part is [5][RED_BLOCKS].
+__global__ __launch_bounds__(256) void k_diag_partial(KP p, const double2* __restrict__ u, double* __restrict__ part) {
+    __shared__ double s[5][256];
+    const size_t total = (size_t)3 * p.nr * p.mp1 * p.nk;
+    const size_t per_c = (size_t)p.nr * p.mp1 * p.nk;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)RED_BLOCKS * 256) {
+        const int kk = e % p.nk;
+        const int m = (e / p.nk) % p.mp1;
+        const int j = (e / ((size_t)p.nk * p.mp1)) % p.nr;
+        const int c = (int)(e / per_c);
+        const double2 x = u[e];
+        const double v = p.w[j] * (m == 0 ? 1.0 : 2.0) * (x.x * x.x + x.y * x.y);
+        acc[0] += c == 0 ? v : 0.0;
+        acc[1] += c == 1 ? v : 0.0;
+        acc[2] += c == 2 ? v : 0.0;
+        acc[3] += m == p.M ? v : 0.0;
+        acc[4] += (kk == p.K || kk == p.nk - p.K) ? v : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) s[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 5) part[threadIdx.x * RED_BLOCKS + blockIdx.x] = s[threadIdx.x][0];
+}
+// out[q] = scale * sum of the partials of quantity q (q = blockIdx.x)
+__global__ __launch_bounds__(256) void k_diag_final(const double* __restrict__ part, double scale,
+                                                    double* __restrict__ out) {
+    __shared__ double s[256];
+    s[threadIdx.x] = part[blockIdx.x * RED_BLOCKS + threadIdx.x];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = s[0] * scale;
+}
+// Energy of each stored mode (m, kk): 1/2 * 2 pi L_z c_m sum_j w_j sum_c |u|^2.
+__global__ void k_mode_energy(KP p, const double2* __restrict__ u, double* __restrict__ spec) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= p.mp1 * p.nk) return;
+    const int m = t / p.nk, kk = t - m * p.nk;
+    double acc = 0.0;
+    for (int c = 0; c < 3; ++c)
+        for (int j = 0; j < p.nr; ++j) {
+            const double2 x = u[fidx(p, c, j, m, kk)];
+            acc = fma(p.w[j], x.x * x.x + x.y * x.y, acc);
+        }
+    spec[t] = M_PI * p.lz * (m == 0 ? 1.0 : 2.0) * acc;
+}
+
 __global__ __launch_bounds__(256) void k_wdot_final(const double* __restrict__ part, double scale,
                                                     double* __restrict__ out) {
     __shared__ double s[256];
@@ -1112,81 +1194,109 @@ __global__ void k_half(const double* __restrict__ en, double* __restrict__ info)
 }
 
 // Device step index of captured step graphs: *d = v or *d += v.
-__global__ void k_step_index(long long* d, long long v, int add) {
+__global__ void k_step_index(long long* d, long long v, int add, const BDesc* __restrict__ bd) {
+    if (bd) d = bd[blockIdx.z].step;
     if (threadIdx.x == 0) *d = add ? *d + v : v;
 }
 
 // ---------------------------------------------------------------- launchers
 static inline size_t field_elems(const npo_plan_s& p) { return (size_t)3 * p.nr * p.mp1 * p.nk; }
 
-hipError_t launch_step_index(long long* d, long long v, int add, hipStream_t st) {
-    hipLaunchKernelGGL(k_step_index, dim3(1), dim3(64), 0, st, d, v, add);
-    return hipGetLastError();
+Recorder*& recorder() {
+    static thread_local Recorder* r = nullptr;
+    return r;
 }
 
+
+hipError_t launch_step_index(long long* d, long long v, int add, hipStream_t st) {
+    if (recorder()) return hipErrorInvalidValue;     // the batch advances its step indices itself
+    hipLaunchKernelGGL(k_step_index, dim3(1), dim3(64), 0, st, d, v, add, nullptr);
+    return hipGetLastError();
+}
+hipError_t launch_step_index_batched(const BDesc* bd, int nb, long long v, int add, hipStream_t st) {
+    hipLaunchKernelGGL(k_step_index, dim3(1, 1, nb), dim3(64), 0, st, nullptr, v, add, bd);
+    return hipGetLastError();
+}
 hipError_t launch_curl_aux(const npo_plan_s& p, const double2* u, double2* aux, hipStream_t st) {
     const size_t per = (size_t)p.nr * p.mp1 * p.nk;
-    prof_begin(p, KID_CURL, st);
-    hipLaunchKernelGGL(k_curl_aux, dim3((per + 255) / 256), dim3(256), 0, st, p.kp, u, aux);
-    prof_end(p, KID_CURL, st);
-    return hipGetLastError();
+    BDesc d = desc_of(p);
+    d.in[0] = u;
+    d.out[0] = aux;
+    const KP kp = p.kp;
+    const unsigned gx = (unsigned)((per + 255) / 256);
+    return issue(p, KID_CURL, d, st, [=](const BDesc* bd, int nb, hipStream_t s) {
+        hipLaunchKernelGGL(k_curl_aux, dim3(gx, 1, nb), dim3(256), 0, s, kp, u, aux, bd);
+    });
 }
-
 template <int R>
-static void launch_solve_r(const npo_plan_s& p, int kind, dim3 grid, const double2* a, const double2* b,
-                           double2* u_out, double2* aux_out, double2* r0_out, hipStream_t st) {
-    if (kind == 1) hipLaunchKernelGGL((k_solve<1, R>), grid, dim3(RT), 0, st, p.kp, a, b, u_out, aux_out, r0_out);
-    else if (kind == 2) hipLaunchKernelGGL((k_solve<2, R>), grid, dim3(RT), 0, st, p.kp, a, b, u_out, aux_out, r0_out);
-    else hipLaunchKernelGGL((k_solve<0, R>), grid, dim3(RT), 0, st, p.kp, a, b, u_out, aux_out, r0_out);
+static hipError_t launch_solve_r(const npo_plan_s& p, int kid, int kind, unsigned gx, const BDesc& d,
+                                 const double2* a, const double2* b, double2* u_out, double2* aux_out,
+                                 double2* r0_out, hipStream_t st) {
+    const KP kp = p.kp;
+    return issue(p, kid, d, st, [=](const BDesc* bd, int nb, hipStream_t s) {
+        const dim3 grid(gx, 1, nb);
+        if (kind == 1) hipLaunchKernelGGL((k_solve<1, R>), grid, dim3(RT), 0, s, kp, a, b, u_out, aux_out, r0_out, bd);
+        else if (kind == 2)
+            hipLaunchKernelGGL((k_solve<2, R>), grid, dim3(RT), 0, s, kp, a, b, u_out, aux_out, r0_out, bd);
+        else hipLaunchKernelGGL((k_solve<0, R>), grid, dim3(RT), 0, s, kp, a, b, u_out, aux_out, r0_out, bd);
+    });
 }
-
 hipError_t launch_solve(const npo_plan_s& p, int kind, const double2* a, const double2* b, double2* u_out,
                         double2* aux_out, hipStream_t st, double2* r0_out) {
     const int kid = kind == 1 ? KID_SOLVE_P : (kind == 2 ? KID_SOLVE_C : KID_SOLVE_R);
-    prof_begin(p, kid, st);
-    const dim3 grid((radial_groups(p.K) * p.mp1 + 7) / 8 * 8);
+    const unsigned gx = (unsigned)((radial_groups(p.K) * p.mp1 + 7) / 8 * 8);
+    BDesc d = desc_of(p);
+    d.in[0] = a; d.in[1] = b;
+    d.out[0] = u_out; d.out[1] = aux_out; d.out[2] = r0_out;
     switch (p.nr) {
-#define NPO_CASE(R)                                                          \
-    case R:                                                                  \
-        launch_solve_r<R>(p, kind, grid, a, b, u_out, aux_out, r0_out, st);    \
-        break;
+#define NPO_CASE(R)                                                                       \
+    case R:                                                                               \
+        return launch_solve_r<R>(p, kid, kind, gx, d, a, b, u_out, aux_out, r0_out, st);
         NPO_NR_SIZES(NPO_CASE)
 #undef NPO_CASE
     default:
-        launch_solve_r<0>(p, kind, grid, a, b, u_out, aux_out, r0_out, st);
+        return launch_solve_r<0>(p, kid, kind, gx, d, a, b, u_out, aux_out, r0_out, st);
     }
-    prof_end(p, kid, st);
-    return hipGetLastError();
 }
-
+template <int R>
+static hipError_t launch_solve_adj_r(const npo_plan_s& p, unsigned gx, const BDesc& d, const double2* A, double ca,
+                                     const double2* B, double cb, AdjOut ao, hipStream_t st) {
+    const KP kp = p.kp;
+    return issue(p, B ? KID_SOLVE_ADJ2 : KID_SOLVE_ADJ, d, st, [=](const BDesc* bd, int nb, hipStream_t s) {
+        const dim3 grid(gx, 1, nb);
+        if (B) hipLaunchKernelGGL((k_solve_adj<true, R>), grid, dim3(RT), 0, s, kp, A, ca, B, cb, ao, bd);
+        else hipLaunchKernelGGL((k_solve_adj<false, R>), grid, dim3(RT), 0, s, kp, A, ca, B, cb, ao, bd);
+    });
+}
 hipError_t launch_solve_adj(const npo_plan_s& p, const double2* A, double ca, const double2* B, double cb,
                             double2* out0, const double2* Yin, double qy, double2* Yout, const double2* Zin,
                             double qz, double2* Zout, hipStream_t st, double sy, double sz) {
     AdjOut ao{out0, Yin, Yout, Zin, Zout, qy, qz, sy, sz};
-    prof_begin(p, B ? KID_SOLVE_ADJ2 : KID_SOLVE_ADJ, st);
-    const dim3 grid((radial_groups(p.K) * p.mp1 + 7) / 8 * 8);
+    const unsigned gx = (unsigned)((radial_groups(p.K) * p.mp1 + 7) / 8 * 8);
+    BDesc d = desc_of(p);
+    d.in[0] = A; d.in[1] = B; d.in[2] = Yin; d.in[3] = Zin;
+    d.out[0] = out0; d.out[1] = Yout; d.out[2] = Zout;
+    d.s[0] = ca; d.s[1] = cb; d.s[2] = qy; d.s[3] = qz; d.s[4] = sy; d.s[5] = sz;
     switch (p.nr) {
-#define NPO_CASE(R)                                                                                        \
-    case R:                                                                                                \
-        if (B) hipLaunchKernelGGL((k_solve_adj<true, R>), grid, dim3(RT), 0, st, p.kp, A, ca, B, cb, ao);    \
-        else hipLaunchKernelGGL((k_solve_adj<false, R>), grid, dim3(RT), 0, st, p.kp, A, ca, B, cb, ao);     \
-        break;
+#define NPO_CASE(R)                                                            \
+    case R:                                                                    \
+        return launch_solve_adj_r<R>(p, gx, d, A, ca, B, cb, ao, st);
         NPO_NR_SIZES(NPO_CASE)
 #undef NPO_CASE
     default:
-        if (B) hipLaunchKernelGGL((k_solve_adj<true, 0>), grid, dim3(RT), 0, st, p.kp, A, ca, B, cb, ao);
-        else hipLaunchKernelGGL((k_solve_adj<false, 0>), grid, dim3(RT), 0, st, p.kp, A, ca, B, cb, ao);
+        return launch_solve_adj_r<0>(p, gx, d, A, ca, B, cb, ao, st);
     }
-    prof_end(p, B ? KID_SOLVE_ADJ2 : KID_SOLVE_ADJ, st);
-    return hipGetLastError();
 }
-
 hipError_t launch_final(const npo_plan_s& p, const double2* Z, const double2* A, const double2* B, double2* out,
                         hipStream_t st) {
-    prof_begin(p, KID_FINAL, st);
-    hipLaunchKernelGGL(k_final, dim3((radial_groups(p.K) * p.mp1 + 7) / 8 * 8), dim3(RT), 0, st, p.kp, Z, A, B, out);
-    prof_end(p, KID_FINAL, st);
-    return hipGetLastError();
+    BDesc d = desc_of(p);
+    d.in[0] = Z; d.in[1] = A; d.in[2] = B;
+    d.out[0] = out;
+    const KP kp = p.kp;
+    const unsigned gx = (unsigned)((radial_groups(p.K) * p.mp1 + 7) / 8 * 8);
+    return issue(p, KID_FINAL, d, st, [=](const BDesc* bd, int nb, hipStream_t s) {
+        hipLaunchKernelGGL(k_final, dim3(gx, 1, nb), dim3(RT), 0, s, kp, Z, A, B, out, bd);
+    });
 }
 
 hipError_t launch_wdot(const npo_plan_s& p, const double2* a, const double2* b, double* partial, double* out,
@@ -1195,6 +1305,17 @@ hipError_t launch_wdot(const npo_plan_s& p, const double2* a, const double2* b, 
     hipLaunchKernelGGL(k_wdot_partial, dim3(RED_BLOCKS), dim3(256), 0, st, p.kp, a, b, partial);
     prof_end(p, KID_WDOT, st);
     hipLaunchKernelGGL(k_wdot_final, dim3(1), dim3(256), 0, st, partial, 2.0 * M_PI * p.lz, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(const npo_plan_s& p, const double2* u, double* partial, double* out, double* spec,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_diag_partial, dim3(RED_BLOCKS), dim3(256), 0, st, p.kp, u, partial);
+    hipLaunchKernelGGL(k_diag_final, dim3(5), dim3(256), 0, st, partial, M_PI * p.lz, out);   // energies: <.,.>/2
+    if (spec) {
+        const int n = p.mp1 * p.nk;
+        hipLaunchKernelGGL(k_mode_energy, dim3((n + 255) / 256), dim3(256), 0, st, p.kp, u, spec);
+    }
     return hipGetLastError();
 }
 

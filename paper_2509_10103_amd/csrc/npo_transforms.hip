@@ -543,8 +543,13 @@ __global__ __launch_bounds__(TB) void k_zinv_t(KP p, const double2* __restrict__
 // round trips and two barriers fewer per field than k_zinv_t.
 template <int NZ, int F0, int NF, int MB>
 __global__ __launch_bounds__(TB) void k_zinv_p(KP p, const double2* __restrict__ u, const double2* __restrict__ aux,
-                                              const double2* __restrict__ y, double2* __restrict__ zb) {
+                                              const double2* __restrict__ y, double2* __restrict__ zb,
+                                              const BDesc* __restrict__ bd) {
     static_assert(NZ % 12 == 0, "N_z = 3P with P a multiple of 4");
+    if (bd) {
+        const BDesc& d = bd[blockIdx.z];
+        p = d.kp; u = d.in[0]; aux = d.in[1]; y = d.in[2]; zb = d.out[0];
+    }
     constexpr int P = NZ / 3, NK = 2 * P - 1;
     constexpr int PB = (P + TB - 1) / TB;             // first-pass butterflies per thread
     constexpr int NB4 = NZ / 4;                       // last-pass butterflies
@@ -679,8 +684,12 @@ __global__ __launch_bounds__(TB) void k_zfwd_t(KP p, const double2* __restrict__
 // them to the spectral field.
 template <int NZ, int NFO, int MB>
 __global__ __launch_bounds__(TB) void k_zfwd_p(KP p, const double2* __restrict__ tb, double2* __restrict__ out0,
-                                              double2* __restrict__ out1, double scale) {
+                                              double2* __restrict__ out1, double scale, const BDesc* __restrict__ bd) {
     static_assert(NZ % 12 == 0, "N_z = 3P with P a multiple of 4");
+    if (bd) {
+        const BDesc& d = bd[blockIdx.z];
+        p = d.kp; tb = d.in[0]; out0 = d.out[0]; out1 = d.out[1];
+    }
     constexpr int P = NZ / 3, NK = 2 * P - 1;
     constexpr int NB4 = NZ / 4;
     constexpr int PB = (NB4 + TB - 1) / TB;           // first-pass butterflies per thread
@@ -979,8 +988,12 @@ __device__ __forceinline__ void theta_last_pair(const double2* R, const double2*
 // instead of eight, and about 40% fewer LDS accesses than the generic plan.
 template <int NT, int ZB>
 __global__ __launch_bounds__(TB) void k_theta_p(KP p, int nq, int Q, const double2* __restrict__ zu, int nfu,
-                                               double2* __restrict__ tb, TimeArg ta) {
+                                               double2* __restrict__ tb, TimeArg ta, const BDesc* __restrict__ bd) {
     static_assert(NT % 12 == 0, "N_theta = 3P with P a multiple of 4");
+    if (bd) {
+        const BDesc& d = bd[blockIdx.z];
+        p = d.kp; zu = d.in[0]; tb = d.out[0]; ta = d.ta;
+    }
     constexpr int P = NT / 3, MP1 = P;
     constexpr int NIN = 3 * ZB, NOUT = 2 * ZB;
     constexpr int PH = P / 2 + 1;                      // first-pass items per sequence: butterflies jj, P - jj
@@ -1090,6 +1103,306 @@ __global__ __launch_bounds__(TB) void k_theta_p(KP p, int nq, int Q, const doubl
     }
 }
 
+// ================================================ wave-resident azimuthal pass
+// Forward azimuthal pass with every sequence in registers.  A column (one
+// axial point of one radial node) is spread over L lanes (L = 8 or 16), so a
+// wave owns 64/L columns; lane (k1, zi) = k1 + L zi holds the L-strided slice
+// k1 + L k2 (k2 = 0..R-1, R = N_theta / L) of the three packed inverse
+// sequences of column zi.  Four-step transform of length L R: a length-R DFT
+// in registers over k2, the twiddles w^(n2 k1), and a length-L DFT across the
+// L lanes of the column as log2(L) radix-2 stages whose partner values come
+// from cross-lane moves (DPP quad permutations for lane distances 1 and 2,
+// ds_swizzle for 4, a DPP row rotation for 8).  That leaves lane k1 holding
+// the points theta = R bitrev(k1) + n2; the products are pointwise, so the
+// forward transform takes them in that order and runs the transposed network
+// (radix-2 stages across the lanes in reverse order with conjugate twiddles,
+// then the twiddles and a length-R DFT) back to the natural slices.  The
+// Hermitian unpacking of the two real outputs of a sequence pairs X[m]
+// (lane k1) with X[N - m] (lane L - k1), fetched with ds_bpermute.  No LDS pass
+// and no barrier besides the twiddle table's.
+
+// Lane-partner moves of one 32-bit value: xor 1, xor 2 (DPP quad_perm), xor 4
+// (ds_swizzle, bit mode) and xor 8 (DPP row rotation by 8 within 16 lanes).
+template <int D>
+__device__ __forceinline__ int xl_i32(int v) {
+    if constexpr (D == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+    else if constexpr (D == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+    else if constexpr (D == 4) return __builtin_amdgcn_ds_swizzle(v, (4 << 10) | 0x1F);
+    else return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
+}
+template <int D>
+__device__ __forceinline__ double xl_f64(double v) {
+    const int lo = xl_i32<D>(__double2loint(v)), hi = xl_i32<D>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+template <int D>
+__device__ __forceinline__ double2 xl(double2 a) { return make_double2(xl_f64<D>(a.x), xl_f64<D>(a.y)); }
+__device__ __forceinline__ double2 bperm(int src_byte, double2 a) {
+    auto f = [&](double v) {
+        const int lo = __builtin_amdgcn_ds_bpermute(src_byte, __double2loint(v));
+        const int hi = __builtin_amdgcn_ds_bpermute(src_byte, __double2hiint(v));
+        return __hiloint2double(hi, lo);
+    };
+    return make_double2(f(a.x), f(a.y));
+}
+// exp(2 pi i k / (2D)), k = 0..D-1: the inverse twiddle of a radix-2 stage of
+// lane distance D (the lane's position k within its half of the sub-DFT)
+template <int D>
+__device__ __forceinline__ double2 wstage_inv(int k) {
+    constexpr double s = 0.70710678118654752440, c1 = 0.92387953251128675613, s1 = 0.38268343236508977173;
+    if constexpr (D == 1) return make_double2(1.0, 0.0);
+    else if constexpr (D == 2) return k ? make_double2(0.0, 1.0) : make_double2(1.0, 0.0);
+    else if constexpr (D == 4)
+        return k == 0 ? make_double2(1.0, 0.0) : k == 1 ? make_double2(s, s) : k == 2 ? make_double2(0.0, 1.0)
+                                                                            : make_double2(-s, s);
+    else {
+        constexpr double cs[8] = {1.0, c1, s, s1, 0.0, -s1, -s, -c1};
+        constexpr double sn[8] = {0.0, s1, s, c1, 1.0, c1, s, s1};
+        return make_double2(cs[k & 7], sn[k & 7]);
+    }
+}
+
+// Inverse length-L DFT across the lanes k1 (decimation in frequency): lane k1
+// ends with output bitrev(k1).
+// Each stage is branch-free: v <- (s v + q) w' with s = +1, w' = 1 on the
+// lanes whose bit D is clear and s = -1, w' = the stage twiddle where it is set.
+template <int D, int N>
+__device__ __forceinline__ void xlane_inv(double2 (&v)[N], int k1) {
+    if constexpr (D >= 1) {
+        const bool hi = k1 & D;
+        const double sg = hi ? -1.0 : 1.0;
+        const double2 w = hi ? wstage_inv<D>(k1 & (D - 1)) : make_double2(1.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const double2 q = xl<D>(v[i]);
+            const double2 d = make_double2(fma(sg, v[i].x, q.x), fma(sg, v[i].y, q.y));
+            v[i] = D > 1 ? cmul(d, w) : d;
+        }
+        if constexpr (D > 1) xlane_inv<D / 2>(v, k1);
+    }
+}
+// Its conjugate transpose (decimation in time across the lanes): input in
+// bitrev order, lane k1 ends with output k1 of the forward length-L DFT.
+template <int D, int DMAX, int N>
+__device__ __forceinline__ void xlane_fwd(double2 (&v)[N], int k1) {
+    const bool hi = k1 & D;
+    const double sg = hi ? -1.0 : 1.0;
+    const double2 w = hi ? cconj(wstage_inv<D>(k1 & (D - 1))) : make_double2(1.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const double2 t = D > 1 ? cmul(v[i], w) : v[i];
+        const double2 q = xl<D>(t);
+        v[i] = make_double2(fma(sg, t.x, q.x), fma(sg, t.y, q.y));
+    }
+    if constexpr (D < DMAX) xlane_fwd<2 * D, DMAX>(v, k1);
+}
+
+template <int NT, int L>
+__global__ __launch_bounds__(TB) void k_theta_w(KP p, int nzb, const double2* __restrict__ zu, int nfu,
+                                               double2* __restrict__ tb, TimeArg ta) {
+    constexpr int R = NT / L, P = NT / 3, MP1 = P;
+    constexpr int CW = 64 / L;             // columns per wave
+    constexpr int KPOS = P / L;            // registers k2 < KPOS hold modes m = k1 + L k2
+    constexpr int KNEG = (NT - P) / L;     // registers k2 >= KNEG hold conj of modes NT - k1 - L k2
+    static_assert(P % L == 0 && (NT - P) % L == 0, "retained band aligned to the lane slices");
+    __shared__ double2 tw[NT];
+    const int nblk = nzb * p.nr;
+    const int per = (nblk + 7) >> 3;
+    const int Lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (Lb >= nblk) return;                                   // whole block
+    for (int t = threadIdx.x; t < NT; t += TB) tw[t] = p.twt[t];
+    __syncthreads();
+    const int j = Lb / nzb, zblk = Lb - j * nzb, nz = p.nz;
+    const int zw = zblk * (TB / 64) * CW + (threadIdx.x >> 6) * CW;   // first column of this wave
+    if (zw >= nz) return;                                     // whole wave (nz is a multiple of CW)
+    const int lane = threadIdx.x & 63, k1 = lane & (L - 1), z = zw + lane / L;
+    double U, Om, cw, sw;
+    phase_of(p, ta, cw, sw);
+    base_at(p, j, cw, sw, U, Om);
+    const size_t fs = (size_t)MP1 * nz;
+    const double2* bz = zu + (size_t)j * nfu * fs + z;
+    // packed inverse sequences (u_r, u_t), (u_z, w_r), (w_t, w_z)
+    double2 X0[R], X1[R], X2[R];
+    auto load = [&](double2 (&X)[R], int f) {
+#pragma unroll
+        for (int k2 = 0; k2 < R; ++k2) {
+            X[k2] = czero();
+            if (k2 < KPOS) {
+                const int m = k1 + L * k2;
+                const double2 a = bz[(size_t)f * fs + (size_t)m * nz], b = bz[(size_t)(f + 1) * fs + (size_t)m * nz];
+                X[k2] = (m == 0) ? make_double2(a.x, b.x) : make_double2(a.x - b.y, a.y + b.x);
+            } else if (k2 >= KNEG) {
+                const int m = NT - k1 - L * k2;
+                if (m < P) {
+                    const double2 a = bz[(size_t)f * fs + (size_t)m * nz];
+                    const double2 b = bz[(size_t)(f + 1) * fs + (size_t)m * nz];
+                    X[k2] = make_double2(a.x + b.y, b.x - a.y);    // conj(a) + i conj(b)
+                }
+            }
+        }
+    };
+    auto inverse = [&](double2 (&X)[R]) {
+        dft<R, true>(X);
+#pragma unroll
+        for (int n2 = 1; n2 < R; ++n2) X[n2] = tw_mul<true>(X[n2], tw[n2 * k1]);
+        xlane_inv<L / 2>(X, k1);
+    };
+    // one sequence's loads in flight while the previous one is transformed;
+    // scheduling barriers keep the compiler from hoisting every load to the
+    // top, which would cost the registers of three more waves per SIMD
+    load(X0, 0);
+    load(X1, 2);
+    __builtin_amdgcn_sched_barrier(0);
+    inverse(X0);
+    __builtin_amdgcn_sched_barrier(0);
+    load(X2, 4);
+    __builtin_amdgcn_sched_barrier(0);
+    inverse(X1);
+    __builtin_amdgcn_sched_barrier(0);
+    inverse(X2);
+    // products at the R points of this lane: N = u x w + U x w + u x Om
+#pragma unroll
+    for (int n2 = 0; n2 < R; ++n2) {
+        const double ur = X0[n2].x, ut = X0[n2].y, uz = X1[n2].x, wr = X1[n2].y, wt = X2[n2].x, wz = X2[n2].y;
+        const double uzU = uz + U;
+        X0[n2] = make_double2(ut * wz - uzU * wt - uz * Om, uzU * wr - ur * wz);
+        X1[n2] = make_double2(ur * (wt + Om) - ut * wr, 0.0);
+    }
+    auto forward = [&](double2 (&X)[R]) {
+        xlane_fwd<1, L / 2>(X, k1);
+#pragma unroll
+        for (int n2 = 1; n2 < R; ++n2) X[n2] = tw_mul<false>(X[n2], tw[n2 * k1]);
+        dft<R, false>(X);
+    };
+    forward(X0);
+    forward(X1);
+    // X[N - m] of m = k1 + L k2 sits in lane L - k1, register R - 1 - k2 (k1 > 0),
+    // or in this lane, register (R - k2) mod R (k1 = 0)
+    const int src = (lane - k1 + ((L - k1) & (L - 1))) * 4;
+    const size_t ob = (size_t)j * 3 * fs + z;
+#pragma unroll
+    for (int k2 = 0; k2 < KPOS; ++k2) {
+        const int m = k1 + L * k2;
+        const double2 p0 = bperm(src, X0[R - 1 - k2]), p1 = bperm(src, X1[R - 1 - k2]);
+        const double2 b0 = cconj(k1 ? p0 : X0[(R - k2) % R]);
+        const double2 b1 = cconj(k1 ? p1 : X1[(R - k2) % R]);
+        const double2 a0 = X0[k2], a1 = X1[k2];
+        tb[ob + (size_t)m * nz] = cscale(cadd(a0, b0), 0.5);
+        tb[ob + fs + (size_t)m * nz] = cscale(cmuli(csub(b0, a0)), 0.5);
+        tb[ob + 2 * fs + (size_t)m * nz] = cscale(cadd(a1, b1), 0.5);
+    }
+}
+
+// Adjoint azimuthal pass in the wave-resident form of k_theta_w: inputs the
+// state (u_r u_t, u_z w_r, w_t w_z from zu) and the adjoint field (y_r y_t and
+// y_z alone from zy), outputs A = (Om + w) x Y and B = Y x (U + u) as the
+// sequences (A_r, A_t), (A_z, B_r), (B_t, B_z) of each column.
+template <int NT, int L>
+__global__ __launch_bounds__(TB) void k_theta_wa(KP p, int nzb, const double2* __restrict__ zu, int nfu,
+                                                const double2* __restrict__ zy, int nfy, double2* __restrict__ tb,
+                                                TimeArg ta) {
+    constexpr int R = NT / L, P = NT / 3, MP1 = P;
+    constexpr int CW = 64 / L;
+    constexpr int KPOS = P / L, KNEG = (NT - P) / L;
+    static_assert(P % L == 0 && (NT - P) % L == 0, "retained band aligned to the lane slices");
+    __shared__ double2 tw[NT];
+    const int nblk = nzb * p.nr;
+    const int per = (nblk + 7) >> 3;
+    const int Lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (Lb >= nblk) return;
+    for (int t = threadIdx.x; t < NT; t += TB) tw[t] = p.twt[t];
+    __syncthreads();
+    const int j = Lb / nzb, zblk = Lb - j * nzb, nz = p.nz;
+    const int zw = zblk * (TB / 64) * CW + (threadIdx.x >> 6) * CW;
+    if (zw >= nz) return;
+    const int lane = threadIdx.x & 63, k1 = lane & (L - 1), z = zw + lane / L;
+    double U, Om, cw, sw;
+    phase_of(p, ta, cw, sw);
+    base_at(p, j, cw, sw, U, Om);
+    const size_t fs = (size_t)MP1 * nz;
+    const double2* bu = zu + (size_t)j * nfu * fs + z;
+    const double2* by = zy + (size_t)j * nfy * fs + z;
+    // packed sequence of fields fa + i fb of base b (fb < 0: fa alone)
+    auto load = [&](double2 (&X)[R], const double2* b, int fa, int fb) {
+#pragma unroll
+        for (int k2 = 0; k2 < R; ++k2) {
+            X[k2] = czero();
+            if (k2 < KPOS) {
+                const int m = k1 + L * k2;
+                const double2 a = b[(size_t)fa * fs + (size_t)m * nz];
+                const double2 c = fb >= 0 ? b[(size_t)fb * fs + (size_t)m * nz] : czero();
+                X[k2] = (m == 0) ? make_double2(a.x, c.x) : make_double2(a.x - c.y, a.y + c.x);
+            } else if (k2 >= KNEG) {
+                const int m = NT - k1 - L * k2;
+                if (m < P) {
+                    const double2 a = b[(size_t)fa * fs + (size_t)m * nz];
+                    const double2 c = fb >= 0 ? b[(size_t)fb * fs + (size_t)m * nz] : czero();
+                    X[k2] = make_double2(a.x + c.y, c.x - a.y);
+                }
+            }
+        }
+    };
+    auto inverse = [&](double2 (&X)[R]) {
+        dft<R, true>(X);
+#pragma unroll
+        for (int n2 = 1; n2 < R; ++n2) X[n2] = tw_mul<true>(X[n2], tw[n2 * k1]);
+        xlane_inv<L / 2>(X, k1);
+    };
+    double2 X0[R], X1[R], X2[R], X3[R], X4[R];
+    load(X3, by, 0, 1);
+    load(X4, by, 2, -1);
+    __builtin_amdgcn_sched_barrier(0);
+    inverse(X3);
+    __builtin_amdgcn_sched_barrier(0);
+    load(X0, bu, 0, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    inverse(X4);
+    __builtin_amdgcn_sched_barrier(0);
+    load(X1, bu, 2, 3);
+    __builtin_amdgcn_sched_barrier(0);
+    inverse(X0);
+    __builtin_amdgcn_sched_barrier(0);
+    load(X2, bu, 4, 5);
+    __builtin_amdgcn_sched_barrier(0);
+    inverse(X1);
+    __builtin_amdgcn_sched_barrier(0);
+    inverse(X2);
+#pragma unroll
+    for (int n2 = 0; n2 < R; ++n2) {
+        const double ur = X0[n2].x, ut = X0[n2].y, uz = X1[n2].x, wr = X1[n2].y, wt = X2[n2].x, wz = X2[n2].y;
+        const double yr = X3[n2].x, yt = X3[n2].y, yz = X4[n2].x;
+        const double wtO = wt + Om, uzU = uz + U;
+        X0[n2] = make_double2(wtO * yz - wz * yt, wz * yr - wr * yz);
+        X1[n2] = make_double2(wr * yt - wtO * yr, yt * uzU - yz * ut);
+        X2[n2] = make_double2(yz * ur - yr * uzU, yr * ut - yt * ur);
+    }
+    auto forward = [&](double2 (&X)[R]) {
+        xlane_fwd<1, L / 2>(X, k1);
+#pragma unroll
+        for (int n2 = 1; n2 < R; ++n2) X[n2] = tw_mul<false>(X[n2], tw[n2 * k1]);
+        dft<R, false>(X);
+    };
+    forward(X0);
+    forward(X1);
+    forward(X2);
+    const int src = (lane - k1 + ((L - k1) & (L - 1))) * 4;
+    const size_t ob = (size_t)j * 6 * fs + z;
+    auto emit = [&](const double2 (&X)[R], int f0) {
+#pragma unroll
+        for (int k2 = 0; k2 < KPOS; ++k2) {
+            const int m = k1 + L * k2;
+            const double2 pr = bperm(src, X[R - 1 - k2]);
+            const double2 b = cconj(k1 ? pr : X[(R - k2) % R]);
+            const double2 a = X[k2];
+            tb[ob + (size_t)f0 * fs + (size_t)m * nz] = cscale(cadd(a, b), 0.5);
+            tb[ob + (size_t)(f0 + 1) * fs + (size_t)m * nz] = cscale(cmuli(csub(b, a)), 0.5);
+        }
+    };
+    emit(X0, 0);
+    emit(X1, 2);
+    emit(X2, 4);
+}
+
 // Adjoint azimuthal pass for N_theta = 3P with the pruned, fused plan of
 // k_theta_p: inputs u (u_r u_t, u_z w_r, w_t w_z from zu), y (y_r y_t from zy)
 // and y_z of columns zi and zi + H paired; outputs A = (Om + w) x Y and
@@ -1098,8 +1411,12 @@ __global__ __launch_bounds__(TB) void k_theta_p(KP p, int nq, int Q, const doubl
 template <int NT, int ZB>
 __global__ __launch_bounds__(TB) void k_theta_pa(KP p, int nq, int Q, const double2* __restrict__ zu, int nfu,
                                                 const double2* __restrict__ zy, int nfy, double2* __restrict__ tb,
-                                                TimeArg ta) {
+                                                TimeArg ta, const BDesc* __restrict__ bd) {
     static_assert(NT % 12 == 0, "N_theta = 3P with P a multiple of 4");
+    if (bd) {
+        const BDesc& d = bd[blockIdx.z];
+        p = d.kp; zu = d.in[0]; zy = d.in[1]; tb = d.out[0]; ta = d.ta;
+    }
     constexpr int P = NT / 3, MP1 = P;
     constexpr int H = ZB / 2;
     constexpr int NIN = 4 * ZB + H, NOUT = 3 * ZB;
@@ -1276,14 +1593,26 @@ size_t theta_lds(const npo_plan_s& p, int ZB, int adj) {
 template <int NF>
 constexpr int zpass_mb() { return NF <= 3 ? 2 : 1; }
 
+// A kernel without a batched form met while recording: the batch falls back
+// to launching that instance's step by itself.
+static void not_batched() {
+    if (Recorder* r = recorder()) r->ok = false;
+}
+
 template <int NZ, int F0, int NF>
 static void launch_zinv_k(dim3 grid, size_t sh, const npo_plan_s& p, const double2* u, const double2* aux,
                           const double2* y, double2* zb, hipStream_t st) {
     if constexpr (NZ % 12 == 0) {
         constexpr int MB = zpass_mb<NF>();
-        const dim3 g((p.mp1 + MB - 1) / MB, grid.y);
-        hipLaunchKernelGGL((k_zinv_p<NZ, F0, NF, MB>), g, dim3(TB), sh, st, p.kp, u, aux, y, zb);
+        const unsigned gx = (p.mp1 + MB - 1) / MB, gy = grid.y;
+        BDesc d = desc_of(p);
+        d.in[0] = u; d.in[1] = aux; d.in[2] = y; d.out[0] = zb;
+        const KP kp = p.kp;
+        (void)issue(p, -1, d, st, [=](const BDesc* bd, int nb, hipStream_t s) {
+            hipLaunchKernelGGL((k_zinv_p<NZ, F0, NF, MB>), dim3(gx, gy, nb), dim3(TB), sh, s, kp, u, aux, y, zb, bd);
+        });
     } else {
+        not_batched();
         hipLaunchKernelGGL((k_zinv_t<NZ, F0, NF>), grid, dim3(TB), sh, st, p.kp, u, aux, y, zb);
     }
 }
@@ -1310,6 +1639,7 @@ static void launch_zinv(const npo_plan_s& p, int f0, int nf, const double2* u, c
         NPO_NZ_SIZES(NPO_CASE)
 #undef NPO_CASE
     default:
+        not_batched();
         hipLaunchKernelGGL(k_zinv, grid, dim3(256), sh, st, p.kp, f0, nf, G, u, aux, y, zb);
     }
 }
@@ -1319,9 +1649,16 @@ static void launch_zfwd_k(dim3 grid, size_t sh, const npo_plan_s& p, const doubl
                           double scale, hipStream_t st) {
     if constexpr (NZ % 12 == 0) {
         constexpr int MB = zpass_mb<NFO>();
-        const dim3 g((p.mp1 + MB - 1) / MB, grid.y);
-        hipLaunchKernelGGL((k_zfwd_p<NZ, NFO, MB>), g, dim3(TB), sh, st, p.kp, tb, out0, out1, scale);
+        const unsigned gx = (p.mp1 + MB - 1) / MB, gy = grid.y;
+        BDesc d = desc_of(p);
+        d.in[0] = tb; d.out[0] = out0; d.out[1] = out1;
+        const KP kp = p.kp;
+        (void)issue(p, -1, d, st, [=](const BDesc* bd, int nb, hipStream_t s) {
+            hipLaunchKernelGGL((k_zfwd_p<NZ, NFO, MB>), dim3(gx, gy, nb), dim3(TB), sh, s, kp, tb, out0, out1, scale,
+                               bd);
+        });
     } else {
+        not_batched();
         hipLaunchKernelGGL((k_zfwd_t<NZ, NFO>), grid, dim3(TB), sh, st, p.kp, tb, out0, out1, scale);
     }
 }
@@ -1340,6 +1677,7 @@ static void launch_zfwd(const npo_plan_s& p, int adj, const double2* tb, double2
         NPO_NZ_SIZES(NPO_CASE)
 #undef NPO_CASE
     default:
+        not_batched();
         hipLaunchKernelGGL(k_zfwd, grid, dim3(256), sh, st, p.kp, adj ? 6 : 3, G, tb, out0, out1, scale);
     }
 }
@@ -1356,12 +1694,22 @@ static int theta_tiles_per_block(const npo_plan_s& p, int ZB) {
 template <int NT, int ADJ, int ZB>
 static void launch_theta_k(dim3 grid, size_t sh, const npo_plan_s& p, int nq, int Q, const double2* zu, int nfu,
                            const double2* zy, int nfy, double2* tb, const TimeArg& ta, hipStream_t st) {
-    if constexpr (NT % 12 == 0 && !ADJ)
-        hipLaunchKernelGGL((k_theta_p<NT, ZB>), grid, dim3(TB), sh, st, p.kp, nq, Q, zu, nfu, tb, ta);
-    else if constexpr (NT % 12 == 0)
-        hipLaunchKernelGGL((k_theta_pa<NT, ZB>), grid, dim3(TB), sh, st, p.kp, nq, Q, zu, nfu, zy, nfy, tb, ta);
-    else
+    if constexpr (NT % 12 == 0) {
+        BDesc d = desc_of(p);
+        d.in[0] = zu; d.in[1] = zy; d.out[0] = tb; d.ta = ta;
+        const KP kp = p.kp;
+        const unsigned gx = grid.x;
+        (void)issue(p, -1, d, st, [=](const BDesc* bd, int nb, hipStream_t s) {
+            if constexpr (!ADJ)
+                hipLaunchKernelGGL((k_theta_p<NT, ZB>), dim3(gx, 1, nb), dim3(TB), sh, s, kp, nq, Q, zu, nfu, tb, ta, bd);
+            else
+                hipLaunchKernelGGL((k_theta_pa<NT, ZB>), dim3(gx, 1, nb), dim3(TB), sh, s, kp, nq, Q, zu, nfu, zy, nfy,
+                                   tb, ta, bd);
+        });
+    } else {
+        not_batched();
         hipLaunchKernelGGL((k_theta_t<NT, ADJ, ZB>), grid, dim3(TB), sh, st, p.kp, nq, Q, zu, nfu, zy, nfy, tb, ta);
+    }
 }
 
 template <int NT, int ADJ>
@@ -1372,11 +1720,42 @@ static void launch_theta_zb(const npo_plan_s& p, int ZB, dim3 grid, size_t sh, i
     else launch_theta_k<NT, ADJ, 2>(grid, sh, p, nq, Q, zu, nfu, zy, nfy, tb, ta, st);
 }
 
+// The wave-resident forward kernel with L lanes per column: N_theta in
+// {24, 48, 96} for L = 8, {48, 96} for L = 16; N_z a multiple of 64 / L.
+bool theta_wave_ok(int nt, int nz, int L) {
+    if (L == 8) return (nt == 24 || nt == 48 || nt == 96) && nz % 8 == 0;
+    if (L == 16) return (nt == 48 || nt == 96) && nz % 4 == 0;
+    return false;
+}
+
+template <int L>
+static void launch_theta_w(const npo_plan_s& p, int adj, const double2* zu, int nfu, const double2* zy, int nfy,
+                           double2* tb, const TimeArg& ta, hipStream_t st) {
+    constexpr int cols = (TB / 64) * (64 / L);    // columns per block
+    const int nzb = (p.nz + cols - 1) / cols;
+    const int nblk = nzb * p.nr;
+    const dim3 grid((nblk + 7) / 8 * 8);
+#define NPO_W(N)                                                                                              \
+    if (adj) hipLaunchKernelGGL((k_theta_wa<N, L>), grid, dim3(TB), 0, st, p.kp, nzb, zu, nfu, zy, nfy, tb, ta); \
+    else hipLaunchKernelGGL((k_theta_w<N, L>), grid, dim3(TB), 0, st, p.kp, nzb, zu, nfu, tb, ta);
+    if (p.nt == 96) { NPO_W(96) }
+    else if (p.nt == 48) { NPO_W(48) }
+    else if constexpr (L == 8) { NPO_W(24) }
+#undef NPO_W
+}
+
 static void launch_theta(const npo_plan_s& p, int adj, const double2* zu, int nfu, const double2* zy, int nfy,
                          double2* tb, const TimeArg& ta, hipStream_t st) {
     const int ZB = adj ? p.zb_theta_adj : p.zb_theta_fwd;
+    if (ZB < 0) {                               // tuning value -L: the wave-resident kernels, L lanes per column
+        not_batched();
+        if (ZB == -8) launch_theta_w<8>(p, adj, zu, nfu, zy, nfy, tb, ta, st);
+        else launch_theta_w<16>(p, adj, zu, nfu, zy, nfy, tb, ta, st);
+        return;
+    }
     const size_t sh = theta_lds(p, ZB, adj);
     if (!fast_nt(p.nt)) {
+        not_batched();
         hipLaunchKernelGGL(k_theta, dim3(p.nz / ZB, p.nr), dim3(256), sh, st, p.kp, adj, ZB, zu, nfu, zy, nfy, tb, ta);
         return;
     }

@@ -64,6 +64,12 @@ SIGNATURES = {
     "npo_adjoint_step": (_I32, [_P, _P, _P, _P, _P, _I64, _P]),
     "npo_forward_run": (_I32, [_P, _P, _P, _I32, _P, _P, _P]),
     "npo_adjoint_run": (_I32, [_P, _P, _P, _I32, _P, _P, ctypes.POINTER(_I64), _P]),
+    "npo_forward_run_diag": (_I32, [_P, _P, _P, _I32, _P, _P, _P, _I32, _P]),
+    "npo_forward_run_hybrid": (_I32, [_P, _P, _P, _I32, _P, _I32, _P, _P, _P]),
+    "npo_adjoint_run_hybrid": (_I32, [_P, _P, _P, _I32, _P, _I32, _P, _P, ctypes.POINTER(_I64), _P]),
+    "npo_hybrid_count": (_I32, [_I64, _I32, _I32, ctypes.POINTER(_I64)]),
+    "npo_hybrid_plan": (_I32, [_I64, _I32, _D, _D, _I32, ctypes.POINTER(_I32), _DP]),
+    "npo_energy_diag": (_I32, [_P, _P, _P, _P, _P, _P]),
     "npo_ckpt_count": (_I32, [_I64, _I32, ctypes.POINTER(_I64)]),
     "npo_inner": (_I32, [_P, _P, _P, _P, _P, _P]),
     "npo_project": (_I32, [_P, _P, _P, _P, _P]),
@@ -74,6 +80,15 @@ SIGNATURES = {
     "npo_plan_set_tuning": (_I32, [_P, _I32, _I32, _I32]),
     "npo_plan_get_tuning": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "npo_plan_set_graphs": (_I32, [_P, _I32]),
+    "npo_batch_create": (_I32, [ctypes.POINTER(_P), _I32, ctypes.POINTER(_P)]),
+    "npo_batch_destroy": (_I32, [_P]),
+    "npo_batch_info": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "npo_batch_set_steps": (_I32, [_P, ctypes.POINTER(_P), _I64, _P]),
+    "npo_batch_step": (_I32, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _I32, _P]),
+    "npo_batch_forward_run": (_I32, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _I32, ctypes.POINTER(_P),
+                                     ctypes.POINTER(_P), _P]),
+    "npo_batch_adjoint_run": (_I32, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _I32, ctypes.POINTER(_P),
+                                     ctypes.POINTER(_P), ctypes.POINTER(_I64), _P]),
     "npo_profile_begin": (_I32, [_P, _I32]),
     "npo_profile_read": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), _DP]),
 }
@@ -242,6 +257,65 @@ def npo_forward_run(plan, ws, ckpt, n_ckpt, u0, uN, stream=None):
                                  n_ckpt, _fld(plan, u0, "u0"), _fld(plan, uN, "uN"), _stream(stream)))
 
 
+def _host_tier(plan, t, n_file):
+    """Pinned host memory of n_file fields (torch pin_memory tensor)."""
+    if n_file == 0:
+        return None if t is None else ctypes.c_void_p(t.data_ptr())
+    import torch
+    if t is None or t.is_cuda or not t.is_pinned() or not t.is_contiguous():
+        raise NpoError("host_tier: must be a contiguous pinned host tensor")
+    need = _plan_info(plan)["field_bytes"] * n_file
+    if t.numel() * t.element_size() < need:
+        raise NpoError(f"host_tier: {t.numel() * t.element_size()} bytes, {n_file} fields need {need}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def npo_forward_run_hybrid(plan, ws, ckpt, n_ckpt, host_tier, n_file, u0, uN, stream=None):
+    _check(lib().npo_forward_run_hybrid(plan, _wsp(plan, ws), _fld(plan, ckpt, "checkpoint arena", max(int(n_ckpt), 1)),
+                                        n_ckpt, _host_tier(plan, host_tier, n_file), n_file, _fld(plan, u0, "u0"),
+                                        _fld(plan, uN, "uN"), _stream(stream)))
+
+
+def npo_adjoint_run_hybrid(plan, ws, ckpt, n_ckpt, host_tier, n_file, lamN, lam0, stream=None):
+    c = _I64()
+    _check(lib().npo_adjoint_run_hybrid(plan, _wsp(plan, ws), _fld(plan, ckpt, "checkpoint arena", max(int(n_ckpt), 1)),
+                                        n_ckpt, _host_tier(plan, host_tier, n_file), n_file, _fld(plan, lamN, "lamN"),
+                                        _fld(plan, lam0, "lam0"), ctypes.byref(c), _stream(stream)))
+    return c.value
+
+
+def npo_hybrid_count(nsteps, n_ckpt, n_file):
+    c = _I64()
+    _check(lib().npo_hybrid_count(nsteps, n_ckpt, n_file, ctypes.byref(c)))
+    return c.value
+
+
+def npo_hybrid_plan(nsteps, n_ckpt, t_io, t_step, max_file):
+    f = _I32()
+    t = ctypes.c_double()
+    _check(lib().npo_hybrid_plan(nsteps, n_ckpt, t_io, t_step, max_file, ctypes.byref(f), ctypes.byref(t)))
+    return f.value, t.value
+
+
+def diag_rows(nsteps, stride):
+    """Rows of the history written by npo_forward_run_diag."""
+    return (nsteps - 1) // stride + 2
+
+
+def npo_forward_run_diag(plan, ws, ckpt, n_ckpt, u0, uN, hist_dev, stride, stream=None):
+    rows = diag_rows(_plan_info(plan)["nsteps"], int(stride)) if stride >= 1 else 0
+    _check(lib().npo_forward_run_diag(plan, _wsp(plan, ws), _fld(plan, ckpt, "checkpoint arena", max(int(n_ckpt), 1)),
+                                      n_ckpt, _fld(plan, u0, "u0"), _fld(plan, uN, "uN"),
+                                      _scal(hist_dev, "hist_dev", 5 * rows), stride, _stream(stream)))
+
+
+def npo_energy_diag(plan, ws, u, out_dev, spec_dev=None, stream=None):
+    inf = _plan_info(plan)
+    spec = None if spec_dev is None else _scal(spec_dev, "spec_dev", (inf["M"] + 1) * inf["nk"])
+    _check(lib().npo_energy_diag(plan, _wsp(plan, ws), _fld(plan, u, "u"), _scal(out_dev, "out_dev", 5), spec,
+                                 _stream(stream)))
+
+
 def npo_adjoint_run(plan, ws, ckpt, n_ckpt, lamN, lam0, stream=None):
     c = _I64()
     _check(lib().npo_adjoint_run(plan, _wsp(plan, ws), _fld(plan, ckpt, "checkpoint arena", max(int(n_ckpt), 1)),
@@ -299,6 +373,61 @@ def npo_plan_get_tuning(plan):
 
 def npo_euclid_grad(plan, lam, scale, out, stream=None):
     _check(lib().npo_euclid_grad(plan, _fld(plan, lam, "lam"), scale, _fld(plan, out, "out"), _stream(stream)))
+
+
+# ------------------------------------------------------------- batches
+def _parr(ptrs):
+    return (_P * len(ptrs))(*[p if isinstance(p, ctypes.c_void_p) else ctypes.c_void_p(p) for p in ptrs])
+
+
+def npo_batch_create(plans):
+    """plans: list of plan handles (they must outlive the batch)."""
+    h = _P()
+    _check(lib().npo_batch_create(_parr(plans), len(plans), ctypes.byref(h)))
+    return h
+
+
+def npo_batch_destroy(batch):
+    _check(lib().npo_batch_destroy(batch))
+
+
+def npo_batch_info(batch):
+    a, b_, c = _I32(), _I32(), _I32()
+    _check(lib().npo_batch_info(batch, ctypes.byref(a), ctypes.byref(b_), ctypes.byref(c)))
+    return {"classes": a.value, "batched": b_.value, "launches": c.value}
+
+
+def _batch_ws(plans, ws):
+    return _parr([_wsp(p, w) for p, w in zip(plans, ws)])
+
+
+def npo_batch_set_steps(batch, plans, ws, n, stream=None):
+    _check(lib().npo_batch_set_steps(batch, _batch_ws(plans, ws), n, _stream(stream)))
+
+
+def npo_batch_step(batch, plans, ws, states, phase, stream=None):
+    """phase 0: states = [u_i]; phase 1: states = [u_i, lam_i, u_j, lam_j, ...]."""
+    per = 2 if phase else 1
+    ptrs = [_fld(plans[k // per], t, "state") for k, t in enumerate(states)]
+    if len(ptrs) != per * len(plans):
+        raise NpoError(f"{per * len(plans)} states expected")
+    _check(lib().npo_batch_step(batch, _parr(ptrs), _batch_ws(plans, ws), phase, _stream(stream)))
+
+
+def npo_batch_forward_run(batch, plans, ws, ckpts, n_ckpt, u0s, uNs, stream=None):
+    _check(lib().npo_batch_forward_run(
+        batch, _batch_ws(plans, ws), _parr([_fld(p, c, "checkpoint arena", max(int(n_ckpt), 1)) for p, c in zip(plans, ckpts)]),
+        n_ckpt, _parr([_fld(p, u, "u0") for p, u in zip(plans, u0s)]),
+        _parr([_fld(p, u, "uN") for p, u in zip(plans, uNs)]), _stream(stream)))
+
+
+def npo_batch_adjoint_run(batch, plans, ws, ckpts, n_ckpt, lamNs, lam0s, stream=None):
+    c = _I64()
+    _check(lib().npo_batch_adjoint_run(
+        batch, _batch_ws(plans, ws), _parr([_fld(p, a, "checkpoint arena", max(int(n_ckpt), 1)) for p, a in zip(plans, ckpts)]),
+        n_ckpt, _parr([_fld(p, u, "lamN") for p, u in zip(plans, lamNs)]),
+        _parr([_fld(p, u, "lam0") for p, u in zip(plans, lam0s)]), ctypes.byref(c), _stream(stream)))
+    return c.value
 
 
 def npo_profile_begin(plan, stride=1):

@@ -15,6 +15,7 @@ taken on other kernels are never reported.
 Usage:
   python -m paper_2509_10103_amd.profsum trace  <kernel_stats.csv> <bench.log> <out.md> <command>
   python -m paper_2509_10103_amd.profsum bytes  <fetch.csv> <write.csv> <copy_fetch.csv> <copy_write.csv> <out.md> <commands>
+  python -m paper_2509_10103_amd.profsum counters <counter_collection.csv> <out.md> <command> <nt> <nz> <shapes>
 """
 import collections
 import csv
@@ -62,6 +63,10 @@ def family_kernels(nt, nz, names=(), shapes=(1, 4, 4), nr=64):
     zi = (lambda nf: f"k_zinv_{zk}<{nz}, {6 if nf == 3 else 0}, {nf}{mb(nf)}>") if fz else (lambda nf: "k_zinv")
     zf = (lambda nf: f"k_zfwd_{zk}<{nz}, {nf}{mb(nf)}>") if fz else (lambda nf: "k_zfwd")
     def th(a):
+        if not a and zbf < 0:
+            return f"k_theta_w<{nt}, {-zbf}>"
+        if a and zba < 0:
+            return f"k_theta_wa<{nt}, {-zba}>"
         if not ft:
             return "k_theta"
         if nt % 12 == 0:
@@ -143,6 +148,46 @@ def bytes_summary(fetch_csv, write_csv, cf_csv, cw_csv, out_md, commands, nt, nz
     open(out_md, "w").write("\n".join(lines))
 
 
+def counters_summary(csv_path, out_md, command, nt, nz, shapes, nr=64):
+    """Per-kernel averages (per dispatch) of the SQ counters of one --pmc run,
+    with derived figures: VALU and LDS instructions per wave, the fraction of
+    busy cycles with a VALU instruction issued, LDS bank-conflict cycles per
+    LDS instruction."""
+    rows = list(csv.DictReader(open(csv_path)))
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in rows:
+        per[short_name(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    fam = family_kernels(nt, nz, set(per), shapes, nr)
+    inv = {v: k for k, v in fam.items()}
+    names = sorted({c for k in per.values() for c in k})
+    lines = [f"# SQ counters per dispatch: workload grid {nt}x{nz} (theta x z)", "",
+             f"Command (repository root, one MI355X): `{command}`", "",
+             f"Launch shapes (zgroup, theta z-block forward, adjoint): {shapes}.", "",
+             "Derived: VALU/wave = SQ_INSTS_VALU / SQ_WAVES; LDS/wave = SQ_INSTS_LDS / SQ_WAVES; "
+             "VALU busy = SQ_ACTIVE_INST_VALU / SQ_BUSY_CYCLES (per SE, summed over SEs, so a ratio of "
+             "aggregates); conflict/LDS = SQ_LDS_BANK_CONFLICT / SQ_INSTS_LDS; LDS wait = SQ_WAIT_INST_LDS / "
+             "SQ_WAVE_CYCLES.", "",
+             "| family | kernel | dispatches | waves | VALU/wave | LDS/wave | VALU busy | conflict/LDS | LDS wait |",
+             "|---|---|---:|---:|---:|---:|---:|---:|---:|"]
+    blob = {}
+    for k in sorted(per, key=lambda x: inv.get(x, "~" + x)):
+        c = {n: sum(v) / len(v) for n, v in per[k].items()}
+        nd = max(len(v) for v in per[k].values())
+        w = c.get("SQ_WAVES", 0.0) or 1.0
+        valu = c.get("SQ_INSTS_VALU", 0.0) / w
+        lds = c.get("SQ_INSTS_LDS", 0.0) / w
+        busy = c.get("SQ_ACTIVE_INST_VALU", 0.0) / (c.get("SQ_BUSY_CYCLES", 0.0) or 1.0)
+        conf = c.get("SQ_LDS_BANK_CONFLICT", 0.0) / (c.get("SQ_INSTS_LDS", 0.0) or 1.0)
+        wait = c.get("SQ_WAIT_INST_LDS", 0.0) / (c.get("SQ_WAVE_CYCLES", 0.0) or 1.0)
+        blob[k] = c
+        if k not in inv:
+            continue
+        lines.append(f"| {inv[k]} | `{k}` | {nd} | {w:.0f} | {valu:.0f} | {lds:.0f} | {busy:.3f} | {conf:.3f} | "
+                     f"{wait:.3f} |")
+    lines += ["", "Raw per-dispatch averages:", "", "```json", json.dumps(blob, indent=1, sort_keys=True), "```", ""]
+    open(out_md, "w").write("\n".join(lines))
+
+
 def load_traffic(path, nt, nz):
     """bytes_per_launch from a byte summary, or None if absent or taken on
     other kernel sources or transform lengths (the launch shapes it records
@@ -161,6 +206,9 @@ def load_traffic(path, nt, nz):
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(*sys.argv[2:6])
+    elif sys.argv[1] == "counters":
+        a = sys.argv[2:]
+        counters_summary(a[0], a[1], a[2], int(a[3]), int(a[4]), [int(x) for x in a[5].split(",")])
     elif sys.argv[1] == "bytes":
         a = sys.argv[2:]
         bytes_summary(a[0], a[1], a[2], a[3], a[4], a[5].split(" ;; "), int(a[6]), int(a[7]),

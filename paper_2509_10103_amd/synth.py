@@ -72,7 +72,7 @@ def z_envelope(a, lz, nz_phys, sigma, centre):
     Z[..., pos] = a
     f = np.fft.ifft(Z, axis=-1) * nz_phys
     b = np.fft.fft(f * g, axis=-1) / nz_phys
-    return _hermitian_m0(b[..., pos], K)
+    return np.ascontiguousarray(_hermitian_m0(b[..., pos], K))   # C order: device copies keep the layout
 
 
 def localized_oblique(r, M, K, lz, nz_phys, seed, amin=3.5, amax=6.5, sigma=6.0):

@@ -19,7 +19,7 @@ def candidates(plan):
     """Launch shapes the library accepts for this plan (it checks LDS fit and
     divisibility itself)."""
     out = []
-    for c in itertools.product((1, 2, 3), (2, 4, 8), (2, 4, 8)):
+    for c in itertools.product((1, 2, 3), (-16, -8, 2, 4, 8), (-16, -8, 2, 4, 8)):
         try:
             npo.npo_plan_set_tuning(plan.handle, *c)
         except npo.NpoError:
@@ -52,19 +52,32 @@ def load_cache():
         return {}
 
 
-def tune(plan, nr, nt, nz, reps=3, use_cache=True, save=True):
-    """Pick and set the fastest launch shapes for this plan; returns them."""
+def tune(plan, nr, nt, nz, reps=3, use_cache=True, save=True, batched=False):
+    """Pick and set the fastest launch shapes for this plan; returns them.
+
+    batched: only shapes whose kernels have batched forms (the LDS-staged
+    azimuthal kernels, not the wave-resident ones), for npo_batch_* runs."""
     import torch
     key = f"{nr}x{nt}x{nz}"
     cache = load_cache() if use_cache else {}
     if key in cache:
-        best = tuple(cache[key]["shape"])
+        rec = cache[key]
+        best = tuple(rec["shape"])
+        if batched and min(best) < 0:
+            ok = {k: v for k, v in rec.get("all", {}).items() if min(int(x) for x in k.split(",")) > 0}
+            if ok:
+                best = tuple(int(x) for x in min(ok, key=ok.get).split(","))
+            else:
+                best = npo.npo_plan_get_tuning(plan.handle)
+                best = tuple(max(b, 2) if b < 0 else b for b in best)
         npo.npo_plan_set_tuning(plan.handle, *best)
-        return best, cache[key]
+        return best, rec
     u = torch.randn(plan.shape, dtype=torch.complex128, device=plan.device) * 1e-3
     lam = torch.randn(plan.shape, dtype=torch.complex128, device=plan.device)
     timings = {}
     for c in candidates(plan):
+        if batched and min(c) < 0:
+            continue
         npo.npo_plan_set_tuning(plan.handle, *c)
         timings[c] = _time_steps(plan, u, lam, reps)
     best = min(timings, key=timings.get)

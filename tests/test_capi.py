@@ -85,3 +85,34 @@ def test_null_arguments_are_rejected():
     assert L.npo_forward_step(None, None, None, None, 0, None) == -1
     assert L.npo_ckpt_count(0, 1, None) == -1
     assert b"null" in L.npo_last_error() or b"bad" in L.npo_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libnpo.so not built")
+def test_hybrid_counts_match_the_recovery_model():
+    """Sec. 2.4 two-level checkpoints: with n_file host checkpoints the adjoint
+    sweep re-advances sum_i T(l_i) - (l_last - 1) steps, T(l) = S l - beta(N_G+1, S-1)
+    the advances to recover an interval of l steps from N_G memory checkpoints
+    (the oracle's closed form); no host checkpoints is the device-only count."""
+    from paper_2509_10103_amd import npo
+    from oracle.checkpoint import closed_form
+    for n in (7, 40, 500, 9817):
+        for s in (1, 3, 8, 40):
+            assert npo.npo_hybrid_count(n, s, 0) == npo.npo_ckpt_count(n, s)
+            for f in (1, 2, 5):
+                if f >= n:
+                    continue
+                b = [n * i // (f + 1) for i in range(f + 2)]
+                ls = [b[i + 1] - b[i] for i in range(f + 1)]
+                model = sum(closed_form(l, s)[0] for l in ls) - (ls[-1] - 1)
+                assert npo.npo_hybrid_count(n, s, f) == model, (n, s, f)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libnpo.so not built")
+def test_hybrid_plan_minimises_recovery_time():
+    from paper_2509_10103_amd import npo
+    for n, s, tio, tstep in ((9817, 8, 2e-3, 1.3e-3), (9817, 64, 5e-2, 1.3e-3), (4000, 4, 0.0, 1.0),
+                             (4000, 4000, 1.0, 1.0)):
+        f, t = npo.npo_hybrid_plan(n, s, tio, tstep, 64)
+        costs = [k * tio + npo.npo_hybrid_count(n, s, k) * tstep for k in range(0, 65)]
+        assert abs(t - min(costs)) <= 1e-12 * max(1.0, abs(t))
+        assert costs[f] == min(costs)

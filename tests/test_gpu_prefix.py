@@ -54,7 +54,7 @@ def case(request):
     print(f"[prefix] {request.param} {c['nr']}x{c['nt']}x{c['nz']} nsteps={c['nsteps']}", flush=True)
     torch.cuda.set_device(0)
     G = npo.Plan(c["nr"], c["nt"], c["nz"], c["lz"], c["re"], c["wo"], c["amp"], c["dt"], c["t0"], c["nsteps"])
-    raw = torch.from_numpy(_script().raw_seed(c)).to("cuda")
+    raw = torch.from_numpy(np.ascontiguousarray(_script().raw_seed(c))).to("cuda")
     u0 = G.field()
     npo.npo_project(G.handle, G.ws, raw, u0)
     npo.npo_normalize(G.handle, G.ws, u0, c["e0"])
