@@ -54,3 +54,20 @@ def test_wall_rows_one_sided_any_parity():
         d1 = q * (r - 0.3) ** (q - 1) if q else 0 * r
         for p in (1, -1):
             assert np.max(np.abs((R.D1[p] @ f - d1)[-3:])) < 1e-8
+
+
+def test_poisson_conditioning_at_64_nodes_bounds_the_solve_tolerance():
+    """The kernel-level parity bound at 64 radial nodes (1e-10 for the solves,
+    ten times the others) rests on the conditioning of the interior Poisson
+    operator: kappa_2 ~ 2e6 for m = 0, alpha = 0 on the clustered nodes, so two
+    backward-stable double-precision solves (the oracle's pivoted LAPACK one,
+    the library's unpivoted banded one with long-double factors) may differ by
+    up to ~2 kappa eps ~ 5e-10 relative; the Helmholtz operators are benign."""
+    import numpy as np
+    R = Radial(64)
+    L = R.lap(0, 0.0)[:-1, :-1]
+    k = np.linalg.cond(L)
+    assert 1e6 < k < 1e7
+    assert 2 * k * np.finfo(float).eps > 1e-10
+    H = np.eye(63) / 0.02 - L / (2 * 2000.0)
+    assert np.linalg.cond(H) < 1e2
