@@ -76,6 +76,7 @@ class Server:
         self.done = []
         self.used = 0
         self.closed = False
+        self.halted = False
         self.next_id = 0
         self._threads = []
 
@@ -96,6 +97,15 @@ class Server:
     def close(self):
         with self.lock:
             self.closed = True
+            self.lock.notify_all()
+
+    def halt(self):
+        """Stop at the next iteration boundary: nothing more is admitted, and
+        active jobs are released after their current iteration (they stay
+        unfinished in the report)."""
+        with self.lock:
+            self.closed = True
+            self.halted = True
             self.lock.notify_all()
 
     # ------------------------------------------------------------ scheduling
@@ -129,10 +139,16 @@ class Server:
     def _worker(self):
         while True:
             with self.lock:
+                if self.halted:
+                    self._release_idle_locked()
+                    return
                 self._admit_locked()
                 j = self._next_locked()
                 while j is None:
                     if self.closed and not self.pending and not self.active:
+                        return
+                    if self.halted:
+                        self._release_idle_locked()
                         return
                     self.lock.wait(timeout=0.05)
                     self._admit_locked()
@@ -168,6 +184,12 @@ class Server:
                     j.busy = False
                     self._retire_locked(j)
 
+    def _release_idle_locked(self):
+        for j in list(self.active):
+            if not j.busy and j.runner is not None:
+                j.runner.release()
+                j.runner = None
+
     def start(self):
         for _ in range(self.workers):
             t = threading.Thread(target=self._worker, daemon=True)
@@ -181,16 +203,21 @@ class Server:
 
     # ------------------------------------------------------------ reporting
     def report(self, t_start, t_end):
-        lat = [x for j in self.done for x in j.latencies]
-        waits = [j.admitted - j.arrival for j in self.done if j.admitted is not None]
-        counted = sum(j.counted for j in self.done)
+        jobs = self.done + self.active
+        lat = [x for j in jobs for x in j.latencies]
+        waits = [j.admitted - j.arrival for j in jobs if j.admitted is not None]
+        counted = sum(j.counted for j in jobs)
         a = np.asarray(lat) if lat else np.zeros(1)
         w = np.asarray(waits) if waits else np.zeros(1)
+        still = [t_end - j.arrival for _, _, j in self.pending]
         return {
             "jobs": len(self.done), "failed": sum(1 for j in self.done if j.error),
+            "unfinished_admitted": len(self.active), "never_admitted": len(self.pending),
             "iterations": len(lat),
             "iteration_latency_s": {"p50": float(np.percentile(a, 50)), "p99": float(np.percentile(a, 99))},
             "queue_wait_s": {"p50": float(np.percentile(w, 50)), "p99": float(np.percentile(w, 99))},
+            "wait_of_never_admitted_s": {"p50": float(np.percentile(still, 50)) if still else 0.0,
+                                         "max": float(max(still)) if still else 0.0},
             "gp_steps_per_s": counted / max(t_end - t_start, 1e-9),
             "wall_s": t_end - t_start,
         }
@@ -206,15 +233,32 @@ def poisson_arrivals(n, rate, seed):
     return np.cumsum(rng.exponential(1.0 / rate, size=n))
 
 
-def replay(server, cfgs, iters, arrivals):
-    """Submit cfgs at the given arrival offsets (seconds) and wait for all."""
+def replay(server, cfgs, iters, arrivals, budget=None):
+    """Submit cfgs at the given arrival offsets (seconds) and wait for all, or
+    halt the server after `budget` seconds (then the report counts what was
+    done, what is unfinished and what never got in)."""
     t0 = time.perf_counter()
     server.start()
     jobs = []
     for c, a in zip(cfgs, arrivals):
         now = time.perf_counter() - t0
+        if budget is not None and a > budget:
+            break
         if a > now:
             time.sleep(a - now)
-        jobs.append(server.submit(c, iters))
-    server.join()
+        jobs.append(server.submit(c, iters, arrival=time.perf_counter()))
+    if budget is not None:
+        left = budget - (time.perf_counter() - t0)
+        done = threading.Event()
+
+        def waiter():
+            server.join()
+            done.set()
+        th = threading.Thread(target=waiter, daemon=True)
+        th.start()
+        if not done.wait(timeout=max(left, 0.0)):
+            server.halt()
+            th.join()
+    else:
+        server.join()
     return jobs, server.report(t0, time.perf_counter())

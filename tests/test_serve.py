@@ -110,3 +110,26 @@ def test_late_arrivals_join_running_work():
     e = [i for i, (n, k) in enumerate(FakeRunner.log) if n == "early"]
     l = [i for i, (n, k) in enumerate(FakeRunner.log) if n == "late"]
     assert l[0] < e[-1]       # the late job starts before the early one finishes
+
+
+def test_wall_budget_halts_and_reports_unfinished_work():
+    """replay(..., budget): arrivals after the budget are not submitted; at the
+    budget the server stops at iteration boundaries, and the report separates
+    finished jobs, admitted-but-unfinished ones and requests that never got in."""
+    from paper_2509_10103_amd.serve import replay
+    released = []
+
+    class R(FakeRunner):
+        def release(self):
+            released.append(self.cfg["name"])
+
+    s = Server(hbm_budget=1e15, max_active=2, workers=2, factory=R)
+    cfgs = [cfg(f"b{i}", t=0.05) for i in range(8)]
+    arrivals = [0.0, 0.0, 0.01, 0.02, 0.03, 0.04, 5.0, 6.0]      # the last two arrive after the budget
+    t = time.perf_counter()
+    jobs, rep = replay(s, cfgs, 100, arrivals, budget=0.6)
+    assert time.perf_counter() - t < 2.0
+    assert len(jobs) == 6
+    assert rep["jobs"] == 0 and rep["unfinished_admitted"] == 2 and rep["never_admitted"] == 4
+    assert rep["iterations"] > 0
+    assert sorted(released) == sorted(j.cfg["name"] for j in jobs if j.admitted is not None)
