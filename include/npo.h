@@ -33,6 +33,9 @@
  * Errors: argument and shape errors return synchronously (NPO_EINVAL,
  * NPO_EUNSUPPORTED) before anything is enqueued; launch and runtime errors
  * return NPO_EHIP.  npo_last_error() gives a message for the calling thread.
+ *
+ * Tracing: with NPO_TRACE=1 in the environment the plan, sweep, iteration and
+ * batch calls open roctx ranges (rocprofv3 --marker-trace shows them).
  */
 #ifndef NPO_H
 #define NPO_H
@@ -260,6 +263,28 @@ npo_status npo_plan_get_tuning(npo_plan plan, int32_t* zgroup, int32_t* zb_fwd, 
  * are not used while the sampling profiler runs.  Results are bitwise those of
  * enable = 0.  Default 0. */
 npo_status npo_plan_set_graphs(npo_plan plan, int32_t enable);
+
+/* CFL monitor (enable = 1): every forward step folds the CFL number of its
+ * state u^n, max over the physical 3/2-rule points of
+ * dt (|u_z + U| / dz + |u_theta| / (r dtheta) + |u_r| / dr_j) with dr_j the
+ * smaller gap to a neighbouring radial node (2 r_0 at the first node), into a
+ * device maximum kept in the workspace (the explicit convective terms of the
+ * predictor-corrector step are stable only below a bound of order one).
+ * Supported where the forward azimuthal pass runs the pruned kernel (ntheta
+ * a multiple of 12 with zb_fwd > 0); elsewhere the monitor reads 0.  Drops
+ * captured graphs.  npo_cfl_read copies the maximum so far into out_dev (one
+ * device double) on `stream` and, with reset = 1, clears it; the maximum lives
+ * in the workspace, so clear it (a read with reset = 1) before the first
+ * monitored step of a new workspace. */
+npo_status npo_plan_set_cfl_monitor(npo_plan plan, int32_t enable);
+npo_status npo_cfl_read(npo_plan plan, void* ws, double* out_dev, int32_t reset, void* stream);
+
+/* Failure injection for tests of error handling (no device fault is made):
+ * after `after` more calls of the step driver at `site` (1: forward step,
+ * 2: adjoint step; 0: off), the next call returns NPO_EHIP from the entry point
+ * that made it, as a failed launch would, before enqueueing that step.  Steps
+ * replayed from captured graphs are not counted. */
+npo_status npo_plan_inject_fault(npo_plan plan, int32_t site, int64_t after);
 
 /* out = scale * q (.) lam with q = 2 pi L_z c_m w_j: converts the W-gradient
  * lam of a real functional into the gradient with respect to the real and

@@ -3,10 +3,13 @@
 #include "npo_internal.h"
 #include "../../include/npo.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <string>
@@ -30,6 +33,25 @@ npo_status hipfail(hipError_t e, const char* where) {
     } while (0)
 
 using ld = long double;
+
+// roctx ranges around the plan, sweep, iteration and batch calls when the
+// environment has NPO_TRACE=1.
+bool trace_on() {
+    static const bool on = [] {
+        const char* e = std::getenv("NPO_TRACE");
+        return e && e[0] == '1';
+    }();
+    return on;
+}
+struct Trace {
+    bool on;
+    explicit Trace(const char* name) : on(trace_on()) {
+        if (on) roctxRangePushA(name);
+    }
+    ~Trace() {
+        if (on) roctxRangePop();
+    }
+};
 
 // ---------------------------------------------------------------- tables
 // Radial nodes: positive half of a 2N-point Chebyshev-Gauss-Lobatto grid.
@@ -294,16 +316,29 @@ WsPtrs wsptrs(const npo_plan_s& p, void* ws) {
 
 // Evaluation time t0 + (n + off) dt, with n from the device step index when
 // dstep is given (captured graphs) and by value otherwise.
-npo::TimeArg at_step(const long long* dstep, long long n, int off) { return npo::TimeArg{dstep, n, off, 0, 0.0}; }
+npo::TimeArg at_step(const long long* dstep, long long n, int off, unsigned long long* cfl = nullptr) {
+    return npo::TimeArg{dstep, n, off, 0, 0.0, cfl};
+}
+
+// The device maximum of the CFL monitor sits 64 bytes after the step index.
+unsigned long long* cfl_slot(const WsPtrs& w) { return reinterpret_cast<unsigned long long*>(w.step) + 8; }
+
+// An injected failure (npo_plan_inject_fault) of this step driver.
+bool injected(const npo_plan_s& p, int site) {
+    if (p.fault_site != site) return false;
+    return p.fault_after-- == 0;
+}
 
 // u_out = Phi(u_n).  If have_aux, w.aux0 already holds the vorticity parts of u_n.
 // Stages: w_0 = S(E u + N(u)), w_c = S(E u + (N(u) + N(w_{c-1}))/2), u_out = w_ncorr;
 // the predictor leaves R0 = E u + N(u)/2, and each corrector solves S(R0 + N(w_{c-1})/2).
+
 hipError_t fwd_step(const npo_plan_s& p, void* ws, const double2* un, double2* uout, long long n, bool have_aux,
                     hipStream_t st, const long long* dstep = nullptr) {
+    if (injected(p, 1)) return hipErrorLaunchFailure;
     WsPtrs w = wsptrs(p, ws);
     hipError_t e;
-    const npo::TimeArg t0 = at_step(dstep, n, 0), t1 = at_step(dstep, n, 1);
+    const npo::TimeArg t0 = at_step(dstep, n, 0, p.cfl_monitor ? cfl_slot(w) : nullptr), t1 = at_step(dstep, n, 1);
     if (!have_aux && (e = npo::launch_curl_aux(p, un, w.aux0, st)) != hipSuccess) return e;
     if ((e = npo::launch_nl(p, 0, un, w.aux0, nullptr, t0, w.nn, nullptr, ws, st)) != hipSuccess) return e;
     if ((e = npo::launch_solve(p, 1, un, w.nn, w.st[0], w.auxs[0], st, w.r0)) != hipSuccess) return e;
@@ -323,6 +358,7 @@ hipError_t fwd_step(const npo_plan_s& p, void* ws, const double2* un, double2* u
 //   lam_n = E^+ (sum mu_c) + N'(u_n)^+ (mu_0 + sum_{c>=1} mu_c / 2).
 hipError_t adj_step(const npo_plan_s& p, void* ws, const double2* un, const double2* lamin, double2* lamout,
                     long long n, hipStream_t st, const long long* dstep = nullptr, bool have_aux = false) {
+    if (injected(p, 2)) return hipErrorLaunchFailure;
     WsPtrs w = wsptrs(p, ws);
     hipError_t e;
     const npo::TimeArg t0 = at_step(dstep, n, 0), t1 = at_step(dstep, n, 1);
@@ -447,6 +483,7 @@ const char* npo_last_error(void) { return g_err.c_str(); }
 
 npo_status npo_plan_create(const npo_grid* grid, const npo_flow* flow, const npo_time* time, uint32_t flags,
                            npo_plan* out) {
+    Trace trace_("npo_plan_create");
     g_err.clear();
     if (!grid || !flow || !time || !out) return fail(NPO_EINVAL, "null argument");
     if (flags != 0) return fail(NPO_EINVAL, "flags must be 0");
@@ -781,7 +818,7 @@ npo_status npo_nonlinear(npo_plan p, void* ws, const void* u, double t, void* ou
     if (check_plan(p) || !ws || !u || !out) return fail(NPO_EINVAL, "null argument");
     WsPtrs w = wsptrs(*p, ws);
     HIPCHK(npo::launch_curl_aux(*p, CF(u), w.aux0, ST(stream)));
-    HIPCHK(npo::launch_nl(*p, 0, CF(u), w.aux0, nullptr, npo::TimeArg{nullptr, 0, 0, 1, t}, F(out), nullptr, ws,
+    HIPCHK(npo::launch_nl(*p, 0, CF(u), w.aux0, nullptr, npo::TimeArg{nullptr, 0, 0, 1, t, nullptr}, F(out), nullptr, ws,
                           ST(stream)));
     return NPO_OK;
 }
@@ -790,7 +827,7 @@ npo_status npo_nonlinear_adj(npo_plan p, void* ws, const void* u, double t, cons
     if (check_plan(p) || !ws || !u || !y || !out) return fail(NPO_EINVAL, "null argument");
     WsPtrs w = wsptrs(*p, ws);
     HIPCHK(npo::launch_curl_aux(*p, CF(u), w.aux0, ST(stream)));
-    HIPCHK(npo::launch_nl(*p, 1, CF(u), w.aux0, CF(y), npo::TimeArg{nullptr, 0, 0, 1, t}, w.fa, w.fb, ws,
+    HIPCHK(npo::launch_nl(*p, 1, CF(u), w.aux0, CF(y), npo::TimeArg{nullptr, 0, 0, 1, t, nullptr}, w.fa, w.fb, ws,
                           ST(stream)));
     HIPCHK(npo::launch_final(*p, nullptr, w.fa, w.fb, F(out), ST(stream)));
     return NPO_OK;
@@ -924,6 +961,7 @@ static npo_status forward_run(npo_plan p, void* ws, void* ckpt, int32_t nck, con
 }
 
 npo_status npo_forward_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const void* u0, void* uN, void* stream) {
+    Trace trace_("npo_forward_run");
     return forward_run(p, ws, ckpt, nck, u0, uN, nullptr, 1, stream);
 }
 
@@ -1008,6 +1046,7 @@ static npo_status adjoint_run(npo_plan p, void* ws, void* ckpt, int32_t nck, con
 
 npo_status npo_adjoint_run(npo_plan p, void* ws, void* ckpt, int32_t nck, const void* lamN, void* lam0,
                            int64_t* n_recompute, void* stream) {
+    Trace trace_("npo_adjoint_run");
     return adjoint_run(p, ws, ckpt, nck, lamN, lam0, n_recompute, stream);
 }
 
@@ -1019,6 +1058,7 @@ static long long hybrid_bound(long long nsteps, int n_file, int i) {
 
 npo_status npo_forward_run_hybrid(npo_plan p, void* ws, void* ckpt, int32_t nck, void* host_tier, int32_t n_file,
                                   const void* u0, void* uN, void* stream) {
+    Trace trace_("npo_forward_run_hybrid");
     if (check_plan(p) || !ws || !ckpt || !u0 || !uN || (n_file > 0 && !host_tier))
         return fail(NPO_EINVAL, "null argument");
     if (n_file < 0 || n_file >= p->nsteps) return fail(NPO_EINVAL, "n_file must be in [0, nsteps)");
@@ -1046,6 +1086,7 @@ npo_status npo_forward_run_hybrid(npo_plan p, void* ws, void* ckpt, int32_t nck,
 
 npo_status npo_adjoint_run_hybrid(npo_plan p, void* ws, void* ckpt, int32_t nck, const void* host_tier,
                                   int32_t n_file, const void* lamN, void* lam0, int64_t* n_recompute, void* stream) {
+    Trace trace_("npo_adjoint_run_hybrid");
     if (check_plan(p) || !ws || !ckpt || !lamN || !lam0 || (n_file > 0 && !host_tier))
         return fail(NPO_EINVAL, "null argument");
     if (n_file < 0 || n_file >= p->nsteps) return fail(NPO_EINVAL, "n_file must be in [0, nsteps)");
@@ -1178,6 +1219,7 @@ npo_status npo_update(npo_plan p, void* ws, const void* u0, const void* g, doubl
 
 npo_status npo_iterate(npo_plan p, void* ws, void* ckpt, int32_t nck, void* u0, void* uN, double e0, double tol,
                        int32_t max_halvings, double* stats, void* stream) {
+    Trace trace_("npo_iterate");
     if (check_plan(p) || !ws || !ckpt || !u0 || !uN || !stats) return fail(NPO_EINVAL, "null argument");
     if (!(e0 > 0) || max_halvings < 0) return fail(NPO_EINVAL, "bad e0 or max_halvings");
     const hipStream_t st = ST(stream);
@@ -1247,6 +1289,31 @@ npo_status npo_plan_set_tuning(npo_plan p, int32_t zgroup, int32_t zb_fwd, int32
     p->zb_theta_fwd = zb_fwd;
     p->zb_theta_adj = zb_adj;
     drop_graphs(*p);          // launch shapes are baked into captured graphs
+    return NPO_OK;
+}
+
+npo_status npo_plan_set_cfl_monitor(npo_plan p, int32_t enable) {
+    if (check_plan(p)) return NPO_EINVAL;
+    if (enable != 0 && enable != 1) return fail(NPO_EINVAL, "enable must be 0 or 1");
+    p->cfl_monitor = enable != 0;
+    drop_graphs(*p);          // the monitor's pointer is part of the captured launches
+    return NPO_OK;
+}
+
+npo_status npo_cfl_read(npo_plan p, void* ws, double* out_dev, int32_t reset, void* stream) {
+    if (check_plan(p) || !ws || !out_dev) return fail(NPO_EINVAL, "null argument");
+    WsPtrs w = wsptrs(*p, ws);
+    const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    HIPCHK(hipMemcpyAsync(out_dev, cfl_slot(w), 8, hipMemcpyDeviceToDevice, st));
+    if (reset) HIPCHK(npo::launch_fill_u64(cfl_slot(w), 0ull, st));
+    return NPO_OK;
+}
+
+npo_status npo_plan_inject_fault(npo_plan p, int32_t site, int64_t after) {
+    if (check_plan(p)) return NPO_EINVAL;
+    if (site < 0 || site > 2 || after < 0) return fail(NPO_EINVAL, "site must be 0, 1 or 2 and after >= 0");
+    p->fault_site = site;
+    p->fault_after = after;
     return NPO_OK;
 }
 
@@ -1342,7 +1409,8 @@ namespace {
 
 bool same_class(const npo_plan_s& a, const npo_plan_s& b) {
     return a.nr == b.nr && a.nt == b.nt && a.nz == b.nz && a.ncorr == b.ncorr && a.zgroup == b.zgroup &&
-           a.zb_theta_fwd == b.zb_theta_fwd && a.zb_theta_adj == b.zb_theta_adj && a.device == b.device;
+           a.zb_theta_fwd == b.zb_theta_fwd && a.zb_theta_adj == b.zb_theta_adj && a.device == b.device &&
+           a.cfl_monitor == b.cfl_monitor;
 }
 
 void drop_phase(npo_batch_s::Phase& f) {
@@ -1530,6 +1598,7 @@ npo_status npo_batch_info(npo_batch b, int32_t* n_classes, int32_t* n_batched, i
 }
 
 npo_status npo_batch_step(npo_batch b, void* const* states, void* const* ws, int32_t phase, void* stream) {
+    Trace trace_("npo_batch_step");
     npo_status s = batch_check(b, ws);
     if (s) return s;
     if (!states || (phase != 0 && phase != 1)) return fail(NPO_EINVAL, "states must be given and phase 0 or 1");
@@ -1572,6 +1641,7 @@ npo_status npo_batch_set_steps(npo_batch b, void* const* ws, int64_t n, void* st
 // per-instance device copies between the workspace's cur and the slots.
 npo_status npo_batch_forward_run(npo_batch b, void* const* ws, void* const* ckpt, int32_t nck, void* const* u0,
                                  void* const* uN, void* stream) {
+    Trace trace_("npo_batch_forward_run");
     npo_status s = batch_check(b, ws);
     if (s) return s;
     if (!ckpt || !u0 || !uN || nck < 1) return fail(NPO_EINVAL, "null argument or n_ckpt < 1");
@@ -1616,6 +1686,7 @@ npo_status npo_batch_forward_run(npo_batch b, void* const* ws, void* const* ckpt
 
 npo_status npo_batch_adjoint_run(npo_batch b, void* const* ws, void* const* ckpt, int32_t nck, void* const* lamN,
                                  void* const* lam0, int64_t* n_recompute, void* stream) {
+    Trace trace_("npo_batch_adjoint_run");
     npo_status s = batch_check(b, ws);
     if (s) return s;
     if (!ckpt || !lamN || !lam0 || nck < 1) return fail(NPO_EINVAL, "null argument or n_ckpt < 1");

@@ -64,6 +64,11 @@ struct TimeArg {
     int off;
     int direct;
     double t;
+    // CFL monitor (optional): the evaluation folds the largest
+    // dt (|u_z + U| / dz + |u_theta| / (r dtheta) + |u_r| / dr) over its
+    // physical points into *cfl (a non-negative double's bit pattern, so an
+    // unsigned integer maximum orders it)
+    unsigned long long* cfl;
 };
 
 // Work descriptor of one instance in a batched launch: one launch per kernel
@@ -120,6 +125,12 @@ struct npo_plan_s {
     int zb_theta_fwd = 4, zb_theta_adj = 4;
     int zgroup = 1;
     mutable npo::Profiler prof;
+    // CFL monitor of the forward steps (npo_plan_set_cfl_monitor)
+    bool cfl_monitor = false;
+    // injected failure of the step drivers (npo_plan_inject_fault): site 1
+    // forward steps, 2 adjoint steps; the call after `fault_after` more calls fails
+    int fault_site = 0;
+    mutable long long fault_after = 0;
     // captured step graphs (see npo_plan_set_graphs); rebuilt for a new workspace
     bool use_graphs = false;
     void* graph_ws = nullptr;
@@ -190,6 +201,8 @@ hipError_t launch_nl(const npo_plan_s& p, int adjoint, const double2* u, const d
                      const double2* uw_pre = nullptr, double2* uw_save = nullptr);
 // *d = v (set) or *d += v (add), one thread.
 hipError_t launch_step_index(long long* d, long long v, int add, hipStream_t st);
+// *d = v (one 64-bit word).
+hipError_t launch_fill_u64(unsigned long long* d, unsigned long long v, hipStream_t st);
 // The same for the step index of every instance of a descriptor table.
 hipError_t launch_step_index_batched(const BDesc* bd, int nb, long long v, int add, hipStream_t st);
 

@@ -1208,6 +1208,15 @@ Recorder*& recorder() {
 }
 
 
+// *d = v for one 64-bit word (a fill kernel, so that capture-safe clears need no memset node).
+__global__ void k_fill_u64(unsigned long long* d, unsigned long long v) {
+    if (threadIdx.x == 0) *d = v;
+}
+hipError_t launch_fill_u64(unsigned long long* d, unsigned long long v, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, d, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_step_index(long long* d, long long v, int add, hipStream_t st) {
     if (recorder()) return hipErrorInvalidValue;     // the batch advances its step indices itself
     hipLaunchKernelGGL(k_step_index, dim3(1), dim3(64), 0, st, d, v, add, nullptr);

@@ -986,7 +986,9 @@ __device__ __forceinline__ void theta_last_pair(const double2* R, const double2*
 //    both butterflies unpacks the two real fields and stores them.
 // N_z is transformed as its own (real) sequence.  Five barriers per tile
 // instead of eight, and about 40% fewer LDS accesses than the generic plan.
-template <int NT, int ZB>
+// CFL: also fold the CFL number of u into *ta.cfl (a separate instance, so
+// the plain kernel keeps its register budget and occupancy).
+template <int NT, int ZB, bool CFL>
 __global__ __launch_bounds__(TB) void k_theta_p(KP p, int nq, int Q, const double2* __restrict__ zu, int nfu,
                                                double2* __restrict__ tb, TimeArg ta, const BDesc* __restrict__ bd) {
     static_assert(NT % 12 == 0, "N_theta = 3P with P a multiple of 4");
@@ -1015,6 +1017,17 @@ __global__ __launch_bounds__(TB) void k_theta_p(KP p, int nq, int Q, const doubl
     double U, Om, cw, sw;
     phase_of(p, ta, cw, sw);
     base_at(p, j, cw, sw, U, Om);
+    // CFL monitor: dt / dz, dt / (r dtheta), dt / dr at this radial node (dr:
+    // the smaller neighbour gap; the axis gap of the first node is 2 r_0)
+    double cmax = 0.0, cz = 0.0, cth = 0.0, cr = 0.0;
+    if constexpr (CFL) {
+        const double rj = p.r[j];
+        const double gl = j > 0 ? rj - p.r[j - 1] : 2.0 * rj;
+        const double gr = j + 1 < p.nr ? p.r[j + 1] - rj : gl;
+        cz = p.dt * nz / p.lz;
+        cth = p.dt * NT / (2.0 * M_PI * rj);
+        cr = p.dt / fmin(gl, gr);
+    }
     const double2* bu = zu + (size_t)j * nfu * MP1 * nz;
     // item e: column zi = e % ZB, butterfly pair jj, field pair pi (u_r u_t,
     // u_z w_r, w_t w_z); modes jj and P - jj of both fields
@@ -1071,6 +1084,7 @@ __global__ __launch_bounds__(TB) void k_theta_p(KP p, int nq, int Q, const doubl
                 const double uzU = uz + U;
                 o0[q] = make_double2(ut * wz - uzU * wt - uz * Om, uzU * wr - ur * wz);
                 o1[q] = make_double2(ur * (wt + Om) - ut * wr, 0.0);
+                if constexpr (CFL) cmax = fmax(cmax, fabs(uzU) * cz + fabs(ut) * cth + fabs(ur) * cr);
             }
             theta_fwd_head<NT>(O, zi, jj, o0);
             theta_fwd_head<NT>(O, ZB + zi, jj, o1);
@@ -1100,6 +1114,12 @@ __global__ __launch_bounds__(TB) void k_theta_p(KP p, int nq, int Q, const doubl
             if (jB != jA) emit(jB, yB0, yA2);
         }
         __syncthreads();
+    }
+    if constexpr (CFL) {
+        // wave maximum, then one atomic per wave (non-negative doubles order
+        // as their bit patterns)
+        for (int off = 32; off > 0; off >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, off));
+        if ((threadIdx.x & 63) == 0) atomicMax(ta.cfl, (unsigned long long)__double_as_longlong(cmax));
     }
 }
 
@@ -1700,9 +1720,14 @@ static void launch_theta_k(dim3 grid, size_t sh, const npo_plan_s& p, int nq, in
         const KP kp = p.kp;
         const unsigned gx = grid.x;
         (void)issue(p, -1, d, st, [=](const BDesc* bd, int nb, hipStream_t s) {
-            if constexpr (!ADJ)
-                hipLaunchKernelGGL((k_theta_p<NT, ZB>), dim3(gx, 1, nb), dim3(TB), sh, s, kp, nq, Q, zu, nfu, tb, ta, bd);
-            else
+            if constexpr (!ADJ) {
+                if (ta.cfl)
+                    hipLaunchKernelGGL((k_theta_p<NT, ZB, true>), dim3(gx, 1, nb), dim3(TB), sh, s, kp, nq, Q, zu, nfu,
+                                       tb, ta, bd);
+                else
+                    hipLaunchKernelGGL((k_theta_p<NT, ZB, false>), dim3(gx, 1, nb), dim3(TB), sh, s, kp, nq, Q, zu,
+                                       nfu, tb, ta, bd);
+            } else
                 hipLaunchKernelGGL((k_theta_pa<NT, ZB>), dim3(gx, 1, nb), dim3(TB), sh, s, kp, nq, Q, zu, nfu, zy, nfy,
                                    tb, ta, bd);
         });

@@ -80,6 +80,9 @@ SIGNATURES = {
     "npo_plan_set_tuning": (_I32, [_P, _I32, _I32, _I32]),
     "npo_plan_get_tuning": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "npo_plan_set_graphs": (_I32, [_P, _I32]),
+    "npo_plan_set_cfl_monitor": (_I32, [_P, _I32]),
+    "npo_cfl_read": (_I32, [_P, _P, _P, _I32, _P]),
+    "npo_plan_inject_fault": (_I32, [_P, _I32, _I64]),
     "npo_batch_create": (_I32, [ctypes.POINTER(_P), _I32, ctypes.POINTER(_P)]),
     "npo_batch_destroy": (_I32, [_P]),
     "npo_batch_info": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
@@ -363,6 +366,18 @@ def npo_plan_set_tuning(plan, zgroup, zb_fwd, zb_adj):
 
 def npo_plan_set_graphs(plan, enable):
     _check(lib().npo_plan_set_graphs(plan, int(bool(enable))))
+
+
+def npo_plan_set_cfl_monitor(plan, enable):
+    _check(lib().npo_plan_set_cfl_monitor(plan, int(bool(enable))))
+
+
+def npo_cfl_read(plan, ws, out_dev, reset=False, stream=None):
+    _check(lib().npo_cfl_read(plan, _wsp(plan, ws), _scal(out_dev, "out_dev"), int(bool(reset)), _stream(stream)))
+
+
+def npo_plan_inject_fault(plan, site, after):
+    _check(lib().npo_plan_inject_fault(plan, site, after))
 
 
 def npo_plan_get_tuning(plan):
