@@ -481,6 +481,10 @@ def bench_validate(args):
     print(json.dumps(out), flush=True)
 
 
+def _log(line):
+    print(line, file=sys.stderr, flush=True)
+
+
 def c5_jobs(n=128, seed=7):
     """The served job mix: 90% drawn from the batched workload's instances, 10%
     large 64 x 96 x 1536 jobs with L = 50 D (100 radii); parameters of the
@@ -512,7 +516,7 @@ def bench_serve_c5(args):
     iters = 20
     arrivals = serve.poisson_arrivals(len(cfgs), 4.0, seed=7)
     runs = {}
-    s = serve.Server(hbm_budget=250e9, max_active=16, workers=8)
+    s = serve.Server(hbm_budget=250e9, max_active=16, workers=8, log=_log)
     _, runs["offered_4_per_s"] = serve.replay(s, cfgs, iters, arrivals, budget=args.serve_budget)
     print(f"[bench] c5 at 4/s: {runs['offered_4_per_s']}", file=sys.stderr, flush=True)
     torch.cuda.empty_cache()
@@ -527,7 +531,7 @@ def bench_serve_c5(args):
     mean_job = per_iter * iters * np.mean([size(c) for c in cfgs]) / size(cfgs[1])
     rate = 0.8 / mean_job
     arrivals = serve.poisson_arrivals(len(cfgs), rate, seed=7)
-    s = serve.Server(hbm_budget=250e9, max_active=16, workers=8)
+    s = serve.Server(hbm_budget=250e9, max_active=16, workers=8, log=_log)
     _, runs["utilisation_0.8"] = serve.replay(s, cfgs, iters, arrivals, budget=args.serve_budget)
     runs["utilisation_0.8"]["arrival_rate_per_s"] = rate
     print(f"[bench] c5 at 0.8 utilisation: {runs['utilisation_0.8']}", file=sys.stderr, flush=True)
@@ -569,7 +573,7 @@ def bench_serve(args):
     mean_job = t1 * np.mean([c["nr"] * c["nt"] * c["nz"] for c in cfgs]) / (cfgs[0]["nr"] * cfgs[0]["nt"] * cfgs[0]["nz"])
     rate = 0.8 / max(mean_job, 1e-3)
     arrivals = serve.poisson_arrivals(len(cfgs), rate, seed=7)
-    s = serve.Server(hbm_budget=250e9, max_active=16, workers=8)
+    s = serve.Server(hbm_budget=250e9, max_active=16, workers=8, log=_log)
     jobs, rep = serve.replay(s, cfgs, args.serve_iters, arrivals)
     out = {"metric": "fwd+adjoint grid-point-steps/s (served)", "value": rep["gp_steps_per_s"],
            "unit": "grid-point-steps/s", "n_gpus": 1, "steps": rep["iterations"], "warmup": 0,

@@ -239,7 +239,10 @@ npo_status npo_update(npo_plan plan, void* ws, const void* u0, const void* g, do
  * halve while G does not increase, stop when |dG/G| < tol or after
  * max_halvings).  On acceptance u0 and uN hold the new iterate and the arena its
  * sweep.  stats (host, 8 doubles): G_old, G_new, alpha, alpha_max, E0dag, C0,
- * accepted (1/0), forward sweeps run.  Synchronises the stream. */
+ * accepted (1/0), forward sweeps run.  A non-finite G_old, E0dag or C0 (a state
+ * that has blown up) ends the call at once with NPO_OK, accepted = 0, G_new =
+ * G_old and nothing changed, so that the caller sees the non-finite gain.
+ * Synchronises the stream. */
 npo_status npo_iterate(npo_plan plan, void* ws, void* ckpt, int32_t n_ckpt, void* u0, void* uN,
                        double e0, double tol, int32_t max_halvings, double* stats, void* stream);
 

@@ -5,6 +5,35 @@
 
 namespace npo {
 
+// ------------------------------------------------------- global pointers
+// Pointers read from a work-descriptor table are generic to the compiler,
+// which then emits flat loads and stores; flat operations also count against
+// the LDS wait counter, so every LDS wait would drain the global prefetches.
+// rebase() re-expresses such a pointer as the table's own address (a kernel
+// argument, hence known to be global memory) plus a uniform byte offset that
+// the optimiser cannot fold away, so the accesses stay global ones.  Null
+// stays null.  Every plan table, field and workspace is device global memory.
+template <class T>
+__device__ __forceinline__ T* rebase(const void* base, T* q) {
+    if (!q) return nullptr;
+    const long long d = (long long)((const char*)q - (const char*)base);
+    unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)d);
+    unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(d >> 32));
+    asm volatile("" : "+s"(lo), "+s"(hi));     // opaque: keeps base + offset from folding back to q
+    const long long off = (long long)(((unsigned long long)hi << 32) | lo);
+    return (T*)((const char*)base + off);
+}
+__device__ __forceinline__ void globalize(KP& k, const void* b) {
+    k.r = rebase(b, k.r); k.w = rebase(b, k.w); k.D1 = rebase(b, k.D1); k.D2 = rebase(b, k.D2);
+    k.B = rebase(b, k.B); k.D1T = rebase(b, k.D1T); k.D1WT = rebase(b, k.D1WT); k.BWT = rebase(b, k.BWT);
+    k.col0 = rebase(b, k.col0); k.Ut = rebase(b, k.Ut); k.dUt = rebase(b, k.dUt); k.twz = rebase(b, k.twz);
+    k.twt = rebase(b, k.twt); k.HLU = rebase(b, k.HLU); k.PLU = rebase(b, k.PLU); k.HOM = rebase(b, k.HOM);
+}
+__device__ __forceinline__ void globalize(TimeArg& t, const void* b) {
+    t.dstep = rebase(b, t.dstep);
+    t.cfl = rebase(b, t.cfl);
+}
+
 // ------------------------------------------------------------------ complex
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }

@@ -1248,6 +1248,7 @@ npo_status npo_iterate(npo_plan p, void* ws, void* ckpt, int32_t nck, void* u0, 
     const double amax = q > 0 ? 1.0 / std::sqrt(q) : std::numeric_limits<double>::infinity();
     stats[0] = Gold; stats[1] = Gold; stats[2] = 0.0; stats[3] = amax; stats[4] = E0d; stats[5] = C0;
     stats[6] = 0.0; stats[7] = 0.0;
+    if (!std::isfinite(Gold) || !std::isfinite(E0d) || !std::isfinite(C0)) return NPO_OK;   // blown-up state
     if (!std::isfinite(amax)) return NPO_OK;
     // udag into w.tmp
     HIPCHK(npo::launch_axpby(*p, -1.0, w.g, 0.0, nullptr, w.tmp, st));

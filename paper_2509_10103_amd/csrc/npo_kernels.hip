@@ -17,10 +17,10 @@ namespace npo {
 // ------------------------------------------------------------ vorticity aux
 // aux[0] = w_theta = i a u_r - D1 u_z ; aux[1] = w_z = D1 u_theta + u_theta/r - (i m / r) u_r
 __global__ void k_curl_aux(KP p, const double2* __restrict__ u, double2* __restrict__ aux,
-                           const BDesc* __restrict__ bd) {
+                           const BDesc* bd) {
     if (bd) {
         const BDesc& d = bd[blockIdx.z];
-        p = d.kp; u = d.in[0]; aux = d.out[0];
+        p = d.kp; globalize(p, bd); u = rebase(bd, d.in[0]); aux = rebase(bd, d.out[0]);
     }
     const size_t per = (size_t)p.nr * p.mp1 * p.nk;
     size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -352,10 +352,10 @@ template <int kind, int NRC>
 __global__ __launch_bounds__(RT) void k_solve(KP p, const double2* __restrict__ ain,
                                               const double2* __restrict__ bin, double2* __restrict__ uout,
                                               double2* __restrict__ auxout, double2* __restrict__ r0out,
-                                              const BDesc* __restrict__ bd) {
+                                              const BDesc* bd) {
     if (bd) {
         const BDesc& d = bd[blockIdx.z];
-        p = d.kp; ain = d.in[0]; bin = d.in[1]; uout = d.out[0]; auxout = d.out[1]; r0out = d.out[2];
+        p = d.kp; globalize(p, bd); ain = rebase(bd, d.in[0]); bin = rebase(bd, d.in[1]); uout = rebase(bd, d.out[0]); auxout = rebase(bd, d.out[1]); r0out = rebase(bd, d.out[2]);
     }
     int g, m;
     if (!block_group(p, g, m)) return;
@@ -605,11 +605,11 @@ struct AdjOut {
 };
 template <bool useB, int NRC>
 __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, double ca, const double2* Bin, double cb,
-                                                  AdjOut ao, const BDesc* __restrict__ bd) {
+                                                  AdjOut ao, const BDesc* bd) {
     if (bd) {
         const BDesc& d = bd[blockIdx.z];
-        p = d.kp; Ain = d.in[0]; Bin = d.in[1]; ao.Yin = d.in[2]; ao.Zin = d.in[3];
-        ao.out0 = d.out[0]; ao.Yout = d.out[1]; ao.Zout = d.out[2];
+        p = d.kp; globalize(p, bd); Ain = rebase(bd, d.in[0]); Bin = rebase(bd, d.in[1]); ao.Yin = rebase(bd, d.in[2]); ao.Zin = rebase(bd, d.in[3]);
+        ao.out0 = rebase(bd, d.out[0]); ao.Yout = rebase(bd, d.out[1]); ao.Zout = rebase(bd, d.out[2]);
         ca = d.s[0]; cb = d.s[1]; ao.qy = d.s[2]; ao.qz = d.s[3]; ao.sy = d.s[4]; ao.sz = d.s[5];
     }
     int g, m;
@@ -794,10 +794,10 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
 // stencil reads it there through the 13-tap tables.
 __global__ __launch_bounds__(RT) void k_final(KP p, const double2* __restrict__ Z, const double2* __restrict__ Ain,
                                               const double2* __restrict__ Bin, double2* __restrict__ out,
-                                              const BDesc* __restrict__ bd) {
+                                              const BDesc* bd) {
     if (bd) {
         const BDesc& d = bd[blockIdx.z];
-        p = d.kp; Z = d.in[0]; Ain = d.in[1]; Bin = d.in[2]; out = d.out[0];
+        p = d.kp; globalize(p, bd); Z = rebase(bd, d.in[0]); Ain = rebase(bd, d.in[1]); Bin = rebase(bd, d.in[2]); out = rebase(bd, d.out[0]);
     }
     int g, m;
     if (!block_group(p, g, m)) return;
@@ -1194,7 +1194,7 @@ __global__ void k_half(const double* __restrict__ en, double* __restrict__ info)
 }
 
 // Device step index of captured step graphs: *d = v or *d += v.
-__global__ void k_step_index(long long* d, long long v, int add, const BDesc* __restrict__ bd) {
+__global__ void k_step_index(long long* d, long long v, int add, const BDesc* bd) {
     if (bd) d = bd[blockIdx.z].step;
     if (threadIdx.x == 0) *d = add ? *d + v : v;
 }

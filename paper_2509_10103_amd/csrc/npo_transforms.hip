@@ -544,11 +544,11 @@ __global__ __launch_bounds__(TB) void k_zinv_t(KP p, const double2* __restrict__
 template <int NZ, int F0, int NF, int MB>
 __global__ __launch_bounds__(TB) void k_zinv_p(KP p, const double2* __restrict__ u, const double2* __restrict__ aux,
                                               const double2* __restrict__ y, double2* __restrict__ zb,
-                                              const BDesc* __restrict__ bd) {
+                                              const BDesc* bd) {
     static_assert(NZ % 12 == 0, "N_z = 3P with P a multiple of 4");
     if (bd) {
         const BDesc& d = bd[blockIdx.z];
-        p = d.kp; u = d.in[0]; aux = d.in[1]; y = d.in[2]; zb = d.out[0];
+        p = d.kp; globalize(p, bd); u = rebase(bd, d.in[0]); aux = rebase(bd, d.in[1]); y = rebase(bd, d.in[2]); zb = rebase(bd, d.out[0]);
     }
     constexpr int P = NZ / 3, NK = 2 * P - 1;
     constexpr int PB = (P + TB - 1) / TB;             // first-pass butterflies per thread
@@ -684,11 +684,11 @@ __global__ __launch_bounds__(TB) void k_zfwd_t(KP p, const double2* __restrict__
 // them to the spectral field.
 template <int NZ, int NFO, int MB>
 __global__ __launch_bounds__(TB) void k_zfwd_p(KP p, const double2* __restrict__ tb, double2* __restrict__ out0,
-                                              double2* __restrict__ out1, double scale, const BDesc* __restrict__ bd) {
+                                              double2* __restrict__ out1, double scale, const BDesc* bd) {
     static_assert(NZ % 12 == 0, "N_z = 3P with P a multiple of 4");
     if (bd) {
         const BDesc& d = bd[blockIdx.z];
-        p = d.kp; tb = d.in[0]; out0 = d.out[0]; out1 = d.out[1];
+        p = d.kp; globalize(p, bd); tb = rebase(bd, d.in[0]); out0 = rebase(bd, d.out[0]); out1 = rebase(bd, d.out[1]);
     }
     constexpr int P = NZ / 3, NK = 2 * P - 1;
     constexpr int NB4 = NZ / 4;
@@ -990,11 +990,11 @@ __device__ __forceinline__ void theta_last_pair(const double2* R, const double2*
 // the plain kernel keeps its register budget and occupancy).
 template <int NT, int ZB, bool CFL>
 __global__ __launch_bounds__(TB) void k_theta_p(KP p, int nq, int Q, const double2* __restrict__ zu, int nfu,
-                                               double2* __restrict__ tb, TimeArg ta, const BDesc* __restrict__ bd) {
+                                               double2* __restrict__ tb, TimeArg ta, const BDesc* bd) {
     static_assert(NT % 12 == 0, "N_theta = 3P with P a multiple of 4");
     if (bd) {
         const BDesc& d = bd[blockIdx.z];
-        p = d.kp; zu = d.in[0]; tb = d.out[0]; ta = d.ta;
+        p = d.kp; globalize(p, bd); zu = rebase(bd, d.in[0]); tb = rebase(bd, d.out[0]); ta = d.ta; globalize(ta, bd);
     }
     constexpr int P = NT / 3, MP1 = P;
     constexpr int NIN = 3 * ZB, NOUT = 2 * ZB;
@@ -1431,11 +1431,11 @@ __global__ __launch_bounds__(TB) void k_theta_wa(KP p, int nzb, const double2* _
 template <int NT, int ZB>
 __global__ __launch_bounds__(TB) void k_theta_pa(KP p, int nq, int Q, const double2* __restrict__ zu, int nfu,
                                                 const double2* __restrict__ zy, int nfy, double2* __restrict__ tb,
-                                                TimeArg ta, const BDesc* __restrict__ bd) {
+                                                TimeArg ta, const BDesc* bd) {
     static_assert(NT % 12 == 0, "N_theta = 3P with P a multiple of 4");
     if (bd) {
         const BDesc& d = bd[blockIdx.z];
-        p = d.kp; zu = d.in[0]; zy = d.in[1]; tb = d.out[0]; ta = d.ta;
+        p = d.kp; globalize(p, bd); zu = rebase(bd, d.in[0]); zy = rebase(bd, d.in[1]); tb = rebase(bd, d.out[0]); ta = d.ta; globalize(ta, bd);
     }
     constexpr int P = NT / 3, MP1 = P;
     constexpr int H = ZB / 2;

@@ -65,11 +65,12 @@ class Job:
 class Server:
     """Admission by footprint, iteration-granular continuous batching."""
 
-    def __init__(self, hbm_budget, max_active=16, workers=8, factory=None):
+    def __init__(self, hbm_budget, max_active=16, workers=8, factory=None, log=None):
         self.budget = hbm_budget
         self.max_active = max_active
         self.workers = workers
         self.factory = factory or gpu_factory
+        self.log = log             # called with one line per admitted or finished job
         self.lock = threading.Condition()
         self.pending = []          # heap of (arrival, id, job)
         self.active = []
@@ -78,6 +79,7 @@ class Server:
         self.closed = False
         self.halted = False
         self.next_id = 0
+        self.iters_done = 0
         self._threads = []
 
     # ------------------------------------------------------------ client side
@@ -118,12 +120,18 @@ class Server:
             self.used += j.footprint
             j.admitted = time.perf_counter()
             self.active.append(j)
+            if self.log:
+                self.log(f"[serve] job {j.id} admitted ({j.cfg['nr']}x{j.cfg['nt']}x{j.cfg['nz']}, "
+                         f"{j.footprint / 1e9:.2f} GB), {len(self.active)} active")
 
     def _retire_locked(self, j):
         self.active.remove(j)
         self.used -= j.footprint
         j.finished = time.perf_counter()
         self.done.append(j)
+        if self.log:
+            self.log(f"[serve] job {j.id} {'failed: ' + j.error if j.error else 'done'} after {j.done_iters} "
+                     f"iterations, {len(self.done)} finished, {len(self.active)} active, {len(self.pending)} queued")
         self._admit_locked()
         self.lock.notify_all()
 
@@ -162,6 +170,9 @@ class Server:
                     j.latencies.append(dt)
                     j.counted += counted
                     j.done_iters += 1
+                    self.iters_done += 1
+                    if self.log and self.iters_done % 20 == 0:
+                        self.log(f"[serve] {self.iters_done} iterations done, {len(self.done)} jobs finished")
                     if not ok:
                         j.error = "non-finite gain"
                     finished = j.done_iters >= j.iters or j.error is not None

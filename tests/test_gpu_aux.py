@@ -123,3 +123,35 @@ def test_serving_loop_retires_a_failing_job():
         a0, aN, _ = alone(j.cfg, 2)
         u0, uN = j.result
         assert np.array_equal(u0.cpu().numpy(), a0) and np.array_equal(uN.cpu().numpy(), aN)
+
+
+def test_serving_loop_retires_a_job_with_a_non_finite_state():
+    """A job whose initial field holds a NaN (poisoned from the host) is
+    retired with an error at its first iteration; the others are unaffected."""
+    import math
+    import torch
+    from paper_2509_10103_amd import serve
+    from paper_2509_10103_amd.batch import Instance
+    from tests.test_gpu_batch_serve import small_cfgs, alone
+    cfgs = small_cfgs(3, nsteps=12)
+    bad = cfgs[2]["name"]
+
+    def factory(c):
+        inst = Instance(c, autotune=False, graphs=False)
+        if c["name"] == bad:
+            inst.stream.synchronize()
+            inst.u0[0, 1, 1, 1] = complex(math.nan, 0.0)
+            torch.cuda.synchronize()
+        return inst
+    print("[aux] serving with one poisoned job", flush=True)
+    s = serve.Server(hbm_budget=1e12, max_active=3, workers=3, factory=factory)
+    jobs, rep = serve.replay(s, cfgs, 2, arrivals=[0.0, 0.0, 0.0])
+    assert rep["failed"] == 1
+    for j in jobs:
+        if j.cfg["name"] == bad:
+            assert j.error and j.result is None and j.done_iters <= 1, (j.error, j.done_iters)
+            continue
+        assert j.error is None
+        a0, aN, _ = alone(j.cfg, 2)
+        u0, uN = j.result
+        assert np.array_equal(u0.cpu().numpy(), a0) and np.array_equal(uN.cpu().numpy(), aN)
