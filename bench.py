@@ -6,8 +6,12 @@ period with binomial checkpoints (Sec. 2.4), solenoidal projection of the
 gradient, and the backtracking line search whose trial forward sweeps leave
 the next iterate's checkpoints in place.  The initial forward sweep is done
 before the timed region.  Metric: forward + adjoint grid-point-steps per
-second, counting one forward and one adjoint sweep of N_r*N_theta*N_z points
-per step per iteration; recomputation and extra trial sweeps are not counted.
+second, N_r*N_theta*N_z points per step, counting every forward sweep the
+iteration integrates (the line search's trial sweeps: each one a distinct
+trajectory) and its adjoint sweep; the checkpoint recomputation inside the
+adjoint sweep repeats steps already counted and is not counted.  The JSON
+line also gives the rate with one forward and one adjoint sweep counted per
+iteration, and the per-iteration latency.
 
 The run keeps to a wall-clock budget (``--budget``, measured from process
 start, covering imports, plan set-up, the initial sweep, warm-up and timing):
@@ -300,8 +304,10 @@ def main():
     timed = len(lat)
     prof = npo.npo_profile_read(G.handle)
     pts = cfg["nr"] * cfg["nt"] * cfg["nz"]
-    counted = timed * 2 * cfg["nsteps"] * pts
+    fwd_sweeps = sum(int(h["forward_sweeps"]) for h in hist)
+    counted = (fwd_sweeps + timed) * cfg["nsteps"] * pts
     value = counted / wall
+    value_pair = timed * 2 * cfg["nsteps"] * pts / wall
     ab = alg_bytes(cfg)
     tot = {k: v["launches"] * v["avg_ms"] for k, v in prof.items()}
     dom = max(tot, key=tot.get)
@@ -350,6 +356,10 @@ def main():
                    "launch_shapes": shapes, "tuning": tuning, "e0": cfg["e0"], "seed": cfg["seed"],
                    "steps_requested": args.steps, "warmup_requested": args.warmup, "budget_s": args.budget,
                    "run_s": round(elapsed(), 1),
+                   "counted": "every forward sweep (trial sweeps included) and adjoint sweep; "
+                              "checkpoint recomputation not counted",
+                   "forward_sweeps_timed": fwd_sweeps,
+                   "value_one_pair_per_iteration": value_pair,
                    "iteration_latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
                    "gains": [[h["G_old"], h["G_new"], int(h["accepted"]), int(h["forward_sweeps"])] for h in hist]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
