@@ -37,6 +37,21 @@ W^{-1} A^H W.  The convective adjoint uses the identity
     <y, P_K F[a x b]>_W = <Y, a x b>_phys
 for band-limited y, which gives
     N'(u)^dag y = P_K F[(Om + w_u) x Y] + curl^dag P_K F[Y x (U + u)].
+
+Beside it, the continuous adjoint of the paper (Sec. 2, adjoint Navier-Stokes
+equations, integrated backwards from the compatibility condition): with
+V = U + u the total velocity and Omega = curl V, the adjoint convective term
+-(V . grad) y + (grad V)^T y equals, up to a gradient that the adjoint
+pressure absorbs, -(Omega x y + curl(y x V)), since curl(y x V) =
+(V . grad) y - (y . grad) V and Omega x y = (y . grad) V - (grad V)^T y for
+solenoidal V and y.  Integrated backwards in s = t_N - t, the adjoint field
+obeys dy/ds = Omega x y + curl(y x V) - grad p' + f'_z e_z + (1/Re) lap y with
+y = 0 at the wall and zero flux, the same form as the direct equation, so it
+is discretised with the same stepper (Sec. 2.3) and the same S and E: the
+pseudo-spectral term Nc(u; y) = P_K F[Omega x Y] + curl P_K F[Y x V] is the
+discrete adjoint term with curl in place of curl^dag, the predictor taking the
+direct field at t_{n+1} and the correctors the one at t_n.  Its gradient
+differs from the exact discrete one by the discretisation error.
 """
 import numpy as np
 import scipy.linalg as sl
@@ -444,6 +459,21 @@ class Pipe:
         b = b + np.stack([Uc * y[1], -Uc * y[0], np.zeros_like(y[2])])       # y x U
         return a + self.apply_modes(b, 'C', adjoint=True)
 
+    def N_adj_cont(self, u, t, y):
+        """Continuous-adjoint convective term Omega x y + curl(y x V), V = U + u
+        (Sec. 2, adjoint momentum equation, in rotational form): the products
+        of N_adj with the discrete curl applied to the second one."""
+        U, Om = self.base(t)
+        wu = self.curl(u)
+        Y = self.to_phys(y)
+        a = self.to_spec(self.cross(self.to_phys(wu), Y))
+        b = self.to_spec(self.cross(Y, self.to_phys(u)))
+        Uc = U[:, None, None]
+        Oc = Om[:, None, None]
+        a = a + np.stack([Oc * y[2], np.zeros_like(y[1]), -Oc * y[0]])       # Om x y
+        b = b + np.stack([Uc * y[1], -Uc * y[0], np.zeros_like(y[2])])       # y x U
+        return a + self.curl(b)
+
     # ------------------------------------------------------------ stepping
     def stages(self, u, n):
         """Predictor and corrector iterates w_0..w_C of the step from u^n.
@@ -490,6 +520,32 @@ class Pipe:
             Z = Z + mu
             Y = Y + (mu if c == 1 else 0.5 * mu)
         return self.E_adj(Z) + self.N_adj(u, t0, Y)
+
+    def step_adj_cont(self, u, u_next, n, y):
+        """One backward step of the continuous adjoint (Sec. 2 adjoint equations
+        with the Sec. 2.3 stepper): y^{n+1} at t_{n+1} -> y^n at t_n, with the
+        direct fields u^n and u^{n+1}:
+            v_0 = S(E y + Nc(u^{n+1}, t_{n+1}; y)),
+            v_c = S(E y + (Nc(u^{n+1}, t_{n+1}; y) + Nc(u^n, t_n; v_{c-1})) / 2),
+            y^n = v_ncorr."""
+        t0, t1 = self.time(n), self.time(n + 1)
+        Nn = self.N_adj_cont(u_next, t1, y)
+        Ey = self.E(y)
+        v = self.S(Ey + Nn)
+        for _ in range(self.ncorr):
+            v = self.S(Ey + 0.5 * (Nn + self.N_adj_cont(u, t0, v)))
+        return v
+
+    def gradient_cont(self, u0, nsteps):
+        """J = E(u^N) and the continuous-adjoint gradient y^0 (unprojected),
+        from y^N = u^N (the compatibility condition with the sign that makes
+        y the ascent direction)."""
+        uN, hist = self.forward(u0, nsteps, keep=True)
+        states = hist + [uN]
+        y = uN.copy()
+        for n in range(nsteps - 1, -1, -1):
+            y = self.step_adj_cont(states[n], states[n + 1], n, y)
+        return self.energy(uN), uN, y
 
     def forward(self, u0, nsteps, keep=False):
         """Integrate nsteps; returns u^N (and all u^n, n < N, if keep)."""
