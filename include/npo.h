@@ -140,6 +140,36 @@ npo_status npo_forward_step_noalloc(npo_plan plan, const void* u_n, void* u_np1,
 npo_status npo_adjoint_step(npo_plan plan, void* ws, const void* u_n, const void* lam_np1,
                             void* lam_n, int64_t n, void* stream);
 
+/* The continuous adjoint (Sec. 2: the adjoint momentum and continuity
+ * equations with the zero adjoint flux, integrated backwards from the
+ * compatibility condition), discretised with the direct stepper of Sec. 2.3
+ * rather than transposing it.  Its convective term, in rotational form with
+ * V = U e_z + u and Omega = curl V, is
+ *   Nc(u; y) = P_K F[Omega x Y] + curl P_K F[Y x V]
+ * (the adjoint term -(V.grad) y + (grad V)^T y of the paper up to a gradient
+ * and the sign of the backward time), and the backward step from t_{n+1} to
+ * t_n is
+ *   v_0 = S(E lam + Nc(u^{n+1}; lam)),  v_c = S(E lam + (Nc(u^{n+1}; lam) + Nc(u^n; v_{c-1}))/2),
+ *   lam^n = v_ncorr,
+ * the first term at t_{n+1}, the second at t_n.  Its gradient differs from the
+ * exact discrete one by the discretisation error.
+ *   npo_nonlinear_adj_cont: out = Nc(u; y) at time t;
+ *   npo_adjoint_step_cont:  lam_n from lam_np1 with the direct fields u_n and
+ *                           u_np1 (lam_n may alias lam_np1);
+ *   npo_plan_set_adjoint:   kind 0 (default) makes the adjoint sweeps
+ *                           (npo_adjoint_run, its hybrid form, npo_iterate)
+ *                           use the exact discrete adjoint, kind 1 the
+ *                           continuous one; the continuous sweeps make u^{n+1}
+ *                           of each segment's last step with one forward step
+ *                           and keep it in the workspace, and do not replay
+ *                           captured graphs.  Batches (npo_batch_*) take the
+ *                           discrete adjoint only: NPO_EUNSUPPORTED otherwise. */
+npo_status npo_nonlinear_adj_cont(npo_plan plan, void* ws, const void* u, double t, const void* y, void* out,
+                                  void* stream);
+npo_status npo_adjoint_step_cont(npo_plan plan, void* ws, const void* u_n, const void* u_np1,
+                                 const void* lam_np1, void* lam_n, int64_t n, void* stream);
+npo_status npo_plan_set_adjoint(npo_plan plan, int32_t kind);
+
 /* Forward sweep over the plan's nsteps from u0 to uN, storing binomial
  * checkpoints (Sec. 2.4) into `ckpt`, an arena of n_ckpt fields (n_ckpt >= 1;
  * slot 0 receives u0).  The arena must not be touched before the matching

@@ -405,6 +405,36 @@ hipError_t adj_step(const npo_plan_s& p, void* ws, const double2* un, const doub
     return npo::launch_final(p, w.zb2, w.fa2, w.fb2, lamout, st);
 }
 
+// One backward step of the continuous adjoint (the paper's adjoint equations,
+// integrated backwards with the direct stepper): lam^{n+1} at t_{n+1} ->
+// lam^n at t_n, with the direct fields u^n and u^{n+1} and the convective term
+// Nc(u; y) = P_K F[Omega x Y] + curl P_K F[Y x V]:
+//   v_0 = S(E lam + Nc(u^{n+1}, t_{n+1}; lam)),
+//   v_c = S(E lam + (Nc(u^{n+1}, t_{n+1}; lam) + Nc(u^n, t_n; v_{c-1})) / 2),
+//   lam^n = v_C.
+// lamout may alias lamin (lam is read by the predictor only).
+hipError_t adj_step_cont(const npo_plan_s& p, void* ws, const double2* un, const double2* unp1, const double2* lamin,
+                         double2* lamout, long long n, hipStream_t st) {
+    if (injected(p, 2)) return hipErrorLaunchFailure;
+    WsPtrs w = wsptrs(p, ws);
+    hipError_t e;
+    const npo::TimeArg t0 = at_step(nullptr, n, 0), t1 = at_step(nullptr, n, 1);
+    // vorticity parts: u^{n+1} into auxs[0], u^n into aux0
+    if ((e = npo::launch_curl_aux(p, unp1, w.auxs[0], st)) != hipSuccess) return e;
+    if ((e = npo::launch_curl_aux(p, un, w.aux0, st)) != hipSuccess) return e;
+    if ((e = npo::launch_nl(p, 1, unp1, w.auxs[0], lamin, t1, w.fa, w.fb, ws, st)) != hipSuccess) return e;
+    if ((e = npo::launch_curl_add(p, w.fa, w.fb, w.nn, st)) != hipSuccess) return e;
+    if ((e = npo::launch_solve(p, 1, lamin, w.nn, p.ncorr > 0 ? w.st[0] : lamout, nullptr, st, w.r0)) != hipSuccess)
+        return e;
+    for (int c = 1; c <= p.ncorr; ++c) {
+        if ((e = npo::launch_nl(p, 1, un, w.aux0, w.st[c - 1], t0, w.fa, w.fb, ws, st)) != hipSuccess) return e;
+        if ((e = npo::launch_curl_add(p, w.fa, w.fb, w.ns, st)) != hipSuccess) return e;
+        if ((e = npo::launch_solve(p, 2, w.r0, w.ns, c == p.ncorr ? lamout : w.st[c], nullptr, st)) != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
 // ------------------------------------------------------- captured step graphs
 // The forward advance (cur -> cur, vorticity parts of cur present, then
 // step += 1) and the adjoint step (lam -> lam at u = cur, vorticity parts of
@@ -833,6 +863,34 @@ npo_status npo_nonlinear_adj(npo_plan p, void* ws, const void* u, double t, cons
     return NPO_OK;
 }
 
+npo_status npo_nonlinear_adj_cont(npo_plan p, void* ws, const void* u, double t, const void* y, void* out,
+                                  void* stream) {
+    if (check_plan(p) || !ws || !u || !y || !out) return fail(NPO_EINVAL, "null argument");
+    if (!std::isfinite(t)) return fail(NPO_EINVAL, "t must be finite");
+    WsPtrs w = wsptrs(*p, ws);
+    HIPCHK(npo::launch_curl_aux(*p, CF(u), w.aux0, ST(stream)));
+    HIPCHK(npo::launch_nl(*p, 1, CF(u), w.aux0, CF(y), npo::TimeArg{nullptr, 0, 0, 1, t, nullptr}, w.fa, w.fb, ws,
+                          ST(stream)));
+    HIPCHK(npo::launch_curl_add(*p, w.fa, w.fb, F(out), ST(stream)));
+    return NPO_OK;
+}
+
+npo_status npo_adjoint_step_cont(npo_plan p, void* ws, const void* un, const void* unp1, const void* lam_in,
+                                 void* lam_out, int64_t n, void* stream) {
+    if (check_plan(p) || !ws || !un || !unp1 || !lam_in || !lam_out) return fail(NPO_EINVAL, "null argument");
+    if (n < 0) return fail(NPO_EINVAL, "n must be >= 0");
+    HIPCHK(adj_step_cont(*p, ws, CF(un), CF(unp1), CF(lam_in), F(lam_out), n, ST(stream)));
+    return NPO_OK;
+}
+
+npo_status npo_plan_set_adjoint(npo_plan p, int32_t kind) {
+    if (check_plan(p)) return NPO_EINVAL;
+    if (kind != 0 && kind != 1) return fail(NPO_EINVAL, "kind must be 0 (discrete) or 1 (continuous)");
+    p->adjoint_kind = kind;
+    drop_graphs(*p);
+    return NPO_OK;
+}
+
 npo_status npo_solve(npo_plan p, void* ws, const void* R, void* out, void* stream) {
     if (check_plan(p) || !R || !out) return fail(NPO_EINVAL, "null argument");
     (void)ws;
@@ -996,6 +1054,10 @@ static npo_status adjoint_run(npo_plan p, void* ws, void* ckpt, int32_t nck, con
     const double2* where = w.cur;
     long long pos = nseg - 1, adv = 0;
     bool aux = false, synced = false;   // synced: the device step index equals pos
+    // continuous adjoint: w.tmp holds u^{pos+1} (the state of the step after
+    // this one), made by one forward step for the first step of the segment
+    const bool cont = p->adjoint_kind == 1;
+    bool have_next = false;
     for (size_t i = first_adj(acts); i < acts.size(); ++i) {
         const Act& a = acts[i];
         if (a.kind == A_RESTORE) {
@@ -1026,6 +1088,15 @@ static npo_status adjoint_run(npo_plan p, void* ws, void* ckpt, int32_t nck, con
             where = slot(a.a);
         } else {
             if (a.a != pos) return fail(NPO_ESTATE, "schedule adjoint position mismatch");
+            if (cont) {
+                if (!have_next) HIPCHK(fwd_step(*p, ws, where, w.tmp, n0 + pos, aux, st));
+                HIPCHK(adj_step_cont(*p, ws, where, w.tmp, w.lam, w.lam, n0 + pos, st));
+                HIPCHK(hipMemcpyAsync(w.tmp, where, fb, hipMemcpyDeviceToDevice, st));
+                have_next = true;
+                aux = false;
+                synced = false;
+                continue;
+            }
             // after an advance aux0 already holds the vorticity parts of u^pos
             if (gr && where == w.cur) {
                 if (!aux) HIPCHK(npo::launch_curl_aux(*p, w.cur, w.aux0, st));
@@ -1540,8 +1611,11 @@ npo_status batch_set_steps(npo_batch_s& b, void* const* ws, long long v, hipStre
 
 npo_status batch_check(npo_batch b, void* const* ws) {
     if (!b || !ws) return fail(NPO_EINVAL, "null argument");
-    for (size_t i = 0; i < b->plans.size(); ++i)
+    for (size_t i = 0; i < b->plans.size(); ++i) {
         if (!ws[i]) return fail(NPO_EINVAL, "null workspace");
+        if (b->plans[i]->adjoint_kind != 0)
+            return fail(NPO_EUNSUPPORTED, "batched sweeps take the exact discrete adjoint only");
+    }
     return NPO_OK;
 }
 

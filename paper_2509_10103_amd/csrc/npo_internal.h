@@ -127,6 +127,9 @@ struct npo_plan_s {
     mutable npo::Profiler prof;
     // CFL monitor of the forward steps (npo_plan_set_cfl_monitor)
     bool cfl_monitor = false;
+    // adjoint of the sweeps (npo_plan_set_adjoint): 0 the exact discrete
+    // adjoint, 1 the continuous adjoint equations with the direct stepper
+    int adjoint_kind = 0;
     // injected failure of the step drivers (npo_plan_inject_fault): site 1
     // forward steps, 2 adjoint steps; the call after `fault_after` more calls fails
     int fault_site = 0;
@@ -192,6 +195,8 @@ size_t theta_lds(const npo_plan_s& p, int ZB, int adj);
 // (tuning value zb_fwd = -L) supports these transform lengths.
 bool theta_wave_ok(int nt, int nz, int L);
 hipError_t launch_curl_aux(const npo_plan_s& p, const double2* u, double2* aux, hipStream_t st);
+// out = a + curl b (continuous-adjoint convective term); no batched form
+hipError_t launch_curl_add(const npo_plan_s& p, const double2* a, const double2* b, double2* out, hipStream_t st);
 // uw_pre (adjoint only): the axial transforms of the six u, w fields of this
 // state, left by an earlier forward evaluation (then only y is transformed);
 // uw_save (forward only): where the forward evaluation leaves them (default:

@@ -42,6 +42,37 @@ __global__ void k_curl_aux(KP p, const double2* __restrict__ u, double2* __restr
     aux[fidx(p, 1, j, m, kk)] = csub(caxpy(dut, 1.0 / r, ut), cscale(cmuli(ur), m / r));
 }
 
+// ------------------------------------------------ continuous-adjoint term
+// out = a + curl b (the continuous-adjoint convective term from the two
+// product fields of the adjoint evaluation: a = Omega x y, b = y x V):
+//   (curl b)_r = (i m / r) b_z - i a b_theta
+//   (curl b)_theta = i a b_r - D1 b_z
+//   (curl b)_z = D1 b_theta + b_theta / r - (i m / r) b_r
+__global__ void k_curl_add(KP p, const double2* __restrict__ a, const double2* __restrict__ b,
+                           double2* __restrict__ out) {
+    const size_t per = (size_t)p.nr * p.mp1 * p.nk;
+    size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= per) return;
+    const int kk = idx % p.nk;
+    const int m = (idx / p.nk) % p.mp1;
+    const int j = idx / ((size_t)p.nk * p.mp1);
+    const double al = alpha_of(p, kk), r = p.r[j];
+    const int c0 = p.col0[j];
+    const double* d1e = p.D1 + ((m & 1) * p.nr + j) * 7;
+    const double* d1o = p.D1 + (((m + 1) & 1) * p.nr + j) * 7;
+    double2 dbz = czero(), dbt = czero();
+    for (int t = 0; t < 7; ++t) {
+        dbz = caxpy(dbz, d1e[t], b[fidx(p, 2, c0 + t, m, kk)]);
+        dbt = caxpy(dbt, d1o[t], b[fidx(p, 1, c0 + t, m, kk)]);
+    }
+    const double2 br = b[fidx(p, 0, j, m, kk)], bt = b[fidx(p, 1, j, m, kk)], bz = b[fidx(p, 2, j, m, kk)];
+    const double mr = m / r;
+    out[fidx(p, 0, j, m, kk)] = cadd(a[fidx(p, 0, j, m, kk)], csub(cscale(cmuli(bz), mr), cscale(cmuli(bt), al)));
+    out[fidx(p, 1, j, m, kk)] = cadd(a[fidx(p, 1, j, m, kk)], csub(cscale(cmuli(br), al), dbz));
+    out[fidx(p, 2, j, m, kk)] =
+        cadd(a[fidx(p, 2, j, m, kk)], csub(caxpy(dbt, 1.0 / r, bt), cscale(cmuli(br), mr)));
+}
+
 // ------------------------------------------------------ banded operators
 // Interior operators on nodes 0..nr-2 (the wall node carries a Dirichlet value
 // and its column is removed):
@@ -1239,6 +1270,13 @@ hipError_t launch_curl_aux(const npo_plan_s& p, const double2* u, double2* aux, 
     return issue(p, KID_CURL, d, st, [=](const BDesc* bd, int nb, hipStream_t s) {
         hipLaunchKernelGGL(k_curl_aux, dim3(gx, 1, nb), dim3(256), 0, s, kp, u, aux, bd);
     });
+}
+hipError_t launch_curl_add(const npo_plan_s& p, const double2* a, const double2* b, double2* out, hipStream_t st) {
+    if (Recorder* r = recorder()) r->ok = false;     // no batched form
+    const size_t per = (size_t)p.nr * p.mp1 * p.nk;
+    const unsigned gx = (unsigned)((per + 255) / 256);
+    hipLaunchKernelGGL(k_curl_add, dim3(gx), dim3(256), 0, st, p.kp, a, b, out);
+    return hipGetLastError();
 }
 template <int R>
 static hipError_t launch_solve_r(const npo_plan_s& p, int kid, int kind, unsigned gx, const BDesc& d,

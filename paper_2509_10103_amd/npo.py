@@ -81,6 +81,9 @@ SIGNATURES = {
     "npo_plan_get_tuning": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "npo_plan_set_graphs": (_I32, [_P, _I32]),
     "npo_plan_set_cfl_monitor": (_I32, [_P, _I32]),
+    "npo_plan_set_adjoint": (_I32, [_P, _I32]),
+    "npo_nonlinear_adj_cont": (_I32, [_P, _P, _P, _D, _P, _P, _P]),
+    "npo_adjoint_step_cont": (_I32, [_P, _P, _P, _P, _P, _P, _I64, _P]),
     "npo_cfl_read": (_I32, [_P, _P, _P, _I32, _P]),
     "npo_plan_inject_fault": (_I32, [_P, _I32, _I64]),
     "npo_batch_create": (_I32, [ctypes.POINTER(_P), _I32, ctypes.POINTER(_P)]),
@@ -366,6 +369,22 @@ def npo_plan_set_tuning(plan, zgroup, zb_fwd, zb_adj):
 
 def npo_plan_set_graphs(plan, enable):
     _check(lib().npo_plan_set_graphs(plan, int(bool(enable))))
+
+
+def npo_plan_set_adjoint(plan, kind):
+    """0: exact discrete adjoint sweeps (default); 1: the continuous adjoint equations."""
+    _check(lib().npo_plan_set_adjoint(plan, int(kind)))
+
+
+def npo_nonlinear_adj_cont(plan, ws, u, t, y, out, stream=None):
+    _check(lib().npo_nonlinear_adj_cont(plan, _wsp(plan, ws), _fld(plan, u, "u"), t, _fld(plan, y, "y"),
+                                        _fld(plan, out, "out"), _stream(stream)))
+
+
+def npo_adjoint_step_cont(plan, ws, u_n, u_np1, lam_np1, lam_n, n, stream=None):
+    _check(lib().npo_adjoint_step_cont(plan, _wsp(plan, ws), _fld(plan, u_n, "u_n"), _fld(plan, u_np1, "u_np1"),
+                                       _fld(plan, lam_np1, "lam_np1"), _fld(plan, lam_n, "lam_n"), n,
+                                       _stream(stream)))
 
 
 def npo_plan_set_cfl_monitor(plan, enable):
