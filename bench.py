@@ -185,6 +185,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--stride", type=int, default=8, help="profiler sampling stride")
+    ap.add_argument("--adjoint", default="discrete", choices=["discrete", "continuous"],
+                    help="adjoint of the validation run: the exact discrete one or the paper's continuous "
+                         "adjoint equations (--mode validate)")
     ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "copy", "validate"],
                     help="plain: one instance (the metric); batch / serve: the systems layers; "
                          "copy: the 1 GiB copy that calibrates the byte counters; validate: the steady-pipe "
@@ -449,6 +452,7 @@ def bench_validate(args):
     nsteps = int(round(tau / dt))
     G = npo.Plan(nr, nt, nz, lz, re, 1.0, 0.0, dt, 0.0, nsteps)
     npo.npo_plan_set_graphs(G.handle, 1)
+    npo.npo_plan_set_adjoint(G.handle, 1 if args.adjoint == "continuous" else 0)
     r = npo.npo_plan_tables(G.handle, nr)[0]
     u0 = torch.from_numpy(np.ascontiguousarray(synth.solenoidal_modes(r, G.M, G.K, lz, 11))).to("cuda")
     npo.npo_project(G.handle, G.ws, u0, u0)
@@ -481,7 +485,7 @@ def bench_validate(args):
            "unit": "E(tau)/E0", "n_gpus": 1, "steps": len(hist), "warmup": 0,
            "ms_per_step": wall / max(len(hist), 1) * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "steady-38x54x64-Re1750-Lz-pi-tau80", "e0": e0,
+           "config": {"workload": "steady-38x54x64-Re1750-Lz-pi-tau80", "e0": e0, "adjoint": args.adjoint,
                       "converged": bool(hist) and not hist[-1][2], "gains": hist,
                       "G_max": float(g[k]), "t_of_G_max": float(ts[k]),
                       "G_z_at_max": float(e[k, 2] / e0), "G_rtheta_at_max": float((e[k, 0] + e[k, 1]) / e0),

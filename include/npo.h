@@ -23,7 +23,12 @@
  * Ownership: the caller owns every device buffer passed in (fields, the
  * workspace, the checkpoint arena, device scalars).  A plan owns only its
  * constant device tables, allocated by npo_plan_create and released by
- * npo_plan_destroy.  No call after plan creation allocates device memory.
+ * npo_plan_destroy.  After plan creation, device memory is allocated only by
+ * (a) the first sweep of a workspace with step graphs enabled (the HIP runtime
+ * instantiates the captured graphs; the plan also creates its capture stream
+ * once), (b) the batch calls (device descriptor tables and a capture stream,
+ * owned by the batch and released by npo_batch_destroy) and (c)
+ * npo_profile_begin (HIP events); every other call allocates nothing.
  *
  * Asynchrony: every call that takes `stream` (a hipStream_t; NULL is the
  * default stream) only enqueues work on that stream unless stated otherwise;

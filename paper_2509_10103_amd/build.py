@@ -15,15 +15,35 @@ FLAGS = [
 ]
 
 
-def build(verbose=False):
-    """Compile every source (in parallel) and link libnpo.so."""
+# Host-only sanitizers for the checking build: each -fsanitize= goes to the
+# host compilation only (device code is not instrumented).
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+ASAN_OUT = os.path.join(HERE, "libnpo_asan.so")
+
+
+def asan_runtime():
+    """The AddressSanitizer runtime of the ROCm clang (preloaded by the checking run)."""
+    clang = os.path.join(os.path.dirname(os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")), "..", "lib", "llvm",
+                         "bin", "clang++")
+    out = subprocess.run([clang, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = out.stdout.strip()
+    return path if os.path.isabs(path) and os.path.exists(path) else None
+
+
+def build(verbose=False, sanitize=False):
+    """Compile every source (in parallel) and link libnpo.so, or, with
+    sanitize, libnpo_asan.so with AddressSanitizer and UBSan on the host code
+    (for the host-side checks on the CPU)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objs, procs = [], []
+    tag = "_asan" if sanitize else ""
     for s in SOURCES:
         src = os.path.join(CSRC, s)
-        obj = os.path.join(CSRC, os.path.splitext(s)[0] + ".o")
+        obj = os.path.join(CSRC, os.path.splitext(s)[0] + tag + ".o")
         lang = ["-x", "hip"] if s.endswith(".hip") else []
-        cmd = [hipcc] + [f for f in FLAGS if f != "-shared"] + lang + ["-c", src, "-o", obj]
+        cmd = [hipcc] + [f for f in FLAGS if f != "-shared"] + (SAN_FLAGS if sanitize else []) + lang + \
+            ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((cmd, subprocess.Popen(cmd)))
@@ -31,15 +51,18 @@ def build(verbose=False):
     for cmd, pr in procs:
         if pr.wait() != 0:
             raise subprocess.CalledProcessError(pr.returncode, cmd)
-    tmp = OUT + ".tmp"
+    out = ASAN_OUT if sanitize else OUT
+    tmp = out + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + [
         "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
+    if sanitize:
+        cmd += ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-shared-libasan"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--asan" in sys.argv))

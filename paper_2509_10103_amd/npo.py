@@ -11,7 +11,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libnpo.so")
+# NPO_LIBRARY selects another build of the same library (the sanitizer build
+# used by the host-side checks); the default is the in-tree libnpo.so.
+_LIB_PATH = os.environ.get("NPO_LIBRARY") or os.path.join(_HERE, "libnpo.so")
 _lib = None
 
 
