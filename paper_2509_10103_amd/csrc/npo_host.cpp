@@ -1474,6 +1474,12 @@ struct npo_batch_s {
     std::vector<npo::BDesc*> steptab;           // per class: one descriptor per instance (step index)
     std::vector<void*> step_key;
     hipStream_t cap = nullptr;
+    // class branches of the captured step: one stream per class forked from
+    // and joined back to the capture stream, so the graph runs the classes
+    // concurrently
+    std::vector<hipStream_t> cs;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
     int launches = 0;                           // kernel launches of the last batched step
 };
 
@@ -1549,31 +1555,67 @@ npo_status batch_tables(npo_batch_s& b, void* const* ws, hipStream_t st) {
 
 // One batched step on stream st (phase 0: forward advance of cur, then every
 // step index + 1; phase 1: adjoint step of lam at u = cur, then step index - 1).
-hipError_t batch_issue(npo_batch_s& b, void* const* ws, int phase, hipStream_t st, int* launches) {
+// The launches of one class of one phase on stream st; nl counts them.
+hipError_t batch_issue_class(npo_batch_s& b, void* const* ws, int phase, size_t c, hipStream_t st, int& nl) {
     npo_batch_s::Phase& f = b.ph[phase];
+    const std::vector<int>& cl = b.classes[c];
+    const int nb = (int)cl.size();
+    if (f.batched[c]) {
+        for (size_t sidx = 0; sidx < f.launch[c].size(); ++sidx) {
+            f.launch[c][sidx](f.dtab[c] + sidx * nb, nb, st);
+            ++nl;
+        }
+    } else {
+        for (int i : cl) {
+            const npo_plan_s& p = *b.plans[i];
+            WsPtrs w = wsptrs(p, ws[i]);
+            hipError_t e = phase == 0 ? fwd_step(p, ws[i], w.cur, w.cur, 0, false, st, w.step)
+                                      : adj_step(p, ws[i], w.cur, w.lam, w.lam, 0, st, w.step, false);
+            if (e != hipSuccess) return e;
+            nl += 1;
+        }
+    }
+    hipError_t e = npo::launch_step_index_batched(b.steptab[c], nb, phase == 0 ? 1 : -1, 1, st);
+    if (e != hipSuccess) return e;
+    ++nl;
+    return hipGetLastError();
+}
+
+// Every class one after another on st.
+hipError_t batch_issue(npo_batch_s& b, void* const* ws, int phase, hipStream_t st, int* launches) {
     int nl = 0;
     for (size_t c = 0; c < b.classes.size(); ++c) {
-        const std::vector<int>& cl = b.classes[c];
-        const int nb = (int)cl.size();
-        if (f.batched[c]) {
-            for (size_t sidx = 0; sidx < f.launch[c].size(); ++sidx) {
-                f.launch[c][sidx](f.dtab[c] + sidx * nb, nb, st);
-                ++nl;
-            }
-        } else {
-            for (int i : cl) {
-                const npo_plan_s& p = *b.plans[i];
-                WsPtrs w = wsptrs(p, ws[i]);
-                hipError_t e = phase == 0 ? fwd_step(p, ws[i], w.cur, w.cur, 0, false, st, w.step)
-                                          : adj_step(p, ws[i], w.cur, w.lam, w.lam, 0, st, w.step, false);
-                if (e != hipSuccess) return e;
-                nl += 1;
-            }
-        }
-        hipError_t e = npo::launch_step_index_batched(b.steptab[c], nb, phase == 0 ? 1 : -1, 1, st);
+        hipError_t e = batch_issue_class(b, ws, phase, c, st, nl);
         if (e != hipSuccess) return e;
-        ++nl;
     }
+    if (launches) *launches = nl;
+    return hipGetLastError();
+}
+
+// Every class on its own stream, forked from st and joined back to it (inside
+// a capture this makes the classes parallel branches of the graph).
+hipError_t batch_issue_forked(npo_batch_s& b, void* const* ws, int phase, hipStream_t st, int* launches) {
+    const size_t nc = b.classes.size();
+    hipError_t e = hipSuccess;
+    if (!b.fork) e = hipEventCreateWithFlags(&b.fork, hipEventDisableTiming);
+    while (e == hipSuccess && b.cs.size() < nc) {
+        hipStream_t s = nullptr;
+        hipEvent_t j = nullptr;
+        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e == hipSuccess) b.cs.push_back(s);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&j, hipEventDisableTiming);
+        if (e == hipSuccess) b.join.push_back(j);
+    }
+    if (e != hipSuccess) return e;
+    if ((e = hipEventRecord(b.fork, st)) != hipSuccess) return e;
+    int nl = 0;
+    for (size_t c = 0; c < nc; ++c) {
+        if ((e = hipStreamWaitEvent(b.cs[c], b.fork, 0)) != hipSuccess) return e;
+        if ((e = batch_issue_class(b, ws, phase, c, b.cs[c], nl)) != hipSuccess) return e;
+        if ((e = hipEventRecord(b.join[c], b.cs[c])) != hipSuccess) return e;
+    }
+    for (size_t c = 0; c < nc; ++c)
+        if ((e = hipStreamWaitEvent(st, b.join[c], 0)) != hipSuccess) return e;
     if (launches) *launches = nl;
     return hipGetLastError();
 }
@@ -1590,7 +1632,8 @@ npo_status batch_step(npo_batch_s& b, void* const* ws, int phase, hipStream_t st
         if (!b.cap) HIPCHK(hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking));
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal));
-        hipError_t e1 = batch_issue(b, ws, phase, b.cap, &b.launches);
+        hipError_t e1 = b.classes.size() > 1 ? batch_issue_forked(b, ws, phase, b.cap, &b.launches)
+                                             : batch_issue(b, ws, phase, b.cap, &b.launches);
         hipError_t e = hipStreamEndCapture(b.cap, &g);
         if (e == hipSuccess) e = e1;
         if (e == hipSuccess) e = hipGraphInstantiate(&f.graph, g, nullptr, nullptr, 0);
@@ -1655,6 +1698,9 @@ npo_status npo_batch_destroy(npo_batch b) {
     for (npo::BDesc* d : b->steptab)
         if (d) (void)hipFree(d);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (hipStream_t c : b->cs) (void)hipStreamDestroy(c);
+    for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
+    if (b->fork) (void)hipEventDestroy(b->fork);
     delete b;
     return NPO_OK;
 }
