@@ -209,7 +209,7 @@ def main():
     ap.add_argument("--adjoint", default="discrete", choices=["discrete", "continuous"],
                     help="adjoint of the validation run: the exact discrete one or the paper's continuous "
                          "adjoint equations (--mode validate)")
-    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "copy", "validate"],
+    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "copy", "validate", "grad"],
                     help="plain: one instance (the metric); batch / serve: the systems layers; "
                          "copy: the 1 GiB copy that calibrates the byte counters; validate: the steady-pipe "
                          "validation setting (Re 1750, L_z = pi, tau = 80) run to convergence")
@@ -238,6 +238,8 @@ def main():
 
     if args.mode == "copy":
         return copy_calibration()
+    if args.mode == "grad":
+        return bench_grad(args)
     if args.mode == "validate":
         return bench_validate(args)
     if args.mode == "batch":
@@ -531,6 +533,78 @@ def bench_validate(args):
 
 def _log(line):
     print(line, file=sys.stderr, flush=True)
+
+
+def bench_grad(args):
+    """The differentiation workload at its full horizon: the gradient (one
+    forward sweep and one checkpointed adjoint sweep) at checkpoint budgets
+    {8, 32, 128, all} stored states, recomputation against memory, with the
+    gradients of all budgets compared bitwise; then the gradient against
+    central differences (eps = 1e-6) along 16 seeded solenoidal directions,
+    every product and norm taken on the device."""
+    import torch
+    from paper_2509_10103_amd import npo
+    torch.cuda.set_device(0)
+    cfg = dict(configs.C3)
+    N = cfg["nsteps"]
+    G = npo.Plan(cfg["nr"], cfg["nt"], cfg["nz"], cfg["lz"], cfg["re"], cfg["wo"], cfg["amp"], cfg["dt"], cfg["t0"], N)
+    npo.npo_plan_set_graphs(G.handle, 1)
+    from paper_2509_10103_amd import tune
+    best, _ = tune.tune(G, cfg["nr"], cfg["nt"], cfg["nz"], use_cache=not args.retune, save=False)
+    tuning = list(best)
+    r = npo.npo_plan_tables(G.handle, cfg["nr"])[0]
+    u0 = torch.from_numpy(np.ascontiguousarray(synth.solenoidal_modes(r, G.M, G.K, cfg["lz"], cfg["seed"]))).to("cuda")
+    npo.npo_project(G.handle, G.ws, u0, u0)
+    npo.npo_normalize(G.handle, G.ws, u0, cfg["e0"])
+    pts = cfg["nr"] * cfg["nt"] * cfg["nz"]
+    runs, grads = [], {}
+    for nck in (8, 32, 128, N):
+        ck = G.arena(nck)
+        uN, lam = G.field(), G.field()
+        npo.npo_forward_run(G.handle, G.ws, ck, nck, u0, uN)            # warm-up (graph capture)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        npo.npo_forward_run(G.handle, G.ws, ck, nck, u0, uN)
+        nrec = npo.npo_adjoint_run(G.handle, G.ws, ck, nck, uN, lam)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        grads[nck] = lam
+        runs.append({"n_ckpt": nck, "arena_gb": nck * G.info["field_bytes"] / 1e9, "recompute_steps": nrec,
+                     "gradient_s": wall, "gp_steps_per_s": 2 * N * pts / wall})
+        print(f"[bench] gradient with {nck} slots: {wall:.2f} s, {nrec} recomputed steps (t={elapsed():.0f} s)",
+              file=sys.stderr, flush=True)
+        del ck
+        torch.cuda.empty_cache()
+    lam = grads[N]
+    same = all(torch.equal(grads[k], lam) for k in grads)
+    # central differences along seeded solenoidal directions
+    ck1 = G.arena(1)
+    tmp = G.field()
+    nl = math.sqrt(G.inner(lam, lam))
+    nu = math.sqrt(G.inner(u0, u0))
+    eps, worst = 1e-6, 0.0
+
+    def J(u):
+        npo.npo_forward_run(G.handle, G.ws, ck1, 1, u, tmp)
+        return G.energy(tmp)
+    for s in range(100, 116):
+        d = torch.from_numpy(np.ascontiguousarray(synth.solenoidal_modes(r, G.M, G.K, cfg["lz"], s))).to("cuda")
+        npo.npo_project(G.handle, G.ws, d, d)
+        d *= nu / math.sqrt(G.inner(d, d))
+        fd = (J(u0 + eps * d) - J(u0 - eps * d)) / (2 * eps)
+        worst = max(worst, abs(fd - G.inner(lam, d)) / (nl * nu))
+    print(f"[bench] central differences along 16 directions: worst relative error {worst:.2e} "
+          f"(t={elapsed():.0f} s)", file=sys.stderr, flush=True)
+    best = max(runs, key=lambda x: x["gp_steps_per_s"])
+    out = {"metric": "fwd+adjoint grid-point-steps/s (gradient)", "value": runs[-1]["gp_steps_per_s"],
+           "unit": "grid-point-steps/s", "n_gpus": 1, "steps": len(runs), "warmup": 1,
+           "ms_per_step": runs[-1]["gradient_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": cfg["name"], "grid": [cfg["nr"], cfg["nt"], cfg["nz"]], "nsteps": N,
+                      "dt": cfg["dt"], "e0": cfg["e0"], "launch_shapes": tuning, "budgets": runs,
+                      "gradients_bitwise_equal_across_budgets": same, "fd_worst_relative_error": worst,
+                      "fd_directions": 16, "fd_eps": eps, "fastest_budget": best["n_ckpt"]}}
+    print(json.dumps(out), flush=True)
 
 
 def c5_jobs(n=128, seed=7):
