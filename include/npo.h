@@ -166,8 +166,9 @@ npo_status npo_adjoint_step(npo_plan plan, void* ws, const void* u_n, const void
  *                           use the exact discrete adjoint, kind 1 the
  *                           continuous one; the continuous sweeps make u^{n+1}
  *                           of each segment's last step with one forward step
- *                           and keep it in the workspace, and do not replay
- *                           captured graphs.  Batches (npo_batch_*) take the
+ *                           (not counted in n_recompute) and keep it in the
+ *                           workspace, and replay captured graphs for the
+ *                           forward advances only.  Batches (npo_batch_*) take the
  *                           discrete adjoint only: NPO_EUNSUPPORTED otherwise. */
 npo_status npo_nonlinear_adj_cont(npo_plan plan, void* ws, const void* u, double t, const void* y, void* out,
                                   void* stream);

@@ -98,3 +98,33 @@ def test_batches_refuse_the_continuous_adjoint():
     npo.npo_batch_destroy(b)
     assert npo.lib().npo_plan_set_adjoint(G.handle, 2) == -1
     G.close()
+
+
+@pytest.mark.parametrize("graphs", [0, 1])
+def test_continuous_sweep_with_graphs_and_host_tier_is_bitwise_the_same(graphs):
+    """Forward advances replayed from captured graphs and the two-level
+    checkpoints (each interval makes its own u^{n+1} for its last step) leave
+    the continuous gradient bitwise unchanged."""
+    import torch
+    from paper_2509_10103_amd import npo
+    P, G = make(dict(SMALL, nsteps=24))
+    print(f"[adjoint-cont] host tier, graphs {graphs}", flush=True)
+    N, nck = 24, 4
+    u0 = to_dev(seed_field(P, 3, 1e-2))
+    ck = G.arena(nck)
+    uN, lam = G.field(), G.field()
+    npo.npo_plan_set_adjoint(G.handle, 1)
+    npo.npo_forward_run(G.handle, G.ws, ck, nck, u0, uN)
+    npo.npo_adjoint_run(G.handle, G.ws, ck, nck, uN, lam)
+    ref = to_host(lam)
+    _, _, g = P.gradient_cont(to_host(u0), N)
+    assert relerr(P, ref, g) < 1e-10
+    npo.npo_plan_set_graphs(G.handle, graphs)
+    for nf in (0, 2, 5):
+        host = torch.empty(max(nf, 1) * G.info["field_bytes"], dtype=torch.uint8, pin_memory=True)
+        u2, l2 = G.field(), G.field()
+        npo.npo_forward_run_hybrid(G.handle, G.ws, ck, nck, host, nf, u0, u2)
+        npo.npo_adjoint_run_hybrid(G.handle, G.ws, ck, nck, host, nf, u2, l2)
+        assert np.array_equal(to_host(l2), ref), nf
+    npo.npo_plan_set_graphs(G.handle, 0)
+    G.close()
