@@ -309,9 +309,9 @@ npo_status npo_plan_set_graphs(npo_plan plan, int32_t enable);
  * smaller gap to a neighbouring radial node (2 r_0 at the first node), into a
  * device maximum kept in the workspace (the explicit convective terms of the
  * predictor-corrector step are stable only below a bound of order one).
- * Supported where the forward azimuthal pass runs the pruned kernel (ntheta
- * a multiple of 12 with zb_fwd > 0); elsewhere the monitor reads 0.  Drops
- * captured graphs.  npo_cfl_read copies the maximum so far into out_dev (one
+ * Supported by the LDS-staged azimuthal kernels of every length (tuning
+ * zb_fwd > 0); with the wave-resident kernels (zb_fwd < 0) the monitor reads
+ * 0.  Drops captured graphs.  npo_cfl_read copies the maximum so far into out_dev (one
  * device double) on `stream` and, with reset = 1, clears it; the maximum lives
  * in the workspace, so clear it (a read with reset = 1) before the first
  * monitored step of a new workspace. */

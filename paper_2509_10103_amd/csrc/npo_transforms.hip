@@ -145,6 +145,24 @@ __device__ __forceinline__ void phase_of(const KP& p, const TimeArg& ta, double&
     sincos(p.omega * t, &sw, &cw);
 }
 
+// CFL monitor pieces shared by the azimuthal kernels: the scales dt / dz,
+// dt / (r dtheta) and dt / dr at radial node j (dr: the smaller neighbour gap;
+// the axis gap of the first node is 2 r_0), and the fold of a thread's maximum
+// into *dst: a wave maximum, then one atomic maximum per wave (non-negative
+// doubles order as their bit patterns).  Every lane of the wave must call it.
+__device__ __forceinline__ void cfl_scales(const KP& p, int j, int nt, double& cz, double& cth, double& cr) {
+    const double rj = p.r[j];
+    const double gl = j > 0 ? rj - p.r[j - 1] : 2.0 * rj;
+    const double gr = j + 1 < p.nr ? p.r[j + 1] - rj : gl;
+    cz = p.dt * p.nz / p.lz;
+    cth = p.dt * nt / (2.0 * M_PI * rj);
+    cr = p.dt / fmin(gl, gr);
+}
+__device__ __forceinline__ void cfl_fold(double cmax, unsigned long long* dst) {
+    for (int off = 32; off > 0; off >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(dst, (unsigned long long)__double_as_longlong(cmax));
+}
+
 __global__ void k_theta(KP p, int adj, int ZB, const double2* __restrict__ zu, int nfu, const double2* __restrict__ zy,
                         int nfy, double2* __restrict__ tb, TimeArg ta) {
     extern __shared__ double2 sh[];
@@ -185,6 +203,8 @@ __global__ void k_theta(KP p, int adj, int ZB, const double2* __restrict__ zu, i
     double U, Om, cw, sw;
     phase_of(p, ta, cw, sw);
     base_at(p, j, cw, sw, U, Om);
+    double cmax = 0.0, cz = 0.0, cth = 0.0, cr = 0.0;
+    if (ta.cfl) cfl_scales(p, j, nt, cz, cth, cr);
     for (int t = threadIdx.x; t < ZB * nt; t += blockDim.x) {
         const int zi = t / nt, th = t - zi * nt;
         const double2 s0 = R1[(0 * ZB + zi) * nt + th];
@@ -193,6 +213,7 @@ __global__ void k_theta(KP p, int adj, int ZB, const double2* __restrict__ zu, i
         const double ur = s0.x, ut = s0.y, uz = s1.x, wr = s1.y, wt = s2.x, wz = s2.y;
         if (!adj) {
             const double uzU = uz + U;
+            if (ta.cfl) cmax = fmax(cmax, fabs(uzU) * cz + fabs(ut) * cth + fabs(ur) * cr);
             const double Nr = ut * wz - uzU * wt - uz * Om;
             const double Nt = uzU * wr - ur * wz;
             const double Nz = ur * (wt + Om) - ut * wr;
@@ -234,6 +255,7 @@ __global__ void k_theta(KP p, int adj, int ZB, const double2* __restrict__ zu, i
         else v = cscale(cmuli(csub(b, a)), 0.5);          // (a - b) / (2i)
         tb[((size_t)(j * nfo + f) * mp1 + m) * nz + z0 + zi] = v;
     }
+    if (ta.cfl) cfl_fold(cmax, ta.cfl);
 }
 
 // ------------------------------------------------------ axial forward FFT
@@ -750,7 +772,9 @@ __global__ __launch_bounds__(TB) void k_zfwd_p(KP p, const double2* __restrict__
 // placed so that consecutive tiles of one j run on the same XCD (hardware
 // round-robin over 8 XCDs by workgroup id), where they share L2 lines of the
 // [j][f][m][z] intermediates.
-template <int NT, int ADJ, int ZB>
+// CFL (forward only): also fold the CFL number of u into *ta.cfl, as a
+// separate instance so that the plain kernel keeps its registers.
+template <int NT, int ADJ, int ZB, bool CFL = false>
 __global__ __launch_bounds__(TB) void k_theta_t(KP p, int nq, int Q, const double2* __restrict__ zu, int nfu,
                                                const double2* __restrict__ zy, int nfy, double2* __restrict__ tb,
                                                TimeArg ta) {
@@ -778,6 +802,8 @@ __global__ __launch_bounds__(TB) void k_theta_t(KP p, int nq, int Q, const doubl
     double U, Om, cw, sw;
     phase_of(p, ta, cw, sw);
     base_at(p, j, cw, sw, U, Om);
+    double cmax = 0.0, cz = 0.0, cth = 0.0, cr = 0.0;
+    if constexpr (CFL) cfl_scales(p, j, NT, cz, cth, cr);
     // u, w pairs from zu (nfu fields per node), y pairs from zy (nfy per node)
     const double2* bu = zu + (size_t)j * nfu * MP1 * nz;
     const double2* by = ADJ ? zy + (size_t)j * nfy * MP1 * nz : nullptr;
@@ -850,6 +876,7 @@ __global__ __launch_bounds__(TB) void k_theta_t(KP p, int nq, int Q, const doubl
             const double ur = s0.x, ut = s0.y, uz = s1.x, wr = s1.y, wt = s2.x, wz = s2.y;
             if constexpr (!ADJ) {
                 const double uzU = uz + U;
+                if constexpr (CFL) cmax = fmax(cmax, fabs(uzU) * cz + fabs(ut) * cth + fabs(ur) * cr);
                 const double Nr = ut * wz - uzU * wt - uz * Om;
                 const double Nt = uzU * wr - ur * wz;
                 const double Nz = ur * (wt + Om) - ut * wr;
@@ -895,6 +922,7 @@ __global__ __launch_bounds__(TB) void k_theta_t(KP p, int nq, int Q, const doubl
         }
         __syncthreads();
     }
+    if constexpr (CFL) cfl_fold(cmax, ta.cfl);
 }
 
 // Pieces shared by the pruned azimuthal kernels (N_theta = 3P, sequences of
@@ -1020,14 +1048,7 @@ __global__ __launch_bounds__(TB) void k_theta_p(KP p, int nq, int Q, const doubl
     // CFL monitor: dt / dz, dt / (r dtheta), dt / dr at this radial node (dr:
     // the smaller neighbour gap; the axis gap of the first node is 2 r_0)
     double cmax = 0.0, cz = 0.0, cth = 0.0, cr = 0.0;
-    if constexpr (CFL) {
-        const double rj = p.r[j];
-        const double gl = j > 0 ? rj - p.r[j - 1] : 2.0 * rj;
-        const double gr = j + 1 < p.nr ? p.r[j + 1] - rj : gl;
-        cz = p.dt * nz / p.lz;
-        cth = p.dt * NT / (2.0 * M_PI * rj);
-        cr = p.dt / fmin(gl, gr);
-    }
+    if constexpr (CFL) cfl_scales(p, j, NT, cz, cth, cr);
     const double2* bu = zu + (size_t)j * nfu * MP1 * nz;
     // item e: column zi = e % ZB, butterfly pair jj, field pair pi (u_r u_t,
     // u_z w_r, w_t w_z); modes jj and P - jj of both fields
@@ -1115,12 +1136,7 @@ __global__ __launch_bounds__(TB) void k_theta_p(KP p, int nq, int Q, const doubl
         }
         __syncthreads();
     }
-    if constexpr (CFL) {
-        // wave maximum, then one atomic per wave (non-negative doubles order
-        // as their bit patterns)
-        for (int off = 32; off > 0; off >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, off));
-        if ((threadIdx.x & 63) == 0) atomicMax(ta.cfl, (unsigned long long)__double_as_longlong(cmax));
-    }
+    if constexpr (CFL) cfl_fold(cmax, ta.cfl);
 }
 
 // ================================================ wave-resident azimuthal pass
@@ -1733,7 +1749,11 @@ static void launch_theta_k(dim3 grid, size_t sh, const npo_plan_s& p, int nq, in
         });
     } else {
         not_batched();
-        hipLaunchKernelGGL((k_theta_t<NT, ADJ, ZB>), grid, dim3(TB), sh, st, p.kp, nq, Q, zu, nfu, zy, nfy, tb, ta);
+        if (!ADJ && ta.cfl)
+            hipLaunchKernelGGL((k_theta_t<NT, 0, ZB, true>), grid, dim3(TB), sh, st, p.kp, nq, Q, zu, nfu, zy, nfy,
+                               tb, ta);
+        else
+            hipLaunchKernelGGL((k_theta_t<NT, ADJ, ZB>), grid, dim3(TB), sh, st, p.kp, nq, Q, zu, nfu, zy, nfy, tb, ta);
     }
 }
 

@@ -62,7 +62,7 @@ def family_kernels(nt, nz, names=(), shapes=(1, 4, 4), nr=64):
     zk = "p" if pz else "t"
     mb = (lambda nf: f", {2 if nf <= 3 else 1}") if pz else (lambda nf: "")
     fz = f"k_zinv_{zk}<{nz}, 0, 6{mb(6)}>" in names or not names
-    ft = f"k_theta_t<{nt}, 0, {zbf}>" in names or f"k_theta_p<{nt}, {zbf}, false>" in names or not names
+    ft = f"k_theta_t<{nt}, 0, {zbf}, false>" in names or f"k_theta_p<{nt}, {zbf}, false>" in names or not names
     zi = (lambda nf: f"k_zinv_{zk}<{nz}, {6 if nf == 3 else 0}, {nf}{mb(nf)}>") if fz else (lambda nf: "k_zinv")
     zf = (lambda nf: f"k_zfwd_{zk}<{nz}, {nf}{mb(nf)}>") if fz else (lambda nf: "k_zfwd")
     def th(a):
@@ -74,7 +74,7 @@ def family_kernels(nt, nz, names=(), shapes=(1, 4, 4), nr=64):
             return "k_theta"
         if nt % 12 == 0:
             return f"k_theta_pa<{nt}, {zba}>" if a else f"k_theta_p<{nt}, {zbf}, false>"
-        return f"k_theta_t<{nt}, {a}, {zba if a else zbf}>"
+        return f"k_theta_t<{nt}, {a}, {zba if a else zbf}, false>"
     return {
         "curl": "k_curl_aux", "zinv_fwd": zi(6), "theta_fwd": th(0), "zfwd_fwd": zf(3),
         "zinv_adj": zi(9), "theta_adj": th(1), "zfwd_adj": zf(6), "zinv_adjy": zi(3),

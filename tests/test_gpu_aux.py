@@ -35,10 +35,16 @@ def _read(G, reset=False):
     return float(out.item())
 
 
-def test_cfl_monitor_matches_the_physical_maximum():
+# the pruned azimuthal kernel (N_theta = 24), the compiled-length one (64) and
+# the generic one (54)
+CFL_GRIDS = [CFG, dict(CFG, nt=64, nz=48, lz=5.0), dict(CFG, nt=54, nz=36, lz=4.0)]
+
+
+@pytest.mark.parametrize("grid", CFL_GRIDS, ids=["pruned", "compiled", "generic"])
+def test_cfl_monitor_matches_the_physical_maximum(grid):
     from paper_2509_10103_amd import npo
-    P, G = make(dict(CFG, nsteps=3))
-    print("[aux] cfl monitor 10x24x24", flush=True)
+    P, G = make(dict(grid, nsteps=3))
+    print(f"[aux] cfl monitor {grid['nr']}x{grid['nt']}x{grid['nz']}", flush=True)
     zg, _, zba = npo.npo_plan_get_tuning(G.handle)
     npo.npo_plan_set_tuning(G.handle, zg, 2, zba)          # pruned forward azimuthal kernel
     u = seed_field(P, 11, 3e-2)
