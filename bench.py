@@ -283,11 +283,20 @@ def main():
     n_rec = npo.npo_ckpt_count(cfg["nsteps"], nck)
     print(f"[bench] {cfg['name']} nsteps={cfg['nsteps']} n_ckpt={nck} arena={arena.numel() * 16 / 2**30:.1f} GiB "
           f"recompute/sweep={n_rec} launch shapes {shapes} (t={elapsed():.1f} s)", file=sys.stderr, flush=True)
+    # the untimed initial sweep also records the largest CFL number of the
+    # trajectory (the monitor is off in the timed iterations)
+    cfl = torch.zeros(1, dtype=torch.float64, device="cuda")
+    npo.npo_plan_set_cfl_monitor(G.handle, 1)
+    npo.npo_cfl_read(G.handle, G.ws, cfl, reset=True)
     t = time.perf_counter()
     npo.npo_forward_run(G.handle, G.ws, arena, nck, u0, uN)
     torch.cuda.synchronize()
     t_sweep = time.perf_counter() - t
-    print(f"[bench] initial forward sweep {t_sweep:.2f} s (t={elapsed():.1f} s)", file=sys.stderr, flush=True)
+    npo.npo_cfl_read(G.handle, G.ws, cfl, reset=True)
+    npo.npo_plan_set_cfl_monitor(G.handle, 0)
+    cfl_max = float(cfl.item())
+    print(f"[bench] initial forward sweep {t_sweep:.2f} s, CFL max {cfl_max:.3f} (t={elapsed():.1f} s)",
+          file=sys.stderr, flush=True)
 
     def one_iter():
         st = npo.npo_iterate(G.handle, G.ws, arena, nck, u0, uN, cfg["e0"])
@@ -393,6 +402,7 @@ def main():
                    "counted": "one forward and one adjoint sweep per iteration; recomputation and extra "
                               "line-search trial sweeps not counted",
                    "forward_sweeps_timed": fwd_sweeps,
+                   "cfl_max_initial_sweep": cfl_max,
                    "value_counting_every_trial_sweep": value_all,
                    "iteration_latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
                    "gains": [[h["G_old"], h["G_new"], int(h["accepted"]), int(h["forward_sweeps"])] for h in hist]},
@@ -512,7 +522,11 @@ def bench_validate(args):
     h = torch.zeros((rows, 5), dtype=torch.float64, device="cuda")
     a2 = H.arena(1)
     u1 = H.field()
+    cfl = torch.zeros(1, dtype=torch.float64, device="cuda")
+    npo.npo_plan_set_cfl_monitor(H.handle, 1)
+    npo.npo_cfl_read(H.handle, H.ws, cfl, reset=True)
     npo.npo_forward_run_diag(H.handle, H.ws, a2, 1, u0, u1, h, 10)
+    npo.npo_cfl_read(H.handle, H.ws, cfl, reset=True)
     e = h.cpu().numpy()
     g = e[:, :3].sum(axis=1) / e0
     ts = np.array([min(10 * i, nsteps + extra) for i in range(rows)]) * dt
@@ -523,7 +537,7 @@ def bench_validate(args):
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "steady-38x54x64-Re1750-Lz-pi-tau80", "e0": e0, "adjoint": args.adjoint,
                       "converged": bool(hist) and not hist[-1][2], "gains": hist,
-                      "G_max": float(g[k]), "t_of_G_max": float(ts[k]),
+                      "G_max": float(g[k]), "t_of_G_max": float(ts[k]), "cfl_max_of_history": float(cfl.item()),
                       "G_z_at_max": float(e[k, 2] / e0), "G_rtheta_at_max": float((e[k, 0] + e[k, 1]) / e0),
                       "energy_fraction_m_M_at_max": float(e[k, 3] / e[k, :3].sum()),
                       "energy_fraction_k_K_at_max": float(e[k, 4] / e[k, :3].sum()),
