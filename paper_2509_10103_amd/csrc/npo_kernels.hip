@@ -163,9 +163,12 @@ __device__ void gsubst_T(const double* __restrict__ LU, int n1, double* x, int s
 // the chain through a ring of PF rows in registers: the row used at step i is
 // refilled with row i + PF, and a scheduling barrier after every step keeps
 // those loads where they are written, so PF rows' loads stay in flight and the
-// L2 latency is paid once per PF rows rather than once per few rows (without
-// unrolling, loads carried around a loop are drained at every iteration).
-template <int N1, int PF>
+// cache latency is paid once per PF rows rather than once per few rows (without
+// unrolling, loads carried around a loop are drained at every iteration).  The
+// entries of x are read DB steps ahead into a second ring, so no LDS read is on
+// the dependence chain either (a row of x is read before its own step writes
+// it; the arithmetic and its order are unchanged).
+template <int N1, int PF, int DB = 4>
 __device__ __forceinline__ void gsubst_u(const double* __restrict__ LU, double* x, int s) {
     double y1 = 0.0, y2 = 0.0, y3 = 0.0, y4 = 0.0, y5 = 0.0;   // y_{i-1} .. y_{i-5}
     double Lr[PF][5];
@@ -174,10 +177,15 @@ __device__ __forceinline__ void gsubst_u(const double* __restrict__ LU, double* 
         if (r < N1)
 #pragma unroll
             for (int c = 0; c < 5; ++c) Lr[r][c] = LU[r * LUW + c];
+    double xb[DB];
+#pragma unroll
+    for (int r = 0; r < DB; ++r)
+        if (r < N1) xb[r] = x[r * s];
 #pragma unroll
     for (int i = 0; i < N1; ++i) {
         const int r = i % PF;
-        double y = x[i * s];
+        double y = xb[i % DB];
+        if (i + DB < N1) xb[i % DB] = x[(i + DB) * s];
         y = fma(-Lr[r][0], y5, y);
         y = fma(-Lr[r][1], y4, y);
         y = fma(-Lr[r][2], y3, y);
@@ -198,9 +206,13 @@ __device__ __forceinline__ void gsubst_u(const double* __restrict__ LU, double* 
 #pragma unroll
             for (int c = 0; c < 4; ++c) Ur[r][c] = LU[(N1 - 1 - r) * LUW + 5 + c];
 #pragma unroll
+    for (int r = 0; r < DB; ++r)
+        if (r < N1) xb[r] = x[(N1 - 1 - r) * s];
+#pragma unroll
     for (int k = 0; k < N1; ++k) {
         const int i = N1 - 1 - k, r = k % PF;
-        double v = x[i * s];
+        double v = xb[k % DB];
+        if (k + DB < N1) xb[k % DB] = x[(i - DB) * s];
         v = fma(-Ur[r][3], x3, v);
         v = fma(-Ur[r][2], x2, v);
         v = fma(-Ur[r][1], x1, v);
@@ -214,7 +226,7 @@ __device__ __forceinline__ void gsubst_u(const double* __restrict__ LU, double* 
     }
 }
 
-template <int N1, int PF>
+template <int N1, int PF, int DB = 4>
 __device__ __forceinline__ void gsubst_T_u(const double* __restrict__ LU, double* x, int s) {
     double z1 = 0.0, z2 = 0.0, z3 = 0.0;                       // z_{i-1} .. z_{i-3}
     double u61 = 0.0, u71 = 0.0, u72 = 0.0, u81 = 0.0, u82 = 0.0, u83 = 0.0;
@@ -224,11 +236,16 @@ __device__ __forceinline__ void gsubst_T_u(const double* __restrict__ LU, double
         if (r < N1)
 #pragma unroll
             for (int c = 0; c < 4; ++c) Ur[r][c] = LU[r * LUW + 5 + c];
+    double xb[DB];
+#pragma unroll
+    for (int r = 0; r < DB; ++r)
+        if (r < N1) xb[r] = x[r * s];
 #pragma unroll
     for (int i = 0; i < N1; ++i) {
         const int r = i % PF;
         const double inv = Ur[r][0], r6 = Ur[r][1], r7 = Ur[r][2], r8 = Ur[r][3];
-        double v = x[i * s];
+        double v = xb[i % DB];
+        if (i + DB < N1) xb[i % DB] = x[(i + DB) * s];
         v = fma(-u83, z3, v);
         v = fma(-u72, z2, v);
         v = fma(-u61, z1, v);
@@ -253,9 +270,13 @@ __device__ __forceinline__ void gsubst_T_u(const double* __restrict__ LU, double
 #pragma unroll
             for (int c = 0; c < 5; ++c) Lr[r][c] = LU[(N1 - 1 - r) * LUW + c];
 #pragma unroll
+    for (int r = 0; r < DB; ++r)
+        if (r < N1) xb[r] = x[(N1 - 1 - r) * s];
+#pragma unroll
     for (int k = 0; k < N1; ++k) {
         const int i = N1 - 1 - k, r = k % PF;
-        double v = x[i * s];
+        double v = xb[k % DB];
+        if (k + DB < N1) xb[k % DB] = x[(i - DB) * s];
         v = fma(-l05, x5, v);
         v = fma(-l14, x4, v);
         v = fma(-l23, x3, v);
@@ -276,10 +297,11 @@ __device__ __forceinline__ void gsubst_T_u(const double* __restrict__ LU, double
 }
 
 // Substitutions for a compile-time interior size N1C (0: the size n1 given at
-// run time).  Ring depths: 8 rows in the forward solve, 6 in the adjoint one
-// (which keeps its accumulator inputs in registers across the chains and must
-// stay within 256 VGPRs for two waves per SIMD).
-constexpr int PF_FWD = 8, PF_ADJ = 6;
+// run time).  Ring depths: 12 rows in the forward solve (about 220 VGPRs; 16
+// would spill), 6 in the adjoint one (which keeps its accumulator inputs in
+// registers across the chains and must stay within 256 VGPRs for two waves per
+// SIMD).
+constexpr int PF_FWD = 12, PF_ADJ = 6;
 template <int N1C>
 __device__ __forceinline__ void subst(const double* __restrict__ LU, int n1, double* x, int s) {
     if constexpr (N1C > 0) gsubst_u<N1C, PF_FWD>(LU, x, s);

@@ -158,9 +158,16 @@ __device__ __forceinline__ void cfl_scales(const KP& p, int j, int nt, double& c
     cth = p.dt * nt / (2.0 * M_PI * rj);
     cr = p.dt / fmin(gl, gr);
 }
+// The running maximum only grows between resets, and a device-scope load never
+// returns more than it holds, so a wave whose maximum does not exceed the value
+// read skips the atomic: after the first blocks almost every wave does, instead
+// of some ten thousand atomics per launch queueing on one address.
 __device__ __forceinline__ void cfl_fold(double cmax, unsigned long long* dst) {
     for (int off = 32; off > 0; off >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, off));
-    if ((threadIdx.x & 63) == 0) atomicMax(dst, (unsigned long long)__double_as_longlong(cmax));
+    if ((threadIdx.x & 63) == 0) {
+        const unsigned long long v = (unsigned long long)__double_as_longlong(cmax);
+        if (v > __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(dst, v);
+    }
 }
 
 __global__ void k_theta(KP p, int adj, int ZB, const double2* __restrict__ zu, int nfu, const double2* __restrict__ zy,
@@ -1015,9 +1022,11 @@ __device__ __forceinline__ void theta_last_pair(const double2* R, const double2*
 // N_z is transformed as its own (real) sequence.  Five barriers per tile
 // instead of eight, and about 40% fewer LDS accesses than the generic plan.
 // CFL: also fold the CFL number of u into *ta.cfl (a separate instance, so
-// the plain kernel keeps its register budget and occupancy).
+// the plain kernel keeps its register budget and occupancy; the monitoring
+// instance is held to three waves per SIMD as well, at the cost of three
+// spilled registers: 172 VGPRs would leave it two).
 template <int NT, int ZB, bool CFL>
-__global__ __launch_bounds__(TB) void k_theta_p(KP p, int nq, int Q, const double2* __restrict__ zu, int nfu,
+__global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(CFL ? 3 : 1))) void k_theta_p(KP p, int nq, int Q, const double2* __restrict__ zu, int nfu,
                                                double2* __restrict__ tb, TimeArg ta, const BDesc* bd) {
     static_assert(NT % 12 == 0, "N_theta = 3P with P a multiple of 4");
     if (bd) {
