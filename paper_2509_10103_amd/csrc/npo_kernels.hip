@@ -297,11 +297,9 @@ __device__ __forceinline__ void gsubst_T_u(const double* __restrict__ LU, double
 }
 
 // Substitutions for a compile-time interior size N1C (0: the size n1 given at
-// run time).  Ring depths: 12 rows in the forward solve (about 220 VGPRs; 16
-// would spill), 6 in the adjoint one (which keeps its accumulator inputs in
-// registers across the chains and must stay within 256 VGPRs for two waves per
-// SIMD).
-constexpr int PF_FWD = 12, PF_ADJ = 6;
+// run time).  Ring depths: 12 rows in both solves (about 220 VGPRs of the 256
+// that two waves per SIMD allow; 16 would spill).
+constexpr int PF_FWD = 12, PF_ADJ = 12;
 template <int N1C>
 __device__ __forceinline__ void subst(const double* __restrict__ LU, int n1, double* x, int s) {
     if constexpr (N1C > 0) gsubst_u<N1C, PF_FWD>(LU, x, s);
@@ -680,8 +678,10 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
     __shared__ double2 sphi[NR_MAX][RQ];
     __shared__ double2 sa[RQ];
     __shared__ double2 sred[RJ][RQ];
-    // every global input is requested up front: A, B (staged in LDS for the
-    // curl stencils), the homogeneous solutions and the accumulators Y, Z
+    // A, B (staged in LDS for the curl stencils) and the homogeneous solutions
+    // are requested up front; the accumulators Y, Z only after the
+    // substitutions (held across the chains they would take some 100 VGPRs and
+    // leave the factor ring 6 rows deep)
     const double* hom = p.HOM + ((size_t)sl.ka * p.mp1 + m) * (3 * nr + 1);
     double2 V[NJ][3], Yv[NJ][3], Zv[NJ][3];
     double hv[NJ][3];
@@ -696,8 +696,6 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
             for (int c = 0; c < 3; ++c) {
                 const size_t id = fidx(p, c, j, m, sl.kk);
                 V[jj][c] = cscale(Ain[id], ca);
-                if (ao.Yout && ao.Yin) Yv[jj][c] = cscale(ao.Yin[id], ao.sy);
-                if (ao.Zout && ao.Zin) Zv[jj][c] = cscale(ao.Zin[id], ao.sz);
                 if constexpr (useB) sy[c][j][q] = Bin[id];
             }
             if (j < N1) {
@@ -807,6 +805,20 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
             subst_T<NRC ? NRC - 1 : 0>(p.PLU + ((size_t)s2.ka * p.mp1 + m) * opsz, N1,
                                        reinterpret_cast<double*>(&sphi[0][qq]) + part,
                      2 * RQ);
+    }
+    if (sl.valid) {
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) {
+            const int j = jg + jj * RJ;
+            if (j < nr) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const size_t id = fidx(p, c, j, m, sl.kk);
+                    if (ao.Yout && ao.Yin) Yv[jj][c] = cscale(ao.Yin[id], ao.sy);
+                    if (ao.Zout && ao.Zin) Zv[jj][c] = cscale(ao.Zin[id], ao.sz);
+                }
+            }
+        }
     }
     __syncthreads();
     if (!sl.valid) return;

@@ -1023,10 +1023,11 @@ __device__ __forceinline__ void theta_last_pair(const double2* R, const double2*
 // instead of eight, and about 40% fewer LDS accesses than the generic plan.
 // CFL: also fold the CFL number of u into *ta.cfl (a separate instance, so
 // the plain kernel keeps its register budget and occupancy; the monitoring
-// instance is held to three waves per SIMD as well, at the cost of three
-// spilled registers: 172 VGPRs would leave it two).
+// instance is held to three waves per SIMD as well where the LDS allows three
+// blocks per CU, at the cost of three spilled registers: 172 VGPRs would leave
+// it two).
 template <int NT, int ZB, bool CFL>
-__global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(CFL ? 3 : 1))) void k_theta_p(KP p, int nq, int Q, const double2* __restrict__ zu, int nfu,
+__global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(CFL && ZB <= 4 ? 3 : 1))) void k_theta_p(KP p, int nq, int Q, const double2* __restrict__ zu, int nfu,
                                                double2* __restrict__ tb, TimeArg ta, const BDesc* bd) {
     static_assert(NT % 12 == 0, "N_theta = 3P with P a multiple of 4");
     if (bd) {
