@@ -396,7 +396,8 @@ def main():
         "config": {"workload": cfg["name"], "grid": [cfg["nr"], cfg["nt"], cfg["nz"]], "lz_radii": cfg["lz"],
                    "re": cfg["re"], "wo": cfg["wo"], "amp": cfg["amp"], "dt": cfg["dt"], "t0": cfg["t0"],
                    "nsteps": cfg["nsteps"], "ncorr": ncorr, "n_ckpt": nck, "recompute_per_sweep": n_rec,
-                   "launch_shapes": shapes, "tuning": tuning, "e0": cfg["e0"], "seed": cfg["seed"],
+                   "launch_shapes": shapes, "radial_block": npo.npo_plan_get_radial_block(G.handle),
+                   "tuning": tuning, "e0": cfg["e0"], "seed": cfg["seed"],
                    "steps_requested": args.steps, "warmup_requested": args.warmup, "budget_s": args.budget,
                    "run_s": round(elapsed(), 1),
                    "counted": "one forward and one adjoint sweep per iteration; recomputation and extra "

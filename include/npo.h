@@ -293,6 +293,15 @@ npo_status npo_iterate(npo_plan plan, void* ws, void* ckpt, int32_t n_ckpt, void
 npo_status npo_plan_set_tuning(npo_plan plan, int32_t zgroup, int32_t zb_fwd, int32_t zb_adj);
 npo_status npo_plan_get_tuning(npo_plan plan, int32_t* zgroup, int32_t* zb_fwd, int32_t* zb_adj);
 
+/* Launch shape of the radial kernels (the per-mode solves of Sec. 2.3 and
+ * their transposes, the autotuner's other knob): rg = axial wavenumbers |k|
+ * per block (4, 8 or 16; a block holds the +k and -k modes of rg wavenumbers
+ * at one azimuthal index, 32 rg threads).  Larger blocks read longer runs of
+ * each radial row, smaller ones give small grids more blocks.  Any other value
+ * is NPO_EINVAL.  Results do not depend on rg.  Default 16. */
+npo_status npo_plan_set_radial_block(npo_plan plan, int32_t rg);
+npo_status npo_plan_get_radial_block(npo_plan plan, int32_t* rg);
+
 /* Step graphs for the checkpointed sweeps (enable = 1): npo_forward_run and
  * npo_adjoint_run (and so npo_iterate) replay one captured HIP graph per
  * forward advance and per adjoint step (Sec. 2.3 step, Sec. 2.4 sweeps)

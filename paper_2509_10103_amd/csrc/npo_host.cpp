@@ -1405,6 +1405,20 @@ npo_status npo_plan_get_tuning(npo_plan p, int32_t* zgroup, int32_t* zb_fwd, int
     return NPO_OK;
 }
 
+npo_status npo_plan_set_radial_block(npo_plan p, int32_t rg) {
+    if (check_plan(p)) return NPO_EINVAL;
+    if (rg != 4 && rg != 8 && rg != 16) return fail(NPO_EINVAL, "rg must be 4, 8 or 16");
+    p->rg = rg;
+    drop_graphs(*p);          // launch shapes are baked into captured graphs
+    return NPO_OK;
+}
+
+npo_status npo_plan_get_radial_block(npo_plan p, int32_t* rg) {
+    if (check_plan(p) || !rg) return fail(NPO_EINVAL, "null argument");
+    *rg = p->rg;
+    return NPO_OK;
+}
+
 npo_status npo_euclid_grad(npo_plan p, const void* lam, double scale, void* out, void* stream) {
     if (check_plan(p) || !lam || !out) return fail(NPO_EINVAL, "null argument");
     HIPCHK(npo::launch_wscale(*p, CF(lam), F(out), scale, ST(stream)));
@@ -1488,7 +1502,7 @@ namespace {
 bool same_class(const npo_plan_s& a, const npo_plan_s& b) {
     return a.nr == b.nr && a.nt == b.nt && a.nz == b.nz && a.ncorr == b.ncorr && a.zgroup == b.zgroup &&
            a.zb_theta_fwd == b.zb_theta_fwd && a.zb_theta_adj == b.zb_theta_adj && a.device == b.device &&
-           a.cfl_monitor == b.cfl_monitor;
+           a.cfl_monitor == b.cfl_monitor && a.rg == b.rg;
 }
 
 void drop_phase(npo_batch_s::Phase& f) {

@@ -124,6 +124,7 @@ struct npo_plan_s {
     // launch shapes
     int zb_theta_fwd = 4, zb_theta_adj = 4;
     int zgroup = 1;
+    int rg = 16;          // |k| per radial block (4, 8 or 16)
     mutable npo::Profiler prof;
     // CFL monitor of the forward steps (npo_plan_set_cfl_monitor)
     bool cfl_monitor = false;

@@ -357,19 +357,19 @@ __device__ __forceinline__ double2 taps13(const KP& p, const double* T, int pi, 
 // times a few m: neighbouring groups share the 128-byte lines their runs
 // straddle (a row is 8176 bytes at K = 255, so most runs are not line
 // aligned), and neighbouring m share Helmholtz operators (n = m +- 1).
-// Sixteen |k| per block (256-byte runs, eight waves, one block per CU by LDS)
-// measured 7-10% faster than eight (two blocks of four waves per CU) and 30%
-// faster than four at 64 x 96 x 768.
-constexpr int RG = 16;
-constexpr int RQ = 2 * RG;
-constexpr int RT = 512;    // threads per radial block
-constexpr int RJ = RT / RQ; // radial rows handled concurrently
+// RG |k| per block is the plan's tuning value rg (4, 8 or 16; RQ = 2 RG
+// modes, 32 RG threads, RJ = 16 radial rows at a time): sixteen (256-byte
+// runs, eight waves, one block per CU by LDS) measured 7-10% faster than eight
+// (two blocks of four waves per CU) and 30% faster than four at 64 x 96 x 768,
+// but a small grid then has few blocks (a 32 x 24 x 96 instance: 16).
+constexpr int RJ = 16;     // radial rows handled concurrently
 constexpr int GB = 8;      // |k| groups per band of logical blocks
 
-__host__ __device__ __forceinline__ int radial_groups(int K) { return (K + 1 + RG - 1) / RG; }
+__host__ __device__ __forceinline__ int radial_groups(int K, int rg) { return (K + 1 + rg - 1) / rg; }
 
+template <int RG>
 __device__ __forceinline__ bool block_group(const KP& p, int& g, int& m) {
-    const int ng = radial_groups(p.K);
+    const int ng = radial_groups(p.K, RG);
     const int nb = ng * p.mp1;
     const int per = (nb + 7) / 8;
     const int b = blockIdx.x;
@@ -388,6 +388,7 @@ struct Slot {
     double al;
     bool valid, mean;
 };
+template <int RG>
 __device__ __forceinline__ Slot slot_of(const KP& p, int g, int m, int q) {
     Slot s;
     s.ka = g * RG + (q >> 1);
@@ -402,8 +403,8 @@ __device__ __forceinline__ Slot slot_of(const KP& p, int g, int m, int q) {
 // ------------------------------------------------------------ forward solve
 // Lanes are (radial row, mode) in the pointwise phases and independent real
 // right-hand sides (operator, mode, re/im) in the substitution phases.
-template <int kind, int NRC>
-__global__ __launch_bounds__(RT) void k_solve(KP p, const double2* __restrict__ ain,
+template <int kind, int NRC, int RG>
+__global__ __launch_bounds__(32 * RG) void k_solve(KP p, const double2* __restrict__ ain,
                                               const double2* __restrict__ bin, double2* __restrict__ uout,
                                               double2* __restrict__ auxout, double2* __restrict__ r0out,
                                               const BDesc* bd) {
@@ -412,13 +413,14 @@ __global__ __launch_bounds__(RT) void k_solve(KP p, const double2* __restrict__ 
         p = d.kp; globalize(p, bd); ain = rebase(bd, d.in[0]); bin = rebase(bd, d.in[1]); uout = rebase(bd, d.out[0]); auxout = rebase(bd, d.out[1]); r0out = rebase(bd, d.out[2]);
     }
     int g, m;
-    if (!block_group(p, g, m)) return;
+    constexpr int RQ = 2 * RG;
+    if (!block_group<RG>(p, g, m)) return;
     const int t = threadIdx.x, q = t % RQ, jg = t / RQ;
     const int nr = p.nr, N1 = nr - 1;
     const double re2 = 0.5 / p.re, idt = 1.0 / p.dt;
     const int pe = m & 1, po = (m + 1) & 1;
     const size_t opsz = (size_t)N1 * LUW;
-    const Slot sl = slot_of(p, g, m, q);
+    const Slot sl = slot_of<RG>(p, g, m, q);
     const double a2 = sl.al * sl.al;
     __shared__ double2 sR[3][NR_MAX][RQ];
     __shared__ double2 sp[NR_MAX][RQ];
@@ -533,7 +535,7 @@ __global__ __launch_bounds__(RT) void k_solve(KP p, const double2* __restrict__ 
     __syncthreads();
     if (t < 2 * RQ) {
         const int qq = t % RQ, part = t / RQ;
-        const Slot s2 = slot_of(p, g, m, qq);
+        const Slot s2 = slot_of<RG>(p, g, m, qq);
         if (s2.valid && !s2.mean)
             subst<NRC ? NRC - 1 : 0>(p.PLU + ((size_t)s2.ka * p.mp1 + m) * opsz, N1,
                                      reinterpret_cast<double*>(&sp[0][qq]) + part, 2 * RQ);
@@ -559,7 +561,7 @@ __global__ __launch_bounds__(RT) void k_solve(KP p, const double2* __restrict__ 
     if (t < 6 * RQ) {
         // lane = (operator, mode, re/im): H_{m+1} u+, H_{|m-1|} u-, H_m u_z (mean mode: H_1 u_theta, H_0 u_z)
         const int qq = t % RQ, part = (t / RQ) & 1, op = t / (2 * RQ);
-        const Slot s2 = slot_of(p, g, m, qq);
+        const Slot s2 = slot_of<RG>(p, g, m, qq);
         if (s2.valid && !(s2.mean && op == 0)) {
             const int n = op == 0 ? m + 1 : (op == 1 ? abs(m - 1) : m);
             subst<NRC ? NRC - 1 : 0>(p.HLU + ((size_t)s2.ka * (p.M + 2) + n) * opsz, N1,
@@ -657,8 +659,8 @@ struct AdjOut {
     double2* Zout;
     double qy, qz, sy, sz;
 };
-template <bool useB, int NRC>
-__global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, double ca, const double2* Bin, double cb,
+template <bool useB, int NRC, int RG>
+__global__ __launch_bounds__(32 * RG) void k_solve_adj(KP p, const double2* Ain, double ca, const double2* Bin, double cb,
                                                   AdjOut ao, const BDesc* bd) {
     if (bd) {
         const BDesc& d = bd[blockIdx.z];
@@ -667,12 +669,13 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
         ca = d.s[0]; cb = d.s[1]; ao.qy = d.s[2]; ao.qz = d.s[3]; ao.sy = d.s[4]; ao.sz = d.s[5];
     }
     int g, m;
-    if (!block_group(p, g, m)) return;
+    constexpr int RQ = 2 * RG;
+    if (!block_group<RG>(p, g, m)) return;
     const int t = threadIdx.x, q = t % RQ, jg = t / RQ;
     const int nr = p.nr, N1 = nr - 1;
     const int pe = m & 1, po = (m + 1) & 1;
     const size_t opsz = (size_t)N1 * LUW;
-    const Slot sl = slot_of(p, g, m, q);
+    const Slot sl = slot_of<RG>(p, g, m, q);
     constexpr int NJ = NR_MAX / RJ;
     __shared__ double2 sy[3][NR_MAX][RQ];
     __shared__ double2 sphi[NR_MAX][RQ];
@@ -777,7 +780,7 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
     __syncthreads();
     if (t < 6 * RQ) {
         const int qq = t % RQ, part = (t / RQ) & 1, op = t / (2 * RQ);
-        const Slot s2 = slot_of(p, g, m, qq);
+        const Slot s2 = slot_of<RG>(p, g, m, qq);
         if (s2.valid && !(s2.mean && op == 0)) {
             const int n = op == 0 ? m + 1 : (op == 1 ? abs(m - 1) : m);
             subst_T<NRC ? NRC - 1 : 0>(p.HLU + ((size_t)s2.ka * (p.M + 2) + n) * opsz, N1,
@@ -800,7 +803,7 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
     __syncthreads();
     if (t < 2 * RQ) {
         const int qq = t % RQ, part = t / RQ;
-        const Slot s2 = slot_of(p, g, m, qq);
+        const Slot s2 = slot_of<RG>(p, g, m, qq);
         if (s2.valid && !s2.mean)
             subst_T<NRC ? NRC - 1 : 0>(p.PLU + ((size_t)s2.ka * p.mp1 + m) * opsz, N1,
                                        reinterpret_cast<double*>(&sphi[0][qq]) + part,
@@ -860,7 +863,8 @@ __global__ __launch_bounds__(RT) void k_solve_adj(KP p, const double2* Ain, doub
 // out = E^dag Z + A + curl^dag B  (Z, A, B optional).  All inputs are
 // requested up front; Z, then B, is staged in LDS and every transposed
 // stencil reads it there through the 13-tap tables.
-__global__ __launch_bounds__(RT) void k_final(KP p, const double2* __restrict__ Z, const double2* __restrict__ Ain,
+template <int RG>
+__global__ __launch_bounds__(32 * RG) void k_final(KP p, const double2* __restrict__ Z, const double2* __restrict__ Ain,
                                               const double2* __restrict__ Bin, double2* __restrict__ out,
                                               const BDesc* bd) {
     if (bd) {
@@ -868,10 +872,11 @@ __global__ __launch_bounds__(RT) void k_final(KP p, const double2* __restrict__ 
         p = d.kp; globalize(p, bd); Z = rebase(bd, d.in[0]); Ain = rebase(bd, d.in[1]); Bin = rebase(bd, d.in[2]); out = rebase(bd, d.out[0]);
     }
     int g, m;
-    if (!block_group(p, g, m)) return;
+    constexpr int RQ = 2 * RG;
+    if (!block_group<RG>(p, g, m)) return;
     const int t = threadIdx.x, q = t % RQ, jg = t / RQ;
     const int nr = p.nr;
-    const Slot sl = slot_of(p, g, m, q);
+    const Slot sl = slot_of<RG>(p, g, m, q);
     const int kk = sl.kk;
     const double a2 = sl.al * sl.al;
     const double re2 = 0.5 / p.re, idt = 1.0 / p.dt;
@@ -1312,75 +1317,103 @@ hipError_t launch_curl_add(const npo_plan_s& p, const double2* a, const double2*
     hipLaunchKernelGGL(k_curl_add, dim3(gx), dim3(256), 0, st, p.kp, a, b, out);
     return hipGetLastError();
 }
-template <int R>
+// Radial launches: blocks of 32 RG threads over radial_groups(K, RG) |k|
+// groups times M + 1 azimuthal indices (padded to a multiple of 8 for the
+// XCD placement), RG the plan's rg.
+static unsigned radial_grid(const npo_plan_s& p) {
+    return (unsigned)((radial_groups(p.K, p.rg) * p.mp1 + 7) / 8 * 8);
+}
+template <int R, int G>
 static hipError_t launch_solve_r(const npo_plan_s& p, int kid, int kind, unsigned gx, const BDesc& d,
                                  const double2* a, const double2* b, double2* u_out, double2* aux_out,
                                  double2* r0_out, hipStream_t st) {
     const KP kp = p.kp;
     return issue(p, kid, d, st, [=](const BDesc* bd, int nb, hipStream_t s) {
-        const dim3 grid(gx, 1, nb);
-        if (kind == 1) hipLaunchKernelGGL((k_solve<1, R>), grid, dim3(RT), 0, s, kp, a, b, u_out, aux_out, r0_out, bd);
+        const dim3 grid(gx, 1, nb), blk(32 * G);
+        if (kind == 1) hipLaunchKernelGGL((k_solve<1, R, G>), grid, blk, 0, s, kp, a, b, u_out, aux_out, r0_out, bd);
         else if (kind == 2)
-            hipLaunchKernelGGL((k_solve<2, R>), grid, dim3(RT), 0, s, kp, a, b, u_out, aux_out, r0_out, bd);
-        else hipLaunchKernelGGL((k_solve<0, R>), grid, dim3(RT), 0, s, kp, a, b, u_out, aux_out, r0_out, bd);
+            hipLaunchKernelGGL((k_solve<2, R, G>), grid, blk, 0, s, kp, a, b, u_out, aux_out, r0_out, bd);
+        else hipLaunchKernelGGL((k_solve<0, R, G>), grid, blk, 0, s, kp, a, b, u_out, aux_out, r0_out, bd);
     });
+}
+template <int G>
+static hipError_t launch_solve_g(const npo_plan_s& p, int kid, int kind, unsigned gx, const BDesc& d,
+                                 const double2* a, const double2* b, double2* u_out, double2* aux_out,
+                                 double2* r0_out, hipStream_t st) {
+    switch (p.nr) {
+#define NPO_CASE(R)                                                                          \
+    case R:                                                                                  \
+        return launch_solve_r<R, G>(p, kid, kind, gx, d, a, b, u_out, aux_out, r0_out, st);
+        NPO_NR_SIZES(NPO_CASE)
+#undef NPO_CASE
+    default:
+        return launch_solve_r<0, G>(p, kid, kind, gx, d, a, b, u_out, aux_out, r0_out, st);
+    }
 }
 hipError_t launch_solve(const npo_plan_s& p, int kind, const double2* a, const double2* b, double2* u_out,
                         double2* aux_out, hipStream_t st, double2* r0_out) {
     const int kid = kind == 1 ? KID_SOLVE_P : (kind == 2 ? KID_SOLVE_C : KID_SOLVE_R);
-    const unsigned gx = (unsigned)((radial_groups(p.K) * p.mp1 + 7) / 8 * 8);
+    const unsigned gx = radial_grid(p);
     BDesc d = desc_of(p);
     d.in[0] = a; d.in[1] = b;
     d.out[0] = u_out; d.out[1] = aux_out; d.out[2] = r0_out;
-    switch (p.nr) {
-#define NPO_CASE(R)                                                                       \
-    case R:                                                                               \
-        return launch_solve_r<R>(p, kid, kind, gx, d, a, b, u_out, aux_out, r0_out, st);
-        NPO_NR_SIZES(NPO_CASE)
-#undef NPO_CASE
-    default:
-        return launch_solve_r<0>(p, kid, kind, gx, d, a, b, u_out, aux_out, r0_out, st);
-    }
+    if (p.rg == 4) return launch_solve_g<4>(p, kid, kind, gx, d, a, b, u_out, aux_out, r0_out, st);
+    if (p.rg == 8) return launch_solve_g<8>(p, kid, kind, gx, d, a, b, u_out, aux_out, r0_out, st);
+    return launch_solve_g<16>(p, kid, kind, gx, d, a, b, u_out, aux_out, r0_out, st);
 }
-template <int R>
+template <int R, int G>
 static hipError_t launch_solve_adj_r(const npo_plan_s& p, unsigned gx, const BDesc& d, const double2* A, double ca,
                                      const double2* B, double cb, AdjOut ao, hipStream_t st) {
     const KP kp = p.kp;
     return issue(p, B ? KID_SOLVE_ADJ2 : KID_SOLVE_ADJ, d, st, [=](const BDesc* bd, int nb, hipStream_t s) {
-        const dim3 grid(gx, 1, nb);
-        if (B) hipLaunchKernelGGL((k_solve_adj<true, R>), grid, dim3(RT), 0, s, kp, A, ca, B, cb, ao, bd);
-        else hipLaunchKernelGGL((k_solve_adj<false, R>), grid, dim3(RT), 0, s, kp, A, ca, B, cb, ao, bd);
+        const dim3 grid(gx, 1, nb), blk(32 * G);
+        if (B) hipLaunchKernelGGL((k_solve_adj<true, R, G>), grid, blk, 0, s, kp, A, ca, B, cb, ao, bd);
+        else hipLaunchKernelGGL((k_solve_adj<false, R, G>), grid, blk, 0, s, kp, A, ca, B, cb, ao, bd);
     });
+}
+template <int G>
+static hipError_t launch_solve_adj_g(const npo_plan_s& p, unsigned gx, const BDesc& d, const double2* A, double ca,
+                                     const double2* B, double cb, AdjOut ao, hipStream_t st) {
+    switch (p.nr) {
+#define NPO_CASE(R)                                                               \
+    case R:                                                                       \
+        return launch_solve_adj_r<R, G>(p, gx, d, A, ca, B, cb, ao, st);
+        NPO_NR_SIZES(NPO_CASE)
+#undef NPO_CASE
+    default:
+        return launch_solve_adj_r<0, G>(p, gx, d, A, ca, B, cb, ao, st);
+    }
 }
 hipError_t launch_solve_adj(const npo_plan_s& p, const double2* A, double ca, const double2* B, double cb,
                             double2* out0, const double2* Yin, double qy, double2* Yout, const double2* Zin,
                             double qz, double2* Zout, hipStream_t st, double sy, double sz) {
     AdjOut ao{out0, Yin, Yout, Zin, Zout, qy, qz, sy, sz};
-    const unsigned gx = (unsigned)((radial_groups(p.K) * p.mp1 + 7) / 8 * 8);
+    const unsigned gx = radial_grid(p);
     BDesc d = desc_of(p);
     d.in[0] = A; d.in[1] = B; d.in[2] = Yin; d.in[3] = Zin;
     d.out[0] = out0; d.out[1] = Yout; d.out[2] = Zout;
     d.s[0] = ca; d.s[1] = cb; d.s[2] = qy; d.s[3] = qz; d.s[4] = sy; d.s[5] = sz;
-    switch (p.nr) {
-#define NPO_CASE(R)                                                            \
-    case R:                                                                    \
-        return launch_solve_adj_r<R>(p, gx, d, A, ca, B, cb, ao, st);
-        NPO_NR_SIZES(NPO_CASE)
-#undef NPO_CASE
-    default:
-        return launch_solve_adj_r<0>(p, gx, d, A, ca, B, cb, ao, st);
-    }
+    if (p.rg == 4) return launch_solve_adj_g<4>(p, gx, d, A, ca, B, cb, ao, st);
+    if (p.rg == 8) return launch_solve_adj_g<8>(p, gx, d, A, ca, B, cb, ao, st);
+    return launch_solve_adj_g<16>(p, gx, d, A, ca, B, cb, ao, st);
+}
+template <int G>
+static hipError_t launch_final_g(const npo_plan_s& p, unsigned gx, const BDesc& d, const double2* Z,
+                                 const double2* A, const double2* B, double2* out, hipStream_t st) {
+    const KP kp = p.kp;
+    return issue(p, KID_FINAL, d, st, [=](const BDesc* bd, int nb, hipStream_t s) {
+        hipLaunchKernelGGL((k_final<G>), dim3(gx, 1, nb), dim3(32 * G), 0, s, kp, Z, A, B, out, bd);
+    });
 }
 hipError_t launch_final(const npo_plan_s& p, const double2* Z, const double2* A, const double2* B, double2* out,
                         hipStream_t st) {
     BDesc d = desc_of(p);
     d.in[0] = Z; d.in[1] = A; d.in[2] = B;
     d.out[0] = out;
-    const KP kp = p.kp;
-    const unsigned gx = (unsigned)((radial_groups(p.K) * p.mp1 + 7) / 8 * 8);
-    return issue(p, KID_FINAL, d, st, [=](const BDesc* bd, int nb, hipStream_t s) {
-        hipLaunchKernelGGL(k_final, dim3(gx, 1, nb), dim3(RT), 0, s, kp, Z, A, B, out, bd);
-    });
+    const unsigned gx = radial_grid(p);
+    if (p.rg == 4) return launch_final_g<4>(p, gx, d, Z, A, B, out, st);
+    if (p.rg == 8) return launch_final_g<8>(p, gx, d, Z, A, B, out, st);
+    return launch_final_g<16>(p, gx, d, Z, A, B, out, st);
 }
 
 hipError_t launch_wdot(const npo_plan_s& p, const double2* a, const double2* b, double* partial, double* out,

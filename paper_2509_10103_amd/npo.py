@@ -81,6 +81,8 @@ SIGNATURES = {
     "npo_euclid_grad": (_I32, [_P, _P, _D, _P, _P]),
     "npo_plan_set_tuning": (_I32, [_P, _I32, _I32, _I32]),
     "npo_plan_get_tuning": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "npo_plan_set_radial_block": (_I32, [_P, _I32]),
+    "npo_plan_get_radial_block": (_I32, [_P, ctypes.POINTER(_I32)]),
     "npo_plan_set_graphs": (_I32, [_P, _I32]),
     "npo_plan_set_cfl_monitor": (_I32, [_P, _I32]),
     "npo_plan_set_adjoint": (_I32, [_P, _I32]),
@@ -367,6 +369,16 @@ def npo_normalize(plan, ws, u, e0, stream=None):
 
 def npo_plan_set_tuning(plan, zgroup, zb_fwd, zb_adj):
     _check(lib().npo_plan_set_tuning(plan, zgroup, zb_fwd, zb_adj))
+
+
+def npo_plan_set_radial_block(plan, rg):
+    _check(lib().npo_plan_set_radial_block(plan, rg))
+
+
+def npo_plan_get_radial_block(plan):
+    a = _I32()
+    _check(lib().npo_plan_get_radial_block(plan, ctypes.byref(a)))
+    return a.value
 
 
 def npo_plan_set_graphs(plan, enable):

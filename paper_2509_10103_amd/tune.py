@@ -1,11 +1,15 @@
-"""Autotuner of the transform launch shapes.
+"""Autotuner of the launch shapes.
 
 For one grid shape it times the forward and the adjoint step of a plan under
-every admissible (zgroup, zb_fwd, zb_adj), with HIP events on the stream the
-kernels run on, and keeps the fastest.  Results are cached per shape class
-(nr, ntheta, nz) in a JSON file so that batched and served runs tune once.
+every admissible transform shape (zgroup, zb_fwd, zb_adj), with HIP events on
+the stream the kernels run on, keeps the fastest, and then times the radial
+kernels' block size rg (|k| per block: 4, 8 or 16) under that shape.
+Results are cached per shape class (nr, ntheta, nz) in a JSON file so that
+batched and served runs tune once; an entry without rg keeps the default 16.
 Shapes never change results (the tests run under several of them).
 """
+
+RADIAL_BLOCKS = (4, 8, 16)
 import itertools
 import json
 import os
@@ -71,6 +75,7 @@ def tune(plan, nr, nt, nz, reps=3, use_cache=True, save=True, batched=False):
                 best = npo.npo_plan_get_tuning(plan.handle)
                 best = tuple(max(b, 2) if b < 0 else b for b in best)
         npo.npo_plan_set_tuning(plan.handle, *best)
+        npo.npo_plan_set_radial_block(plan.handle, int(rec.get("rg", 16)))
         return best, rec
     u = torch.randn(plan.shape, dtype=torch.complex128, device=plan.device) * 1e-3
     lam = torch.randn(plan.shape, dtype=torch.complex128, device=plan.device)
@@ -82,8 +87,15 @@ def tune(plan, nr, nt, nz, reps=3, use_cache=True, save=True, batched=False):
         timings[c] = _time_steps(plan, u, lam, reps)
     best = min(timings, key=timings.get)
     npo.npo_plan_set_tuning(plan.handle, *best)
-    rec = {"shape": list(best), "ms_fwd_plus_adj": timings[best],
-           "all": {",".join(map(str, c)): v for c, v in timings.items()}}
+    rg_ms = {}
+    for rg in RADIAL_BLOCKS:
+        npo.npo_plan_set_radial_block(plan.handle, rg)
+        rg_ms[rg] = _time_steps(plan, u, lam, reps)
+    rg = min(rg_ms, key=rg_ms.get)
+    npo.npo_plan_set_radial_block(plan.handle, rg)
+    rec = {"shape": list(best), "rg": rg, "ms_fwd_plus_adj": min(timings[best], rg_ms[rg]),
+           "all": {",".join(map(str, c)): v for c, v in timings.items()},
+           "rg_ms": {str(k): v for k, v in rg_ms.items()}}
     if save:
         cache = load_cache()
         cache[key] = rec

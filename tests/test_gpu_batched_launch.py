@@ -67,6 +67,40 @@ def test_batched_sweeps_equal_alone_bitwise():
         G.close()
 
 
+def test_radial_block_sizes_split_classes_and_keep_results():
+    """Instances of one grid with different radial block sizes fall into
+    classes of their own; every instance still equals its own calls bitwise."""
+    from paper_2509_10103_amd import npo
+    plans, u0s = _setup()
+    npo.npo_plan_set_radial_block(plans[1].handle, 4)
+    npo.npo_plan_set_radial_block(plans[3].handle, 8)
+    nck = 4
+    ref = []
+    for G, u0 in zip(plans, u0s):
+        ck = G.arena(nck)
+        uN, lam = G.field(), G.field()
+        npo.npo_forward_run(G.handle, G.ws, ck, nck, u0, uN)
+        npo.npo_adjoint_run(G.handle, G.ws, ck, nck, uN, lam)
+        ref.append((to_host(uN), to_host(lam)))
+    handles = [G.handle for G in plans]
+    b = npo.npo_batch_create(handles)
+    ws = [G.ws for G in plans]
+    cks = [G.arena(nck) for G in plans]
+    uNs = [G.field() for G in plans]
+    lams = [G.field() for G in plans]
+    print("[batch] lockstep sweeps with mixed radial blocks", flush=True)
+    npo.npo_batch_forward_run(b, handles, ws, cks, nck, u0s, uNs)
+    npo.npo_batch_adjoint_run(b, handles, ws, cks, nck, uNs, lams)
+    for i, (ru, rl) in enumerate(ref):
+        assert np.array_equal(to_host(uNs[i]), ru), i
+        assert np.array_equal(to_host(lams[i]), rl), i
+    info = npo.npo_batch_info(b)
+    assert info["classes"] == 5 and info["batched"] == 5
+    npo.npo_batch_destroy(b)
+    for G in plans:
+        G.close()
+
+
 def test_batched_step_launches_do_not_grow_with_instances():
     """One batched step: bitwise equal to each instance's npo_forward_step /
     npo_adjoint_step at its step index, and the launch count of a batched class

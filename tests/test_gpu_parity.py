@@ -188,6 +188,33 @@ def test_adjoint_step(prob):
     assert relerr(P, to_host(out), ref) < 1e-11 * f
 
 
+def test_radial_block_size_does_not_change_results(prob):
+    """The radial kernels' block size (|k| per block) regroups the modes over
+    blocks without touching any mode's arithmetic: the solve, its transpose and
+    whole steps are bitwise the same for rg = 4, 8 and 16."""
+    P, G, u, y, f = prob
+    from paper_2509_10103_amd import npo
+    base = npo.npo_plan_get_radial_block(G.handle)
+    R = to_dev(P.N(u, 0.3))
+    outs = {}
+    for rg in (16, 8, 4):
+        npo.npo_plan_set_radial_block(G.handle, rg)
+        assert npo.npo_plan_get_radial_block(G.handle) == rg
+        s, sa, a, b = G.field(), G.field(), G.field(), G.field()
+        npo.npo_solve(G.handle, G.ws, R, s)
+        npo.npo_solve_adj(G.handle, G.ws, to_dev(y), sa)
+        npo.npo_forward_step(G.handle, G.ws, to_dev(u), a, 2)
+        npo.npo_adjoint_step(G.handle, G.ws, to_dev(u), to_dev(y), b, 2)
+        outs[rg] = [to_host(x) for x in (s, sa, a, b)]
+    npo.npo_plan_set_radial_block(G.handle, base)
+    for rg in (8, 4):
+        for got, ref in zip(outs[rg], outs[16]):
+            assert np.array_equal(got, ref), rg
+    for bad in (0, 2, 12, 32):
+        assert npo.lib().npo_plan_set_radial_block(G.handle, bad) == -1      # NPO_EINVAL
+    assert npo.npo_plan_get_radial_block(G.handle) == base
+
+
 def test_launch_shapes_do_not_change_results(prob):
     P, G, u, y, f = prob
     from paper_2509_10103_amd import npo, tune
