@@ -50,13 +50,13 @@ def short_name(full):
     return n
 
 
-def family_kernels(nt, nz, names=(), shapes=(1, 4, 4), nr=64):
+def family_kernels(nt, nz, names=(), shapes=(1, 4, 4), nr=64, rg=16):
     """Kernel name of each bench.py kernel family for transform lengths nt, nz,
-    radial size nr and launch shapes (zgroup, azimuthal z-block forward,
-    adjoint); the generic kernels stand in where `names` (the names seen in a
-    profile) holds no compile-time-sized one."""
+    radial size nr, launch shapes (zgroup, azimuthal z-block forward,
+    adjoint) and radial block size rg; the generic kernels stand in where
+    `names` (the names seen in a profile) holds no compile-time-sized one."""
     zbf, zba = shapes[1], shapes[2]
-    nrc = nr if (f"k_solve<1, {nr}>" in names or f"k_solve<2, {nr}>" in names or not names) else 0
+    nrc = nr if (f"k_solve<1, {nr}, {rg}>" in names or f"k_solve<2, {nr}, {rg}>" in names or not names) else 0
     pz = nz % 12 == 0                       # pruned axial kernels for N_z = 3P,
     # with two m per block for the three-field passes
     zk = "p" if pz else "t"
@@ -78,8 +78,9 @@ def family_kernels(nt, nz, names=(), shapes=(1, 4, 4), nr=64):
     return {
         "curl": "k_curl_aux", "zinv_fwd": zi(6), "theta_fwd": th(0), "zfwd_fwd": zf(3),
         "zinv_adj": zi(9), "theta_adj": th(1), "zfwd_adj": zf(6), "zinv_adjy": zi(3),
-        "solve_pred": f"k_solve<1, {nrc}>", "solve_corr": f"k_solve<2, {nrc}>", "solve_raw": f"k_solve<0, {nrc}>",
-        "solve_adj": f"k_solve_adj<false, {nrc}>", "solve_adj2": f"k_solve_adj<true, {nrc}>", "adj_combine": "k_final",
+        "solve_pred": f"k_solve<1, {nrc}, {rg}>", "solve_corr": f"k_solve<2, {nrc}, {rg}>",
+        "solve_raw": f"k_solve<0, {nrc}, {rg}>", "solve_adj": f"k_solve_adj<false, {nrc}, {rg}>",
+        "solve_adj2": f"k_solve_adj<true, {nrc}, {rg}>", "adj_combine": f"k_final<{rg}>",
         "wdot": "k_wdot_partial", "project": "k_project", "axpby": "k_axpby",
     }
 
@@ -97,7 +98,7 @@ def trace(stats_csv, bench_log, out_md, command):
     bench = json.loads([ln for ln in open(bench_log).read().splitlines() if ln.startswith('{"metric"')][-1])
     cfg = bench["config"]
     fam = family_kernels(cfg["grid"][1], cfg["grid"][2], {short_name(r["Name"]) for r in rows},
-                         cfg.get("launch_shapes") or (1, 4, 4), cfg["grid"][0])
+                         cfg.get("launch_shapes") or (1, 4, 4), cfg["grid"][0], cfg.get("radial_block", 16))
     inv = {v: k for k, v in fam.items()}
     lines = [f"# Kernel trace: {cfg['workload']}", "",
              f"Command (repository root, one MI355X): `{command}`", "",
