@@ -76,3 +76,22 @@ def test_footprint_estimate_bounds_the_workspace(ncorr):
                      c["nsteps"], ncorr)
         assert serve.estimate_workspace(c) >= G.info["workspace_bytes"], (c["nr"], c["nt"], c["nz"], ncorr)
         del G
+
+
+def test_autotuner_times_the_radial_block_sizes(tmp_path, monkeypatch):
+    """The tuner times every transform shape, then the radial block sizes
+    under the winner, leaves the plan on the fastest of each, and a cached
+    entry restores both."""
+    from paper_2509_10103_amd import npo, tune
+    monkeypatch.setattr(tune, "CACHE", str(tmp_path / "tune.json"))
+    G = npo.Plan(16, 12, 24, 2 * np.pi, 1500.0, 8.0, 1.0, 0.02, 0.3, 1)
+    print("[tune] 16x12x24", flush=True)
+    best, rec = tune.tune(G, 16, 12, 24, reps=1)
+    assert sorted(rec["rg_ms"]) == ["16", "4", "8"]
+    assert str(rec["rg"]) == min(rec["rg_ms"], key=lambda k: rec["rg_ms"][k]) and isinstance(rec["rg"], int)
+    assert tuple(npo.npo_plan_get_tuning(G.handle)) == tuple(best)
+    assert npo.npo_plan_get_radial_block(G.handle) == rec["rg"]
+    npo.npo_plan_set_radial_block(G.handle, 16 if rec["rg"] != 16 else 4)
+    best2, rec2 = tune.tune(G, 16, 12, 24)
+    assert tuple(best2) == tuple(best) and npo.npo_plan_get_radial_block(G.handle) == rec["rg"]
+    G.close()
