@@ -16,30 +16,37 @@ namespace npo {
 
 // ------------------------------------------------------------ vorticity aux
 // aux[0] = w_theta = i a u_r - D1 u_z ; aux[1] = w_z = D1 u_theta + u_theta/r - (i m / r) u_r
-__global__ void k_curl_aux(KP p, const double2* __restrict__ u, double2* __restrict__ aux,
-                           const BDesc* bd) {
+// Grid: x over kk in tiles of CURL_T, y over (j, m) = j (M + 1) + m, so every
+// row offset is uniform over the block and no thread divides its index.
+constexpr int CURL_T = 128;
+__global__ __launch_bounds__(CURL_T) void k_curl_aux(KP p, const double2* __restrict__ u, double2* __restrict__ aux,
+                                                   const BDesc* bd) {
     if (bd) {
         const BDesc& d = bd[blockIdx.z];
         p = d.kp; globalize(p, bd); u = rebase(bd, d.in[0]); aux = rebase(bd, d.out[0]);
     }
-    const size_t per = (size_t)p.nr * p.mp1 * p.nk;
-    size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= per) return;
-    const int kk = idx % p.nk;
-    const int m = (idx / p.nk) % p.mp1;
-    const int j = idx / ((size_t)p.nk * p.mp1);
+    const int kk = blockIdx.x * CURL_T + threadIdx.x;
+    const int jm = blockIdx.y, j = jm / p.mp1, m = jm - j * p.mp1;
+    if (kk >= p.nk) return;
+    const size_t comp = (size_t)p.nr * p.mp1 * p.nk;      // one component
+    const size_t rrow = (size_t)p.mp1 * p.nk;             // one radial row of a component
+    const double2* ur0 = u + (size_t)jm * p.nk + kk;      // u_r at (j, m, kk)
     const double a = alpha_of(p, kk), r = p.r[j];
     const int c0 = p.col0[j];
     const double* d1e = p.D1 + ((m & 1) * p.nr + j) * 7;
     const double* d1o = p.D1 + (((m + 1) & 1) * p.nr + j) * 7;
+    const double2* ut0 = ur0 + comp + (ptrdiff_t)(c0 - j) * (ptrdiff_t)rrow;
+    const double2* uz0 = ut0 + comp;
     double2 duz = czero(), dut = czero();
+#pragma unroll
     for (int t = 0; t < 7; ++t) {
-        duz = caxpy(duz, d1e[t], u[fidx(p, 2, c0 + t, m, kk)]);
-        dut = caxpy(dut, d1o[t], u[fidx(p, 1, c0 + t, m, kk)]);
+        duz = caxpy(duz, d1e[t], uz0[(size_t)t * rrow]);
+        dut = caxpy(dut, d1o[t], ut0[(size_t)t * rrow]);
     }
-    const double2 ur = u[fidx(p, 0, j, m, kk)], ut = u[fidx(p, 1, j, m, kk)];
-    aux[fidx(p, 0, j, m, kk)] = csub(cscale(cmuli(ur), a), duz);
-    aux[fidx(p, 1, j, m, kk)] = csub(caxpy(dut, 1.0 / r, ut), cscale(cmuli(ur), m / r));
+    const double2 ur = ur0[0], ut = ur0[comp];
+    double2* o = aux + (size_t)jm * p.nk + kk;
+    o[0] = csub(cscale(cmuli(ur), a), duz);
+    o[comp] = csub(caxpy(dut, 1.0 / r, ut), cscale(cmuli(ur), m / r));
 }
 
 // ------------------------------------------------ continuous-adjoint term
@@ -1300,14 +1307,13 @@ hipError_t launch_step_index_batched(const BDesc* bd, int nb, long long v, int a
     return hipGetLastError();
 }
 hipError_t launch_curl_aux(const npo_plan_s& p, const double2* u, double2* aux, hipStream_t st) {
-    const size_t per = (size_t)p.nr * p.mp1 * p.nk;
     BDesc d = desc_of(p);
     d.in[0] = u;
     d.out[0] = aux;
     const KP kp = p.kp;
-    const unsigned gx = (unsigned)((per + 255) / 256);
+    const unsigned gx = (unsigned)((p.nk + CURL_T - 1) / CURL_T), gy = (unsigned)(p.nr * p.mp1);
     return issue(p, KID_CURL, d, st, [=](const BDesc* bd, int nb, hipStream_t s) {
-        hipLaunchKernelGGL(k_curl_aux, dim3(gx, 1, nb), dim3(256), 0, s, kp, u, aux, bd);
+        hipLaunchKernelGGL(k_curl_aux, dim3(gx, gy, nb), dim3(CURL_T), 0, s, kp, u, aux, bd);
     });
 }
 hipError_t launch_curl_add(const npo_plan_s& p, const double2* a, const double2* b, double2* out, hipStream_t st) {
