@@ -174,11 +174,15 @@ __device__ void gsubst_T(const double* __restrict__ LU, int n1, double* x, int s
 // unrolling, loads carried around a loop are drained at every iteration).  The
 // entries of x are read DB steps ahead into a second ring, so no LDS read is on
 // the dependence chain either (a row of x is read before its own step writes
-// it; the arithmetic and its order are unchanged).
+// it; the arithmetic and its order are unchanged).  The last PF steps of the
+// first pass, which have no rows of their own left to load, load the first PF
+// rows of the second pass, so its ring starts full instead of waiting once
+// for the whole latency.
 template <int N1, int PF, int DB = 4>
 __device__ __forceinline__ void gsubst_u(const double* __restrict__ LU, double* x, int s) {
     double y1 = 0.0, y2 = 0.0, y3 = 0.0, y4 = 0.0, y5 = 0.0;   // y_{i-1} .. y_{i-5}
     double Lr[PF][5];
+    double Ur[PF][4];                  // ring of the back substitution
 #pragma unroll
     for (int r = 0; r < PF; ++r)
         if (r < N1)
@@ -200,18 +204,24 @@ __device__ __forceinline__ void gsubst_u(const double* __restrict__ LU, double* 
         y = fma(-Lr[r][4], y1, y);
         x[i * s] = y;
         y5 = y4; y4 = y3; y3 = y2; y2 = y1; y1 = y;
-        if (i + PF < N1)
+        if (i + PF < N1) {
 #pragma unroll
             for (int c = 0; c < 5; ++c) Lr[r][c] = LU[(i + PF) * LUW + c];
+        } else if (N1 >= PF) {
+            const int kb = i + PF - N1;            // back-substitution step of this row
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Ur[kb][c] = LU[(N1 - 1 - kb) * LUW + 5 + c];
+        }
         __builtin_amdgcn_sched_barrier(0);
     }
     double x1 = 0.0, x2 = 0.0, x3 = 0.0;                       // x_{i+1} .. x_{i+3}
-    double Ur[PF][4];
+    if (N1 < PF) {
 #pragma unroll
-    for (int r = 0; r < PF; ++r)
-        if (r < N1)
+        for (int r = 0; r < PF; ++r)
+            if (r < N1)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) Ur[r][c] = LU[(N1 - 1 - r) * LUW + 5 + c];
+                for (int c = 0; c < 4; ++c) Ur[r][c] = LU[(N1 - 1 - r) * LUW + 5 + c];
+    }
 #pragma unroll
     for (int r = 0; r < DB; ++r)
         if (r < N1) xb[r] = x[(N1 - 1 - r) * s];
@@ -238,6 +248,7 @@ __device__ __forceinline__ void gsubst_T_u(const double* __restrict__ LU, double
     double z1 = 0.0, z2 = 0.0, z3 = 0.0;                       // z_{i-1} .. z_{i-3}
     double u61 = 0.0, u71 = 0.0, u72 = 0.0, u81 = 0.0, u82 = 0.0, u83 = 0.0;
     double Ur[PF][4];
+    double Lr[PF][5];                  // ring of the second pass, started in the first
 #pragma unroll
     for (int r = 0; r < PF; ++r)
         if (r < N1)
@@ -262,20 +273,26 @@ __device__ __forceinline__ void gsubst_T_u(const double* __restrict__ LU, double
         u83 = u82; u82 = u81; u81 = r8;
         u72 = u71; u71 = r7;
         u61 = r6;
-        if (i + PF < N1)
+        if (i + PF < N1) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) Ur[r][c] = LU[(i + PF) * LUW + 5 + c];
+        } else if (N1 >= PF) {
+            const int kb = i + PF - N1;            // second-pass step of this row
+#pragma unroll
+            for (int c = 0; c < 5; ++c) Lr[kb][c] = LU[(N1 - 1 - kb) * LUW + c];
+        }
         __builtin_amdgcn_sched_barrier(0);
     }
     double x1 = 0.0, x2 = 0.0, x3 = 0.0, x4 = 0.0, x5 = 0.0;   // x_{i+1} .. x_{i+5}
     double l41 = 0.0, l31 = 0.0, l32 = 0.0, l21 = 0.0, l22 = 0.0, l23 = 0.0;
     double l11 = 0.0, l12 = 0.0, l13 = 0.0, l14 = 0.0, l01 = 0.0, l02 = 0.0, l03 = 0.0, l04 = 0.0, l05 = 0.0;
-    double Lr[PF][5];
+    if (N1 < PF) {
 #pragma unroll
-    for (int r = 0; r < PF; ++r)
-        if (r < N1)
+        for (int r = 0; r < PF; ++r)
+            if (r < N1)
 #pragma unroll
-            for (int c = 0; c < 5; ++c) Lr[r][c] = LU[(N1 - 1 - r) * LUW + c];
+                for (int c = 0; c < 5; ++c) Lr[r][c] = LU[(N1 - 1 - r) * LUW + c];
+    }
 #pragma unroll
     for (int r = 0; r < DB; ++r)
         if (r < N1) xb[r] = x[(N1 - 1 - r) * s];
